@@ -27,11 +27,11 @@ def test_value_ranges():
 
 
 def test_chime_channel_statistics():
-    # noise power 3^2 * 1/2 per part (before clipping) plus a weak common term
+    # power 3^2 * (1 noise + 0.1 sky + 3 * 0.3^2 tones) = 12.3, plus rounding
     x = synth.chime_channel(256, 8192, seed=2)
     re, im = _parts(x)
     p = (re.astype(float) ** 2 + im.astype(float) ** 2).mean()
-    assert 9.0 < p < 12.0
+    assert 11.5 < p < 13.5
     z = re + 1j * im
     c = (z[:, 0] * np.conj(z[:, 1])).mean()          # common sky + tones correlate inputs
     assert abs(c) > 0.3
