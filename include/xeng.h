@@ -1,0 +1,198 @@
+/*
+ * xeng -- X-engine correlator for AMD MI355X (gfx950).  C ABI.
+ *
+ * The operation (Sec. 2.2, "Computational Requirements"; the per-channel
+ * GPU task of Sec. 2.3 and Table tab:computing): for one frequency channel
+ * of an N-input array, every time sample t carries one complex value per
+ * input, 4 bits real + 4 bits imaginary.  The correlator forms, for every
+ * pair 0 <= i <= j < N (the N(N+1)/2 products of the cost model eta,
+ * autocorrelations included),
+ *
+ *         V_ij = sum_t x_i(t) * conj(x_j(t))
+ *
+ * and integrates it over time in exact int32 accumulators that live on the
+ * device; the integrated visibilities are exported ("dumped") at a cadence
+ * chosen by the caller (Sec. 2.1 and Sec. 3.1: visibilities leave the node
+ * after substantial time integration).
+ *
+ * Sample format: one byte per complex sample; each part is offset-binary,
+ * value = nibble - 8 (range -8..7); the real part is in the high nibble
+ * unless XENG_NIBBLE_RE_LOW is set.  A flagged input is represented by the
+ * zero sample, byte 0x88.  Sample arrays are time-major: sample t of input i
+ * is at d_samples[t * row_stride + i], row_stride >= N.
+ *
+ * Visibility format (xeng_dump): int32 pairs (Re, Im), upper triangle row by
+ * row: pair (i, j), i <= j, at index k = i*N - i*(i-1)/2 + (j - i); the
+ * buffer holds N(N+1)/2 pairs = 4*N*(N+1) bytes.
+ *
+ * Exactness: every product has |Re| <= 128 and |Im| <= 120, so a slot can
+ * integrate at most xeng_max_integration() = 16,777,215 samples between
+ * dumps (128 * 16,777,215 <= 2^31 - 1).  Calls that would pass this bound
+ * are refused with XENG_EOVERFLOW, whatever the data, and change nothing.
+ *
+ * Errors: every call returns a status (never throws across the ABI).
+ * Argument, bound and budget errors are detected on the host before any
+ * work is queued and leave all state unchanged.  Device-side faults are
+ * reported as XENG_EDEVICE by the call that observes them.
+ *
+ * Streams: `hip_stream` is a hipStream_t (NULL = the default stream).  Work
+ * is queued asynchronously; buffers passed in must stay valid until the
+ * stream reaches the queued work.  Calls on one slot must be ordered on one
+ * stream.  One context is not thread-safe; distinct contexts are.
+ */
+#ifndef XENG_H
+#define XENG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define XENG_ABI_VERSION 1
+
+typedef struct xeng_ctx xeng_ctx;
+
+enum xeng_status {
+    XENG_OK = 0,
+    XENG_EINVAL = -1,     /* bad argument (null pointer, size, slot, flags) */
+    XENG_EOVERFLOW = -2,  /* integration would exceed xeng_max_integration() */
+    XENG_ENOMEM = -3,     /* device allocation failed or exceeds mem_budget */
+    XENG_EDEVICE = -4,    /* HIP runtime error or device fault */
+    XENG_EBUSY = -5,      /* resource in use */
+    XENG_ENOTSUP = -6     /* not supported on this device */
+};
+
+/* config flags */
+#define XENG_NIBBLE_RE_LOW 0x1u   /* real part in the low nibble */
+
+typedef struct {
+    int32_t n_inputs;          /* 1 <= N <= 65535 receiver-polarizations per channel */
+    int32_t n_slots;           /* independent accumulators (channels) >= 1 */
+    int32_t device;            /* HIP device ordinal */
+    uint32_t flags;            /* XENG_NIBBLE_RE_LOW or 0 */
+    int64_t mem_budget_bytes;  /* cap on device bytes for accumulators; 0 = none */
+} xeng_config;
+
+/*
+ * Create a correlator context: allocates n_slots zeroed int32 accumulators
+ * of xeng_slot_bytes(n_inputs) bytes each on `device`.  The library owns
+ * them until xeng_destroy.  Returns XENG_EINVAL for bad fields,
+ * XENG_ENOMEM if the accumulators exceed mem_budget_bytes or hipMalloc
+ * fails, XENG_EDEVICE / XENG_ENOTSUP for device problems.
+ */
+int xeng_create(const xeng_config *cfg, xeng_ctx **out);
+
+/* Free the context and its accumulators (synchronizes the device first). */
+int xeng_destroy(xeng_ctx *ctx);
+
+/*
+ * Correlate n_samples time samples of one channel into slot `slot`
+ * (Sec. 2.2, eta; the "Correlation" task of Table tab:computing):
+ *   acc[slot] += V(d_samples[0 : n_samples])
+ * d_samples: device pointer, time-major [n_samples][row_stride] bytes,
+ *   owned by the caller.  n_samples >= 0 (0 is a no-op).
+ *   row_stride >= N.
+ * Asynchronous on hip_stream.  Refuses with XENG_EOVERFLOW if the slot
+ * would integrate more than xeng_max_integration() samples.
+ */
+int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples,
+                   int64_t n_samples, int64_t row_stride, void *hip_stream);
+
+/* One unit of a batched correlation: correlate d_samples into ctx/slot. */
+typedef struct {
+    xeng_ctx *ctx;
+    int32_t slot;
+    int32_t reserved;          /* must be 0 */
+    const uint8_t *d_samples;  /* device, [n_samples][row_stride] */
+    int64_t n_samples;
+    int64_t row_stride;
+} xeng_job;
+
+/*
+ * Correlate many channels or sub-arrays, of uneven N and T, in one
+ * persistent launch (the paper runs one channel per GPU, Sec. 2.3; this
+ * call lets one GPU serve many).  Every result equals what xeng_correlate
+ * would give for that job alone.  All contexts must be on one device; a
+ * (ctx, slot) pair may appear at most once per batch.  Checks every job
+ * before queuing anything.
+ */
+int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream);
+
+/*
+ * Export the integrated visibilities of a slot (Sec. 2.1 / Sec. 3.1:
+ * integrated visibilities are exported at a chosen cadence).
+ * out: int32 [N(N+1)/2][2], device memory or host memory from
+ *   hipHostMalloc; owned by the caller.  reset != 0 zeroes the slot and its
+ *   sample counter after the export.  Asynchronous on hip_stream.
+ */
+int xeng_dump(xeng_ctx *ctx, int32_t slot, int32_t *out, int32_t reset, void *hip_stream);
+
+/* Zero one slot's accumulators and sample counter (asynchronous). */
+int xeng_reset(xeng_ctx *ctx, int32_t slot, void *hip_stream);
+
+/* Samples integrated in a slot since its last reset; -1 on bad arguments. */
+int64_t xeng_samples_integrated(const xeng_ctx *ctx, int32_t slot);
+
+/* Largest number of samples a slot may integrate between resets. */
+int64_t xeng_max_integration(void);
+
+/* Device bytes of one slot's accumulators for N inputs (admission control); -1 if N < 1. */
+int64_t xeng_slot_bytes(int32_t n_inputs);
+
+/* N and slot count of a context (-1 on NULL). */
+int32_t xeng_n_inputs(const xeng_ctx *ctx);
+int32_t xeng_n_slots(const xeng_ctx *ctx);
+
+/* Human-readable text for a status code (static storage). */
+const char *xeng_strerror(int status);
+
+/*
+ * Simple GPU reference correlator (one thread per pair, scalar int32 sums,
+ * no MFMA, no tiling) writing the packed visibilities of one call straight
+ * into d_out (overwritten, int32 [N(N+1)/2][2], device).  A debugging and
+ * cross-checking path; n_samples <= xeng_max_integration().
+ */
+int xeng_correlate_reference(const uint8_t *d_samples, int64_t n_samples, int32_t n_inputs,
+                             int64_t row_stride, uint32_t flags, int32_t *d_out,
+                             void *hip_stream);
+
+/*
+ * Work decomposition (host only, no device needed).  The correlation of a
+ * batch is split into pieces: one 128 x 128 tile of the upper triangle of
+ * one job over a contiguous range of samples, each piece run by one
+ * workgroup of the persistent launch.  Tiles cut into several pieces are
+ * flushed with integer atomic adds, the others with a plain add.
+ */
+typedef struct {
+    int32_t job;       /* index into the batch */
+    int32_t ti, tj;    /* tile row / column (units of 128 inputs), ti <= tj */
+    int32_t atomic;    /* 1 if the tile is shared with other pieces */
+    int64_t t0, t1;    /* sample range [t0, t1) */
+    int32_t workgroup; /* workgroup that runs the piece */
+    int32_t reserved;
+} xeng_piece_info;
+
+/*
+ * Fill `out` (capacity `cap`) with the pieces the library would launch for
+ * jobs of sizes (n_inputs[k], n_samples[k]) on `n_workgroups` workgroups
+ * with at least `min_stages` 32-sample stages per piece (0 = library
+ * default).  Returns the number of pieces (which may exceed cap: then only
+ * cap are written), or a negative status.
+ */
+int64_t xeng_plan_inspect(const int32_t *n_inputs, const int64_t *n_samples, int32_t n_jobs,
+                          int32_t n_workgroups, int32_t min_stages,
+                          xeng_piece_info *out, int64_t cap);
+
+/*
+ * Launch tuning: workgroups per compute unit of the persistent launch
+ * (1 or 2) and the minimum piece length in 32-sample stages.  Values <= 0
+ * keep the current setting.  Applies to later calls on every device.
+ */
+int xeng_set_tuning(int32_t wgs_per_cu, int32_t min_stages);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XENG_H */

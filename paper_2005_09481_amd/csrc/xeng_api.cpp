@@ -1,0 +1,489 @@
+// Host runtime and C ABI of the X-engine correlator: contexts and their
+// device-resident accumulators, the integration-length guard, the plan cache
+// and batched launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <list>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/xeng.h"
+#include "xeng_internal.h"
+#include "xeng_plan.h"
+
+namespace xeng {
+hipError_t launch_correlate(const KernelArgs &a, int grid, hipStream_t stream);
+hipError_t launch_dump(const int32_t *acc, int n, int nt, int32_t *out, hipStream_t stream);
+hipError_t launch_zero(int32_t *p, int64_t n_i32, hipStream_t stream);
+hipError_t launch_reference(const uint8_t *s, int64_t n_samples, int n, int64_t stride,
+                            uint32_t re_low, int32_t *out, hipStream_t stream);
+}  // namespace xeng
+
+using namespace xeng;
+
+namespace {
+
+std::atomic<int> g_wgs_per_cu{2};
+std::atomic<int> g_min_stages{8};
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+struct DevicePlan {
+    Piece *d_pieces = nullptr;
+    int32_t *d_off = nullptr;
+    int32_t grid = 0;
+};
+
+// A device buffer for job tables of batched launches, reused once the
+// event recorded after its last launch has completed.
+struct JobTable {
+    JobDesc *h = nullptr;   // pinned host staging
+    JobDesc *d = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+};
+
+constexpr int PLAN_CACHE_MAX = 64;
+constexpr int JOB_RING = 8;
+
+struct DeviceState {
+    int device = 0;
+    int cu_count = 0;
+    std::mutex mu;
+    std::unordered_map<std::string, DevicePlan> plans;
+    std::list<std::string> lru;
+    JobTable ring[JOB_RING];
+    int ring_next = 0;
+};
+
+std::mutex g_states_mu;
+std::map<int, std::unique_ptr<DeviceState>> g_states;
+
+DeviceState *device_state(int device)
+{
+    std::lock_guard<std::mutex> lk(g_states_mu);
+    auto it = g_states.find(device);
+    if (it != g_states.end()) return it->second.get();
+    auto st = std::make_unique<DeviceState>();
+    st->device = device;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        cus <= 0)
+        return nullptr;
+    st->cu_count = cus;
+    DeviceState *p = st.get();
+    g_states[device] = std::move(st);
+    return p;
+}
+
+std::string plan_key(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages)
+{
+    std::string k;
+    k.reserve(32 + 16 * (size_t)n_jobs);
+    k.append(reinterpret_cast<const char *>(&max_wgs), sizeof max_wgs);
+    k.append(reinterpret_cast<const char *>(&min_stages), sizeof min_stages);
+    for (int j = 0; j < n_jobs; ++j) {
+        k.append(reinterpret_cast<const char *>(&jobs[j].n), sizeof jobs[j].n);
+        k.append(reinterpret_cast<const char *>(&jobs[j].t), sizeof jobs[j].t);
+    }
+    return k;
+}
+
+// Look up (or build and upload) the plan for these job sizes.  Called with
+// st->mu held and the device current.
+int get_plan(DeviceState *st, const PlanJob *jobs, int n_jobs, hipStream_t stream,
+             DevicePlan *out)
+{
+    const int max_wgs = st->cu_count * std::max(1, g_wgs_per_cu.load());
+    const int min_stages = std::max(1, g_min_stages.load());
+    const std::string key = plan_key(jobs, n_jobs, max_wgs, min_stages);
+    auto it = st->plans.find(key);
+    if (it != st->plans.end()) {
+        st->lru.remove(key);
+        st->lru.push_front(key);
+        *out = it->second;
+        return XENG_OK;
+    }
+    Plan plan = make_plan(jobs, n_jobs, max_wgs, min_stages);
+    DevicePlan dp;
+    dp.grid = plan.grid;
+    if (plan.grid > 0) {
+        if (hipMalloc(&dp.d_pieces, plan.pieces.size() * sizeof(Piece)) != hipSuccess)
+            return XENG_ENOMEM;
+        if (hipMalloc(&dp.d_off, plan.wg_off.size() * sizeof(int32_t)) != hipSuccess) {
+            (void)hipFree(dp.d_pieces);
+            return XENG_ENOMEM;
+        }
+        // synchronous copies: a plan is built once per shape
+        if (hipMemcpy(dp.d_pieces, plan.pieces.data(), plan.pieces.size() * sizeof(Piece),
+                      hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(dp.d_off, plan.wg_off.data(), plan.wg_off.size() * sizeof(int32_t),
+                      hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(dp.d_pieces);
+            (void)hipFree(dp.d_off);
+            return XENG_EDEVICE;
+        }
+    }
+    (void)stream;
+    if ((int)st->plans.size() >= PLAN_CACHE_MAX) {
+        // hipFree waits for the device, so no queued launch still reads it
+        const std::string victim = st->lru.back();
+        st->lru.pop_back();
+        DevicePlan old = st->plans[victim];
+        st->plans.erase(victim);
+        if (old.d_pieces) (void)hipFree(old.d_pieces);
+        if (old.d_off) (void)hipFree(old.d_off);
+    }
+    st->plans.emplace(key, dp);
+    st->lru.push_front(key);
+    *out = dp;
+    return XENG_OK;
+}
+
+int map_err(hipError_t e)
+{
+    if (e == hipSuccess) return XENG_OK;
+    if (e == hipErrorOutOfMemory) return XENG_ENOMEM;
+    return XENG_EDEVICE;
+}
+
+}  // namespace
+
+struct xeng_ctx {
+    int32_t n = 0;
+    int32_t n_slots = 0;
+    int32_t device = 0;
+    uint32_t flags = 0;
+    int32_t nt = 0;
+    int64_t slot_i32 = 0;
+    int32_t *d_acc = nullptr;
+    std::vector<int64_t> acc_t;
+    DeviceState *st = nullptr;
+};
+
+namespace {
+
+bool slot_ok(const xeng_ctx *c, int32_t slot) { return c && slot >= 0 && slot < c->n_slots; }
+
+JobDesc make_job(const xeng_ctx *c, int32_t slot, const uint8_t *d_samples, int64_t stride)
+{
+    JobDesc jd;
+    jd.samples = d_samples;
+    jd.acc = c->d_acc + (int64_t)slot * c->slot_i32;
+    jd.stride = stride;
+    jd.n = c->n;
+    jd.nt = c->nt;
+    jd.flags = 0;
+    if (c->flags & XENG_NIBBLE_RE_LOW) jd.flags |= JOB_RE_LOW;
+    if ((stride % 4) == 0 && (reinterpret_cast<uintptr_t>(d_samples) % 4) == 0)
+        jd.flags |= JOB_ALIGNED4;
+    jd.pad = 0;
+    return jd;
+}
+
+}  // namespace
+
+extern "C" {
+
+int xeng_create(const xeng_config *cfg, xeng_ctx **out)
+{
+    if (!cfg || !out) return XENG_EINVAL;
+    *out = nullptr;
+    if (cfg->n_inputs < 1 || cfg->n_inputs > 65535 || cfg->n_slots < 1 ||
+        cfg->device < 0 || (cfg->flags & ~XENG_NIBBLE_RE_LOW) || cfg->mem_budget_bytes < 0)
+        return XENG_EINVAL;
+    const int64_t slot_bytes = slot_i32(cfg->n_inputs) * 4;
+    if (slot_bytes > INT64_MAX / cfg->n_slots) return XENG_ENOMEM;
+    const int64_t bytes = slot_bytes * cfg->n_slots;
+    if (cfg->mem_budget_bytes > 0 && bytes > cfg->mem_budget_bytes) return XENG_ENOMEM;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device >= ndev) return XENG_EDEVICE;
+
+    DeviceGuard guard(cfg->device);
+    if (!guard.ok) return XENG_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, cfg->device) != hipSuccess) return XENG_EDEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return XENG_ENOTSUP;
+    DeviceState *st = device_state(cfg->device);
+    if (!st) return XENG_EDEVICE;
+
+    auto *c = new (std::nothrow) xeng_ctx;
+    if (!c) return XENG_ENOMEM;
+    c->n = cfg->n_inputs;
+    c->n_slots = cfg->n_slots;
+    c->device = cfg->device;
+    c->flags = cfg->flags;
+    c->nt = n_tiles_side(cfg->n_inputs);
+    c->slot_i32 = slot_i32(cfg->n_inputs);
+    c->acc_t.assign((size_t)cfg->n_slots, 0);
+    c->st = st;
+    hipError_t e = hipMalloc(&c->d_acc, (size_t)bytes);
+    if (e != hipSuccess) {
+        delete c;
+        return map_err(e);
+    }
+    e = launch_zero(c->d_acc, bytes / 4, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipFree(c->d_acc);
+        delete c;
+        return map_err(e);
+    }
+    *out = c;
+    return XENG_OK;
+}
+
+int xeng_destroy(xeng_ctx *ctx)
+{
+    if (!ctx) return XENG_EINVAL;
+    int rc = XENG_OK;
+    {
+        DeviceGuard guard(ctx->device);
+        if (ctx->d_acc && hipFree(ctx->d_acc) != hipSuccess) rc = XENG_EDEVICE;
+    }
+    delete ctx;
+    return rc;
+}
+
+int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_t n_samples,
+                   int64_t row_stride, void *hip_stream)
+{
+    if (!slot_ok(ctx, slot) || n_samples < 0 || row_stride < ctx->n) return XENG_EINVAL;
+    if (n_samples > 0 && !d_samples) return XENG_EINVAL;
+    if (n_samples > T_MAX - ctx->acc_t[(size_t)slot]) return XENG_EOVERFLOW;
+    if (n_samples == 0) return XENG_OK;
+    // sample offsets t * row_stride must stay addressable
+    if (row_stride > INT64_MAX / n_samples) return XENG_EINVAL;
+
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return XENG_EDEVICE;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    PlanJob pj{ctx->n, n_samples};
+    DevicePlan dp;
+    KernelArgs a;
+    // held through the launch so that no other thread evicts the plan first
+    std::lock_guard<std::mutex> lk(ctx->st->mu);
+    int rc = get_plan(ctx->st, &pj, 1, stream, &dp);
+    if (rc != XENG_OK) return rc;
+    a.job0 = make_job(ctx, slot, d_samples, row_stride);
+    a.jobs = nullptr;
+    a.pieces = dp.d_pieces;
+    a.wg_off = dp.d_off;
+    hipError_t e = launch_correlate(a, dp.grid, stream);
+    if (e != hipSuccess) return map_err(e);
+    ctx->acc_t[(size_t)slot] += n_samples;
+    return XENG_OK;
+}
+
+int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
+{
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return XENG_EINVAL;
+    if (n_jobs == 0) return XENG_OK;
+    const int device = jobs[0].ctx ? jobs[0].ctx->device : -1;
+    std::set<std::pair<const xeng_ctx *, int32_t>> seen;
+    for (int32_t k = 0; k < n_jobs; ++k) {
+        const xeng_job &j = jobs[k];
+        if (!slot_ok(j.ctx, j.slot) || j.reserved != 0 || j.n_samples < 0 ||
+            j.row_stride < j.ctx->n || (j.n_samples > 0 && !j.d_samples) ||
+            j.ctx->device != device)
+            return XENG_EINVAL;
+        if (j.n_samples > 0 && j.row_stride > INT64_MAX / j.n_samples) return XENG_EINVAL;
+        if (!seen.insert({j.ctx, j.slot}).second) return XENG_EINVAL;
+        if (j.n_samples > T_MAX - j.ctx->acc_t[(size_t)j.slot]) return XENG_EOVERFLOW;
+    }
+    // keep only jobs with work
+    std::vector<PlanJob> pj;
+    std::vector<JobDesc> descs;
+    std::vector<int32_t> idx;
+    for (int32_t k = 0; k < n_jobs; ++k) {
+        if (jobs[k].n_samples == 0) continue;
+        pj.push_back(PlanJob{jobs[k].ctx->n, jobs[k].n_samples});
+        descs.push_back(make_job(jobs[k].ctx, jobs[k].slot, jobs[k].d_samples, jobs[k].row_stride));
+        idx.push_back(k);
+    }
+    if (pj.empty()) return XENG_OK;
+
+    DeviceGuard guard(device);
+    if (!guard.ok) return XENG_EDEVICE;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    DeviceState *st = jobs[0].ctx->st;
+    std::lock_guard<std::mutex> lk(st->mu);
+    DevicePlan dp;
+    int rc = get_plan(st, pj.data(), (int)pj.size(), stream, &dp);
+    if (rc != XENG_OK) return rc;
+
+    // stage the job table through the ring
+    JobTable &tb = st->ring[st->ring_next];
+    st->ring_next = (st->ring_next + 1) % JOB_RING;
+    hipError_t e = hipSuccess;
+    if (tb.pending) {
+        e = hipEventSynchronize(tb.ev);
+        if (e != hipSuccess) return map_err(e);
+        tb.pending = false;
+    }
+    if (!tb.ev && (e = hipEventCreateWithFlags(&tb.ev, hipEventDisableTiming)) != hipSuccess)
+        return map_err(e);
+    if (tb.cap < descs.size()) {
+        if (tb.h) (void)hipHostFree(tb.h);
+        if (tb.d) (void)hipFree(tb.d);
+        tb.h = nullptr;
+        tb.d = nullptr;
+        tb.cap = 0;
+        const size_t cap = std::max<size_t>(descs.size(), 64);
+        if ((e = hipHostMalloc(&tb.h, cap * sizeof(JobDesc), hipHostMallocDefault)) != hipSuccess)
+            return map_err(e);
+        if ((e = hipMalloc(&tb.d, cap * sizeof(JobDesc))) != hipSuccess) {
+            (void)hipHostFree(tb.h);
+            tb.h = nullptr;
+            return map_err(e);
+        }
+        tb.cap = cap;
+    }
+    std::memcpy(tb.h, descs.data(), descs.size() * sizeof(JobDesc));
+    e = hipMemcpyAsync(tb.d, tb.h, descs.size() * sizeof(JobDesc), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return map_err(e);
+    KernelArgs a;
+    std::memset(&a.job0, 0, sizeof a.job0);
+    a.jobs = tb.d;
+    a.pieces = dp.d_pieces;
+    a.wg_off = dp.d_off;
+    e = launch_correlate(a, dp.grid, stream);
+    if (e == hipSuccess) e = hipEventRecord(tb.ev, stream);
+    if (e != hipSuccess) return map_err(e);
+    tb.pending = true;
+    for (int32_t k : idx) jobs[k].ctx->acc_t[(size_t)jobs[k].slot] += jobs[k].n_samples;
+    return XENG_OK;
+}
+
+int xeng_dump(xeng_ctx *ctx, int32_t slot, int32_t *out, int32_t reset, void *hip_stream)
+{
+    if (!slot_ok(ctx, slot) || !out) return XENG_EINVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return XENG_EDEVICE;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    int32_t *acc = ctx->d_acc + (int64_t)slot * ctx->slot_i32;
+    hipError_t e = launch_dump(acc, ctx->n, ctx->nt, out, stream);
+    if (e == hipSuccess && reset) e = launch_zero(acc, ctx->slot_i32, stream);
+    if (e != hipSuccess) return map_err(e);
+    if (reset) ctx->acc_t[(size_t)slot] = 0;
+    return XENG_OK;
+}
+
+int xeng_reset(xeng_ctx *ctx, int32_t slot, void *hip_stream)
+{
+    if (!slot_ok(ctx, slot)) return XENG_EINVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return XENG_EDEVICE;
+    hipError_t e = launch_zero(ctx->d_acc + (int64_t)slot * ctx->slot_i32, ctx->slot_i32,
+                               static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return map_err(e);
+    ctx->acc_t[(size_t)slot] = 0;
+    return XENG_OK;
+}
+
+int64_t xeng_samples_integrated(const xeng_ctx *ctx, int32_t slot)
+{
+    if (!slot_ok(ctx, slot)) return -1;
+    return ctx->acc_t[(size_t)slot];
+}
+
+int64_t xeng_max_integration(void) { return T_MAX; }
+
+int64_t xeng_slot_bytes(int32_t n_inputs)
+{
+    if (n_inputs < 1) return -1;
+    return slot_i32(n_inputs) * 4;
+}
+
+int32_t xeng_n_inputs(const xeng_ctx *ctx) { return ctx ? ctx->n : -1; }
+int32_t xeng_n_slots(const xeng_ctx *ctx) { return ctx ? ctx->n_slots : -1; }
+
+const char *xeng_strerror(int status)
+{
+    switch (status) {
+    case XENG_OK: return "ok";
+    case XENG_EINVAL: return "invalid argument";
+    case XENG_EOVERFLOW: return "integration length would exceed the exact int32 bound";
+    case XENG_ENOMEM: return "out of device memory or over the memory budget";
+    case XENG_EDEVICE: return "HIP runtime error or device fault";
+    case XENG_EBUSY: return "resource busy";
+    case XENG_ENOTSUP: return "not supported on this device";
+    default: return "unknown status";
+    }
+}
+
+int xeng_correlate_reference(const uint8_t *d_samples, int64_t n_samples, int32_t n_inputs,
+                             int64_t row_stride, uint32_t flags, int32_t *d_out, void *hip_stream)
+{
+    if (!d_out || n_inputs < 1 || n_samples < 0 || row_stride < n_inputs ||
+        (flags & ~XENG_NIBBLE_RE_LOW) || (n_samples > 0 && !d_samples))
+        return XENG_EINVAL;
+    if (n_samples > T_MAX) return XENG_EOVERFLOW;
+    if (n_samples > 0 && row_stride > INT64_MAX / n_samples) return XENG_EINVAL;
+    hipError_t e = launch_reference(d_samples, n_samples, n_inputs, row_stride,
+                                    (flags & XENG_NIBBLE_RE_LOW) ? 1u : 0u, d_out,
+                                    static_cast<hipStream_t>(hip_stream));
+    return map_err(e);
+}
+
+int64_t xeng_plan_inspect(const int32_t *n_inputs, const int64_t *n_samples, int32_t n_jobs,
+                          int32_t n_workgroups, int32_t min_stages, xeng_piece_info *out,
+                          int64_t cap)
+{
+    if (n_jobs < 0 || (n_jobs > 0 && (!n_inputs || !n_samples)) || n_workgroups < 1 || cap < 0 ||
+        (cap > 0 && !out))
+        return XENG_EINVAL;
+    std::vector<PlanJob> pj((size_t)n_jobs);
+    for (int32_t k = 0; k < n_jobs; ++k) {
+        if (n_inputs[k] < 1 || n_samples[k] < 0 || n_samples[k] > T_MAX) return XENG_EINVAL;
+        pj[(size_t)k] = PlanJob{n_inputs[k], n_samples[k]};
+    }
+    if (min_stages <= 0) min_stages = g_min_stages.load();
+    Plan plan = make_plan(pj.data(), n_jobs, n_workgroups, min_stages);
+    const int64_t np = (int64_t)plan.pieces.size();
+    for (int64_t k = 0; k < np && k < cap; ++k) {
+        const Piece &p = plan.pieces[(size_t)k];
+        xeng_piece_info &o = out[k];
+        o.job = p.job;
+        o.ti = p.tile & 0xFFFF;
+        o.tj = (p.tile >> 16) & 0xFFFF;
+        o.atomic = p.t1_atomic < 0 ? 1 : 0;
+        o.t0 = p.t0;
+        o.t1 = p.t1_atomic & 0x7FFFFFFF;
+        o.workgroup = plan.piece_wg[(size_t)k];
+        o.reserved = 0;
+    }
+    return np;
+}
+
+int xeng_set_tuning(int32_t wgs_per_cu, int32_t min_stages)
+{
+    if (wgs_per_cu > 2) return XENG_EINVAL;
+    if (wgs_per_cu > 0) g_wgs_per_cu.store(wgs_per_cu);
+    if (min_stages > 0) g_min_stages.store(min_stages);
+    return XENG_OK;
+}
+
+}  // extern "C"

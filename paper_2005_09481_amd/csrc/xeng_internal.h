@@ -1,0 +1,66 @@
+// Internal layout constants and structures shared by the host runtime and
+// the gfx950 kernels.  Nothing here is part of the public ABI.
+#pragma once
+
+#include <stdint.h>
+
+namespace xeng {
+
+// ---------------------------------------------------------------------------
+// Tiling.  The upper triangle of the N x N visibility matrix (Sec. 2.2: the
+// N(N+1)/2 pairs including autocorrelations) is covered by TILE x TILE tiles
+// (ti <= tj).  A tile is computed by one workgroup as 4 x 4 MFMA blocks of
+// 32 x 32.
+// ---------------------------------------------------------------------------
+constexpr int TILE = 128;          // inputs per tile side
+constexpr int BLK = 32;            // MFMA block side
+constexpr int BLKS = TILE / BLK;   // 4 blocks per tile side
+constexpr int STAGE = 32;          // samples per pipeline stage (LDS buffer)
+constexpr int KSTEP = 16;          // samples per MFMA k-step (32 int8 values)
+
+// Accumulator layout of one slot (device, int32): tile-major over the upper
+// triangle of tiles, tile index ti*nt - ti*(ti-1)/2 + (tj-ti).  Inside a
+// tile: [ca][cb][comp][reg][lane] with ca, cb the 4 x 4 blocks, comp 0 = Re,
+// 1 = Im, and (reg, lane) the MFMA 32 x 32 accumulator register layout.
+// Rows inside a tile are permuted: tile row offset r (0..127) lives at
+// position p = 32*(r % 4) + r / 4, block ca = p / 32, row-in-block p % 32.
+constexpr int64_t TILE_I32 = (int64_t)BLKS * BLKS * 2 * 16 * 64;   // 32768 int32
+constexpr int64_t BLOCK_I32 = 2 * 16 * 64;                          // 2048 int32
+
+inline int64_t tri64(int64_t n) { return n * (n + 1) / 2; }
+inline int n_tiles_side(int n) { return (n + TILE - 1) / TILE; }
+inline int64_t slot_i32(int n) { return tri64(n_tiles_side(n)) * TILE_I32; }
+
+// Largest number of samples a slot may integrate: the largest |term| of
+// x_i conj(x_j) with parts in [-8, 7] is 128 (Re), so 128 * T_MAX <= 2^31-1.
+constexpr int64_t T_MAX = (INT64_C(2147483647)) / 128;   // 16,777,215
+
+// Job descriptor read by the kernels (one per channel / sub-array).
+struct JobDesc {
+    const uint8_t *samples;   // [T][stride]
+    int32_t *acc;             // slot accumulator base
+    int64_t stride;           // bytes between time samples
+    int32_t n;                // inputs
+    int32_t nt;               // tiles per side
+    uint32_t flags;           // JOB_* bits
+    int32_t pad;
+};
+constexpr uint32_t JOB_RE_LOW = 1u;    // real part in the low nibble
+constexpr uint32_t JOB_ALIGNED4 = 2u;  // samples and stride are 4-byte aligned
+
+// One piece of work: tile (ti, tj) of job `job` over samples [t0, t1).
+struct Piece {
+    int32_t job;
+    int32_t tile;       // ti | tj << 16
+    int32_t t0;
+    int32_t t1_atomic;  // t1 | (atomic << 31)
+};
+
+struct KernelArgs {
+    JobDesc job0;             // used when jobs == nullptr (single job)
+    const JobDesc *jobs;
+    const Piece *pieces;
+    const int32_t *wg_off;    // pieces of workgroup w: [wg_off[w], wg_off[w+1])
+};
+
+}  // namespace xeng

@@ -1,0 +1,80 @@
+// Stream-K style decomposition of the upper-triangle tiles into pieces.
+#include "xeng_plan.h"
+
+#include <algorithm>
+
+namespace xeng {
+
+Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages)
+{
+    Plan plan;
+    if (min_stages < 1) min_stages = 1;
+    if (max_wgs < 1) max_wgs = 1;
+
+    // Total work in stage units over all (job, tile) pairs.
+    int64_t total = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        if (jobs[j].t <= 0 || jobs[j].n <= 0) continue;
+        const int64_t ns = (jobs[j].t + STAGE - 1) / STAGE;
+        total += tri64(n_tiles_side(jobs[j].n)) * ns;
+    }
+    if (total == 0) {
+        plan.grid = 0;
+        plan.wg_off.assign(1, 0);
+        return plan;
+    }
+    int64_t grid = std::min<int64_t>(max_wgs, (total + min_stages - 1) / min_stages);
+    grid = std::max<int64_t>(grid, 1);
+    plan.grid = (int32_t)grid;
+    plan.wg_off.assign((size_t)grid + 1, 0);
+
+    // Workgroup w owns the linear stage range [bound(w), bound(w + 1)).
+    auto bound = [&](int64_t w) { return (w * total) / grid; };
+
+    struct Raw { Piece p; int32_t wg; };
+    std::vector<Raw> raw;
+    int64_t u = 0;   // linear stage offset of the current tile
+    for (int j = 0; j < n_jobs; ++j) {
+        if (jobs[j].t <= 0 || jobs[j].n <= 0) continue;
+        const int64_t t = jobs[j].t;
+        const int64_t ns = (t + STAGE - 1) / STAGE;
+        const int nt = n_tiles_side(jobs[j].n);
+        for (int ti = 0; ti < nt; ++ti) {
+            for (int tj = ti; tj < nt; ++tj) {
+                const int64_t lo = u, hi = u + ns;
+                // first workgroup whose range intersects [lo, hi)
+                int64_t w = (lo * grid) / total;
+                while (w > 0 && bound(w) > lo) --w;
+                while (bound(w + 1) <= lo) ++w;
+                const size_t first = raw.size();
+                for (; w < grid && bound(w) < hi; ++w) {
+                    const int64_t a = std::max(lo, bound(w)), b = std::min(hi, bound(w + 1));
+                    if (a >= b) continue;
+                    Raw r;
+                    r.p.job = j;
+                    r.p.tile = ti | (tj << 16);
+                    r.p.t0 = (int32_t)((a - lo) * STAGE);
+                    r.p.t1_atomic = (int32_t)std::min<int64_t>((b - lo) * STAGE, t);
+                    r.wg = (int32_t)w;
+                    raw.push_back(r);
+                }
+                if (raw.size() - first > 1)
+                    for (size_t k = first; k < raw.size(); ++k)
+                        raw[k].p.t1_atomic |= (int32_t)0x80000000u;
+                u = hi;
+            }
+        }
+    }
+    // Raw pieces come out ordered by workgroup already (linear order).
+    plan.pieces.reserve(raw.size());
+    plan.piece_wg.reserve(raw.size());
+    for (const Raw &r : raw) {
+        plan.pieces.push_back(r.p);
+        plan.piece_wg.push_back(r.wg);
+        plan.wg_off[(size_t)r.wg + 1]++;
+    }
+    for (size_t w = 0; w < (size_t)grid; ++w) plan.wg_off[w + 1] += plan.wg_off[w];
+    return plan;
+}
+
+}  // namespace xeng

@@ -1,0 +1,251 @@
+"""ctypes binding of ``libxeng.so`` (argument marshalling only).
+
+Every step of the correlation runs in the library's gfx950 kernels; this
+module only turns PyTorch tensors and streams into the pointers and sizes
+the C ABI takes.  PyTorch provides device memory and streams.  Importing
+the binding fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libxeng.so")
+
+XENG_OK = 0
+XENG_EINVAL = -1
+XENG_EOVERFLOW = -2
+XENG_ENOMEM = -3
+XENG_EDEVICE = -4
+XENG_EBUSY = -5
+XENG_ENOTSUP = -6
+XENG_NIBBLE_RE_LOW = 1
+
+
+class XengError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("n_inputs", ctypes.c_int32), ("n_slots", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("mem_budget_bytes", ctypes.c_int64)]
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("slot", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("d_samples", ctypes.c_void_p), ("n_samples", ctypes.c_int64),
+                ("row_stride", ctypes.c_int64)]
+
+
+class _PieceInfo(ctypes.Structure):
+    _fields_ = [("job", ctypes.c_int32), ("ti", ctypes.c_int32), ("tj", ctypes.c_int32),
+                ("atomic", ctypes.c_int32), ("t0", ctypes.c_int64), ("t1", ctypes.c_int64),
+                ("workgroup", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the library (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it first "
+                           "(python -m paper_2005_09481_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    sig = {
+        "xeng_create": (ctypes.c_int, [ctypes.POINTER(_Config), ctypes.POINTER(vp)]),
+        "xeng_destroy": (ctypes.c_int, [vp]),
+        "xeng_correlate": (ctypes.c_int, [vp, i32, vp, i64, i64, vp]),
+        "xeng_correlate_batch": (ctypes.c_int, [ctypes.POINTER(_Job), i32, vp]),
+        "xeng_dump": (ctypes.c_int, [vp, i32, vp, i32, vp]),
+        "xeng_reset": (ctypes.c_int, [vp, i32, vp]),
+        "xeng_samples_integrated": (i64, [vp, i32]),
+        "xeng_max_integration": (i64, []),
+        "xeng_slot_bytes": (i64, [i32]),
+        "xeng_n_inputs": (i32, [vp]),
+        "xeng_n_slots": (i32, [vp]),
+        "xeng_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "xeng_correlate_reference": (ctypes.c_int, [vp, i64, i32, i64, u32, vp, vp]),
+        "xeng_plan_inspect": (i64, [ctypes.POINTER(i32), ctypes.POINTER(i64), i32, i32, i32,
+                                    ctypes.POINTER(_PieceInfo), i64]),
+        "xeng_set_tuning": (ctypes.c_int, [i32, i32]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    return lib().xeng_strerror(status).decode()
+
+
+def _check(status: int, what: str):
+    if status != XENG_OK:
+        raise XengError(status, what)
+
+
+def tri(n: int) -> int:
+    return n * (n + 1) // 2
+
+
+def max_integration() -> int:
+    return int(lib().xeng_max_integration())
+
+
+def slot_bytes(n_inputs: int) -> int:
+    return int(lib().xeng_slot_bytes(n_inputs))
+
+
+def set_tuning(wgs_per_cu: int = 0, min_stages: int = 0):
+    _check(lib().xeng_set_tuning(wgs_per_cu, min_stages), "xeng_set_tuning")
+
+
+def _stream_handle(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _samples_args(samples, n_inputs: int, device: int):
+    import torch
+    if not isinstance(samples, torch.Tensor) or samples.dtype != torch.uint8:
+        raise TypeError("samples must be a torch.uint8 tensor")
+    if samples.dim() != 2:
+        raise ValueError("samples must be 2-D [T, >=N]")
+    if samples.shape[0] == 0:
+        return None, 0, max(n_inputs, samples.shape[1])
+    if samples.device.type != "cuda" or samples.device.index != device:
+        raise ValueError(f"samples must live on cuda:{device}")
+    if samples.shape[1] < n_inputs or samples.stride(1) != 1:
+        raise ValueError("samples must be [T, >=N] with unit stride along inputs")
+    row_stride = samples.stride(0) if samples.shape[0] > 1 else max(samples.stride(0), n_inputs)
+    return ctypes.c_void_p(samples.data_ptr()), samples.shape[0], row_stride
+
+
+class Correlator:
+    """N-input correlator with ``n_slots`` device-resident int32 accumulators."""
+
+    def __init__(self, n_inputs: int, n_slots: int = 1, device: int | None = None,
+                 re_low: bool = False, mem_budget_bytes: int = 0):
+        import torch
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        cfg = _Config(n_inputs, n_slots, self.device, XENG_NIBBLE_RE_LOW if re_low else 0,
+                      mem_budget_bytes)
+        h = ctypes.c_void_p()
+        _check(lib().xeng_create(ctypes.byref(cfg), ctypes.byref(h)), "xeng_create")
+        self._h = h
+        self.n_inputs = n_inputs
+        self.n_slots = n_slots
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("correlator is closed")
+        return self._h
+
+    def correlate(self, slot: int, samples, stream=None):
+        """acc[slot] += V(samples); ``samples`` is uint8 [T, >=N] on the device."""
+        ptr, t, row_stride = _samples_args(samples, self.n_inputs, self.device)
+        _check(lib().xeng_correlate(self.handle, slot, ptr, t, row_stride,
+                                    _stream_handle(stream, self.device)), "xeng_correlate")
+
+    def dump(self, slot: int, out=None, reset: bool = True, stream=None):
+        """Integrated visibilities int32 [N(N+1)/2, 2] (Re, Im), upper triangle row-major."""
+        import torch
+        if out is None:
+            out = torch.empty((tri(self.n_inputs), 2), dtype=torch.int32,
+                              device=f"cuda:{self.device}")
+        if out.dtype != torch.int32 or out.numel() != 2 * tri(self.n_inputs) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int32 tensor of N(N+1)/2 x 2")
+        _check(lib().xeng_dump(self.handle, slot, ctypes.c_void_p(out.data_ptr()), int(bool(reset)),
+                               _stream_handle(stream, self.device)), "xeng_dump")
+        return out
+
+    def reset(self, slot: int, stream=None):
+        _check(lib().xeng_reset(self.handle, slot, _stream_handle(stream, self.device)),
+               "xeng_reset")
+
+    def samples_integrated(self, slot: int) -> int:
+        v = int(lib().xeng_samples_integrated(self.handle, slot))
+        if v < 0:
+            raise XengError(XENG_EINVAL, "xeng_samples_integrated")
+        return v
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _check(lib().xeng_destroy(self._h), "xeng_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def correlate_batch(jobs, stream=None):
+    """One persistent launch over ``jobs`` = [(correlator, slot, samples), ...]."""
+    if not jobs:
+        return
+    arr = (_Job * len(jobs))()
+    keep = []
+    dev = jobs[0][0].device
+    for k, (corr, slot, samples) in enumerate(jobs):
+        ptr, t, row_stride = _samples_args(samples, corr.n_inputs, corr.device)
+        keep.append(samples)
+        arr[k] = _Job(corr.handle, slot, 0, ptr, t, row_stride)
+    _check(lib().xeng_correlate_batch(arr, len(jobs), _stream_handle(stream, dev)),
+           "xeng_correlate_batch")
+
+
+def correlate_reference(samples, n_inputs: int | None = None, re_low: bool = False, stream=None):
+    """Scalar GPU reference kernel; returns int32 [N(N+1)/2, 2] for one call."""
+    import torch
+    n = samples.shape[1] if n_inputs is None else n_inputs
+    dev = samples.device.index if samples.device.type == "cuda" else torch.cuda.current_device()
+    ptr, t, row_stride = _samples_args(samples, n, dev)
+    out = torch.empty((tri(n), 2), dtype=torch.int32, device=f"cuda:{dev}")
+    _check(lib().xeng_correlate_reference(ptr, t, n, row_stride,
+                                          XENG_NIBBLE_RE_LOW if re_low else 0,
+                                          ctypes.c_void_p(out.data_ptr()),
+                                          _stream_handle(stream, dev)), "xeng_correlate_reference")
+    return out
+
+
+@dataclass
+class PieceInfo:
+    job: int
+    ti: int
+    tj: int
+    atomic: bool
+    t0: int
+    t1: int
+    workgroup: int
+
+
+def plan_inspect(n_inputs, n_samples, n_workgroups: int, min_stages: int = 0):
+    """Pieces the library would launch for jobs of these sizes (host only)."""
+    n = len(n_inputs)
+    ni = (ctypes.c_int32 * n)(*n_inputs)
+    ns = (ctypes.c_int64 * n)(*n_samples)
+    cnt = lib().xeng_plan_inspect(ni, ns, n, n_workgroups, min_stages, None, 0)
+    if cnt < 0:
+        raise XengError(int(cnt), "xeng_plan_inspect")
+    out = (_PieceInfo * max(cnt, 1))()
+    cnt2 = lib().xeng_plan_inspect(ni, ns, n, n_workgroups, min_stages, out, cnt)
+    assert cnt2 == cnt
+    return [PieceInfo(p.job, p.ti, p.tj, bool(p.atomic), p.t0, p.t1, p.workgroup)
+            for p in out[:cnt]]

@@ -1,0 +1,124 @@
+"""Host-side checks of the C ABI library: it loads, exports every symbol the
+header declares, validates arguments before touching the device, and its
+work decomposition covers every (pair, sample) exactly once."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "xeng.h")
+
+
+@pytest.fixture(scope="module")
+def X():
+    from paper_2005_09481_amd import xeng
+    xeng.lib()
+    return xeng
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(xeng_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(X):
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(X.lib(), name), name
+
+
+def test_constants(X):
+    assert X.max_integration() == (2 ** 31 - 1) // 128 == 16_777_215
+    assert X.slot_bytes(0) == -1
+    # tile-major accumulators: tri(ceil(N/128)) tiles of 128 x 128 x (Re, Im) int32
+    for n in (1, 128, 129, 2048):
+        nt = -(-n // 128)
+        assert X.slot_bytes(n) == nt * (nt + 1) // 2 * 128 * 128 * 8
+    assert X.strerror(0) == "ok"
+    assert "exact int32" in X.strerror(X.XENG_EOVERFLOW)
+
+
+def test_argument_checks_without_device(X):
+    L = X.lib()
+    h = ctypes.c_void_p()
+    assert L.xeng_create(None, ctypes.byref(h)) == X.XENG_EINVAL
+    for bad in (X._Config(0, 1, 0, 0, 0), X._Config(8, 0, 0, 0, 0),
+                X._Config(8, 1, -1, 0, 0), X._Config(8, 1, 0, 4, 0),
+                X._Config(8, 1, 0, 0, -5)):
+        assert L.xeng_create(ctypes.byref(bad), ctypes.byref(h)) == X.XENG_EINVAL
+    # a memory budget below one slot is refused before any allocation
+    cfg = X._Config(2048, 4, 0, 0, X.slot_bytes(2048) * 4 - 1)
+    assert L.xeng_create(ctypes.byref(cfg), ctypes.byref(h)) == X.XENG_ENOMEM
+    assert L.xeng_correlate(None, 0, None, 10, 10, None) == X.XENG_EINVAL
+    assert L.xeng_dump(None, 0, None, 1, None) == X.XENG_EINVAL
+    assert L.xeng_reset(None, 0, None) == X.XENG_EINVAL
+    assert L.xeng_destroy(None) == X.XENG_EINVAL
+    assert L.xeng_samples_integrated(None, 0) == -1
+    assert L.xeng_correlate_batch(None, 1, None) == X.XENG_EINVAL
+    assert L.xeng_correlate_batch(None, 0, None) == X.XENG_OK
+    assert L.xeng_correlate_reference(None, 10, 4, 4, 0, None, None) == X.XENG_EINVAL
+    assert L.xeng_set_tuning(3, 0) == X.XENG_EINVAL
+
+
+def _check_cover(pieces, jobs, grid):
+    """Every (job, tile, sample) covered by exactly one piece."""
+    cover = {}
+    per_wg = {}
+    for p in pieces:
+        assert 0 <= p.workgroup < grid
+        assert p.ti <= p.tj
+        n, t = jobs[p.job]
+        nt = -(-n // 128)
+        assert p.tj < nt
+        assert 0 <= p.t0 < p.t1 <= t
+        assert p.t0 % 32 == 0
+        cover.setdefault((p.job, p.ti, p.tj), []).append((p.t0, p.t1, p.atomic))
+        per_wg[p.workgroup] = per_wg.get(p.workgroup, 0) + (p.t1 - p.t0)
+    for j, (n, t) in enumerate(jobs):
+        nt = -(-n // 128)
+        for ti in range(nt):
+            for tj in range(ti, nt):
+                segs = sorted(cover.get((j, ti, tj), []))
+                if t == 0:
+                    assert not segs
+                    continue
+                assert segs, (j, ti, tj)
+                assert segs[0][0] == 0 and segs[-1][1] == t
+                for a, b in zip(segs, segs[1:]):
+                    assert a[1] == b[0]
+                assert all(s[2] == (len(segs) > 1) for s in segs)
+    return per_wg
+
+
+@pytest.mark.parametrize("jobs,grid,min_st", [
+    ([(2048, 32768)], 512, 8),
+    ([(2048, 32768)], 256, 8),
+    ([(64, 4096)], 512, 8),
+    ([(1, 1)], 512, 8),
+    ([(129, 33)], 7, 1),
+    ([(300, 1000), (5, 0), (1024, 16384), (256, 4097)], 512, 4),
+])
+def test_plan_covers_exactly_once(X, jobs, grid, min_st):
+    pieces = X.plan_inspect([j[0] for j in jobs], [j[1] for j in jobs], grid, min_st)
+    per_wg = _check_cover(pieces, jobs, grid)
+    # balance: every workgroup gets the same number of stages, +-1 per tile boundary
+    stages = {w: -(-s // 32) for w, s in per_wg.items()}
+    if len(stages) > 1:
+        vals = np.array(list(stages.values()))
+        assert vals.max() - vals.min() <= 3
+
+
+def test_plan_random_batches(X):
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        k = int(rng.integers(1, 6))
+        jobs = [(int(rng.integers(1, 700)), int(rng.integers(0, 5000))) for _ in range(k)]
+        grid = int(rng.integers(1, 600))
+        pieces = X.plan_inspect([j[0] for j in jobs], [j[1] for j in jobs], grid,
+                                int(rng.integers(1, 10)))
+        _check_cover(pieces, jobs, grid)

@@ -1,0 +1,258 @@
+"""GPU parity: the gfx950 correlator against the CPU oracle, bit for bit.
+
+Integer work, so the bar is exact equality.  Small cases compare every
+visibility; the full-size N=2048 workload compares sampled pairs computed by
+the oracle plus properties that hold at any size (diagonal power, a rank-1
+tone's closed form)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def X():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_09481_amd import xeng
+    xeng.lib()
+    return xeng
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def run(X, x, n=None, re_low=False, reset=True):
+    n = x.shape[1] if n is None else n
+    c = X.Correlator(n, 1, re_low=re_low)
+    c.correlate(0, gpu(x))
+    out = c.dump(0, reset=reset).cpu().numpy().astype(np.int64)
+    c.close()
+    return out
+
+
+SHAPES = [(1, 1), (1, 100), (2, 33), (3, 7), (5, 64), (31, 31), (64, 4096), (100, 1000),
+          (127, 65), (128, 128), (129, 300), (200, 257), (256, 32), (300, 1000), (513, 129)]
+
+
+@pytest.mark.parametrize("n,t", SHAPES)
+def test_mfma_matches_oracle(X, n, t):
+    print(f"mfma parity n={n} t={t}", flush=True)
+    x = synth.uniform_bytes(n, t, seed=1000 + n + t)
+    np.testing.assert_array_equal(run(X, x), oracle.correlate(x))
+
+
+@pytest.mark.parametrize("n,t", [(1, 5), (7, 33), (64, 4096), (130, 257)])
+def test_reference_kernel_matches_oracle(X, n, t):
+    x = synth.uniform_bytes(n, t, seed=2000 + n)
+    got = X.correlate_reference(gpu(x)).cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(got, oracle.correlate(x))
+
+
+def test_small_workload_n64_t4096(X):
+    x = synth.uniform_bytes(64, 4096, seed=1)
+    np.testing.assert_array_equal(run(X, x), oracle.correlate(x))
+
+
+def test_chime_statistics_n256(X):
+    x = synth.chime_channel(256, 2000, seed=2)
+    np.testing.assert_array_equal(run(X, x), oracle.correlate(x))
+
+
+def test_empty_time_axis(X):
+    c = X.Correlator(40, 1)
+    c.correlate(0, torch.empty((0, 40), dtype=torch.uint8, device="cuda"))
+    assert c.samples_integrated(0) == 0
+    assert not c.dump(0).any().item()
+
+
+def test_re_low_order(X):
+    x = synth.uniform_bytes(70, 300, seed=3)
+    np.testing.assert_array_equal(run(X, x, re_low=True), oracle.correlate(x, re_low=True))
+
+
+@pytest.mark.parametrize("n,stride,offset", [(100, 101, 0), (100, 128, 1), (61, 67, 3), (128, 130, 2)])
+def test_strides_and_misaligned_base(X, n, stride, offset):
+    t = 77
+    big = synth.uniform_bytes(stride + offset, t, seed=4 + n)
+    dev = gpu(big)[:, offset:offset + n]          # row stride = stride + offset
+    c = X.Correlator(n, 1)
+    c.correlate(0, dev)
+    got = c.dump(0).cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(got, oracle.correlate(big[:, offset:offset + n]))
+
+
+def test_accumulates_across_calls(X):
+    n = 150
+    chunks = [37, 1000, 5, 2048, 1]
+    x = synth.uniform_bytes(n, sum(chunks), seed=5)
+    c = X.Correlator(n, 2)
+    t = 0
+    for k in chunks:
+        c.correlate(1, gpu(x[t:t + k]))
+        t += k
+    assert c.samples_integrated(1) == t and c.samples_integrated(0) == 0
+    np.testing.assert_array_equal(c.dump(1, reset=False).cpu().numpy(), oracle.correlate(x))
+    # keep integrating after a non-resetting dump
+    c.correlate(1, gpu(x[:100]))
+    ref = oracle.correlate(x) + oracle.correlate(x[:100])
+    np.testing.assert_array_equal(c.dump(1).cpu().numpy(), ref)
+    assert c.samples_integrated(1) == 0
+    assert not c.dump(1).any().item()
+    assert not c.dump(0).any().item()
+
+
+def test_slots_are_independent(X):
+    n = 64
+    xs = [synth.uniform_bytes(n, 200 + 50 * s, seed=10 + s) for s in range(3)]
+    c = X.Correlator(n, 3)
+    for s in (2, 0, 1):
+        c.correlate(s, gpu(xs[s]))
+    for s in range(3):
+        np.testing.assert_array_equal(c.dump(s).cpu().numpy(), oracle.correlate(xs[s]))
+
+
+def test_reset(X):
+    x = synth.uniform_bytes(64, 100, seed=20)
+    c = X.Correlator(64, 1)
+    c.correlate(0, gpu(x))
+    c.reset(0)
+    assert c.samples_integrated(0) == 0
+    c.correlate(0, gpu(x[:10]))
+    np.testing.assert_array_equal(c.dump(0).cpu().numpy(), oracle.correlate(x[:10]))
+
+
+def test_overflow_guard_and_exact_bound(X):
+    """All samples -8-8j: every Re term is 128, the largest there is.  At the
+    integration bound Re = 128 * 16,777,215 = 2,147,483,520 in every pair;
+    one more sample is refused and changes nothing."""
+    n = 64
+    tmax = X.max_integration()
+    chunk = 1 << 20
+    zeros = torch.zeros((chunk, n), dtype=torch.uint8, device="cuda")
+    c = X.Correlator(n, 1)
+    done = 0
+    while done < tmax:
+        k = min(chunk, tmax - done)
+        c.correlate(0, zeros[:k])
+        done += k
+    assert c.samples_integrated(0) == tmax
+    with pytest.raises(X.XengError) as e:
+        c.correlate(0, zeros[:1])
+    assert e.value.status == X.XENG_EOVERFLOW
+    assert c.samples_integrated(0) == tmax
+    v = c.dump(0, reset=False).cpu().numpy()
+    assert (v[:, 0] == 128 * tmax).all() and (v[:, 0] == 2_147_483_520).all()
+    assert (v[:, 1] == 0).all()
+    # the refused call changed nothing; after a reset integration resumes
+    c.reset(0)
+    c.correlate(0, zeros[:1])
+    assert (c.dump(0).cpu().numpy()[:, 0] == 128).all()
+
+
+def test_argument_errors(X):
+    c = X.Correlator(32, 2)
+    L = X.lib()
+    buf = torch.zeros((10, 32), dtype=torch.uint8, device="cuda")
+    p = ctypes.c_void_p(buf.data_ptr())
+    assert L.xeng_correlate(c.handle, 2, p, 10, 32, None) == X.XENG_EINVAL     # bad slot
+    assert L.xeng_correlate(c.handle, -1, p, 10, 32, None) == X.XENG_EINVAL
+    assert L.xeng_correlate(c.handle, 0, p, 10, 31, None) == X.XENG_EINVAL     # stride < N
+    assert L.xeng_correlate(c.handle, 0, None, 10, 32, None) == X.XENG_EINVAL  # null samples
+    assert L.xeng_correlate(c.handle, 0, p, -1, 32, None) == X.XENG_EINVAL
+    assert L.xeng_dump(c.handle, 0, None, 1, None) == X.XENG_EINVAL
+    assert c.samples_integrated(0) == 0
+
+
+def test_dump_to_pinned_host(X):
+    x = synth.uniform_bytes(90, 64, seed=21)
+    c = X.Correlator(90, 1)
+    c.correlate(0, gpu(x))
+    host = torch.empty((X.tri(90), 2), dtype=torch.int32, pin_memory=True)
+    c.dump(0, out=host)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host.numpy(), oracle.correlate(x))
+
+
+def test_tuning_does_not_change_results(X):
+    x = synth.uniform_bytes(300, 2000, seed=22)
+    outs = []
+    try:
+        for wpc, ms in ((2, 8), (1, 1), (2, 1), (1, 64)):
+            X.set_tuning(wpc, ms)
+            outs.append(run(X, x))
+    finally:
+        X.set_tuning(2, 8)
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+    np.testing.assert_array_equal(outs[0], oracle.correlate(x))
+
+
+# ---------------------------------------------------------------------------
+# Full-size workload: N=2048, T=32768, in the launch configuration the
+# benchmark times.
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def full_size(X):
+    print("full-size n=2048 t=32768: generating", flush=True)
+    x = synth.chime_channel(2048, 32768, seed=2)
+    c = X.Correlator(2048, 1)
+    c.correlate(0, gpu(x))
+    v = c.dump(0).cpu().numpy().astype(np.int64)
+    c.close()
+    return x, v
+
+
+def test_full_size_sampled_pairs(X, full_size):
+    x, v = full_size
+    n = 2048
+    rng = np.random.default_rng(123)
+    # 96 random inputs plus the tile edges: all their pairs, by the oracle
+    s = np.unique(np.concatenate([rng.choice(n, 96, replace=False),
+                                  [0, 1, 127, 128, 1023, 1024, 2046, 2047]]))
+    ref = oracle.correlate(x[:, s])
+    k = 0
+    for a in range(len(s)):
+        for b in range(a, len(s)):
+            np.testing.assert_array_equal(v[oracle.tri_index(int(s[a]), int(s[b]), n)], ref[k])
+            k += 1
+
+
+def test_full_size_diagonal_is_power(X, full_size):
+    x, v = full_size
+    n = 2048
+    re = (x >> 4).astype(np.int64) - 8
+    im = (x & 15).astype(np.int64) - 8
+    p = (re * re + im * im).sum(axis=0)
+    d = np.array([oracle.tri_index(i, i, n) for i in range(n)])
+    np.testing.assert_array_equal(v[d, 0], p)
+    assert not v[d, 1].any()
+
+
+def test_full_size_rank1_tone_closed_form(X):
+    n, t = 2048, 32768
+    x, g_re, g_im = synth.rank1_tone(n, t, seed=9, quarter_turns=1)
+    c = X.Correlator(n, 1)
+    c.correlate(0, gpu(x))
+    v = c.dump(0).cpu().numpy().astype(np.int64)
+    iu, ju = np.triu_indices(n)
+    # T * g_i * conj(g_j)
+    re = t * (g_re[iu] * g_re[ju] + g_im[iu] * g_im[ju])
+    im = t * (g_im[iu] * g_re[ju] - g_re[iu] * g_im[ju])
+    np.testing.assert_array_equal(v[:, 0], re)
+    np.testing.assert_array_equal(v[:, 1], im)
+
+
+def test_full_size_deterministic(X, full_size):
+    x, v = full_size
+    c = X.Correlator(2048, 1)
+    c.correlate(0, gpu(x))
+    np.testing.assert_array_equal(c.dump(0).cpu().numpy(), v)
