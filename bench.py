@@ -57,6 +57,9 @@ def main():
     ap.add_argument("--t", type=int, default=32768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after timing, run one plain device copy of this many MiB "
+                         "(reference kernel for scaling hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -130,6 +133,13 @@ def main():
         "correlate_kernel_ms": round(kern_s * 1e3, 4),
         "correlate_tcmacs": round(cmac / kern_s / 1e12, 3),
     }
+    if args.copy_mib > 0:
+        src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(x_np, n, args.cpu_seconds)
     print(json.dumps(res), flush=True)

@@ -92,7 +92,7 @@ int xeng_destroy(xeng_ctx *ctx);
  *   acc[slot] += V(d_samples[0 : n_samples])
  * d_samples: device pointer, time-major [n_samples][row_stride] bytes,
  *   owned by the caller.  n_samples >= 0 (0 is a no-op).
- *   row_stride >= N.
+ *   N <= row_stride <= 2^26.
  * Asynchronous on hip_stream.  Refuses with XENG_EOVERFLOW if the slot
  * would integrate more than xeng_max_integration() samples.
  */
@@ -176,7 +176,7 @@ typedef struct {
 /*
  * Fill `out` (capacity `cap`) with the pieces the library would launch for
  * jobs of sizes (n_inputs[k], n_samples[k]) on `n_workgroups` workgroups
- * with at least `min_stages` 32-sample stages per piece (0 = library
+ * with at least `min_stages` 64-sample stages per piece (0 = library
  * default).  Returns the number of pieces (which may exceed cap: then only
  * cap are written), or a negative status.
  */
@@ -186,7 +186,7 @@ int64_t xeng_plan_inspect(const int32_t *n_inputs, const int64_t *n_samples, int
 
 /*
  * Launch tuning: workgroups per compute unit of the persistent launch
- * (1 or 2) and the minimum piece length in 32-sample stages.  Values <= 0
+ * (1 or 2) and the minimum piece length in 64-sample stages.  Values <= 0
  * keep the current setting.  Applies to later calls on every device.
  */
 int xeng_set_tuning(int32_t wgs_per_cu, int32_t min_stages);

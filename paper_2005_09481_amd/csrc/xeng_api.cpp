@@ -20,7 +20,7 @@
 #include "xeng_plan.h"
 
 namespace xeng {
-hipError_t launch_correlate(const KernelArgs &a, int grid, hipStream_t stream);
+hipError_t launch_correlate(const KernelArgs &a, int grid, bool aligned, hipStream_t stream);
 hipError_t launch_dump(const int32_t *acc, int n, int nt, int32_t *out, hipStream_t stream);
 hipError_t launch_zero(int32_t *p, int64_t n_i32, hipStream_t stream);
 hipError_t launch_reference(const uint8_t *s, int64_t n_samples, int n, int64_t stride,
@@ -197,8 +197,8 @@ JobDesc make_job(const xeng_ctx *c, int32_t slot, const uint8_t *d_samples, int6
     jd.nt = c->nt;
     jd.flags = 0;
     if (c->flags & XENG_NIBBLE_RE_LOW) jd.flags |= JOB_RE_LOW;
-    if ((stride % 4) == 0 && (reinterpret_cast<uintptr_t>(d_samples) % 4) == 0)
-        jd.flags |= JOB_ALIGNED4;
+    if ((stride % 8) == 0 && (reinterpret_cast<uintptr_t>(d_samples) % 8) == 0 && c->n % 8 == 0)
+        jd.flags |= JOB_ALIGNED8;
     jd.pad = 0;
     return jd;
 }
@@ -270,7 +270,8 @@ int xeng_destroy(xeng_ctx *ctx)
 int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_t n_samples,
                    int64_t row_stride, void *hip_stream)
 {
-    if (!slot_ok(ctx, slot) || n_samples < 0 || row_stride < ctx->n) return XENG_EINVAL;
+    if (!slot_ok(ctx, slot) || n_samples < 0 || row_stride < ctx->n || row_stride > MAX_STRIDE)
+        return XENG_EINVAL;
     if (n_samples > 0 && !d_samples) return XENG_EINVAL;
     if (n_samples > T_MAX - ctx->acc_t[(size_t)slot]) return XENG_EOVERFLOW;
     if (n_samples == 0) return XENG_OK;
@@ -291,7 +292,7 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_
     a.jobs = nullptr;
     a.pieces = dp.d_pieces;
     a.wg_off = dp.d_off;
-    hipError_t e = launch_correlate(a, dp.grid, stream);
+    hipError_t e = launch_correlate(a, dp.grid, (a.job0.flags & JOB_ALIGNED8) != 0, stream);
     if (e != hipSuccess) return map_err(e);
     ctx->acc_t[(size_t)slot] += n_samples;
     return XENG_OK;
@@ -306,7 +307,8 @@ int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
     for (int32_t k = 0; k < n_jobs; ++k) {
         const xeng_job &j = jobs[k];
         if (!slot_ok(j.ctx, j.slot) || j.reserved != 0 || j.n_samples < 0 ||
-            j.row_stride < j.ctx->n || (j.n_samples > 0 && !j.d_samples) ||
+            j.row_stride < j.ctx->n || j.row_stride > MAX_STRIDE ||
+            (j.n_samples > 0 && !j.d_samples) ||
             j.ctx->device != device)
             return XENG_EINVAL;
         if (j.n_samples > 0 && j.row_stride > INT64_MAX / j.n_samples) return XENG_EINVAL;
@@ -369,7 +371,9 @@ int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
     a.jobs = tb.d;
     a.pieces = dp.d_pieces;
     a.wg_off = dp.d_off;
-    e = launch_correlate(a, dp.grid, stream);
+    bool aligned = true;
+    for (const JobDesc &jd : descs) aligned = aligned && (jd.flags & JOB_ALIGNED8);
+    e = launch_correlate(a, dp.grid, aligned, stream);
     if (e == hipSuccess) e = hipEventRecord(tb.ev, stream);
     if (e != hipSuccess) return map_err(e);
     tb.pending = true;

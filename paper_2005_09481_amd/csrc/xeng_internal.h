@@ -15,7 +15,7 @@ namespace xeng {
 constexpr int TILE = 128;          // inputs per tile side
 constexpr int BLK = 32;            // MFMA block side
 constexpr int BLKS = TILE / BLK;   // 4 blocks per tile side
-constexpr int STAGE = 32;          // samples per pipeline stage (LDS buffer)
+constexpr int STAGE = 64;          // samples per pipeline stage (LDS buffer)
 constexpr int KSTEP = 16;          // samples per MFMA k-step (32 int8 values)
 
 // Accumulator layout of one slot (device, int32): tile-major over the upper
@@ -23,13 +23,20 @@ constexpr int KSTEP = 16;          // samples per MFMA k-step (32 int8 values)
 // tile: [ca][cb][comp][reg][lane] with ca, cb the 4 x 4 blocks, comp 0 = Re,
 // 1 = Im, and (reg, lane) the MFMA 32 x 32 accumulator register layout.
 // Rows inside a tile are permuted: tile row offset r (0..127) lives at
-// position p = 32*(r % 4) + r / 4, block ca = p / 32, row-in-block p % 32.
+// position p = 16*(r % 8) + r / 8, block ca = p / 32, row-in-block p % 32.
 constexpr int64_t TILE_I32 = (int64_t)BLKS * BLKS * 2 * 16 * 64;   // 32768 int32
 constexpr int64_t BLOCK_I32 = 2 * 16 * 64;                          // 2048 int32
 
 inline int64_t tri64(int64_t n) { return n * (n + 1) / 2; }
 inline int n_tiles_side(int n) { return (n + TILE - 1) / TILE; }
 inline int64_t slot_i32(int n) { return tri64(n_tiles_side(n)) * TILE_I32; }
+
+// B operands carry 16x the sample values, so the int32 register sums of one
+// piece reach 16 * 128 * length: pieces are capped below 2^20 samples.
+constexpr int MAX_PIECE_STAGES = ((1 << 20) - 1) / STAGE;     // 16383 stages
+
+// Largest row stride: lane offsets inside a stage (up to 31 rows) stay 32-bit.
+constexpr int64_t MAX_STRIDE = INT64_C(1) << 26;
 
 // Largest number of samples a slot may integrate: the largest |term| of
 // x_i conj(x_j) with parts in [-8, 7] is 128 (Re), so 128 * T_MAX <= 2^31-1.
@@ -46,7 +53,7 @@ struct JobDesc {
     int32_t pad;
 };
 constexpr uint32_t JOB_RE_LOW = 1u;    // real part in the low nibble
-constexpr uint32_t JOB_ALIGNED4 = 2u;  // samples and stride are 4-byte aligned
+constexpr uint32_t JOB_ALIGNED8 = 2u;  // samples, stride and N are multiples of 8 bytes
 
 // One piece of work: tile (ti, tj) of job `job` over samples [t0, t1).
 struct Piece {

@@ -29,38 +29,44 @@ namespace xeng {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
-// LDS stage layout.  For each k-step q (16 samples) a component region holds
-// 128 tile positions x 16 bytes (the 16 samples of one input, in time
-// order).  A rows keep Re, Im, -Re; B rows keep Re, Im.  Position p of a
-// tile row offset r is 32*(r % 4) + r/4, so that the staging writes of a
-// wave land on consecutive 16-byte slots (no bank conflicts) while the MFMA
-// operand reads stay contiguous too.
+// LDS stage layout.  A stage is 64 samples = 4 MFMA k-steps.  For each
+// k-step q a component region holds 128 tile positions x 16 bytes (the 16
+// samples of one input, in time order).  A rows keep Re, Im, -Re as int8;
+// B rows keep 16*Re, 16*Im as int8 (the scale makes their unpack three bit
+// operations per four samples; every product is then 16x the true one and
+// the flush divides it out exactly).  Tile row offset r lives at position
+// 16*(r % 8) + r/8: the staging writes of 16 lanes then fill 8 consecutive
+// 16-byte slots (no bank conflicts) and the MFMA operand reads of 32 lanes
+// stay contiguous.
 constexpr int CH = TILE * 16;       // 2048 bytes
+constexpr int QSTEPS = STAGE / KSTEP;   // 4
 constexpr int A_Q = 3 * CH;
 constexpr int B_Q = 2 * CH;
-constexpr int A_BYTES = 2 * A_Q;    // 2 k-steps per stage
-constexpr int B_BYTES = 2 * B_Q;
-constexpr int STAGE_BYTES = A_BYTES + B_BYTES;   // 20480
+constexpr int A_BYTES = QSTEPS * A_Q;   // 24 KB
+constexpr int B_BYTES = QSTEPS * B_Q;   // 16 KB
+constexpr int STAGE_BYTES = A_BYTES + B_BYTES;   // 40 KB
+constexpr int NBUF = 2;
 
 __device__ __forceinline__ uint32_t vperm(uint32_t s0, uint32_t s1, uint32_t sel)
 {
     return __builtin_amdgcn_perm(s0, s1, sel);
 }
 
-// 4 x 4 byte transpose: rows a, b, c, d are 4 inputs at 4 consecutive times;
-// out[k] holds input k at the 4 times (byte = time).
-__device__ __forceinline__ void transpose4(uint32_t a, uint32_t b, uint32_t c, uint32_t d,
-                                           uint32_t out[4])
+// 4 x 4 byte transpose: in[t] holds 4 inputs at time t; out[c] holds input
+// c at the 4 times (byte = time).
+__device__ __forceinline__ void transpose4(uint32_t i0, uint32_t i1, uint32_t i2, uint32_t i3,
+                                           uint32_t &o0, uint32_t &o1, uint32_t &o2, uint32_t &o3)
 {
-    const uint32_t ab_lo = vperm(b, a, 0x05010400u);   // a0 b0 a1 b1
-    const uint32_t ab_hi = vperm(b, a, 0x07030602u);   // a2 b2 a3 b3
-    const uint32_t cd_lo = vperm(d, c, 0x05010400u);
-    const uint32_t cd_hi = vperm(d, c, 0x07030602u);
-    out[0] = vperm(cd_lo, ab_lo, 0x05040100u);         // a0 b0 c0 d0
-    out[1] = vperm(cd_lo, ab_lo, 0x07060302u);         // a1 b1 c1 d1
-    out[2] = vperm(cd_hi, ab_hi, 0x05040100u);
-    out[3] = vperm(cd_hi, ab_hi, 0x07060302u);
+    const uint32_t ab_lo = vperm(i1, i0, 0x05010400u);   // a0 b0 a1 b1
+    const uint32_t ab_hi = vperm(i1, i0, 0x07030602u);   // a2 b2 a3 b3
+    const uint32_t cd_lo = vperm(i3, i2, 0x05010400u);
+    const uint32_t cd_hi = vperm(i3, i2, 0x07030602u);
+    o0 = vperm(cd_lo, ab_lo, 0x05040100u);               // a0 b0 c0 d0
+    o1 = vperm(cd_lo, ab_lo, 0x07060302u);               // a1 b1 c1 d1
+    o2 = vperm(cd_hi, ab_hi, 0x05040100u);
+    o3 = vperm(cd_hi, ab_hi, 0x07060302u);
 }
 
 // Offset-binary nibbles (0..15, one per byte) -> signed int8 value and its
@@ -69,164 +75,287 @@ __device__ __forceinline__ void transpose4(uint32_t a, uint32_t b, uint32_t c, u
 __device__ __forceinline__ uint32_t nib_to_i8(uint32_t n) { return (n + 0x78787878u) ^ 0x80808080u; }
 __device__ __forceinline__ uint32_t nib_to_neg_i8(uint32_t n) { return (0x88888888u - n) ^ 0x80808080u; }
 
-// Load the 4 inputs [i0, i0+4) of one lane for 8 consecutive samples
-// starting at t_first; samples at or past t1 and inputs past n read as the
-// zero sample 0x88.
-__device__ __forceinline__ void stage_load(uint32_t d[8], const uint8_t *col, int64_t stride,
-                                           int t_first, int t1, bool fast, int nvalid)
+// Global-memory views: loads through these pointers are global (not flat)
+// instructions, so they only count against the vector-memory counter and
+// stay in flight while the LDS reads and MFMAs of the current stage run.
+typedef __attribute__((address_space(1))) const u32x2 gcu64;
+typedef __attribute__((address_space(1))) const uint8_t gcu8;
+typedef __attribute__((address_space(1))) int32_t gi32;
+
+// One lane's share of a stage: 8 inputs x 8 consecutive samples of one
+// block (d[k] = the 8 inputs at sample k), as loaded, plus a mask of which
+// samples are real (bit k) -- the others become the zero sample at unpack.
+struct StageRegs {
+    u32x2 d[8];
+    uint32_t valid;
+};
+constexpr uint32_t ALL_VALID = 0xFFu;
+
+// Per-piece constants of one lane.
+struct PieceCtx {
+    const uint8_t *samples;
+    int64_t stride;
+    int n, t0, t1;
+    int i0;               // first of the 8 inputs this lane stages
+    uint32_t off;         // lane byte offset from a stage's first time row
+    bool full_rows;       // all 128 inputs of this lane's block are < n
+    int t_lane;           // first sample of this lane inside a stage
+};
+
+// Fast stage: every sample and input in range.  Eight 8-byte loads at a
+// uniform row base plus a 32-bit lane offset.
+__device__ __forceinline__ void load_fast(StageRegs &r, const uint8_t *row0, int64_t stride,
+                                          uint32_t off)
 {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r.d[k] = *(gcu64 *)(row0 + (int64_t)k * stride + off);
+    r.valid = ALL_VALID;
+}
+
+// Edge stage: the same eight loads with every address clamped into the
+// array.  Nothing loaded is consumed here, so the loads of both paths stay
+// in flight and the memory-counter waits stay precise.
+__device__ __forceinline__ void load_clamped(StageRegs &r, const PieceCtx &pc, int t_first)
+{
+    const bool vi = pc.i0 < pc.n;
+    uint32_t valid = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const int t = t_first + k;
-        const int tc = t < t1 ? t : t1 - 1;
-        const uint8_t *p = col + (int64_t)tc * stride;
-        uint32_t v;
-        if (fast) {
-            v = *(const uint32_t *)p;
-        } else {
-            v = 0x88888888u;
-            for (int b = 0; b < nvalid; ++b)
-                v = (v & ~(0xFFu << (8 * b))) | ((uint32_t)p[b] << (8 * b));
-        }
-        d[k] = t < t1 ? v : 0x88888888u;
+        const bool vt = t < pc.t1;
+        const uint8_t *row = pc.samples + (int64_t)(vt ? t : pc.t0) * pc.stride;
+        r.d[k] = *(gcu64 *)(row + (vi ? pc.i0 : 0));
+        valid |= ((vt && vi) ? 1u : 0u) << k;
     }
+    r.valid = valid;
 }
 
-// Transpose + unpack one lane's 4 inputs x 8 samples into the stage buffer.
-__device__ __forceinline__ void stage_write(uint8_t *region, const uint32_t d[8], int g, int hl,
-                                            bool role_a, bool re_low)
+// Unaligned data, or N not a multiple of 8: byte loads, clamped the same way.
+__device__ __forceinline__ void load_bytes(StageRegs &r, const PieceCtx &pc, int t_first)
 {
-    uint32_t p0[4], p1[4];
-    transpose4(d[0], d[1], d[2], d[3], p0);
-    transpose4(d[4], d[5], d[6], d[7], p1);
+    uint32_t valid = 0;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const uint32_t h0 = (p0[c] >> 4) & 0x0F0F0F0Fu, l0 = p0[c] & 0x0F0F0F0Fu;
-        const uint32_t h1 = (p1[c] >> 4) & 0x0F0F0F0Fu, l1 = p1[c] & 0x0F0F0F0Fu;
-        const uint32_t re0 = re_low ? l0 : h0, im0 = re_low ? h0 : l0;
-        const uint32_t re1 = re_low ? l1 : h1, im1 = re_low ? h1 : l1;
-        const int off = 16 * (32 * c + g) + 8 * hl;
-        *(uint2 *)(region + off) = make_uint2(nib_to_i8(re0), nib_to_i8(re1));
-        *(uint2 *)(region + CH + off) = make_uint2(nib_to_i8(im0), nib_to_i8(im1));
-        if (role_a)
-            *(uint2 *)(region + 2 * CH + off) = make_uint2(nib_to_neg_i8(re0), nib_to_neg_i8(re1));
+    for (int k = 0; k < 8; ++k) {
+        const int t = t_first + k;
+        const bool vt = t < pc.t1;
+        const uint8_t *row = pc.samples + (int64_t)(vt ? t : pc.t0) * pc.stride;
+        uint32_t w[2] = {0, 0};
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool ok = pc.i0 + b < pc.n;
+            const uint32_t x = ((gcu8 *)row)[ok ? pc.i0 + b : 0];
+            w[b >> 2] |= (ok ? x : 0x88u) << (8 * (b & 3));
+        }
+        r.d[k] = u32x2{w[0], w[1]};
+        valid |= (vt ? 1u : 0u) << k;
+    }
+    r.valid = valid;
+}
+
+template <bool ALIGNED>
+__device__ __forceinline__ void load_stage(StageRegs &r, const PieceCtx &pc, int s)
+{
+    const int ts = pc.t0 + s * STAGE;
+    if (!ALIGNED)
+        load_bytes(r, pc, ts + pc.t_lane);
+    else if (pc.full_rows && ts + STAGE <= pc.t1)
+        load_fast(r, pc.samples + (int64_t)ts * pc.stride, pc.stride, pc.off);
+    else
+        load_clamped(r, pc, ts + pc.t_lane);
+}
+
+// Unpack one lane's share of a stage into the stage buffer.  `slot` is the
+// byte offset of this lane's (position, half) in a component region; input
+// c of the lane sits 16 * 16 * c bytes further.
+template <bool ROLE_A, bool RE_LOW>
+__device__ __forceinline__ void stage_write(uint8_t *region, const StageRegs &r, int slot)
+{
+    uint32_t lo[8], hi[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        lo[k] = r.d[k].x;
+        hi[k] = r.d[k].y;
+    }
+    if (r.valid != ALL_VALID) {     // uniform in the steady state
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const bool ok = (r.valid >> k) & 1u;
+            lo[k] = ok ? lo[k] : 0x88888888u;
+            hi[k] = ok ? hi[k] : 0x88888888u;
+        }
+    }
+    // p[c][h]: input c, samples 4h..4h+3
+    uint32_t p[8][2];
+    transpose4(lo[0], lo[1], lo[2], lo[3], p[0][0], p[1][0], p[2][0], p[3][0]);
+    transpose4(lo[4], lo[5], lo[6], lo[7], p[0][1], p[1][1], p[2][1], p[3][1]);
+    transpose4(hi[0], hi[1], hi[2], hi[3], p[4][0], p[5][0], p[6][0], p[7][0]);
+    transpose4(hi[4], hi[5], hi[6], hi[7], p[4][1], p[5][1], p[6][1], p[7][1]);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        uint8_t *dst = region + slot + 256 * c;
+        if (ROLE_A) {
+            const uint32_t h0 = (p[c][0] >> 4) & 0x0F0F0F0Fu, l0 = p[c][0] & 0x0F0F0F0Fu;
+            const uint32_t h1 = (p[c][1] >> 4) & 0x0F0F0F0Fu, l1 = p[c][1] & 0x0F0F0F0Fu;
+            const uint32_t re0 = RE_LOW ? l0 : h0, im0 = RE_LOW ? h0 : l0;
+            const uint32_t re1 = RE_LOW ? l1 : h1, im1 = RE_LOW ? h1 : l1;
+            *(uint2 *)(dst) = make_uint2(nib_to_i8(re0), nib_to_i8(re1));
+            *(uint2 *)(dst + CH) = make_uint2(nib_to_i8(im0), nib_to_i8(im1));
+            *(uint2 *)(dst + 2 * CH) = make_uint2(nib_to_neg_i8(re0), nib_to_neg_i8(re1));
+        } else {
+            // flipping bit 3 of an offset-binary nibble gives its 4-bit two's
+            // complement; in the high half of a byte that is 16x the value
+            const uint32_t x0 = p[c][0] ^ 0x88888888u, x1 = p[c][1] ^ 0x88888888u;
+            const uint32_t xh0 = x0 & 0xF0F0F0F0u, xl0 = (x0 << 4) & 0xF0F0F0F0u;
+            const uint32_t xh1 = x1 & 0xF0F0F0F0u, xl1 = (x1 << 4) & 0xF0F0F0F0u;
+            *(uint2 *)(dst) = RE_LOW ? make_uint2(xl0, xl1) : make_uint2(xh0, xh1);
+            *(uint2 *)(dst + CH) = RE_LOW ? make_uint2(xh0, xh1) : make_uint2(xl0, xl1);
+        }
     }
 }
 
 __device__ __forceinline__ v4i lds128(const uint8_t *p) { return *(const v4i *)p; }
 
-__device__ __forceinline__ void flush_block(int32_t *blk, const v16i &re, const v16i &im,
+// Accumulators hold 16x the visibilities (B operands are scaled by 16), so
+// the flush adds acc >> 4; every value is a multiple of 16, so this is exact.
+__device__ __forceinline__ void flush_block(int32_t *blk_, const v16i &re, const v16i &im,
                                             bool atomic)
 {
+    gi32 *blk = (gi32 *)blk_;
     if (atomic) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            __hip_atomic_fetch_add(blk + r * 64, re[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(blk + 1024 + r * 64, im[r], __ATOMIC_RELAXED,
+            __hip_atomic_fetch_add(blk + r * 64, re[r] >> 4, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(blk + 1024 + r * 64, im[r] >> 4, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         }
     } else {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            blk[r * 64] += re[r];
-            blk[1024 + r * 64] += im[r];
+            blk[r * 64] += re[r] >> 4;
+            blk[1024 + r * 64] += im[r] >> 4;
         }
+    }
+}
+
+struct Acc {
+    v16i re[2][2];
+    v16i im[2][2];
+};
+
+// The 32 MFMAs of one stage (4 k-steps x 2 x 2 blocks x Re/Im) on `buf`.
+__device__ __forceinline__ void stage_mfma(Acc &acc, const uint8_t *buf, int lane, int wa, int wb)
+{
+#pragma unroll
+    for (int q = 0; q < QSTEPS; ++q) {
+        const uint8_t *aq = buf + q * A_Q + (lane >> 5) * CH + 16 * (lane & 31);
+        const v4i re_a0 = lds128(aq + 512 * (2 * wa));
+        const v4i re_a1 = lds128(aq + 512 * (2 * wa + 1));
+        const v4i im_a0 = lds128(aq + CH + 512 * (2 * wa));
+        const v4i im_a1 = lds128(aq + CH + 512 * (2 * wa + 1));
+        const uint8_t *bp = buf + A_BYTES + q * B_Q + (lane >> 5) * CH + 16 * (lane & 31);
+        const v4i b0 = lds128(bp + 512 * (2 * wb));
+        const v4i b1 = lds128(bp + 512 * (2 * wb + 1));
+        acc.re[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(re_a0, b0, acc.re[0][0], 0, 0, 0);
+        acc.im[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im_a0, b0, acc.im[0][0], 0, 0, 0);
+        acc.re[0][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(re_a0, b1, acc.re[0][1], 0, 0, 0);
+        acc.im[0][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im_a0, b1, acc.im[0][1], 0, 0, 0);
+        acc.re[1][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(re_a1, b0, acc.re[1][0], 0, 0, 0);
+        acc.im[1][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im_a1, b0, acc.im[1][0], 0, 0, 0);
+        acc.re[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(re_a1, b1, acc.re[1][1], 0, 0, 0);
+        acc.im[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im_a1, b1, acc.im[1][1], 0, 0, 0);
+    }
+}
+
+// Correlate one piece: tile (ti, tj) over samples [t0, t1).  Stage s is in
+// LDS being multiplied while stage s+1 (in registers) is unpacked into the
+// other LDS buffer and stage s+2 loads from memory.  Steps run in pairs with
+// no early exit: a stage past the end of the piece holds zero samples and
+// adds exactly nothing.
+template <bool ALIGNED, bool ROLE_A, bool RE_LOW>
+__device__ __forceinline__ void run_piece(Acc &acc, uint8_t *smem, const PieceCtx &pc, int lane,
+                                          int wa, int wb, int wslot)
+{
+    const int nst = (pc.t1 - pc.t0 + STAGE - 1) / STAGE;
+    uint8_t *buf0 = smem, *buf1 = smem + STAGE_BYTES;
+    StageRegs r0, r1;
+
+    load_stage<ALIGNED>(r0, pc, 0);
+    load_stage<ALIGNED>(r1, pc, 1);
+    stage_write<ROLE_A, RE_LOW>(buf0, r0, wslot);
+    __syncthreads();
+
+    for (int s = 0; s < nst; s += NBUF) {
+        load_stage<ALIGNED>(r0, pc, s + 2);
+        stage_mfma(acc, buf0, lane, wa, wb);
+        stage_write<ROLE_A, RE_LOW>(buf1, r1, wslot);
+        __syncthreads();
+        load_stage<ALIGNED>(r1, pc, s + 3);
+        stage_mfma(acc, buf1, lane, wa, wb);
+        stage_write<ROLE_A, RE_LOW>(buf0, r0, wslot);
+        __syncthreads();
     }
 }
 
 // Persistent correlation kernel: workgroup w runs pieces [wg_off[w], wg_off[w+1]).
 // 256 threads = 4 waves; wave (wa, wb) owns MFMA blocks ca in {2wa, 2wa+1},
-// cb in {2wb, 2wb+1} of the tile (64 x 64 outputs, Re and Im).
+// cb in {2wb, 2wb+1} of the tile (64 x 64 outputs, Re and Im).  Staging:
+// waves 0-1 unpack the A (row) block, waves 2-3 the B (column) block; a lane
+// takes 8 inputs x 8 samples (lane bits 0-2 and 4 pick the 8-input group,
+// bit 3 the half of a k-step, bit 5 and the wave the k-step).
+template <bool ALIGNED>
 __global__ __launch_bounds__(256, 2) void xcorr_mfma(KernelArgs args)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t smem[2 * STAGE_BYTES];
+    __shared__ __attribute__((aligned(16))) uint8_t smem[NBUF * STAGE_BYTES];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wa = wave >> 1, wb = wave & 1;
-    // staging role of this lane: input group g (4 inputs), half hl of a
-    // k-step, k-step q_st of the stage, A rows (waves 0, 1) or B rows (2, 3)
-    const int g = (lane & 7) + 8 * (lane >> 4);
-    const int hl = (lane >> 3) & 1;
-    const int q_st = wave & 1;
     const bool role_a = wave < 2;
+    const int g8 = (lane & 7) | (((lane >> 4) & 1) << 3);   // 8-input group 0..15
+    const int half = (lane >> 3) & 1;                        // samples 0-7 / 8-15 of a k-step
+    const int q = 2 * (wave & 1) + (lane >> 5);              // k-step 0..3
+    // LDS byte offset of this lane's (position g8 of input 0, half, k-step)
+    const int wslot = (role_a ? q * A_Q : A_BYTES + q * B_Q) + 16 * g8 + 8 * half;
 
     const int p_begin = args.wg_off[blockIdx.x], p_end = args.wg_off[blockIdx.x + 1];
     for (int pi = p_begin; pi < p_end; ++pi) {
-        const Piece pc = args.pieces[pi];
-        const JobDesc jd = args.jobs ? args.jobs[pc.job] : args.job0;
-        const int ti = pc.tile & 0xFFFF, tj = (pc.tile >> 16) & 0xFFFF;
-        const bool diag = ti == tj;
-        const int t0 = pc.t0;
-        const int t1 = pc.t1_atomic & 0x7FFFFFFF;
-        const bool atomic = pc.t1_atomic < 0;
-        const bool re_low = (jd.flags & JOB_RE_LOW) != 0;
+        const Piece pce = args.pieces[pi];
+        const JobDesc jd = args.jobs ? args.jobs[pce.job] : args.job0;
+        const int ti = pce.tile & 0xFFFF, tj = (pce.tile >> 16) & 0xFFFF;
+        const bool atomic = pce.t1_atomic < 0;
+        const int blk0 = (role_a ? ti : tj) * TILE;
 
-        // this lane's staging source: 4 inputs of the A (ti) or B (tj) block
-        const bool stager = role_a || !diag;
-        const int i0 = (role_a ? ti : tj) * TILE + 4 * g;
-        const int nvalid = min(max(jd.n - i0, 0), 4);
-        const bool fast = (jd.flags & JOB_ALIGNED4) && nvalid == 4;
-        const uint8_t *col = jd.samples + (nvalid > 0 ? i0 : 0);
-        const int t_lane = 16 * q_st + 8 * hl;     // first sample of this lane in a stage
+        PieceCtx pc;
+        pc.samples = jd.samples;
+        pc.stride = jd.stride;
+        pc.n = jd.n;
+        pc.t0 = pce.t0;
+        pc.t1 = pce.t1_atomic & 0x7FFFFFFF;
+        pc.i0 = blk0 + 8 * g8;
+        pc.t_lane = 16 * q + 8 * half;
+        // lane offset from a stage's first row: fits 32 bits (stride <= 2^26)
+        pc.off = (uint32_t)(pc.t_lane * jd.stride) + (uint32_t)pc.i0;
+        pc.full_rows = blk0 + TILE <= jd.n;
 
-        v16i acc_re[2][2], acc_im[2][2];
+        Acc acc;
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    acc_re[a][b][r] = 0;
-                    acc_im[a][b][r] = 0;
+                    acc.re[a][b][r] = 0;
+                    acc.im[a][b][r] = 0;
                 }
 
-        const int nst = (t1 - t0 + STAGE - 1) / STAGE;
-        uint32_t d[8];
-        if (stager) {
-            if (nvalid > 0) stage_load(d, col, jd.stride, t0 + t_lane, t1, fast, nvalid);
-            else for (int k = 0; k < 8; ++k) d[k] = 0x88888888u;
-            uint8_t *region = smem + (role_a ? q_st * A_Q : A_BYTES + q_st * B_Q);
-            stage_write(region, d, g, hl, role_a, re_low);
-        }
-        __syncthreads();
-
-        for (int s = 0; s < nst; ++s) {
-            const bool more = s + 1 < nst;
-            if (more && stager && nvalid > 0)
-                stage_load(d, col, jd.stride, t0 + (s + 1) * STAGE + t_lane, t1, fast, nvalid);
-
-            const uint8_t *buf = smem + (s & 1) * STAGE_BYTES;
-            const uint8_t *bbuf = diag ? buf : buf + A_BYTES;
-            const int bq = diag ? A_Q : B_Q;
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const uint8_t *aq = buf + q * A_Q + (lane >> 5) * CH + 16 * (lane & 31);
-                const v4i re_a0 = lds128(aq + 512 * (2 * wa));
-                const v4i re_a1 = lds128(aq + 512 * (2 * wa + 1));
-                const v4i im_a0 = lds128(aq + CH + 512 * (2 * wa));
-                const v4i im_a1 = lds128(aq + CH + 512 * (2 * wa + 1));
-                const uint8_t *bp = bbuf + q * bq + (lane >> 5) * CH + 16 * (lane & 31);
-                const v4i b0 = lds128(bp + 512 * (2 * wb));
-                const v4i b1 = lds128(bp + 512 * (2 * wb + 1));
-                acc_re[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(re_a0, b0, acc_re[0][0], 0, 0, 0);
-                acc_im[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im_a0, b0, acc_im[0][0], 0, 0, 0);
-                acc_re[0][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(re_a0, b1, acc_re[0][1], 0, 0, 0);
-                acc_im[0][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im_a0, b1, acc_im[0][1], 0, 0, 0);
-                acc_re[1][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(re_a1, b0, acc_re[1][0], 0, 0, 0);
-                acc_im[1][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im_a1, b0, acc_im[1][0], 0, 0, 0);
-                acc_re[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(re_a1, b1, acc_re[1][1], 0, 0, 0);
-                acc_im[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im_a1, b1, acc_im[1][1], 0, 0, 0);
-            }
-
-            if (more && stager) {
-                if (nvalid == 0)
-                    for (int k = 0; k < 8; ++k) d[k] = 0x88888888u;
-                uint8_t *region = smem + ((s + 1) & 1) * STAGE_BYTES +
-                                  (role_a ? q_st * A_Q : A_BYTES + q_st * B_Q);
-                stage_write(region, d, g, hl, role_a, re_low);
-            }
-            __syncthreads();
+        const bool re_low = (jd.flags & JOB_RE_LOW) != 0;
+        if (role_a) {
+            if (re_low) run_piece<ALIGNED, true, true>(acc, smem, pc, lane, wa, wb, wslot);
+            else run_piece<ALIGNED, true, false>(acc, smem, pc, lane, wa, wb, wslot);
+        } else {
+            if (re_low) run_piece<ALIGNED, false, true>(acc, smem, pc, lane, wa, wb, wslot);
+            else run_piece<ALIGNED, false, false>(acc, smem, pc, lane, wa, wb, wslot);
         }
 
         // integrate into the slot's accumulators
@@ -236,8 +365,8 @@ __global__ __launch_bounds__(256, 2) void xcorr_mfma(KernelArgs args)
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b)
-                flush_block(tb + ((2 * wa + a) * BLKS + (2 * wb + b)) * BLOCK_I32,
-                            acc_re[a][b], acc_im[a][b], atomic);
+                flush_block(tb + ((2 * wa + a) * BLKS + (2 * wb + b)) * BLOCK_I32, acc.re[a][b],
+                            acc.im[a][b], atomic);
     }
 }
 
@@ -250,7 +379,7 @@ __global__ __launch_bounds__(256) void vis_dump(const int32_t *__restrict__ acc,
     if (j >= n) return;
     const int ti = i >> 7, tj = j >> 7;
     const int ri = i & 127, rj = j & 127;
-    const int pa = 32 * (ri & 3) + (ri >> 2), pb = 32 * (rj & 3) + (rj >> 2);
+    const int pa = 16 * (ri & 7) + (ri >> 3), pb = 16 * (rj & 7) + (rj >> 3);
     const int ca = pa >> 5, ra = pa & 31, cb = pb >> 5, lb = pb & 31;
     const int reg = 4 * (ra >> 3) + (ra & 3);
     const int ln = lb + 32 * ((ra >> 2) & 1);
@@ -300,10 +429,15 @@ __global__ __launch_bounds__(256) void xcorr_scalar(const uint8_t *__restrict__ 
 // ---------------------------------------------------------------------------
 // Launchers (host)
 // ---------------------------------------------------------------------------
-hipError_t launch_correlate(const KernelArgs &a, int grid, hipStream_t stream)
+// `aligned`: every job's samples pointer and row stride are multiples of 4
+// bytes and its N is a multiple of 4, so whole dwords can be loaded.
+hipError_t launch_correlate(const KernelArgs &a, int grid, bool aligned, hipStream_t stream)
 {
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(xcorr_mfma, dim3(grid), dim3(256), 0, stream, a);
+    if (aligned)
+        hipLaunchKernelGGL(xcorr_mfma<true>, dim3(grid), dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL(xcorr_mfma<false>, dim3(grid), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 

@@ -49,14 +49,17 @@ Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages)
                 const size_t first = raw.size();
                 for (; w < grid && bound(w) < hi; ++w) {
                     const int64_t a = std::max(lo, bound(w)), b = std::min(hi, bound(w + 1));
-                    if (a >= b) continue;
-                    Raw r;
-                    r.p.job = j;
-                    r.p.tile = ti | (tj << 16);
-                    r.p.t0 = (int32_t)((a - lo) * STAGE);
-                    r.p.t1_atomic = (int32_t)std::min<int64_t>((b - lo) * STAGE, t);
-                    r.wg = (int32_t)w;
-                    raw.push_back(r);
+                    // long ranges are cut so that no piece exceeds MAX_PIECE_STAGES
+                    for (int64_t c = a; c < b; c += MAX_PIECE_STAGES) {
+                        const int64_t e = std::min<int64_t>(b, c + MAX_PIECE_STAGES);
+                        Raw r;
+                        r.p.job = j;
+                        r.p.tile = ti | (tj << 16);
+                        r.p.t0 = (int32_t)((c - lo) * STAGE);
+                        r.p.t1_atomic = (int32_t)std::min<int64_t>((e - lo) * STAGE, t);
+                        r.wg = (int32_t)w;
+                        raw.push_back(r);
+                    }
                 }
                 if (raw.size() - first > 1)
                     for (size_t k = first; k < raw.size(); ++k)

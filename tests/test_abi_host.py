@@ -76,7 +76,7 @@ def _check_cover(pieces, jobs, grid):
         nt = -(-n // 128)
         assert p.tj < nt
         assert 0 <= p.t0 < p.t1 <= t
-        assert p.t0 % 32 == 0
+        assert p.t0 % 64 == 0
         cover.setdefault((p.job, p.ti, p.tj), []).append((p.t0, p.t1, p.atomic))
         per_wg[p.workgroup] = per_wg.get(p.workgroup, 0) + (p.t1 - p.t0)
     for j, (n, t) in enumerate(jobs):
@@ -107,7 +107,7 @@ def test_plan_covers_exactly_once(X, jobs, grid, min_st):
     pieces = X.plan_inspect([j[0] for j in jobs], [j[1] for j in jobs], grid, min_st)
     per_wg = _check_cover(pieces, jobs, grid)
     # balance: every workgroup gets the same number of stages, +-1 per tile boundary
-    stages = {w: -(-s // 32) for w, s in per_wg.items()}
+    stages = {w: -(-s // 64) for w, s in per_wg.items()}
     if len(stages) > 1:
         vals = np.array(list(stages.values()))
         assert vals.max() - vals.min() <= 3
@@ -122,3 +122,13 @@ def test_plan_random_batches(X):
         pieces = X.plan_inspect([j[0] for j in jobs], [j[1] for j in jobs], grid,
                                 int(rng.integers(1, 10)))
         _check_cover(pieces, jobs, grid)
+
+
+def test_plan_caps_piece_length(X):
+    # B operands are scaled by 16 inside a piece: no piece may exceed 2^20 - 1 samples
+    jobs = [(128, 3_000_000)]
+    pieces = X.plan_inspect([128], [3_000_000], 1, 1)
+    _check_cover(pieces, jobs, 1)
+    assert max(p.t1 - p.t0 for p in pieces) <= (1 << 20) - 1
+    assert len(pieces) == -(-3_000_000 // (16383 * 64))
+    assert all(p.atomic for p in pieces)
