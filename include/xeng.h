@@ -159,37 +159,46 @@ int xeng_correlate_reference(const uint8_t *d_samples, int64_t n_samples, int32_
 
 /*
  * Work decomposition (host only, no device needed).  The correlation of a
- * batch is split into pieces: one 128 x 128 tile of the upper triangle of
- * one job over a contiguous range of samples, each piece run by one
- * workgroup of the persistent launch.  Tiles cut into several pieces are
- * flushed with integer atomic adds, the others with a plain add.
+ * batch is split into pieces: a tile of the upper triangle of one job over
+ * a contiguous range of samples, each piece run by one workgroup of the
+ * persistent launch.  Tiles cut into several pieces are flushed with integer
+ * atomic adds, the others with a plain add.  Jobs whose samples pointer and
+ * row stride are multiples of 16 bytes and whose N is a multiple of 256 use
+ * workgroup tiles of 128 x 256 inputs ("wide"), others 128 x 128.
  */
 typedef struct {
     int32_t job;       /* index into the batch */
-    int32_t ti, tj;    /* tile row / column (units of 128 inputs), ti <= tj */
+    int32_t ti, tj;    /* first accumulator tile: row / column in units of 128 inputs */
     int32_t atomic;    /* 1 if the tile is shared with other pieces */
     int64_t t0, t1;    /* sample range [t0, t1) */
     int32_t workgroup; /* workgroup that runs the piece */
-    int32_t reserved;
+    int32_t n_tiles;   /* accumulator tiles (ti, tj .. tj + n_tiles - 1) computed */
 } xeng_piece_info;
 
 /*
  * Fill `out` (capacity `cap`) with the pieces the library would launch for
  * jobs of sizes (n_inputs[k], n_samples[k]) on `n_workgroups` workgroups
  * with at least `min_stages` 64-sample stages per piece (0 = library
- * default).  Returns the number of pieces (which may exceed cap: then only
- * cap are written), or a negative status.
+ * default), for square (wide = 0) or wide (wide = 1) tiles.  Returns the
+ * number of pieces (which may exceed cap: then only cap are written), or a
+ * negative status.  A wide piece's tile below the diagonal or past N is
+ * computed but not stored.
  */
 int64_t xeng_plan_inspect(const int32_t *n_inputs, const int64_t *n_samples, int32_t n_jobs,
-                          int32_t n_workgroups, int32_t min_stages,
+                          int32_t n_workgroups, int32_t min_stages, int32_t wide,
                           xeng_piece_info *out, int64_t cap);
 
+/* Kernel selection for xeng_set_tuning. */
+#define XENG_KERNEL_AUTO 0     /* wide DMA kernel where the job allows it, else general */
+#define XENG_KERNEL_GENERAL 1  /* always the general kernel */
+
 /*
- * Launch tuning: workgroups per compute unit of the persistent launch
- * (1 or 2) and the minimum piece length in 64-sample stages.  Values <= 0
- * keep the current setting.  Applies to later calls on every device.
+ * Launch tuning: workgroups per compute unit of the general kernel (1 or 2),
+ * the minimum piece length in 64-sample stages, and the kernel selection.
+ * Values < 0 (or 0 for the first two) keep the current setting.  Applies to
+ * later calls on every device.  Results never depend on these settings.
  */
-int xeng_set_tuning(int32_t wgs_per_cu, int32_t min_stages);
+int xeng_set_tuning(int32_t wgs_per_cu, int32_t min_stages, int32_t kernel);
 
 #ifdef __cplusplus
 }

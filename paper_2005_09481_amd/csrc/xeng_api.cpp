@@ -21,6 +21,7 @@
 
 namespace xeng {
 hipError_t launch_correlate(const KernelArgs &a, int grid, bool aligned, hipStream_t stream);
+hipError_t launch_correlate_dma(const KernelArgs &a, int grid, hipStream_t stream);
 hipError_t launch_dump(const int32_t *acc, int n, int nt, int32_t *out, hipStream_t stream);
 hipError_t launch_zero(int32_t *p, int64_t n_i32, hipStream_t stream);
 hipError_t launch_reference(const uint8_t *s, int64_t n_samples, int n, int64_t stride,
@@ -31,8 +32,9 @@ using namespace xeng;
 
 namespace {
 
-std::atomic<int> g_wgs_per_cu{2};
-std::atomic<int> g_min_stages{8};
+std::atomic<int> g_wgs_per_cu{2};      // general kernel
+std::atomic<int> g_min_stages{4};
+std::atomic<int> g_kernel{XENG_KERNEL_AUTO};
 
 // Restores the caller's current device on scope exit.
 struct DeviceGuard {
@@ -98,10 +100,11 @@ DeviceState *device_state(int device)
     return p;
 }
 
-std::string plan_key(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages)
+std::string plan_key(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, TileShape shape)
 {
     std::string k;
     k.reserve(32 + 16 * (size_t)n_jobs);
+    k.push_back(shape == TileShape::Wide ? 'w' : 's');
     k.append(reinterpret_cast<const char *>(&max_wgs), sizeof max_wgs);
     k.append(reinterpret_cast<const char *>(&min_stages), sizeof min_stages);
     for (int j = 0; j < n_jobs; ++j) {
@@ -113,12 +116,14 @@ std::string plan_key(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stage
 
 // Look up (or build and upload) the plan for these job sizes.  Called with
 // st->mu held and the device current.
-int get_plan(DeviceState *st, const PlanJob *jobs, int n_jobs, hipStream_t stream,
-             DevicePlan *out)
+int get_plan(DeviceState *st, const PlanJob *jobs, int n_jobs, TileShape shape, DevicePlan *out)
 {
-    const int max_wgs = st->cu_count * std::max(1, g_wgs_per_cu.load());
+    // the DMA kernel holds one 256-thread workgroup per CU (its LDS ring
+    // fills most of the CU); the general kernel fits two
+    const int per_cu = shape == TileShape::Wide ? 1 : std::max(1, g_wgs_per_cu.load());
+    const int max_wgs = st->cu_count * per_cu;
     const int min_stages = std::max(1, g_min_stages.load());
-    const std::string key = plan_key(jobs, n_jobs, max_wgs, min_stages);
+    const std::string key = plan_key(jobs, n_jobs, max_wgs, min_stages, shape);
     auto it = st->plans.find(key);
     if (it != st->plans.end()) {
         st->lru.remove(key);
@@ -126,7 +131,7 @@ int get_plan(DeviceState *st, const PlanJob *jobs, int n_jobs, hipStream_t strea
         *out = it->second;
         return XENG_OK;
     }
-    Plan plan = make_plan(jobs, n_jobs, max_wgs, min_stages);
+    Plan plan = make_plan(jobs, n_jobs, max_wgs, min_stages, shape);
     DevicePlan dp;
     dp.grid = plan.grid;
     if (plan.grid > 0) {
@@ -146,7 +151,6 @@ int get_plan(DeviceState *st, const PlanJob *jobs, int n_jobs, hipStream_t strea
             return XENG_EDEVICE;
         }
     }
-    (void)stream;
     if ((int)st->plans.size() >= PLAN_CACHE_MAX) {
         // hipFree waits for the device, so no queued launch still reads it
         const std::string victim = st->lru.back();
@@ -197,10 +201,26 @@ JobDesc make_job(const xeng_ctx *c, int32_t slot, const uint8_t *d_samples, int6
     jd.nt = c->nt;
     jd.flags = 0;
     if (c->flags & XENG_NIBBLE_RE_LOW) jd.flags |= JOB_RE_LOW;
-    if ((stride % 8) == 0 && (reinterpret_cast<uintptr_t>(d_samples) % 8) == 0 && c->n % 8 == 0)
-        jd.flags |= JOB_ALIGNED8;
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(d_samples);
+    if ((stride % 8) == 0 && (addr % 8) == 0 && c->n % 8 == 0) jd.flags |= JOB_ALIGNED8;
+    if ((stride % 16) == 0 && (addr % 16) == 0 && c->n % 256 == 0) jd.flags |= JOB_DMA;
     jd.pad = 0;
     return jd;
+}
+
+// Kernel choice for a launch whose jobs all have `flags_and` in common.
+bool use_dma(uint32_t flags_and)
+{
+    const int k = g_kernel.load();
+    if (k == XENG_KERNEL_GENERAL) return false;
+    return (flags_and & JOB_DMA) != 0;
+}
+
+hipError_t launch(const KernelArgs &a, const DevicePlan &dp, bool dma, uint32_t flags_and,
+                  hipStream_t stream)
+{
+    if (dma) return launch_correlate_dma(a, dp.grid, stream);
+    return launch_correlate(a, dp.grid, (flags_and & JOB_ALIGNED8) != 0, stream);
 }
 
 }  // namespace
@@ -284,15 +304,16 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_
     PlanJob pj{ctx->n, n_samples};
     DevicePlan dp;
     KernelArgs a;
-    // held through the launch so that no other thread evicts the plan first
-    std::lock_guard<std::mutex> lk(ctx->st->mu);
-    int rc = get_plan(ctx->st, &pj, 1, stream, &dp);
-    if (rc != XENG_OK) return rc;
     a.job0 = make_job(ctx, slot, d_samples, row_stride);
     a.jobs = nullptr;
+    const bool dma = use_dma(a.job0.flags);
+    // held through the launch so that no other thread evicts the plan first
+    std::lock_guard<std::mutex> lk(ctx->st->mu);
+    int rc = get_plan(ctx->st, &pj, 1, dma ? TileShape::Wide : TileShape::Square, &dp);
+    if (rc != XENG_OK) return rc;
     a.pieces = dp.d_pieces;
     a.wg_off = dp.d_off;
-    hipError_t e = launch_correlate(a, dp.grid, (a.job0.flags & JOB_ALIGNED8) != 0, stream);
+    hipError_t e = launch(a, dp, dma, a.job0.flags, stream);
     if (e != hipSuccess) return map_err(e);
     ctx->acc_t[(size_t)slot] += n_samples;
     return XENG_OK;
@@ -331,9 +352,12 @@ int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
     if (!guard.ok) return XENG_EDEVICE;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     DeviceState *st = jobs[0].ctx->st;
+    uint32_t flags_and = ~0u;
+    for (const JobDesc &jd : descs) flags_and &= jd.flags;
+    const bool dma = use_dma(flags_and);
     std::lock_guard<std::mutex> lk(st->mu);
     DevicePlan dp;
-    int rc = get_plan(st, pj.data(), (int)pj.size(), stream, &dp);
+    int rc = get_plan(st, pj.data(), (int)pj.size(), dma ? TileShape::Wide : TileShape::Square, &dp);
     if (rc != XENG_OK) return rc;
 
     // stage the job table through the ring
@@ -371,9 +395,7 @@ int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
     a.jobs = tb.d;
     a.pieces = dp.d_pieces;
     a.wg_off = dp.d_off;
-    bool aligned = true;
-    for (const JobDesc &jd : descs) aligned = aligned && (jd.flags & JOB_ALIGNED8);
-    e = launch_correlate(a, dp.grid, aligned, stream);
+    e = launch(a, dp, dma, flags_and, stream);
     if (e == hipSuccess) e = hipEventRecord(tb.ev, stream);
     if (e != hipSuccess) return map_err(e);
     tb.pending = true;
@@ -453,11 +475,11 @@ int xeng_correlate_reference(const uint8_t *d_samples, int64_t n_samples, int32_
 }
 
 int64_t xeng_plan_inspect(const int32_t *n_inputs, const int64_t *n_samples, int32_t n_jobs,
-                          int32_t n_workgroups, int32_t min_stages, xeng_piece_info *out,
-                          int64_t cap)
+                          int32_t n_workgroups, int32_t min_stages, int32_t wide,
+                          xeng_piece_info *out, int64_t cap)
 {
     if (n_jobs < 0 || (n_jobs > 0 && (!n_inputs || !n_samples)) || n_workgroups < 1 || cap < 0 ||
-        (cap > 0 && !out))
+        (cap > 0 && !out) || (wide != 0 && wide != 1))
         return XENG_EINVAL;
     std::vector<PlanJob> pj((size_t)n_jobs);
     for (int32_t k = 0; k < n_jobs; ++k) {
@@ -465,28 +487,31 @@ int64_t xeng_plan_inspect(const int32_t *n_inputs, const int64_t *n_samples, int
         pj[(size_t)k] = PlanJob{n_inputs[k], n_samples[k]};
     }
     if (min_stages <= 0) min_stages = g_min_stages.load();
-    Plan plan = make_plan(pj.data(), n_jobs, n_workgroups, min_stages);
+    const TileShape shape = wide ? TileShape::Wide : TileShape::Square;
+    Plan plan = make_plan(pj.data(), n_jobs, n_workgroups, min_stages, shape);
     const int64_t np = (int64_t)plan.pieces.size();
     for (int64_t k = 0; k < np && k < cap; ++k) {
         const Piece &p = plan.pieces[(size_t)k];
         xeng_piece_info &o = out[k];
+        const int a = p.tile & 0xFFFF, b = (p.tile >> 16) & 0xFFFF;
         o.job = p.job;
-        o.ti = p.tile & 0xFFFF;
-        o.tj = (p.tile >> 16) & 0xFFFF;
+        o.ti = a;
+        o.tj = wide ? 2 * b : b;
         o.atomic = p.t1_atomic < 0 ? 1 : 0;
         o.t0 = p.t0;
         o.t1 = p.t1_atomic & 0x7FFFFFFF;
         o.workgroup = plan.piece_wg[(size_t)k];
-        o.reserved = 0;
+        o.n_tiles = wide ? 2 : 1;
     }
     return np;
 }
 
-int xeng_set_tuning(int32_t wgs_per_cu, int32_t min_stages)
+int xeng_set_tuning(int32_t wgs_per_cu, int32_t min_stages, int32_t kernel)
 {
-    if (wgs_per_cu > 2) return XENG_EINVAL;
+    if (wgs_per_cu > 2 || kernel > XENG_KERNEL_GENERAL) return XENG_EINVAL;
     if (wgs_per_cu > 0) g_wgs_per_cu.store(wgs_per_cu);
     if (min_stages > 0) g_min_stages.store(min_stages);
+    if (kernel >= 0) g_kernel.store(kernel);
     return XENG_OK;
 }
 

@@ -21,9 +21,10 @@ constexpr int KSTEP = 16;          // samples per MFMA k-step (32 int8 values)
 // Accumulator layout of one slot (device, int32): tile-major over the upper
 // triangle of tiles, tile index ti*nt - ti*(ti-1)/2 + (tj-ti).  Inside a
 // tile: [ca][cb][comp][reg][lane] with ca, cb the 4 x 4 blocks, comp 0 = Re,
-// 1 = Im, and (reg, lane) the MFMA 32 x 32 accumulator register layout.
-// Rows inside a tile are permuted: tile row offset r (0..127) lives at
-// position p = 16*(r % 8) + r / 8, block ca = p / 32, row-in-block p % 32.
+// 1 = Im, and (reg, lane) the MFMA 32 x 32 accumulator register layout:
+// row r of the tile is in block ca = r / 32, column c in block cb = c / 32,
+// and within a block row i, column j sit in register 4*(i/8) + i%4 of lane
+// j + 32*((i/4)%2).
 constexpr int64_t TILE_I32 = (int64_t)BLKS * BLKS * 2 * 16 * 64;   // 32768 int32
 constexpr int64_t BLOCK_I32 = 2 * 16 * 64;                          // 2048 int32
 
@@ -53,7 +54,12 @@ struct JobDesc {
     int32_t pad;
 };
 constexpr uint32_t JOB_RE_LOW = 1u;    // real part in the low nibble
-constexpr uint32_t JOB_ALIGNED8 = 2u;  // samples, stride and N are multiples of 8 bytes
+constexpr uint32_t JOB_ALIGNED8 = 2u;   // samples, stride and N are multiples of 8 bytes
+constexpr uint32_t JOB_DMA = 4u;        // samples, stride multiples of 16, N of 256: DMA kernel
+
+// Work decomposition shapes: 128 x 128 tiles (general kernel) or
+// 128 x 256 workgroup tiles covering two accumulator tiles (DMA kernel).
+enum class TileShape { Square = 0, Wide = 1 };
 
 // One piece of work: tile (ti, tj) of job `job` over samples [t0, t1).
 struct Piece {

@@ -32,14 +32,12 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // LDS stage layout.  A stage is 64 samples = 4 MFMA k-steps.  For each
-// k-step q a component region holds 128 tile positions x 16 bytes (the 16
+// k-step q a component region holds 128 tile rows x 16 bytes (the 16
 // samples of one input, in time order).  A rows keep Re, Im, -Re as int8;
 // B rows keep 16*Re, 16*Im as int8 (the scale makes their unpack three bit
 // operations per four samples; every product is then 16x the true one and
-// the flush divides it out exactly).  Tile row offset r lives at position
-// 16*(r % 8) + r/8: the staging writes of 16 lanes then fill 8 consecutive
-// 16-byte slots (no bank conflicts) and the MFMA operand reads of 32 lanes
-// stay contiguous.
+// the flush divides it out exactly).  This is the general kernel, for any
+// alignment and N; 16-byte-aligned arrays take the DMA kernel instead.
 constexpr int CH = TILE * 16;       // 2048 bytes
 constexpr int QSTEPS = STAGE / KSTEP;   // 4
 constexpr int A_Q = 3 * CH;
@@ -165,8 +163,8 @@ __device__ __forceinline__ void load_stage(StageRegs &r, const PieceCtx &pc, int
 }
 
 // Unpack one lane's share of a stage into the stage buffer.  `slot` is the
-// byte offset of this lane's (position, half) in a component region; input
-// c of the lane sits 16 * 16 * c bytes further.
+// byte offset of this lane's (first input, half) in a component region;
+// input c of the lane sits 16 * c bytes further.
 template <bool ROLE_A, bool RE_LOW>
 __device__ __forceinline__ void stage_write(uint8_t *region, const StageRegs &r, int slot)
 {
@@ -192,7 +190,7 @@ __device__ __forceinline__ void stage_write(uint8_t *region, const StageRegs &r,
     transpose4(hi[4], hi[5], hi[6], hi[7], p[4][1], p[5][1], p[6][1], p[7][1]);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        uint8_t *dst = region + slot + 256 * c;
+        uint8_t *dst = region + slot + 16 * c;
         if (ROLE_A) {
             const uint32_t h0 = (p[c][0] >> 4) & 0x0F0F0F0Fu, l0 = p[c][0] & 0x0F0F0F0Fu;
             const uint32_t h1 = (p[c][1] >> 4) & 0x0F0F0F0Fu, l1 = p[c][1] & 0x0F0F0F0Fu;
@@ -315,8 +313,9 @@ __global__ __launch_bounds__(256, 2) void xcorr_mfma(KernelArgs args)
     const int g8 = (lane & 7) | (((lane >> 4) & 1) << 3);   // 8-input group 0..15
     const int half = (lane >> 3) & 1;                        // samples 0-7 / 8-15 of a k-step
     const int q = 2 * (wave & 1) + (lane >> 5);              // k-step 0..3
-    // LDS byte offset of this lane's (position g8 of input 0, half, k-step)
-    const int wslot = (role_a ? q * A_Q : A_BYTES + q * B_Q) + 16 * g8 + 8 * half;
+    // LDS byte offset of this lane's (input 8*g8, half, k-step); input c of
+    // the lane is 16 * c bytes further
+    const int wslot = (role_a ? q * A_Q : A_BYTES + q * B_Q) + 128 * g8 + 8 * half;
 
     const int p_begin = args.wg_off[blockIdx.x], p_end = args.wg_off[blockIdx.x + 1];
     for (int pi = p_begin; pi < p_end; ++pi) {
@@ -379,8 +378,7 @@ __global__ __launch_bounds__(256) void vis_dump(const int32_t *__restrict__ acc,
     if (j >= n) return;
     const int ti = i >> 7, tj = j >> 7;
     const int ri = i & 127, rj = j & 127;
-    const int pa = 16 * (ri & 7) + (ri >> 3), pb = 16 * (rj & 7) + (rj >> 3);
-    const int ca = pa >> 5, ra = pa & 31, cb = pb >> 5, lb = pb & 31;
+    const int ca = ri >> 5, ra = ri & 31, cb = rj >> 5, lb = rj & 31;
     const int reg = 4 * (ra >> 3) + (ra & 3);
     const int ln = lb + 32 * ((ra >> 2) & 1);
     const int64_t tile = (int64_t)ti * nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <stdint.h>
+#include <utility>
 #include <vector>
 
 #include "xeng_internal.h"
@@ -26,6 +27,16 @@ struct Plan {
 // ranges of a linear (job, tile, stage) order: the stream-K decomposition.
 // A tile cut into several pieces is marked atomic.  Every (i <= j, t) of
 // every job is covered by exactly one piece.
-Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages);
+//
+// Square: units are the tiles (ti <= tj) of 128 x 128.  Wide: units are
+// workgroup tiles (I, J2) of 128 rows x 256 columns, i.e. accumulator tiles
+// (I, 2 J2) and (I, 2 J2 + 1), for every I <= 2 J2 + 1 (the half below the
+// diagonal, if any, is computed but not stored).
+Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages,
+               TileShape shape = TileShape::Square);
+
+// Units of one job in the plan's order: pairs (row index, column index)
+// in the shape's own units.
+std::vector<std::pair<int, int>> plan_units(int n, TileShape shape);
 
 }  // namespace xeng

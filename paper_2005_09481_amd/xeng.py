@@ -22,6 +22,8 @@ XENG_EDEVICE = -4
 XENG_EBUSY = -5
 XENG_ENOTSUP = -6
 XENG_NIBBLE_RE_LOW = 1
+XENG_KERNEL_AUTO = 0
+XENG_KERNEL_GENERAL = 1
 
 
 class XengError(RuntimeError):
@@ -45,7 +47,7 @@ class _Job(ctypes.Structure):
 class _PieceInfo(ctypes.Structure):
     _fields_ = [("job", ctypes.c_int32), ("ti", ctypes.c_int32), ("tj", ctypes.c_int32),
                 ("atomic", ctypes.c_int32), ("t0", ctypes.c_int64), ("t1", ctypes.c_int64),
-                ("workgroup", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("workgroup", ctypes.c_int32), ("n_tiles", ctypes.c_int32)]
 
 
 _lib = None
@@ -75,9 +77,9 @@ def lib() -> ctypes.CDLL:
         "xeng_n_slots": (i32, [vp]),
         "xeng_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "xeng_correlate_reference": (ctypes.c_int, [vp, i64, i32, i64, u32, vp, vp]),
-        "xeng_plan_inspect": (i64, [ctypes.POINTER(i32), ctypes.POINTER(i64), i32, i32, i32,
+        "xeng_plan_inspect": (i64, [ctypes.POINTER(i32), ctypes.POINTER(i64), i32, i32, i32, i32,
                                     ctypes.POINTER(_PieceInfo), i64]),
-        "xeng_set_tuning": (ctypes.c_int, [i32, i32]),
+        "xeng_set_tuning": (ctypes.c_int, [i32, i32, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -108,8 +110,11 @@ def slot_bytes(n_inputs: int) -> int:
     return int(lib().xeng_slot_bytes(n_inputs))
 
 
-def set_tuning(wgs_per_cu: int = 0, min_stages: int = 0):
-    _check(lib().xeng_set_tuning(wgs_per_cu, min_stages), "xeng_set_tuning")
+def set_tuning(wgs_per_cu: int = 0, min_stages: int = 0, kernel: int = -1):
+    """Launch tuning (results never depend on it): general-kernel workgroups
+    per CU, minimum piece length in 64-sample stages, kernel selection
+    (XENG_KERNEL_AUTO / XENG_KERNEL_GENERAL; -1 keeps the current one)."""
+    _check(lib().xeng_set_tuning(wgs_per_cu, min_stages, kernel), "xeng_set_tuning")
 
 
 def _stream_handle(stream, device):
@@ -234,18 +239,19 @@ class PieceInfo:
     t0: int
     t1: int
     workgroup: int
+    n_tiles: int
 
 
-def plan_inspect(n_inputs, n_samples, n_workgroups: int, min_stages: int = 0):
+def plan_inspect(n_inputs, n_samples, n_workgroups: int, min_stages: int = 0, wide: bool = False):
     """Pieces the library would launch for jobs of these sizes (host only)."""
     n = len(n_inputs)
     ni = (ctypes.c_int32 * n)(*n_inputs)
     ns = (ctypes.c_int64 * n)(*n_samples)
-    cnt = lib().xeng_plan_inspect(ni, ns, n, n_workgroups, min_stages, None, 0)
+    cnt = lib().xeng_plan_inspect(ni, ns, n, n_workgroups, min_stages, int(wide), None, 0)
     if cnt < 0:
         raise XengError(int(cnt), "xeng_plan_inspect")
     out = (_PieceInfo * max(cnt, 1))()
-    cnt2 = lib().xeng_plan_inspect(ni, ns, n, n_workgroups, min_stages, out, cnt)
+    cnt2 = lib().xeng_plan_inspect(ni, ns, n, n_workgroups, min_stages, int(wide), out, cnt)
     assert cnt2 == cnt
-    return [PieceInfo(p.job, p.ti, p.tj, bool(p.atomic), p.t0, p.t1, p.workgroup)
+    return [PieceInfo(p.job, p.ti, p.tj, bool(p.atomic), p.t0, p.t1, p.workgroup, p.n_tiles)
             for p in out[:cnt]]

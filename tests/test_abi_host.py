@@ -62,22 +62,25 @@ def test_argument_checks_without_device(X):
     assert L.xeng_correlate_batch(None, 1, None) == X.XENG_EINVAL
     assert L.xeng_correlate_batch(None, 0, None) == X.XENG_OK
     assert L.xeng_correlate_reference(None, 10, 4, 4, 0, None, None) == X.XENG_EINVAL
-    assert L.xeng_set_tuning(3, 0) == X.XENG_EINVAL
+    assert L.xeng_set_tuning(3, 0, -1) == X.XENG_EINVAL
+    assert L.xeng_set_tuning(0, 0, 7) == X.XENG_EINVAL
 
 
 def _check_cover(pieces, jobs, grid):
-    """Every (job, tile, sample) covered by exactly one piece."""
+    """Every (job, accumulator tile, sample) covered by exactly one piece."""
     cover = {}
     per_wg = {}
     for p in pieces:
         assert 0 <= p.workgroup < grid
-        assert p.ti <= p.tj
         n, t = jobs[p.job]
         nt = -(-n // 128)
-        assert p.tj < nt
+        assert p.n_tiles in (1, 2)
+        assert p.ti <= p.tj + p.n_tiles - 1 and p.tj < nt
         assert 0 <= p.t0 < p.t1 <= t
         assert p.t0 % 64 == 0
-        cover.setdefault((p.job, p.ti, p.tj), []).append((p.t0, p.t1, p.atomic))
+        for tj in range(p.tj, p.tj + p.n_tiles):
+            if p.ti <= tj < nt:          # stored tiles only
+                cover.setdefault((p.job, p.ti, tj), []).append((p.t0, p.t1, p.atomic))
         per_wg[p.workgroup] = per_wg.get(p.workgroup, 0) + (p.t1 - p.t0)
     for j, (n, t) in enumerate(jobs):
         nt = -(-n // 128)
@@ -95,6 +98,7 @@ def _check_cover(pieces, jobs, grid):
     return per_wg
 
 
+@pytest.mark.parametrize("wide", [False, True])
 @pytest.mark.parametrize("jobs,grid,min_st", [
     ([(2048, 32768)], 512, 8),
     ([(2048, 32768)], 256, 8),
@@ -103,8 +107,8 @@ def _check_cover(pieces, jobs, grid):
     ([(129, 33)], 7, 1),
     ([(300, 1000), (5, 0), (1024, 16384), (256, 4097)], 512, 4),
 ])
-def test_plan_covers_exactly_once(X, jobs, grid, min_st):
-    pieces = X.plan_inspect([j[0] for j in jobs], [j[1] for j in jobs], grid, min_st)
+def test_plan_covers_exactly_once(X, jobs, grid, min_st, wide):
+    pieces = X.plan_inspect([j[0] for j in jobs], [j[1] for j in jobs], grid, min_st, wide)
     per_wg = _check_cover(pieces, jobs, grid)
     # balance: every workgroup gets the same number of stages, +-1 per tile boundary
     stages = {w: -(-s // 64) for w, s in per_wg.items()}
@@ -119,9 +123,10 @@ def test_plan_random_batches(X):
         k = int(rng.integers(1, 6))
         jobs = [(int(rng.integers(1, 700)), int(rng.integers(0, 5000))) for _ in range(k)]
         grid = int(rng.integers(1, 600))
-        pieces = X.plan_inspect([j[0] for j in jobs], [j[1] for j in jobs], grid,
-                                int(rng.integers(1, 10)))
-        _check_cover(pieces, jobs, grid)
+        for wide in (False, True):
+            pieces = X.plan_inspect([j[0] for j in jobs], [j[1] for j in jobs], grid,
+                                    int(rng.integers(1, 10)), wide)
+            _check_cover(pieces, jobs, grid)
 
 
 def test_plan_caps_piece_length(X):

@@ -182,17 +182,50 @@ def test_dump_to_pinned_host(X):
 
 
 def test_tuning_does_not_change_results(X):
-    x = synth.uniform_bytes(300, 2000, seed=22)
+    x = synth.uniform_bytes(512, 2000, seed=22)
     outs = []
     try:
-        for wpc, ms in ((2, 8), (1, 1), (2, 1), (1, 64)):
-            X.set_tuning(wpc, ms)
+        for wpc, ms, kern in ((2, 4, X.XENG_KERNEL_AUTO), (1, 1, X.XENG_KERNEL_GENERAL),
+                              (2, 1, X.XENG_KERNEL_GENERAL), (1, 64, X.XENG_KERNEL_AUTO),
+                              (2, 1, X.XENG_KERNEL_AUTO)):
+            X.set_tuning(wpc, ms, kern)
             outs.append(run(X, x))
     finally:
-        X.set_tuning(2, 8)
+        X.set_tuning(2, 4, X.XENG_KERNEL_AUTO)
     for o in outs[1:]:
         np.testing.assert_array_equal(o, outs[0])
     np.testing.assert_array_equal(outs[0], oracle.correlate(x))
+
+
+# N a multiple of 256 with aligned arrays takes the DMA kernel; the sample
+# counts straddle its 64-sample stages and the pieces' boundaries.
+@pytest.mark.parametrize("n,t", [(256, 1), (256, 63), (256, 64), (256, 65), (512, 1000),
+                                 (768, 4097), (1024, 333)])
+@pytest.mark.parametrize("kernel", ["auto", "general"])
+def test_both_kernels_match_oracle(X, n, t, kernel):
+    print(f"kernel={kernel} n={n} t={t}", flush=True)
+    x = synth.uniform_bytes(n, t, seed=3000 + n + t)
+    try:
+        X.set_tuning(0, 0, X.XENG_KERNEL_GENERAL if kernel == "general" else X.XENG_KERNEL_AUTO)
+        got = run(X, x)
+    finally:
+        X.set_tuning(0, 0, X.XENG_KERNEL_AUTO)
+    np.testing.assert_array_equal(got, oracle.correlate(x))
+
+
+def test_kernels_mixed_on_one_slot(X):
+    # both kernels accumulate into the same layout
+    n = 512
+    x = synth.uniform_bytes(n, 700, seed=31)
+    c = X.Correlator(n, 1)
+    try:
+        X.set_tuning(0, 0, X.XENG_KERNEL_GENERAL)
+        c.correlate(0, gpu(x[:300]))
+        X.set_tuning(0, 0, X.XENG_KERNEL_AUTO)
+        c.correlate(0, gpu(x[300:]))
+    finally:
+        X.set_tuning(0, 0, X.XENG_KERNEL_AUTO)
+    np.testing.assert_array_equal(c.dump(0).cpu().numpy(), oracle.correlate(x))
 
 
 # ---------------------------------------------------------------------------
