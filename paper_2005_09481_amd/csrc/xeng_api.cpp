@@ -73,6 +73,7 @@ constexpr int JOB_RING = 8;
 struct DeviceState {
     int device = 0;
     int cu_count = 0;
+    uint8_t *d_zeros = nullptr;   // ZERO_BYTES zero samples (0x88) for the DMA kernel
     std::mutex mu;
     std::unordered_map<std::string, DevicePlan> plans;
     std::list<std::string> lru;
@@ -95,6 +96,13 @@ DeviceState *device_state(int device)
         cus <= 0)
         return nullptr;
     st->cu_count = cus;
+    // zero samples that the DMA kernel reads in place of rows past a
+    // piece's end; written once, before any launch that could read them
+    if (hipMalloc(&st->d_zeros, ZERO_BYTES) != hipSuccess) return nullptr;
+    if (hipMemset(st->d_zeros, 0x88, ZERO_BYTES) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(st->d_zeros);
+        return nullptr;
+    }
     DeviceState *p = st.get();
     g_states[device] = std::move(st);
     return p;
@@ -306,6 +314,7 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_
     KernelArgs a;
     a.job0 = make_job(ctx, slot, d_samples, row_stride);
     a.jobs = nullptr;
+    a.zeros = ctx->st->d_zeros;
     const bool dma = use_dma(a.job0.flags);
     // held through the launch so that no other thread evicts the plan first
     std::lock_guard<std::mutex> lk(ctx->st->mu);
@@ -393,6 +402,7 @@ int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
     KernelArgs a;
     std::memset(&a.job0, 0, sizeof a.job0);
     a.jobs = tb.d;
+    a.zeros = st->d_zeros;
     a.pieces = dp.d_pieces;
     a.wg_off = dp.d_off;
     e = launch(a, dp, dma, flags_and, stream);

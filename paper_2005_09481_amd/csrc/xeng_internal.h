@@ -32,9 +32,12 @@ inline int64_t tri64(int64_t n) { return n * (n + 1) / 2; }
 inline int n_tiles_side(int n) { return (n + TILE - 1) / TILE; }
 inline int64_t slot_i32(int n) { return tri64(n_tiles_side(n)) * TILE_I32; }
 
-// B operands carry 16x the sample values, so the int32 register sums of one
-// piece reach 16 * 128 * length: pieces are capped below 2^20 samples.
-constexpr int MAX_PIECE_STAGES = ((1 << 20) - 1) / STAGE;     // 16383 stages
+// Register sums of one piece: the general kernel's B operands carry 16x the
+// sample values, so its sums reach 16 * 128 * length (pieces below 2^20
+// samples); the DMA kernel's A and B both do, 256 * 128 * length (pieces
+// below 2^16 samples).
+constexpr int MAX_PIECE_STAGES = ((1 << 20) - 1) / STAGE;       // 16383 stages
+constexpr int MAX_PIECE_STAGES_WIDE = ((1 << 16) - 1) / STAGE;  // 1023 stages
 
 // Largest row stride: lane offsets inside a stage (up to 31 rows) stay 32-bit.
 constexpr int64_t MAX_STRIDE = INT64_C(1) << 26;
@@ -74,6 +77,8 @@ struct KernelArgs {
     const JobDesc *jobs;
     const Piece *pieces;
     const int32_t *wg_off;    // pieces of workgroup w: [wg_off[w], wg_off[w+1])
+    const uint8_t *zeros;     // ZERO_BYTES bytes of zero samples (0x88), 16-byte aligned
 };
+constexpr int ZERO_BYTES = 256;
 
 }  // namespace xeng

@@ -3,22 +3,38 @@
 //
 // Same product as the general kernel -- for a tile of the upper triangle,
 //   V_ij = sum_t x_i(t) conj(x_j(t))                      (Sec. 2.2, eta)
-// with Re V = [Re x_i | Im x_i] . [Re x_j | Im x_j] and
-//      Im V = [Im x_i | -Re x_i] . [Re x_j | Im x_j]
 // on v_mfma_i32_32x32x32_i8 -- but the packed samples never leave their
 // 4-bit form in shared memory:
 //   * global -> LDS by DMA (global_load_lds_dwordx4): 16 bytes per lane, no
 //     registers and no instructions beyond the load itself, into a ring of
-//     NSLOT 64-sample stages so that NSLOT - 1 stages are in flight;
+//     NSLOT 64-sample stages, AHEAD of them issued before they are needed;
 //   * LDS -> registers by transposed reads (ds_read_b64_tr_b8): a 16-lane
 //     group reads 8 time rows x 16 inputs and each lane receives the 8
 //     samples of one input -- exactly one lane's share of an MFMA operand;
-//   * the nibble unpack to int8 happens in registers right before the MFMA.
-// The LDS bytes per MFMA are a quarter of an unpacked layout's.
+//   * the nibble unpack to int8 happens in registers, one k-step ahead of
+//     the MFMAs that use it.
+//
+// Operands.  With R, I the 4-bit parts of a sample (two's complement values
+// in [-8, 7]) and ~R = -R - 1:
+//   B (columns j)      = [16 R_j | 16 I_j]
+//   A, real part       = [16 R_i | 16 I_i]   -> 256 (R_i R_j + I_i I_j)
+//   A, imaginary part  = [16 I_i | 16 ~R_i]  -> 256 (I_i R_j - R_i I_j - I_j)
+// Every byte is a 4-bit value in the high half of a byte, made from the
+// packed sample by one XOR and one AND (no sign extension), and ~R never
+// overflows int8 where -R would (R = -8).  The imaginary accumulator thus
+// holds Im V_ij - S_j with S_j = sum_t I_j(t); since Im V_jj = 0 its diagonal
+// holds -S_j, and the dump subtracts it.  The general kernel stores the same
+// form.
 //
 // Workgroup tile: 128 rows (A) x 256 columns (B), four waves; wave (wa, wb)
 // computes rows 64wa..64wa+63 against columns 128wb..128wb+127, i.e. 2 x 4
 // MFMA blocks for both Re and Im (256 accumulator registers).
+//
+// LDS stage layout ("chunk-major" in 8-row groups): the A region holds 8
+// groups of 8 time rows x 8 chunks of 16 inputs, chunk c of row r at byte
+// 128 c + 16 r of its group; the B region the same with 16 chunks.  The 8
+// rows a transposed read touches are then 128 contiguous bytes, and every
+// read of a stage is a per-lane base plus a compile-time offset.
 #include <hip/hip_runtime.h>
 
 #include "xeng_internal.h"
@@ -28,59 +44,57 @@ namespace dma {
 
 typedef int v2i __attribute__((ext_vector_type(2)));
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 typedef __attribute__((address_space(3))) v2i lds_v2i;
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
 typedef __attribute__((address_space(1))) int32_t gi32;
 
 constexpr int WA_ROWS = 128;            // A rows per workgroup tile
 constexpr int WB_COLS = 256;            // B columns per workgroup tile
-constexpr int CA = WA_ROWS / 16;        // 16-input chunks per A time row (8)
-constexpr int CB = WB_COLS / 16;        // 16
+constexpr int GRP_A = 8 * WA_ROWS;      // bytes of an 8-row group, A region: 1 KB
+constexpr int GRP_B = 8 * WB_COLS;      // 2 KB
 constexpr int A_STAGE = STAGE * WA_ROWS;    // 8 KB of packed samples
 constexpr int B_STAGE = STAGE * WB_COLS;    // 16 KB
 constexpr int SLOT = A_STAGE + B_STAGE;     // 24 KB
-constexpr int NSLOT = 6;                    // ring depth: 144 KB of LDS
-constexpr int DEPTH = NSLOT - 1;            // stages in flight
+constexpr int NSLOT = 6;                    // ring: 144 KB of LDS
+constexpr int AHEAD = NSLOT - 1;            // stages issued ahead
 constexpr int DMA_A = A_STAGE / 1024;       // 1 KB DMA instructions per stage: 8
 constexpr int DMA_B = B_STAGE / 1024;       // 16
 constexpr int DMA_PER_WAVE = (DMA_A + DMA_B) / 4;   // 6
 
-// Swizzled position of 16-byte chunk c of time row t in a region with C
-// chunks per row: the 8 rows a transposed read touches land in 8 different
-// bank groups.
-__device__ __forceinline__ int chunk_index(int t, int c, int C) { return t * C + (c ^ (t & 7)); }
-
 // s_waitcnt immediates: vmcnt in bits 3:0 and 15:14, expcnt 6:4 and
-// lgkmcnt 11:8 at their maxima (no wait on those).
+// lgkmcnt 11:8 at their maxima (no wait on those); and lgkmcnt(0) alone.
 #define XENG_VMCNT(n) (((n) & 0xF) | (((n) >> 4) << 14) | (0x7 << 4) | (0xF << 8))
+#define XENG_LGKMCNT0 (0xF | (0x3 << 14) | (0x7 << 4))
 
 struct Tile {
     const uint8_t *samples;
+    const uint8_t *zeros;   // 16 bytes of zero samples (0x88)
     int64_t stride;
-    int n;
-    int row0, col0;       // first A input, first B input
+    int row0, col0;         // first A input, first B input
     int t0, t1;
 };
 
-// One 16-byte-per-lane DMA from global memory (uniform base + 32-bit lane
-// offset) into LDS at byte offset `lds_base` + 16 * lane.  Written as
-// inline assembly so that the compiler, which cannot tell that reads of
-// other ring slots never alias the slot being filled, does not drain every
-// load in flight before each LDS read; the ring's own vmcnt waits
-// order the accesses.  The instruction has no register result; M0 (its LDS
-// base) is saved and restored around it.
-__device__ __forceinline__ void dma16(const uint8_t *base, uint32_t lane_off, uint32_t lds_base)
+// One 16-byte-per-lane DMA into LDS at byte address `lds_addr` + 16 * lane,
+// written as inline assembly so that the compiler, which cannot tell that
+// reads of other ring slots never alias the slot being filled, does not
+// drain every load in flight before each LDS read; the ring's own vmcnt
+// waits order the accesses.  The instruction has no register result; M0
+// (its LDS base) is saved and restored around it.  s_nop 4: the DMA may read
+// M0 only one wait state after an SALU write to it, and an SGPR address only
+// five after a VALU write.
+//
+// Scalar-base form: wave-uniform 64-bit base + per-lane 32-bit offset.
+__device__ __forceinline__ void dma16_s(const uint8_t *base, uint32_t lane_off, uint32_t lds_addr)
 {
-    // both are wave-uniform; readfirstlane puts them in scalar registers (its
-    // result is a signed int: widen each half as unsigned)
+    // readfirstlane returns a signed int: widen each half as unsigned
     const uint64_t b = (uint64_t)(uintptr_t)base;
     const uint32_t b_hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
     const uint32_t b_lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)b);
     const uint64_t sb = ((uint64_t)b_hi << 32) | (uint64_t)b_lo;
-    const uint32_t sl = (uint32_t)__builtin_amdgcn_readfirstlane(lds_base);
+    const uint32_t sl = (uint32_t)__builtin_amdgcn_readfirstlane(lds_addr);
     uint32_t saved;
-    // s_nop 4: the LDS DMA may read M0 only one wait state after an SALU
-    // write to it, and an SGPR address only five after a VALU write
     asm volatile("s_mov_b32 %0, m0\n\t"
                  "s_mov_b32 m0, %3\n\t"
                  "s_nop 4\n\t"
@@ -91,20 +105,41 @@ __device__ __forceinline__ void dma16(const uint8_t *base, uint32_t lane_off, ui
                  : "memory");
 }
 
-// Lane geometry of this wave's k-th DMA instruction of a stage: time row in
-// the stage and input byte offset in a row (inputs at or past N are
-// redirected to input 0; their samples are masked at unpack).
-__device__ __forceinline__ void dma_lane(const Tile &tl, int wave, int lane, int k, int &t, uint32_t &col)
+// Vector-address form: a 64-bit address per lane.
+__device__ __forceinline__ void dma16_v(const uint8_t *addr, uint32_t lds_addr)
 {
-    const int inst = wave + 4 * k;
-    const bool in_a = inst < DMA_A;
-    const int C = in_a ? CA : CB;
-    const int first = in_a ? inst * 64 : (inst - DMA_A) * 64;
-    const int ci = first + lane;
-    t = ci / C;
-    const int c = (ci % C) ^ (t & 7);
-    const int in0 = (in_a ? tl.row0 : tl.col0) + 16 * c;
-    col = (uint32_t)(in0 < tl.n ? in0 : 0);
+    const uint32_t sl = (uint32_t)__builtin_amdgcn_readfirstlane(lds_addr);
+    uint32_t saved;
+    asm volatile("s_mov_b32 %0, m0\n\t"
+                 "s_mov_b32 m0, %2\n\t"
+                 "s_nop 4\n\t"
+                 "global_load_lds_dwordx4 %1, off\n\t"
+                 "s_mov_b32 m0, %0"
+                 : "=&s"(saved)
+                 : "v"(addr), "s"(sl)
+                 : "memory");
+}
+
+// Geometry of DMA instruction `inst` (0..23) of a stage for this lane: its
+// LDS offset in the slot (wave-uniform), the time row in the stage and the
+// first of the 16 inputs the lane fetches.  Instructions 0..7 fill A group
+// `inst`; 8..23 fill half h of B group g.  Lane l fetches chunk l / 8 of
+// the instruction's 8 chunks at time row l % 8 of the group, which lands at
+// byte 16 l = 128 (l / 8) + 16 (l % 8) of the instruction's kilobyte.
+__device__ __forceinline__ void dma_geom(int inst, int lane, int row0, int col0, int &lds_off, int &t,
+                                         int &in)
+{
+    const int r = lane & 7, c = lane >> 3;
+    if (inst < DMA_A) {
+        lds_off = inst * GRP_A;
+        t = 8 * inst + r;
+        in = row0 + 16 * c;
+    } else {
+        const int i = inst - DMA_A, g = i >> 1, h = i & 1;
+        lds_off = A_STAGE + g * GRP_B + h * 1024;
+        t = 8 * g + r;
+        in = col0 + 16 * (8 * h + c);
+    }
 }
 
 // Per-lane byte offsets (row * stride + input) of this wave's six DMA
@@ -117,207 +152,226 @@ __device__ __forceinline__ void dma_lane_setup(DmaLane &dl, const Tile &tl, int 
 {
 #pragma unroll
     for (int k = 0; k < DMA_PER_WAVE; ++k) {
-        int t;
-        uint32_t col;
-        dma_lane(tl, wave, lane, k, t, col);
-        dl.off[k] = (uint32_t)(t * tl.stride) + col;
+        int lds_off, t, in;
+        dma_geom(wave + 4 * k, lane, tl.row0, tl.col0, lds_off, t, in);
+        dl.off[k] = (uint32_t)((int64_t)t * tl.stride) + (uint32_t)in;
     }
 }
 
 // This wave's share of one stage's DMA: instructions wave, wave+4, ... of the
-// 24 (8 for A, 16 for B).  Rows at or past t1 (the last, partial stage of a
-// piece, and the dummy stages past its end that keep the count of loads in
-// flight constant) are redirected to the piece's first row.
-__device__ __forceinline__ void issue_dma(uint32_t slot_lds, const Tile &tl, const DmaLane &dl, int stage,
-                                          int wave, int lane)
+// 24.  Rows at or past t1 (the last, partial stage of a piece, and stages
+// past its end, issued so that the count of loads in flight stays
+// constant) are read from the zero-sample buffer, so that every stage the
+// compute loop sees is whole.
+__device__ __forceinline__ void issue_stage(uint32_t slot_addr, const Tile &tl, const DmaLane &dl, int stage,
+                                            int wave, int lane)
 {
     const int ts = tl.t0 + stage * STAGE;
     if (ts + STAGE <= tl.t1) {
-        const uint8_t *row0 = tl.samples + (int64_t)ts * tl.stride;
+        const uint8_t *row = tl.samples + (int64_t)ts * tl.stride;
 #pragma unroll
         for (int k = 0; k < DMA_PER_WAVE; ++k) {
-            const int inst = wave + 4 * k;
-            const bool in_a = inst < DMA_A;
-            const int first = in_a ? inst * 64 : (inst - DMA_A) * 64;
-            dma16(row0, dl.off[k], slot_lds + (in_a ? 0 : A_STAGE) + 16 * first);
+            int lds_off, t, in;
+            dma_geom(wave + 4 * k, lane, tl.row0, tl.col0, lds_off, t, in);
+            dma16_s(row, dl.off[k], slot_addr + (uint32_t)lds_off);
         }
     } else {
-        const uint8_t *row0 = tl.samples + (int64_t)tl.t0 * tl.stride;
 #pragma unroll
         for (int k = 0; k < DMA_PER_WAVE; ++k) {
-            const int inst = wave + 4 * k;
-            const bool in_a = inst < DMA_A;
-            const int first = in_a ? inst * 64 : (inst - DMA_A) * 64;
-            int t;
-            uint32_t col;
-            dma_lane(tl, wave, lane, k, t, col);
-            const uint32_t off = ts + t < tl.t1 ? (uint32_t)((ts - tl.t0 + t) * tl.stride) + col : col;
-            dma16(row0, off, slot_lds + (in_a ? 0 : A_STAGE) + 16 * first);
+            int lds_off, t, in;
+            dma_geom(wave + 4 * k, lane, tl.row0, tl.col0, lds_off, t, in);
+            const uint8_t *src =
+                ts + t < tl.t1 ? tl.samples + (int64_t)(ts + t) * tl.stride + in : tl.zeros;
+            dma16_v(src, slot_addr + (uint32_t)lds_off);
         }
     }
 }
 
-// Transposed read of one MFMA operand's packed samples: the lane gets the 8
-// samples (k-step q, half lane / 32) of input 16 * chunk + lane % 32, as laid
-// out by issue_dma.  `region` is an LDS byte offset.
-__device__ __forceinline__ v2i read_tr(uint32_t region, int C, int q, int chunk, int lane)
-{
-    const int grp = lane >> 4, j = lane & 15;
-    const int c = chunk + (grp & 1);
-    const int t = 16 * q + 8 * (grp >> 1) + (j >> 1);
-    const uint32_t off = region + 16 * chunk_index(t, c, C) + 8 * (j & 1);
-    return __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i *)(uintptr_t)off);
-}
-
-__device__ __forceinline__ uint32_t nib_to_i8(uint32_t n) { return (n + 0x78787878u) ^ 0x80808080u; }
-__device__ __forceinline__ uint32_t nib_to_neg_i8(uint32_t n) { return (0x88888888u - n) ^ 0x80808080u; }
-
-// A operands: Re-A = [Re | Im], Im-A = [Im | -Re] (int8).
-template <bool RE_LOW>
-__device__ __forceinline__ void unpack_a(v2i p, v4i &re_a, v4i &im_a)
-{
-    const uint32_t h0 = ((uint32_t)p.x >> 4) & 0x0F0F0F0Fu, l0 = (uint32_t)p.x & 0x0F0F0F0Fu;
-    const uint32_t h1 = ((uint32_t)p.y >> 4) & 0x0F0F0F0Fu, l1 = (uint32_t)p.y & 0x0F0F0F0Fu;
-    const uint32_t r0 = RE_LOW ? l0 : h0, i0 = RE_LOW ? h0 : l0;
-    const uint32_t r1 = RE_LOW ? l1 : h1, i1 = RE_LOW ? h1 : l1;
-    const uint32_t re0 = nib_to_i8(r0), re1 = nib_to_i8(r1);
-    const uint32_t im0 = nib_to_i8(i0), im1 = nib_to_i8(i1);
-    re_a = v4i{(int)re0, (int)re1, (int)im0, (int)im1};
-    im_a = v4i{(int)im0, (int)im1, (int)nib_to_neg_i8(r0), (int)nib_to_neg_i8(r1)};
-}
-
-// B operand: [16 Re | 16 Im] (flipping bit 3 of an offset-binary nibble gives
-// its 4-bit two's complement; in the high half of a byte that is 16x).
-template <bool RE_LOW>
-__device__ __forceinline__ v4i unpack_b(v2i p)
-{
-    const uint32_t x0 = (uint32_t)p.x ^ 0x88888888u, x1 = (uint32_t)p.y ^ 0x88888888u;
-    const uint32_t h0 = x0 & 0xF0F0F0F0u, l0 = (x0 << 4) & 0xF0F0F0F0u;
-    const uint32_t h1 = x1 & 0xF0F0F0F0u, l1 = (x1 << 4) & 0xF0F0F0F0u;
-    return RE_LOW ? v4i{(int)l0, (int)l1, (int)h0, (int)h1} : v4i{(int)h0, (int)h1, (int)l0, (int)l1};
-}
-
-// Replace samples past t1 by the zero sample 0x88: `keep` holds the byte
-// masks of the lane's 8 samples.
-__device__ __forceinline__ v2i mask_samples(v2i p, uint32_t keep_lo, uint32_t keep_hi)
-{
-    return v2i{(int)(((uint32_t)p.x & keep_lo) | (0x88888888u & ~keep_lo)),
-               (int)(((uint32_t)p.y & keep_hi) | (0x88888888u & ~keep_hi))};
-}
-
-// Byte mask of the first `n` (clamped to 0..4) bytes of a dword.
-__device__ __forceinline__ uint32_t byte_mask(int n)
-{
-    return n >= 4 ? 0xFFFFFFFFu : n <= 0 ? 0u : (1u << (8 * n)) - 1u;
-}
-
+// Packed operand data of one k-step (2 A blocks, 4 B blocks) and its
+// unpacked form.
+struct Raw {
+    v2i a[2];
+    v2i b[4];
+};
+struct Ops {
+    v8i a[2];   // {16R, 16R, 16I, 16I, 16~R, 16~R, -, -}: real A = s0123, imaginary A = s2345
+    v4i b[4];   // {16R, 16R, 16I, 16I}
+};
 struct Acc {
     v16i re[2][4];
     v16i im[2][4];
 };
 
-// Packed operand data of one k-step: 2 A blocks and 4 B blocks.
-struct Raw {
-    v2i a[2];
-    v2i b[4];
-};
-
-__device__ __forceinline__ void read_kstep(Raw &r, uint32_t slot, int q, int lane, int wa, int wb)
+// Transposed reads of k-step q: `pa`, `pb` are this lane's bases in the
+// slot's A and B regions (group lane / 32, chunk of the lane's 16-lane
+// group, byte 8 (lane % 16)); k-step q adds 2 groups, block a / b 2 chunks.
+__device__ __forceinline__ void read_k(Raw &r, const lds_u8 *pa, const lds_u8 *pb, int q)
 {
 #pragma unroll
-    for (int a = 0; a < 2; ++a) r.a[a] = read_tr(slot, CA, q, 4 * wa + 2 * a, lane);
+    for (int a = 0; a < 2; ++a)
+        r.a[a] = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i *)(pa + 2 * GRP_A * q + 256 * a));
 #pragma unroll
-    for (int b = 0; b < 4; ++b) r.b[b] = read_tr(slot + A_STAGE, CB, q, 8 * wb + 2 * b, lane);
+    for (int b = 0; b < 4; ++b)
+        r.b[b] = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i *)(pb + 2 * GRP_B * q + 256 * b));
 }
 
-// The 64 MFMAs of one stage for wave (wa, wb) from ring slot `slot`.  The
-// packed operands of k-step q+1 are read while those of k-step q are
-// unpacked and multiplied.  EDGE: the stage has samples past t1, which are
-// masked to zero samples.
-template <bool RE_LOW, bool EDGE>
-__device__ __forceinline__ void stage_compute(Acc &acc, uint32_t slot, const Tile &tl, int ts,
-                                              int lane, int wa, int wb)
+// 16 x (4-bit value) in the high half of each byte: from the high nibbles,
+// (p ^ 0x88) & 0xF0 per byte; from the low nibbles, the same on p << 4.
+// XOR with 0x77 instead of 0x88 gives 16 x the bitwise complement.
+template <bool RE_LOW>
+__device__ __forceinline__ void unpack_k(Ops &o, const Raw &r)
 {
-    Raw raw;
-    read_kstep(raw, slot, 0, lane, wa, wb);
 #pragma unroll
-    for (int q = 0; q < STAGE / KSTEP; ++q) {
-        Raw cur = raw;
-        if (q + 1 < STAGE / KSTEP) read_kstep(raw, slot, q + 1, lane, wa, wb);
-        if (EDGE) {
-            const int nt = tl.t1 - (ts + 16 * q + 8 * (lane >> 5));
-            const uint32_t lo = byte_mask(nt), hi = byte_mask(nt - 4);
-#pragma unroll
-            for (int a = 0; a < 2; ++a) cur.a[a] = mask_samples(cur.a[a], lo, hi);
-#pragma unroll
-            for (int b = 0; b < 4; ++b) cur.b[b] = mask_samples(cur.b[b], lo, hi);
+    for (int a = 0; a < 2; ++a) {
+        const uint32_t x0 = (uint32_t)r.a[a].x, x1 = (uint32_t)r.a[a].y;
+        const uint32_t s0 = x0 << 4, s1 = x1 << 4;
+        const uint32_t h0 = (x0 ^ 0x88888888u) & 0xF0F0F0F0u, h1 = (x1 ^ 0x88888888u) & 0xF0F0F0F0u;
+        const uint32_t l0 = (s0 ^ 0x80808080u) & 0xF0F0F0F0u, l1 = (s1 ^ 0x80808080u) & 0xF0F0F0F0u;
+        if (RE_LOW) {
+            const uint32_t n0 = (s0 ^ 0x70707070u) & 0xF0F0F0F0u, n1 = (s1 ^ 0x70707070u) & 0xF0F0F0F0u;
+            o.a[a] = v8i{(int)l0, (int)l1, (int)h0, (int)h1, (int)n0, (int)n1, 0, 0};
+        } else {
+            const uint32_t n0 = (x0 ^ 0x77777777u) & 0xF0F0F0F0u, n1 = (x1 ^ 0x77777777u) & 0xF0F0F0F0u;
+            o.a[a] = v8i{(int)h0, (int)h1, (int)l0, (int)l1, (int)n0, (int)n1, 0, 0};
         }
-        v4i re_a[2], im_a[2], bo[4];
+    }
 #pragma unroll
-        for (int a = 0; a < 2; ++a) unpack_a<RE_LOW>(cur.a[a], re_a[a], im_a[a]);
-#pragma unroll
-        for (int b = 0; b < 4; ++b) bo[b] = unpack_b<RE_LOW>(cur.b[b]);
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                acc.re[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(re_a[a], bo[b], acc.re[a][b], 0, 0, 0);
-                acc.im[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im_a[a], bo[b], acc.im[a][b], 0, 0, 0);
-            }
+    for (int b = 0; b < 4; ++b) {
+        const uint32_t x0 = (uint32_t)r.b[b].x, x1 = (uint32_t)r.b[b].y;
+        const uint32_t h0 = (x0 ^ 0x88888888u) & 0xF0F0F0F0u, h1 = (x1 ^ 0x88888888u) & 0xF0F0F0F0u;
+        const uint32_t l0 = ((x0 << 4) ^ 0x80808080u) & 0xF0F0F0F0u;
+        const uint32_t l1 = ((x1 << 4) ^ 0x80808080u) & 0xF0F0F0F0u;
+        o.b[b] = RE_LOW ? v4i{(int)l0, (int)l1, (int)h0, (int)h1} : v4i{(int)h0, (int)h1, (int)l0, (int)l1};
     }
 }
 
-// Accumulators hold 16x the visibilities (B operands are scaled by 16), so
-// the flush adds acc >> 4; every value is a multiple of 16, so this is exact.
+__device__ __forceinline__ void mfma_k(Acc &acc, const Ops &o)
+{
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const v4i re_a = __builtin_shufflevector(o.a[a], o.a[a], 0, 1, 2, 3);
+            const v4i im_a = __builtin_shufflevector(o.a[a], o.a[a], 2, 3, 4, 5);
+            acc.re[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(re_a, o.b[b], acc.re[a][b], 0, 0, 0);
+            acc.im[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im_a, o.b[b], acc.im[a][b], 0, 0, 0);
+        }
+}
+
+// Instruction order of a k-step: the six LDS reads of a later k-step first,
+// then the 16 MFMAs, each followed by a share of the unpack of the next
+// k-step, which the matrix core's 32-cycle MFMAs hide.
+__device__ __forceinline__ void kstep_schedule()
+{
+    __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);   // DS read
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);   // VALU
+    }
+}
+
+__device__ __forceinline__ void wait_stage_and_sync()
+{
+    // this wave's loads of the next stage have landed (AHEAD - 1 newer
+    // stages in flight) and its LDS reads are done; the barrier extends both
+    // to the workgroup
+    __builtin_amdgcn_s_waitcnt(XENG_VMCNT((AHEAD - 1) * DMA_PER_WAVE));
+    __builtin_amdgcn_s_waitcnt(XENG_LGKMCNT0);
+    __syncthreads();
+}
+
+// One piece, software-pipelined over its stages.  Entering iteration s, the
+// unpacked operands of (s, k-step 0) and the raw data of (s, 1) are in
+// registers; the iteration reads (s, 2), (s, 3), (s+1, 0), (s+1, 1) and
+// unpacks one k-step ahead of its MFMAs.  The DMA of stage s + AHEAD goes
+// into the slot stage s - 1 used, which every wave finished reading before
+// the barrier of iteration s - 1; that barrier sits before the first read of
+// stage s.  The last iteration's reads of "stage ns" touch a slot whose
+// contents are never used.
+template <bool RE_LOW>
+__device__ __forceinline__ void run_piece(Acc &acc, uint32_t ring, const Tile &tl, int wave, int lane,
+                                          uint32_t a_lane, uint32_t b_lane)
+{
+    const int ns = (tl.t1 - tl.t0 + STAGE - 1) / STAGE;
+    DmaLane dl;
+    dma_lane_setup(dl, tl, wave, lane);
+    // nothing else in flight: the ring's vmcnt waits then count DMA only
+    __builtin_amdgcn_s_waitcnt(XENG_VMCNT(0));
+#pragma unroll
+    for (int d = 0; d < AHEAD; ++d) issue_stage(ring + d * SLOT, tl, dl, d, wave, lane);
+    wait_stage_and_sync();
+
+    Raw r0, r1;
+    Ops u0, u1;
+    {
+        const lds_u8 *pa = (const lds_u8 *)(uintptr_t)(ring + a_lane);
+        const lds_u8 *pb = (const lds_u8 *)(uintptr_t)(ring + b_lane);
+        read_k(r0, pa, pb, 0);
+        read_k(r1, pa, pb, 1);
+        unpack_k<RE_LOW>(u0, r0);
+    }
+    int cur = 0;    // slot of stage s
+    for (int s = 0; s < ns; ++s) {
+        const int nxt = cur == NSLOT - 1 ? 0 : cur + 1;
+        const int iss = cur == 0 ? NSLOT - 1 : cur - 1;   // slot of stage s - 1 = s + AHEAD
+        issue_stage(ring + iss * SLOT, tl, dl, s + AHEAD, wave, lane);
+        const lds_u8 *pa = (const lds_u8 *)(uintptr_t)(ring + cur * SLOT + a_lane);
+        const lds_u8 *pb = (const lds_u8 *)(uintptr_t)(ring + cur * SLOT + b_lane);
+        const lds_u8 *qa = (const lds_u8 *)(uintptr_t)(ring + nxt * SLOT + a_lane);
+        const lds_u8 *qb = (const lds_u8 *)(uintptr_t)(ring + nxt * SLOT + b_lane);
+        __builtin_amdgcn_sched_barrier(0);
+        // k-step 0
+        read_k(r0, pa, pb, 2);
+        unpack_k<RE_LOW>(u1, r1);
+        mfma_k(acc, u0);
+        kstep_schedule();
+        __builtin_amdgcn_sched_barrier(0);
+        // k-step 1
+        read_k(r1, pa, pb, 3);
+        unpack_k<RE_LOW>(u0, r0);
+        mfma_k(acc, u1);
+        kstep_schedule();
+        __builtin_amdgcn_sched_barrier(0);
+        // k-step 2: stage s + 1 must be in LDS before its first read
+        wait_stage_and_sync();
+        read_k(r0, qa, qb, 0);
+        unpack_k<RE_LOW>(u1, r1);
+        mfma_k(acc, u0);
+        kstep_schedule();
+        __builtin_amdgcn_sched_barrier(0);
+        // k-step 3
+        read_k(r1, qa, qb, 1);
+        unpack_k<RE_LOW>(u0, r0);
+        mfma_k(acc, u1);
+        kstep_schedule();
+        __builtin_amdgcn_sched_barrier(0);
+        cur = nxt;
+    }
+    __builtin_amdgcn_s_waitcnt(XENG_VMCNT(0));
+    __syncthreads();       // the next piece's DMA reuses the slots
+}
+
+// Accumulators hold 256x the stored values (both operands carry 16x the
+// sample parts), so the flush adds acc >> 8; every value is a multiple of
+// 256, so this is exact.
 __device__ __forceinline__ void flush_block(int32_t *blk_, const v16i &re, const v16i &im, bool atomic)
 {
     gi32 *blk = (gi32 *)blk_;
     if (atomic) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            __hip_atomic_fetch_add(blk + r * 64, re[r] >> 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(blk + 1024 + r * 64, im[r] >> 4, __ATOMIC_RELAXED,
+            __hip_atomic_fetch_add(blk + r * 64, re[r] >> 8, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(blk + 1024 + r * 64, im[r] >> 8, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         }
     } else {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            blk[r * 64] += re[r] >> 4;
-            blk[1024 + r * 64] += im[r] >> 4;
+            blk[r * 64] += re[r] >> 8;
+            blk[1024 + r * 64] += im[r] >> 8;
         }
     }
-}
-
-// One piece: full stages in a single-path loop (the accumulators stay in
-// place), then the partial last stage, if any, with masking.  Every stage
-// slot gets exactly DMA_PER_WAVE loads per wave, so one constant wait
-// (4 newer stages in flight) makes stage s complete.
-template <bool RE_LOW>
-__device__ __forceinline__ void run_piece(Acc &acc, uint32_t ring, const Tile &tl, int wave, int lane,
-                                          int wa, int wb)
-{
-    const int len = tl.t1 - tl.t0;
-    const int nfull = len / STAGE;
-    DmaLane dl;
-    dma_lane_setup(dl, tl, wave, lane);
-    // nothing else in flight: the ring's vmcnt waits then count DMA only
-    __builtin_amdgcn_s_waitcnt(XENG_VMCNT(0));
-#pragma unroll
-    for (int d = 0; d < DEPTH; ++d) issue_dma(ring + d * SLOT, tl, dl, d, wave, lane);
-    int s = 0;
-    for (; s < nfull; ++s) {
-        __builtin_amdgcn_s_waitcnt(XENG_VMCNT((DEPTH - 1) * DMA_PER_WAVE));
-        __syncthreads();   // stage s complete in LDS; stage s-1 no longer read
-        issue_dma(ring + ((s + DEPTH) % NSLOT) * SLOT, tl, dl, s + DEPTH, wave, lane);
-        stage_compute<RE_LOW, false>(acc, ring + (s % NSLOT) * SLOT, tl, tl.t0 + s * STAGE, lane, wa, wb);
-    }
-    if (nfull * STAGE < len) {
-        __builtin_amdgcn_s_waitcnt(XENG_VMCNT((DEPTH - 1) * DMA_PER_WAVE));
-        __syncthreads();
-        stage_compute<RE_LOW, true>(acc, ring + (s % NSLOT) * SLOT, tl, tl.t0 + s * STAGE, lane, wa, wb);
-    }
-    __builtin_amdgcn_s_waitcnt(XENG_VMCNT(0));
-    __syncthreads();       // the next piece's DMA reuses the slots
 }
 
 // Persistent kernel: workgroup w runs pieces [wg_off[w], wg_off[w+1]).  A
@@ -333,6 +387,10 @@ __global__ __launch_bounds__(256, 1) void xcorr_dma(KernelArgs args)
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wa = wave >> 1, wb = wave & 1;
+    // per-lane parts of the transposed-read addresses (see read_k)
+    const int grp = lane >> 4, jl = lane & 15;
+    const uint32_t a_lane = GRP_A * (grp >> 1) + 128 * (grp & 1) + 8 * jl + 512 * wa;
+    const uint32_t b_lane = A_STAGE + GRP_B * (grp >> 1) + 128 * (grp & 1) + 8 * jl + 1024 * wb;
 
     const int p_begin = args.wg_off[blockIdx.x], p_end = args.wg_off[blockIdx.x + 1];
     for (int pi = p_begin; pi < p_end; ++pi) {
@@ -342,14 +400,14 @@ __global__ __launch_bounds__(256, 1) void xcorr_dma(KernelArgs args)
         const bool atomic = pce.t1_atomic < 0;
         Tile tl;
         tl.samples = jd.samples;
+        tl.zeros = args.zeros;
         tl.stride = jd.stride;
-        tl.n = jd.n;
         tl.row0 = ti * WA_ROWS;
         tl.col0 = tj2 * WB_COLS;
         tl.t0 = pce.t0;
         tl.t1 = pce.t1_atomic & 0x7FFFFFFF;
-        // this wave's accumulator tile; a half below the diagonal or past N
-        // is computed (the workgroup stays in step) but not stored
+        // this wave's accumulator tile; a half below the diagonal is
+        // computed (the workgroup stays in step) but not stored
         const int tj = 2 * tj2 + wb;
         const bool valid = tj >= ti && tj < jd.nt;
 
@@ -364,9 +422,9 @@ __global__ __launch_bounds__(256, 1) void xcorr_dma(KernelArgs args)
                     acc.im[a][b][r] = 0;
                 }
         if (jd.flags & JOB_RE_LOW)
-            run_piece<true>(acc, ring, tl, wave, lane, wa, wb);
+            run_piece<true>(acc, ring, tl, wave, lane, a_lane, b_lane);
         else
-            run_piece<false>(acc, ring, tl, wave, lane, wa, wb);
+            run_piece<false>(acc, ring, tl, wave, lane, a_lane, b_lane);
 
         if (valid) {
             const int64_t tile_idx = (int64_t)ti * jd.nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);

@@ -8,11 +8,15 @@
 // The complex product is split into two real int8 contractions over a
 // K axis that carries the real parts of a k-step's 16 samples on MFMA lanes
 // 0-31 and the imaginary parts on lanes 32-63:
-//   Re V = [Re x_i | Im x_i] . [Re x_j | Im x_j]   = Re_i Re_j + Im_i Im_j
-//   Im V = [Im x_i | -Re x_i] . [Re x_j | Im x_j]  = Im_i Re_j - Re_i Im_j
-// so the row (A) side keeps three int8 vectors per sample group (Re, Im,
-// -Re) and the column (B) side two (Re, Im); one B operand feeds both
-// products.  Every partial sum is an exact int32.
+//   Re V = [Re x_i | Im x_i] . [Re x_j | Im x_j]    = Re_i Re_j + Im_i Im_j
+//   Im'  = [Im x_i | ~Re x_i] . [Re x_j | Im x_j]   = Im_i Re_j - Re_i Im_j - Im_j
+// with ~Re = -Re - 1 (the bitwise complement of the 4-bit value, which,
+// unlike -Re, never leaves [-8, 7]).  So the row (A) side keeps three int8
+// vectors per sample group (Re, Im, ~Re) and the column (B) side two (Re,
+// Im); one B operand feeds both products.  The stored imaginary part is
+// Im V_ij - S_j with S_j = sum_t Im x_j(t); as Im V_jj = 0, the diagonal
+// holds -S_j and the dump adds it back.  Every partial sum is an exact
+// int32.  The DMA kernel stores the same form.
 //
 // Data path per 32-sample stage (double-buffered in LDS):
 //   global (time-major bytes) -> dword loads, 4 inputs x 8 samples per lane
@@ -33,7 +37,7 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // LDS stage layout.  A stage is 64 samples = 4 MFMA k-steps.  For each
 // k-step q a component region holds 128 tile rows x 16 bytes (the 16
-// samples of one input, in time order).  A rows keep Re, Im, -Re as int8;
+// samples of one input, in time order).  A rows keep Re, Im, ~Re as int8;
 // B rows keep 16*Re, 16*Im as int8 (the scale makes their unpack three bit
 // operations per four samples; every product is then 16x the true one and
 // the flush divides it out exactly).  This is the general kernel, for any
@@ -67,11 +71,12 @@ __device__ __forceinline__ void transpose4(uint32_t i0, uint32_t i1, uint32_t i2
     o3 = vperm(cd_hi, ab_hi, 0x07060302u);
 }
 
-// Offset-binary nibbles (0..15, one per byte) -> signed int8 value and its
-// negation, four at a time, with no carries between bytes:
-//   n - 8 = (n + 0x78) ^ 0x80,   8 - n = (0x88 - n) ^ 0x80.
+// Offset-binary nibbles (0..15, one per byte) -> signed int8 value v = n - 8
+// and its complement ~v = -v - 1 = 7 - n, four at a time, with no carries
+// between bytes:
+//   n - 8 = (n + 0x78) ^ 0x80,   7 - n = (0x87 - n) ^ 0x80.
 __device__ __forceinline__ uint32_t nib_to_i8(uint32_t n) { return (n + 0x78787878u) ^ 0x80808080u; }
-__device__ __forceinline__ uint32_t nib_to_neg_i8(uint32_t n) { return (0x88888888u - n) ^ 0x80808080u; }
+__device__ __forceinline__ uint32_t nib_to_not_i8(uint32_t n) { return (0x87878787u - n) ^ 0x80808080u; }
 
 // Global-memory views: loads through these pointers are global (not flat)
 // instructions, so they only count against the vector-memory counter and
@@ -198,7 +203,7 @@ __device__ __forceinline__ void stage_write(uint8_t *region, const StageRegs &r,
             const uint32_t re1 = RE_LOW ? l1 : h1, im1 = RE_LOW ? h1 : l1;
             *(uint2 *)(dst) = make_uint2(nib_to_i8(re0), nib_to_i8(re1));
             *(uint2 *)(dst + CH) = make_uint2(nib_to_i8(im0), nib_to_i8(im1));
-            *(uint2 *)(dst + 2 * CH) = make_uint2(nib_to_neg_i8(re0), nib_to_neg_i8(re1));
+            *(uint2 *)(dst + 2 * CH) = make_uint2(nib_to_not_i8(re0), nib_to_not_i8(re1));
         } else {
             // flipping bit 3 of an offset-binary nibble gives its 4-bit two's
             // complement; in the high half of a byte that is 16x the value
@@ -213,7 +218,7 @@ __device__ __forceinline__ void stage_write(uint8_t *region, const StageRegs &r,
 
 __device__ __forceinline__ v4i lds128(const uint8_t *p) { return *(const v4i *)p; }
 
-// Accumulators hold 16x the visibilities (B operands are scaled by 16), so
+// Accumulators hold 16x the stored values (B operands are scaled by 16), so
 // the flush adds acc >> 4; every value is a multiple of 16, so this is exact.
 __device__ __forceinline__ void flush_block(int32_t *blk_, const v16i &re, const v16i &im,
                                             bool atomic)
@@ -369,22 +374,34 @@ __global__ __launch_bounds__(256, 2) void xcorr_mfma(KernelArgs args)
     }
 }
 
-// Accumulators (tile layout) -> packed row-major upper triangle of (Re, Im).
-__global__ __launch_bounds__(256) void vis_dump(const int32_t *__restrict__ acc, int n, int nt,
-                                                int32_t *__restrict__ out)
+// Position of pair (i <= j) in a slot's tile layout (real part; the
+// imaginary part is 1024 int32 further).
+__device__ __forceinline__ int64_t acc_index(int i, int j, int nt)
 {
-    const int i = blockIdx.y;
-    const int j = i + blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
     const int ti = i >> 7, tj = j >> 7;
     const int ri = i & 127, rj = j & 127;
     const int ca = ri >> 5, ra = ri & 31, cb = rj >> 5, lb = rj & 31;
     const int reg = 4 * (ra >> 3) + (ra & 3);
     const int ln = lb + 32 * ((ra >> 2) & 1);
     const int64_t tile = (int64_t)ti * nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);
-    const int32_t *p = acc + tile * TILE_I32 + (ca * BLKS + cb) * BLOCK_I32 + reg * 64 + ln;
+    return tile * TILE_I32 + (ca * BLKS + cb) * BLOCK_I32 + reg * 64 + ln;
+}
+
+// Accumulators (tile layout) -> packed row-major upper triangle of (Re, Im).
+// The stored imaginary part of (i, j) is Im V_ij - S_j and that of (j, j)
+// is -S_j: their difference is Im V_ij (exact in wrapping int32 arithmetic,
+// since Im V_ij itself fits).
+__global__ __launch_bounds__(256) void vis_dump(const int32_t *__restrict__ acc, int n, int nt,
+                                                int32_t *__restrict__ out)
+{
+    const int i = blockIdx.y;
+    const int j = i + blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const int32_t *p = acc + acc_index(i, j, nt);
+    const int32_t *d = acc + acc_index(j, j, nt);
+    const int32_t im = (int32_t)((uint32_t)p[1024] - (uint32_t)d[1024]);
     const int64_t k = (int64_t)i * n - (int64_t)i * (i - 1) / 2 + (j - i);
-    reinterpret_cast<int2 *>(out)[k] = make_int2(p[0], p[1024]);
+    reinterpret_cast<int2 *>(out)[k] = make_int2(p[0], im);
 }
 
 __global__ __launch_bounds__(256) void fill_zero(int4 *__restrict__ p, int64_t n4)

@@ -38,6 +38,7 @@ Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, Til
         plan.wg_off.assign(1, 0);
         return plan;
     }
+    const int64_t cap = shape == TileShape::Wide ? MAX_PIECE_STAGES_WIDE : MAX_PIECE_STAGES;
     int64_t grid = std::min<int64_t>(max_wgs, (total + min_stages - 1) / min_stages);
     grid = std::max<int64_t>(grid, 1);
     plan.grid = (int32_t)grid;
@@ -63,9 +64,9 @@ Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, Til
             const size_t first = raw.size();
             for (; w < grid && bound(w) < hi; ++w) {
                 const int64_t a = std::max(lo, bound(w)), b = std::min(hi, bound(w + 1));
-                // long ranges are cut so that no piece exceeds MAX_PIECE_STAGES
-                for (int64_t c = a; c < b; c += MAX_PIECE_STAGES) {
-                    const int64_t e = std::min<int64_t>(b, c + MAX_PIECE_STAGES);
+                // long ranges are cut so that no piece exceeds the shape's cap
+                for (int64_t c = a; c < b; c += cap) {
+                    const int64_t e = std::min<int64_t>(b, c + cap);
                     Raw r;
                     r.p.job = j;
                     r.p.tile = ti | (tj << 16);

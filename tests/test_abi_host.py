@@ -129,11 +129,17 @@ def test_plan_random_batches(X):
             _check_cover(pieces, jobs, grid)
 
 
-def test_plan_caps_piece_length(X):
-    # B operands are scaled by 16 inside a piece: no piece may exceed 2^20 - 1 samples
-    jobs = [(128, 3_000_000)]
-    pieces = X.plan_inspect([128], [3_000_000], 1, 1)
+@pytest.mark.parametrize("wide,cap", [(False, 16383), (True, 1023)])
+def test_plan_caps_piece_length(X, wide, cap):
+    # inside a piece the general kernel's B operands carry 16x the samples
+    # (pieces below 2^20 samples), the DMA kernel's A and B both do (below 2^16)
+    t = 3_000_000
+    jobs = [(256, t)]
+    pieces = X.plan_inspect([256], [t], 1, 1, wide)
     _check_cover(pieces, jobs, 1)
-    assert max(p.t1 - p.t0 for p in pieces) <= (1 << 20) - 1
-    assert len(pieces) == -(-3_000_000 // (16383 * 64))
+    limit = (1 << 16) - 1 if wide else (1 << 20) - 1
+    assert max(p.t1 - p.t0 for p in pieces) <= limit
+    per_unit = -(-t // (cap * 64))
+    # units of N = 256: tiles (0,0), (0,1), (1,1); wide tiles (0,0), (1,0)
+    assert len(pieces) == (2 if wide else 3) * per_unit
     assert all(p.atomic for p in pieces)

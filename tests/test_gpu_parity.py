@@ -213,6 +213,35 @@ def test_both_kernels_match_oracle(X, n, t, kernel):
     np.testing.assert_array_equal(got, oracle.correlate(x))
 
 
+@pytest.mark.parametrize("kernel", ["auto", "general"])
+def test_both_kernels_re_low(X, kernel):
+    n, t = 512, 1000
+    print(f"re_low kernel={kernel} n={n} t={t}", flush=True)
+    x = synth.uniform_bytes(n, t, seed=77)
+    try:
+        X.set_tuning(0, 0, X.XENG_KERNEL_GENERAL if kernel == "general" else X.XENG_KERNEL_AUTO)
+        got = run(X, x, re_low=True)
+    finally:
+        X.set_tuning(0, 0, X.XENG_KERNEL_AUTO)
+    np.testing.assert_array_equal(got, oracle.correlate(x, re_low=True))
+
+
+@pytest.mark.parametrize("kernel", ["auto", "general"])
+def test_pieces_split_past_register_bound(X, kernel):
+    # T beyond 2^16 samples: the DMA kernel's plan cuts every tile into
+    # several pieces (atomic flushes); extreme samples maximise the sums
+    n, t = 256, 70_000
+    print(f"long pieces kernel={kernel} n={n} t={t}", flush=True)
+    rng = np.random.default_rng(5)
+    x = rng.choice(np.array([0x00, 0x0F, 0xF0, 0xFF, 0x80, 0x08], dtype=np.uint8), size=(t, n))
+    try:
+        X.set_tuning(1, 1 << 20, X.XENG_KERNEL_GENERAL if kernel == "general" else X.XENG_KERNEL_AUTO)
+        got = run(X, x)
+    finally:
+        X.set_tuning(2, 4, X.XENG_KERNEL_AUTO)     # the library's defaults
+    np.testing.assert_array_equal(got, oracle.correlate(x))
+
+
 def test_kernels_mixed_on_one_slot(X):
     # both kernels accumulate into the same layout
     n = 512
