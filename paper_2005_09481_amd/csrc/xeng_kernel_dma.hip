@@ -68,6 +68,19 @@ constexpr int DMA_PER_WAVE = (DMA_A + DMA_B) / 4;   // 6
 #define XENG_VMCNT(n) (((n) & 0xF) | (((n) >> 4) << 14) | (0x7 << 4) | (0xF << 8))
 #define XENG_LGKMCNT0 (0xF | (0x3 << 14) | (0x7 << 4))
 
+// A wave-uniform 64-bit value moved to scalar registers.
+template <typename T> __device__ __forceinline__ T uniform(T v)
+{
+    static_assert(sizeof(T) == 8, "64-bit values only");
+    uint64_t u;
+    __builtin_memcpy(&u, &v, 8);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)u);
+    u = ((uint64_t)hi << 32) | lo;
+    __builtin_memcpy(&v, &u, 8);
+    return v;
+}
+
 struct Tile {
     const uint8_t *samples;
     const uint8_t *zeros;   // 16 bytes of zero samples (0x88)
@@ -81,14 +94,17 @@ struct Tile {
 // reads of other ring slots never alias the slot being filled, does not
 // drain every load in flight before each LDS read; the ring's own vmcnt
 // waits order the accesses.  The instruction has no register result; M0
-// (its LDS base) is saved and restored around it.  s_nop 4: the DMA may read
-// M0 only one wait state after an SALU write to it, and an SGPR address only
-// five after a VALU write.
+// (its LDS base) is saved and restored around it.  Wait states: one between
+// an SALU write of M0 and the DMA; five between a VALU write of an SGPR
+// (readfirstlane) and a memory instruction that reads it as its base, which
+// the scalar-base form covers with s_nop 4 whatever the compiler placed
+// before the statement.
 //
 // Scalar-base form: wave-uniform 64-bit base + per-lane 32-bit offset.
 __device__ __forceinline__ void dma16_s(const uint8_t *base, uint32_t lane_off, uint32_t lds_addr)
 {
-    // readfirstlane returns a signed int: widen each half as unsigned
+    // (no-ops on values already in scalar registers; readfirstlane returns a
+    // signed int: widen each half as unsigned)
     const uint64_t b = (uint64_t)(uintptr_t)base;
     const uint32_t b_hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
     const uint32_t b_lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)b);
@@ -112,7 +128,7 @@ __device__ __forceinline__ void dma16_v(const uint8_t *addr, uint32_t lds_addr)
     uint32_t saved;
     asm volatile("s_mov_b32 %0, m0\n\t"
                  "s_mov_b32 m0, %2\n\t"
-                 "s_nop 4\n\t"
+                 "s_nop 0\n\t"
                  "global_load_lds_dwordx4 %1, off\n\t"
                  "s_mov_b32 m0, %0"
                  : "=&s"(saved)
@@ -258,15 +274,16 @@ __device__ __forceinline__ void mfma_k(Acc &acc, const Ops &o)
         }
 }
 
-// Instruction order of a k-step: the six LDS reads of a later k-step first,
-// then the 16 MFMAs, each followed by a share of the unpack of the next
-// k-step, which the matrix core's 32-cycle MFMAs hide.
+// Instruction order of a k-step: 16 MFMAs, each followed by a share of the
+// unpack of the next k-step (which the matrix core's 32-cycle MFMAs hide)
+// and, after the first six, one of the LDS reads of a later k-step -- spread
+// out rather than issued as a burst that would stall the wave at issue.
 __device__ __forceinline__ void kstep_schedule()
 {
-    __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);   // DS read
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+        if (m < 6) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read
         __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);   // VALU
     }
 }
@@ -385,7 +402,9 @@ __global__ __launch_bounds__(256, 1) void xcorr_dma(KernelArgs args)
     const uint32_t ring = (uint32_t)__builtin_amdgcn_readfirstlane(
         (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)lds);
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
+    // wave-uniform, so that everything derived from it stays scalar
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wa = wave >> 1, wb = wave & 1;
     // per-lane parts of the transposed-read addresses (see read_k)
     const int grp = lane >> 4, jl = lane & 15;
@@ -398,14 +417,15 @@ __global__ __launch_bounds__(256, 1) void xcorr_dma(KernelArgs args)
         const JobDesc jd = args.jobs ? args.jobs[pce.job] : args.job0;
         const int ti = pce.tile & 0xFFFF, tj2 = (pce.tile >> 16) & 0xFFFF;
         const bool atomic = pce.t1_atomic < 0;
+        // every field is wave-uniform: keep them in scalar registers
         Tile tl;
-        tl.samples = jd.samples;
-        tl.zeros = args.zeros;
-        tl.stride = jd.stride;
-        tl.row0 = ti * WA_ROWS;
-        tl.col0 = tj2 * WB_COLS;
-        tl.t0 = pce.t0;
-        tl.t1 = pce.t1_atomic & 0x7FFFFFFF;
+        tl.samples = uniform(jd.samples);
+        tl.zeros = uniform(args.zeros);
+        tl.stride = uniform(jd.stride);
+        tl.row0 = __builtin_amdgcn_readfirstlane(ti * WA_ROWS);
+        tl.col0 = __builtin_amdgcn_readfirstlane(tj2 * WB_COLS);
+        tl.t0 = __builtin_amdgcn_readfirstlane(pce.t0);
+        tl.t1 = __builtin_amdgcn_readfirstlane(pce.t1_atomic & 0x7FFFFFFF);
         // this wave's accumulator tile; a half below the diagonal is
         // computed (the workgroup stays in step) but not stored
         const int tj = 2 * tj2 + wb;
