@@ -8,7 +8,9 @@ metric is the paper's cost unit, complex multiply-accumulates per second
 (Sec. 2.2, eta counts N(N+1)/2 products per sample), on one GPU.
 
 Prints one JSON line.  Inputs are synthetic (seeded) and resident in HBM
-before the timed region starts.
+before the timed region starts.  Before the W warm-up steps, untimed steps
+run for --settle-ms of wall time: the GPU's clock takes tens of
+milliseconds of sustained load to ramp up, longer than a few steps.
 """
 from __future__ import annotations
 
@@ -55,6 +57,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--t", type=int, default=32768)
+    ap.add_argument("--settle-ms", type=float, default=300.0,
+                    help="untimed steps for this long before the warm-up steps (clock ramp)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -91,6 +95,11 @@ def main():
             ev[1].record(stream)
         corr.dump(0, out=out, reset=True, stream=stream)
 
+    t_settle = time.perf_counter() + args.settle_ms / 1e3
+    while time.perf_counter() < t_settle:
+        for _ in range(10):
+            step()
+        torch.cuda.synchronize()
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

@@ -137,7 +137,8 @@ int64_t xeng_samples_integrated(const xeng_ctx *ctx, int32_t slot);
 /* Largest number of samples a slot may integrate between resets. */
 int64_t xeng_max_integration(void);
 
-/* Device bytes of one slot's accumulators for N inputs (admission control); -1 if N < 1. */
+/* Device bytes of one slot for N inputs: its int32 accumulators plus the
+ * staging the dump uses (admission control); -1 if N < 1. */
 int64_t xeng_slot_bytes(int32_t n_inputs);
 
 /* N and slot count of a context (-1 on NULL). */

@@ -22,7 +22,8 @@
 namespace xeng {
 hipError_t launch_correlate(const KernelArgs &a, int grid, bool aligned, hipStream_t stream);
 hipError_t launch_correlate_dma(const KernelArgs &a, int grid, hipStream_t stream);
-hipError_t launch_dump(const int32_t *acc, int n, int nt, int32_t *out, hipStream_t stream);
+hipError_t launch_dump(int32_t *acc, int32_t *diag, int n, int nt, int32_t *out, bool reset,
+                       hipStream_t stream);
 hipError_t launch_zero(int32_t *p, int64_t n_i32, hipStream_t stream);
 hipError_t launch_reference(const uint8_t *s, int64_t n_samples, int n, int64_t stride,
                             uint32_t re_low, int32_t *out, hipStream_t stream);
@@ -190,7 +191,8 @@ struct xeng_ctx {
     uint32_t flags = 0;
     int32_t nt = 0;
     int64_t slot_i32 = 0;
-    int32_t *d_acc = nullptr;
+    int32_t *d_acc = nullptr;    // n_slots accumulators, then n_slots diagonal stagings
+    int32_t *d_diag = nullptr;
     std::vector<int64_t> acc_t;
     DeviceState *st = nullptr;
 };
@@ -242,7 +244,7 @@ int xeng_create(const xeng_config *cfg, xeng_ctx **out)
     if (cfg->n_inputs < 1 || cfg->n_inputs > 65535 || cfg->n_slots < 1 ||
         cfg->device < 0 || (cfg->flags & ~XENG_NIBBLE_RE_LOW) || cfg->mem_budget_bytes < 0)
         return XENG_EINVAL;
-    const int64_t slot_bytes = slot_i32(cfg->n_inputs) * 4;
+    const int64_t slot_bytes = (slot_i32(cfg->n_inputs) + diag_i32(cfg->n_inputs)) * 4;
     if (slot_bytes > INT64_MAX / cfg->n_slots) return XENG_ENOMEM;
     const int64_t bytes = slot_bytes * cfg->n_slots;
     if (cfg->mem_budget_bytes > 0 && bytes > cfg->mem_budget_bytes) return XENG_ENOMEM;
@@ -272,6 +274,7 @@ int xeng_create(const xeng_config *cfg, xeng_ctx **out)
         delete c;
         return map_err(e);
     }
+    c->d_diag = c->d_acc + (int64_t)cfg->n_slots * c->slot_i32;
     e = launch_zero(c->d_acc, bytes / 4, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -420,8 +423,8 @@ int xeng_dump(xeng_ctx *ctx, int32_t slot, int32_t *out, int32_t reset, void *hi
     if (!guard.ok) return XENG_EDEVICE;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     int32_t *acc = ctx->d_acc + (int64_t)slot * ctx->slot_i32;
-    hipError_t e = launch_dump(acc, ctx->n, ctx->nt, out, stream);
-    if (e == hipSuccess && reset) e = launch_zero(acc, ctx->slot_i32, stream);
+    int32_t *diag = ctx->d_diag + (int64_t)slot * diag_i32(ctx->n);
+    hipError_t e = launch_dump(acc, diag, ctx->n, ctx->nt, out, reset != 0, stream);
     if (e != hipSuccess) return map_err(e);
     if (reset) ctx->acc_t[(size_t)slot] = 0;
     return XENG_OK;
@@ -450,7 +453,7 @@ int64_t xeng_max_integration(void) { return T_MAX; }
 int64_t xeng_slot_bytes(int32_t n_inputs)
 {
     if (n_inputs < 1) return -1;
-    return slot_i32(n_inputs) * 4;
+    return (slot_i32(n_inputs) + diag_i32(n_inputs)) * 4;
 }
 
 int32_t xeng_n_inputs(const xeng_ctx *ctx) { return ctx ? ctx->n : -1; }

@@ -31,6 +31,8 @@ constexpr int64_t BLOCK_I32 = 2 * 16 * 64;                          // 2048 int3
 inline int64_t tri64(int64_t n) { return n * (n + 1) / 2; }
 inline int n_tiles_side(int n) { return (n + TILE - 1) / TILE; }
 inline int64_t slot_i32(int n) { return tri64(n_tiles_side(n)) * TILE_I32; }
+// Per-slot staging of the diagonal's imaginary parts for the dump.
+inline int64_t diag_i32(int n) { return ((int64_t)n + 63) / 64 * 64; }
 
 // Register sums of one piece: the general kernel's B operands carry 16x the
 // sample values, so its sums reach 16 * 128 * length (pieces below 2^20

@@ -387,21 +387,78 @@ __device__ __forceinline__ int64_t acc_index(int i, int j, int nt)
     return tile * TILE_I32 + (ca * BLKS + cb) * BLOCK_I32 + reg * 64 + ln;
 }
 
-// Accumulators (tile layout) -> packed row-major upper triangle of (Re, Im).
-// The stored imaginary part of (i, j) is Im V_ij - S_j and that of (j, j)
-// is -S_j: their difference is Im V_ij (exact in wrapping int32 arithmetic,
-// since Im V_ij itself fits).
-__global__ __launch_bounds__(256) void vis_dump(const int32_t *__restrict__ acc, int n, int nt,
-                                                int32_t *__restrict__ out)
+// Stored imaginary parts of the diagonal, d[j] = -S_j (see the operand
+// note at the top), staged before the tiles are exported and zeroed.
+__global__ __launch_bounds__(256) void diag_im(const int32_t *__restrict__ acc, int n, int nt,
+                                               int32_t *__restrict__ d)
 {
-    const int i = blockIdx.y;
-    const int j = i + blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j < n) d[j] = acc[acc_index(j, j, nt) + 1024];
+}
+
+// Accumulators (tile layout) -> packed row-major upper triangle of (Re, Im),
+// optionally zeroing the slot in the same pass.  Workgroup (x, y) takes
+// block row ca = x % 4 (32 rows) of tile (ti, tj) = (y, y + x / 4).  Reads:
+// thread t takes row t / 8 of the block row and 16 consecutive columns,
+// 16 * (t % 8).., which are 16 consecutive int32 of one accumulator register
+// row (4 dwordx4 loads per component, coalesced), and stages them in LDS
+// as (Re, Im) pairs.  Writes: consecutive threads take consecutive pairs of
+// an output row, 128 pairs (1 KB contiguous) per row.  The imaginary part of
+// (i, j) is stored as Im V_ij - S_j, so d[j] is subtracted (exact in
+// wrapping int32 arithmetic, since Im V_ij itself fits).
+constexpr int DUMP_PITCH = TILE + 1;   // int2 per staged row (padding spreads banks)
+
+__global__ __launch_bounds__(256) void vis_dump(int32_t *__restrict__ acc, int n, int nt,
+                                                const int32_t *__restrict__ d,
+                                                int32_t *__restrict__ out, int reset)
+{
+    __shared__ int2 stage[BLK * DUMP_PITCH];
+    const int ti = blockIdx.y;
+    const int tj = ti + (blockIdx.x >> 2);
+    if (tj >= nt) return;
+    const int ca = blockIdx.x & 3;
+    const int t = threadIdx.x;
+    const int64_t tile = (int64_t)ti * nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);
+    {
+        const int ri = t >> 3, c16 = t & 7;
+        const int cb = c16 >> 1, cj0 = 16 * (c16 & 1);
+        const int reg = 4 * (ri >> 3) + (ri & 3), half = (ri >> 2) & 1;
+        int32_t *base = acc + tile * TILE_I32 + (ca * BLKS + cb) * BLOCK_I32 + reg * 64 + 32 * half + cj0;
+        int4 *pre = reinterpret_cast<int4 *>(base);
+        int4 *pim = reinterpret_cast<int4 *>(base + 1024);
+        int4 re[4], im[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            re[q] = pre[q];
+            im[q] = pim[q];
+        }
+        if (reset) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                pre[q] = make_int4(0, 0, 0, 0);
+                pim[q] = make_int4(0, 0, 0, 0);
+            }
+        }
+        const int32_t *rv = reinterpret_cast<const int32_t *>(re);
+        const int32_t *iv = reinterpret_cast<const int32_t *>(im);
+        int2 *row = stage + ri * DUMP_PITCH + BLK * cb + cj0;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) row[e] = make_int2(rv[e], iv[e]);
+    }
+    __syncthreads();
+    const int col = t & (TILE - 1);
+    const int j = TILE * tj + col;
     if (j >= n) return;
-    const int32_t *p = acc + acc_index(i, j, nt);
-    const int32_t *d = acc + acc_index(j, j, nt);
-    const int32_t im = (int32_t)((uint32_t)p[1024] - (uint32_t)d[1024]);
-    const int64_t k = (int64_t)i * n - (int64_t)i * (i - 1) / 2 + (j - i);
-    reinterpret_cast<int2 *>(out)[k] = make_int2(p[0], im);
+    const uint32_t dj = (uint32_t)d[j];
+    int2 *o = reinterpret_cast<int2 *>(out);
+#pragma unroll 4
+    for (int r = t >> 7; r < BLK; r += 2) {
+        const int i = TILE * ti + BLK * ca + r;
+        if (i >= n || j < i) continue;
+        const int64_t k = (int64_t)i * n - (int64_t)i * (i - 1) / 2 + (j - i);
+        const int2 v = stage[r * DUMP_PITCH + col];
+        o[k] = make_int2(v.x, (int32_t)((uint32_t)v.y - dj));
+    }
 }
 
 __global__ __launch_bounds__(256) void fill_zero(int4 *__restrict__ p, int64_t n4)
@@ -456,10 +513,12 @@ hipError_t launch_correlate(const KernelArgs &a, int grid, bool aligned, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_dump(const int32_t *acc, int n, int nt, int32_t *out, hipStream_t stream)
+hipError_t launch_dump(int32_t *acc, int32_t *diag, int n, int nt, int32_t *out, bool reset,
+                       hipStream_t stream)
 {
-    dim3 grid((n + 255) / 256, n);
-    hipLaunchKernelGGL(vis_dump, grid, dim3(256), 0, stream, acc, n, nt, out);
+    hipLaunchKernelGGL(diag_im, dim3((n + 255) / 256), dim3(256), 0, stream, acc, n, nt, diag);
+    hipLaunchKernelGGL(vis_dump, dim3(4 * nt, nt), dim3(256), 0, stream, acc, n, nt, diag, out,
+                       reset ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -20,69 +20,106 @@ std::vector<std::pair<int, int>> plan_units(int n, TileShape shape)
     return u;
 }
 
+namespace {
+
+// Cost of a piece beyond its stages, in stage units: its prologue (the
+// first stages' loads are not yet overlapped) and its flush of the tile's
+// accumulators to memory.  Measured on the DMA kernel's 128 x 256 tiles at
+// about 16 stage times; a 128 x 128 tile flushes half as much.
+int64_t piece_overhead(TileShape shape) { return shape == TileShape::Wide ? 16 : 8; }
+
+struct UnitRef {
+    int job, ti, tj;
+    int64_t ns;   // stages
+    int64_t t;    // samples
+};
+
+// Greedy fill: workgroups in order, each taking pieces of the linear (job,
+// unit, stage) order until its cost (stages + overhead per piece) would
+// exceed `budget`.  Returns the number of workgroups used (or grid + 1 if
+// the work does not fit), emitting pieces when `out` is given.
+template <typename Emit>
+int64_t fill(const std::vector<UnitRef> &units, int64_t budget, int64_t overhead, int64_t cap, int64_t grid,
+             Emit emit)
+{
+    int64_t w = 0, left = budget;
+    for (size_t u = 0; u < units.size(); ++u) {
+        int64_t done = 0;
+        while (done < units[u].ns) {
+            if (left <= overhead) {
+                if (++w >= grid) return grid + 1;
+                left = budget;
+            }
+            const int64_t take = std::min({units[u].ns - done, left - overhead, cap});
+            emit(w, u, done, done + take);
+            done += take;
+            left -= take + overhead;
+        }
+    }
+    return w + 1;
+}
+
+}  // namespace
+
 Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, TileShape shape)
 {
     Plan plan;
     if (min_stages < 1) min_stages = 1;
     if (max_wgs < 1) max_wgs = 1;
+    const int64_t cap = shape == TileShape::Wide ? MAX_PIECE_STAGES_WIDE : MAX_PIECE_STAGES;
+    const int64_t ovh = piece_overhead(shape);
 
-    // Total work in stage units over all (job, tile) pairs.
+    std::vector<UnitRef> units;
     int64_t total = 0;
     for (int j = 0; j < n_jobs; ++j) {
         if (jobs[j].t <= 0 || jobs[j].n <= 0) continue;
         const int64_t ns = (jobs[j].t + STAGE - 1) / STAGE;
-        total += (int64_t)plan_units(jobs[j].n, shape).size() * ns;
+        for (const auto &unit : plan_units(jobs[j].n, shape)) {
+            units.push_back(UnitRef{j, unit.first, unit.second, ns, jobs[j].t});
+            total += ns;
+        }
     }
     if (total == 0) {
         plan.grid = 0;
         plan.wg_off.assign(1, 0);
         return plan;
     }
-    const int64_t cap = shape == TileShape::Wide ? MAX_PIECE_STAGES_WIDE : MAX_PIECE_STAGES;
-    int64_t grid = std::min<int64_t>(max_wgs, (total + min_stages - 1) / min_stages);
-    grid = std::max<int64_t>(grid, 1);
-    plan.grid = (int32_t)grid;
-    plan.wg_off.assign((size_t)grid + 1, 0);
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(max_wgs, (total + min_stages - 1) / min_stages));
 
-    // Workgroup w owns the linear stage range [bound(w), bound(w + 1)).
-    auto bound = [&](int64_t w) { return (w * total) / grid; };
-
-    struct Raw { Piece p; int32_t wg; };
-    std::vector<Raw> raw;
-    int64_t u = 0;   // linear stage offset of the current tile
-    for (int j = 0; j < n_jobs; ++j) {
-        if (jobs[j].t <= 0 || jobs[j].n <= 0) continue;
-        const int64_t t = jobs[j].t;
-        const int64_t ns = (t + STAGE - 1) / STAGE;
-        for (const auto &unit : plan_units(jobs[j].n, shape)) {
-            const int ti = unit.first, tj = unit.second;
-            const int64_t lo = u, hi = u + ns;
-            // first workgroup whose range intersects [lo, hi)
-            int64_t w = (lo * grid) / total;
-            while (w > 0 && bound(w) > lo) --w;
-            while (bound(w + 1) <= lo) ++w;
-            const size_t first = raw.size();
-            for (; w < grid && bound(w) < hi; ++w) {
-                const int64_t a = std::max(lo, bound(w)), b = std::min(hi, bound(w + 1));
-                // long ranges are cut so that no piece exceeds the shape's cap
-                for (int64_t c = a; c < b; c += cap) {
-                    const int64_t e = std::min<int64_t>(b, c + cap);
-                    Raw r;
-                    r.p.job = j;
-                    r.p.tile = ti | (tj << 16);
-                    r.p.t0 = (int32_t)((c - lo) * STAGE);
-                    r.p.t1_atomic = (int32_t)std::min<int64_t>((e - lo) * STAGE, t);
-                    r.wg = (int32_t)w;
-                    raw.push_back(r);
-                }
-            }
-            if (raw.size() - first > 1)
-                for (size_t k = first; k < raw.size(); ++k)
-                    raw[k].p.t1_atomic |= (int32_t)0x80000000u;
-            u = hi;
-        }
+    // Smallest per-workgroup budget with which the greedy fill fits in
+    // `grid` workgroups (the fill is monotone in the budget).
+    auto none = [](int64_t, size_t, int64_t, int64_t) {};
+    int64_t lo = ovh + 1, hi = ovh + total + 1;   // hi always fits: one piece per unit at most... per workgroup
+    hi = std::max(hi, (total + grid - 1) / grid + ovh * ((int64_t)units.size() + 1) + 1);
+    while (fill(units, hi, ovh, cap, grid, none) > grid) hi *= 2;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (fill(units, mid, ovh, cap, grid, none) <= grid)
+            hi = mid;
+        else
+            lo = mid + 1;
     }
-    // Raw pieces come out ordered by workgroup already (linear order).
+
+    struct Raw { Piece p; int32_t wg; size_t unit; };
+    std::vector<Raw> raw;
+    std::vector<int32_t> pieces_of_unit(units.size(), 0);
+    const int64_t used = fill(units, lo, ovh, cap, grid, [&](int64_t w, size_t u, int64_t a, int64_t b) {
+        Raw r;
+        r.p.job = units[u].job;
+        r.p.tile = units[u].ti | (units[u].tj << 16);
+        r.p.t0 = (int32_t)(a * STAGE);
+        r.p.t1_atomic = (int32_t)std::min<int64_t>(b * STAGE, units[u].t);
+        r.wg = (int32_t)w;
+        r.unit = u;
+        raw.push_back(r);
+        pieces_of_unit[u]++;
+    });
+    plan.grid = (int32_t)used;
+    plan.wg_off.assign((size_t)used + 1, 0);
+    // a tile cut into several pieces is flushed with atomics
+    for (Raw &r : raw)
+        if (pieces_of_unit[r.unit] > 1) r.p.t1_atomic |= (int32_t)0x80000000u;
+    // pieces come out ordered by workgroup already
     plan.pieces.reserve(raw.size());
     plan.piece_wg.reserve(raw.size());
     for (const Raw &r : raw) {
@@ -90,7 +127,7 @@ Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, Til
         plan.piece_wg.push_back(r.wg);
         plan.wg_off[(size_t)r.wg + 1]++;
     }
-    for (size_t w = 0; w < (size_t)grid; ++w) plan.wg_off[w + 1] += plan.wg_off[w];
+    for (size_t w = 0; w < (size_t)used; ++w) plan.wg_off[w + 1] += plan.wg_off[w];
     return plan;
 }
 
