@@ -189,6 +189,49 @@ int64_t xeng_plan_inspect(const int32_t *n_inputs, const int64_t *n_samples, int
                           int32_t n_workgroups, int32_t min_stages, int32_t wide,
                           xeng_piece_info *out, int64_t cap);
 
+/*
+ * Prepared batch, for repeated launches of the same jobs (a streaming loop,
+ * a captured graph).  xeng_batch_create checks the jobs as
+ * xeng_correlate_batch does, plans them, and copies the plan and the job
+ * table into device memory that the batch owns (synchronously).  The jobs'
+ * sample pointers are fixed: each launch reads whatever those buffers hold
+ * when it runs.  The contexts must outlive the batch.
+ *
+ * xeng_batch_launch enqueues one kernel launch per kernel kind (at most
+ * two) and nothing else -- no copy, no memset, no allocation -- so it may be
+ * captured into a hipGraph.  Outside a capture it applies the integration
+ * guard and advances the slots' sample counters.  While hip_stream is
+ * capturing it does neither: each replay of the graph integrates again, and
+ * its caller reports replays with xeng_batch_note_replays (which applies the
+ * guard first, XENG_EOVERFLOW leaving the counters unchanged).
+ */
+typedef struct xeng_batch xeng_batch;
+int xeng_batch_create(const xeng_job *jobs, int32_t n_jobs, xeng_batch **out);
+int xeng_batch_launch(xeng_batch *b, void *hip_stream);
+int xeng_batch_note_replays(xeng_batch *b, int64_t n_replays);
+int xeng_batch_destroy(xeng_batch *b);
+
+/* A launch configuration chosen by xeng_autotune. */
+typedef struct {
+    int32_t kernel;        /* XENG_KERNEL_AUTO or XENG_KERNEL_GENERAL */
+    int32_t wgs_per_cu;    /* general kernel's workgroups per compute unit */
+    int32_t min_stages;    /* minimum piece length, 64-sample stages */
+    int32_t reserved;
+    double us_per_launch;  /* measured time of the chosen configuration */
+} xeng_tuning;
+
+/*
+ * Autotuner: times every candidate launch configuration (kernel kind and
+ * so tile shape, workgroups per CU, minimum piece length) on these jobs,
+ * `iters` launches each on hip_stream, and keeps the fastest for every later
+ * call with the same job sizes (N, T in order) on this device.  The jobs'
+ * slots serve as scratch: they are zeroed, and their counters reset, when it
+ * returns.  Synchronous.  Results never depend on the configuration.
+ * xeng_set_tuning discards every autotuned choice.
+ */
+int xeng_autotune(const xeng_job *jobs, int32_t n_jobs, int32_t iters, void *hip_stream,
+                  xeng_tuning *best);
+
 /* Kernel selection for xeng_set_tuning. */
 #define XENG_KERNEL_AUTO 0     /* wide DMA kernel where the job allows it, else general */
 #define XENG_KERNEL_GENERAL 1  /* always the general kernel */
@@ -197,7 +240,8 @@ int64_t xeng_plan_inspect(const int32_t *n_inputs, const int64_t *n_samples, int
  * Launch tuning: workgroups per compute unit of the general kernel (1 or 2),
  * the minimum piece length in 64-sample stages, and the kernel selection.
  * Values < 0 (or 0 for the first two) keep the current setting.  Applies to
- * later calls on every device.  Results never depend on these settings.
+ * later calls on every device and discards the autotuner's choices.  Results
+ * never depend on these settings.
  */
 int xeng_set_tuning(int32_t wgs_per_cu, int32_t min_stages, int32_t kernel);
 

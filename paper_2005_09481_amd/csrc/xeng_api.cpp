@@ -22,6 +22,7 @@
 namespace xeng {
 hipError_t launch_correlate(const KernelArgs &a, int grid, bool aligned, hipStream_t stream);
 hipError_t launch_correlate_dma(const KernelArgs &a, int grid, hipStream_t stream);
+hipError_t init_dma_kernel();
 hipError_t launch_dump(int32_t *acc, int32_t *diag, int n, int nt, int32_t *out, bool reset,
                        hipStream_t stream);
 hipError_t launch_zero(int32_t *p, int64_t n_i32, hipStream_t stream);
@@ -36,6 +37,16 @@ namespace {
 std::atomic<int> g_wgs_per_cu{2};      // general kernel
 std::atomic<int> g_min_stages{4};
 std::atomic<int> g_kernel{XENG_KERNEL_AUTO};
+
+// Launch configuration of one call: the global settings, or what the
+// autotuner found best for calls of the same job sizes.
+struct Tuning {
+    int kernel;       // XENG_KERNEL_*
+    int wgs_per_cu;   // general kernel
+    int min_stages;
+};
+
+Tuning global_tuning() { return Tuning{g_kernel.load(), g_wgs_per_cu.load(), g_min_stages.load()}; }
 
 // Restores the caller's current device on scope exit.
 struct DeviceGuard {
@@ -80,6 +91,7 @@ struct DeviceState {
     std::list<std::string> lru;
     JobTable ring[JOB_RING];
     int ring_next = 0;
+    std::unordered_map<std::string, Tuning> tuned;   // job sizes -> autotuned configuration
 };
 
 std::mutex g_states_mu;
@@ -100,7 +112,8 @@ DeviceState *device_state(int device)
     // zero samples that the DMA kernel reads in place of rows past a
     // piece's end; written once, before any launch that could read them
     if (hipMalloc(&st->d_zeros, ZERO_BYTES) != hipSuccess) return nullptr;
-    if (hipMemset(st->d_zeros, 0x88, ZERO_BYTES) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    if (hipMemset(st->d_zeros, 0x88, ZERO_BYTES) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+        init_dma_kernel() != hipSuccess) {
         (void)hipFree(st->d_zeros);
         return nullptr;
     }
@@ -123,15 +136,38 @@ std::string plan_key(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stage
     return k;
 }
 
+// Key of a list of job sizes (the autotuner's table).
+std::string sizes_key(const PlanJob *jobs, int n_jobs)
+{
+    std::string k;
+    k.reserve(16 * (size_t)n_jobs);
+    for (int j = 0; j < n_jobs; ++j) {
+        k.append(reinterpret_cast<const char *>(&jobs[j].n), sizeof jobs[j].n);
+        k.append(reinterpret_cast<const char *>(&jobs[j].t), sizeof jobs[j].t);
+    }
+    return k;
+}
+
+// Configuration for calls with these job sizes.  Called with st->mu held.
+Tuning tuning_for(DeviceState *st, const PlanJob *jobs, int n_jobs)
+{
+    if (!st->tuned.empty()) {
+        auto it = st->tuned.find(sizes_key(jobs, n_jobs));
+        if (it != st->tuned.end()) return it->second;
+    }
+    return global_tuning();
+}
+
 // Look up (or build and upload) the plan for these job sizes.  Called with
 // st->mu held and the device current.
-int get_plan(DeviceState *st, const PlanJob *jobs, int n_jobs, TileShape shape, DevicePlan *out)
+int get_plan(DeviceState *st, const PlanJob *jobs, int n_jobs, TileShape shape, const Tuning &tu,
+             DevicePlan *out)
 {
     // the DMA kernel holds one 256-thread workgroup per CU (its LDS ring
     // fills most of the CU); the general kernel fits two
-    const int per_cu = shape == TileShape::Wide ? 1 : std::max(1, g_wgs_per_cu.load());
+    const int per_cu = shape == TileShape::Wide ? 1 : std::max(1, tu.wgs_per_cu);
     const int max_wgs = st->cu_count * per_cu;
-    const int min_stages = std::max(1, g_min_stages.load());
+    const int min_stages = std::max(1, tu.min_stages);
     const std::string key = plan_key(jobs, n_jobs, max_wgs, min_stages, shape);
     auto it = st->plans.find(key);
     if (it != st->plans.end()) {
@@ -184,6 +220,26 @@ int map_err(hipError_t e)
 
 }  // namespace
 
+struct xeng_batch {
+    struct Acct {
+        xeng_ctx *ctx;
+        int32_t slot;
+        int64_t n;
+    };
+    struct Launch {
+        bool dma;
+        uint32_t flags_and;
+        int32_t grid;
+        JobDesc *d_jobs;
+        Piece *d_pieces;
+        int32_t *d_off;
+    };
+    int device = 0;
+    const uint8_t *zeros = nullptr;
+    std::vector<Acct> acct;
+    std::vector<Launch> launches;
+};
+
 struct xeng_ctx {
     int32_t n = 0;
     int32_t n_slots = 0;
@@ -218,19 +274,131 @@ JobDesc make_job(const xeng_ctx *c, int32_t slot, const uint8_t *d_samples, int6
     return jd;
 }
 
-// Kernel choice for a launch whose jobs all have `flags_and` in common.
-bool use_dma(uint32_t flags_and)
+// Kernel choice for one job.
+bool use_dma(uint32_t flags, const Tuning &tu) { return tu.kernel != XENG_KERNEL_GENERAL && (flags & JOB_DMA); }
+
+hipError_t launch(const KernelArgs &a, int32_t grid, bool dma, uint32_t flags_and, hipStream_t stream)
 {
-    const int k = g_kernel.load();
-    if (k == XENG_KERNEL_GENERAL) return false;
-    return (flags_and & JOB_DMA) != 0;
+    if (dma) return launch_correlate_dma(a, grid, stream);
+    return launch_correlate(a, grid, (flags_and & JOB_ALIGNED8) != 0, stream);
 }
 
-hipError_t launch(const KernelArgs &a, const DevicePlan &dp, bool dma, uint32_t flags_and,
-                  hipStream_t stream)
+// Validated jobs of a batch that have work, in input order.
+struct JobList {
+    int device = -1;
+    DeviceState *st = nullptr;
+    std::vector<PlanJob> pj;
+    std::vector<JobDesc> descs;
+    std::vector<int32_t> idx;    // index into the caller's array
+};
+
+// Argument checks shared by the batched calls.  `launches` > 0 also applies
+// the integration guard for that many launches of every job.
+int validate_jobs(const xeng_job *jobs, int32_t n_jobs, int64_t launches, JobList *out)
 {
-    if (dma) return launch_correlate_dma(a, dp.grid, stream);
-    return launch_correlate(a, dp.grid, (flags_and & JOB_ALIGNED8) != 0, stream);
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return XENG_EINVAL;
+    if (n_jobs == 0) return XENG_OK;
+    if (!jobs[0].ctx) return XENG_EINVAL;
+    const int device = jobs[0].ctx->device;
+    std::set<std::pair<const xeng_ctx *, int32_t>> seen;
+    for (int32_t k = 0; k < n_jobs; ++k) {
+        const xeng_job &j = jobs[k];
+        if (!slot_ok(j.ctx, j.slot) || j.reserved != 0 || j.n_samples < 0 ||
+            j.row_stride < j.ctx->n || j.row_stride > MAX_STRIDE ||
+            (j.n_samples > 0 && !j.d_samples) || j.ctx->device != device)
+            return XENG_EINVAL;
+        if (j.n_samples > 0 && j.row_stride > INT64_MAX / j.n_samples) return XENG_EINVAL;
+        if (!seen.insert({j.ctx, j.slot}).second) return XENG_EINVAL;
+        if (launches > 0 && j.n_samples > 0 &&
+            (j.n_samples > T_MAX / launches || j.n_samples * launches > T_MAX - j.ctx->acc_t[(size_t)j.slot]))
+            return XENG_EOVERFLOW;
+    }
+    out->device = device;
+    out->st = jobs[0].ctx->st;
+    for (int32_t k = 0; k < n_jobs; ++k) {
+        if (jobs[k].n_samples == 0) continue;
+        out->pj.push_back(PlanJob{jobs[k].ctx->n, jobs[k].n_samples});
+        out->descs.push_back(make_job(jobs[k].ctx, jobs[k].slot, jobs[k].d_samples, jobs[k].row_stride));
+        out->idx.push_back(k);
+    }
+    return XENG_OK;
+}
+
+// One persistent launch: the jobs of a batch that take the same kernel.
+struct Part {
+    bool dma = false;
+    uint32_t flags_and = ~0u;
+    std::vector<PlanJob> pj;
+    std::vector<JobDesc> descs;
+};
+
+std::vector<Part> split_by_kernel(const JobList &jl, const Tuning &tu)
+{
+    Part wide, square;
+    wide.dma = true;
+    for (size_t k = 0; k < jl.descs.size(); ++k) {
+        Part &p = use_dma(jl.descs[k].flags, tu) ? wide : square;
+        p.pj.push_back(jl.pj[k]);
+        p.descs.push_back(jl.descs[k]);
+        p.flags_and &= jl.descs[k].flags;
+    }
+    std::vector<Part> parts;
+    if (!wide.descs.empty()) parts.push_back(std::move(wide));
+    if (!square.descs.empty()) parts.push_back(std::move(square));
+    return parts;
+}
+
+// Launch the parts of a batch, staging each job table through the ring.
+// Called with st->mu held and the device current.
+int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu, hipStream_t stream)
+{
+    for (const Part &part : parts) {
+        DevicePlan dp;
+        int rc = get_plan(st, part.pj.data(), (int)part.pj.size(),
+                          part.dma ? TileShape::Wide : TileShape::Square, tu, &dp);
+        if (rc != XENG_OK) return rc;
+        JobTable &tb = st->ring[st->ring_next];
+        st->ring_next = (st->ring_next + 1) % JOB_RING;
+        hipError_t e = hipSuccess;
+        if (tb.pending) {
+            e = hipEventSynchronize(tb.ev);
+            if (e != hipSuccess) return map_err(e);
+            tb.pending = false;
+        }
+        if (!tb.ev && (e = hipEventCreateWithFlags(&tb.ev, hipEventDisableTiming)) != hipSuccess)
+            return map_err(e);
+        const size_t nd = part.descs.size();
+        if (tb.cap < nd) {
+            if (tb.h) (void)hipHostFree(tb.h);
+            if (tb.d) (void)hipFree(tb.d);
+            tb.h = nullptr;
+            tb.d = nullptr;
+            tb.cap = 0;
+            const size_t cap = std::max<size_t>(nd, 64);
+            if ((e = hipHostMalloc(&tb.h, cap * sizeof(JobDesc), hipHostMallocDefault)) != hipSuccess)
+                return map_err(e);
+            if ((e = hipMalloc(&tb.d, cap * sizeof(JobDesc))) != hipSuccess) {
+                (void)hipHostFree(tb.h);
+                tb.h = nullptr;
+                return map_err(e);
+            }
+            tb.cap = cap;
+        }
+        std::memcpy(tb.h, part.descs.data(), nd * sizeof(JobDesc));
+        e = hipMemcpyAsync(tb.d, tb.h, nd * sizeof(JobDesc), hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return map_err(e);
+        KernelArgs a;
+        std::memset(&a.job0, 0, sizeof a.job0);
+        a.jobs = tb.d;
+        a.zeros = st->d_zeros;
+        a.pieces = dp.d_pieces;
+        a.wg_off = dp.d_off;
+        e = launch(a, dp.grid, part.dma, part.flags_and, stream);
+        if (e == hipSuccess) e = hipEventRecord(tb.ev, stream);
+        if (e != hipSuccess) return map_err(e);
+        tb.pending = true;
+    }
+    return XENG_OK;
 }
 
 }  // namespace
@@ -318,14 +486,15 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_
     a.job0 = make_job(ctx, slot, d_samples, row_stride);
     a.jobs = nullptr;
     a.zeros = ctx->st->d_zeros;
-    const bool dma = use_dma(a.job0.flags);
     // held through the launch so that no other thread evicts the plan first
     std::lock_guard<std::mutex> lk(ctx->st->mu);
-    int rc = get_plan(ctx->st, &pj, 1, dma ? TileShape::Wide : TileShape::Square, &dp);
+    const Tuning tu = tuning_for(ctx->st, &pj, 1);
+    const bool dma = use_dma(a.job0.flags, tu);
+    int rc = get_plan(ctx->st, &pj, 1, dma ? TileShape::Wide : TileShape::Square, tu, &dp);
     if (rc != XENG_OK) return rc;
     a.pieces = dp.d_pieces;
     a.wg_off = dp.d_off;
-    hipError_t e = launch(a, dp, dma, a.job0.flags, stream);
+    hipError_t e = launch(a, dp.grid, dma, a.job0.flags, stream);
     if (e != hipSuccess) return map_err(e);
     ctx->acc_t[(size_t)slot] += n_samples;
     return XENG_OK;
@@ -333,86 +502,16 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_
 
 int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
 {
-    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return XENG_EINVAL;
-    if (n_jobs == 0) return XENG_OK;
-    const int device = jobs[0].ctx ? jobs[0].ctx->device : -1;
-    std::set<std::pair<const xeng_ctx *, int32_t>> seen;
-    for (int32_t k = 0; k < n_jobs; ++k) {
-        const xeng_job &j = jobs[k];
-        if (!slot_ok(j.ctx, j.slot) || j.reserved != 0 || j.n_samples < 0 ||
-            j.row_stride < j.ctx->n || j.row_stride > MAX_STRIDE ||
-            (j.n_samples > 0 && !j.d_samples) ||
-            j.ctx->device != device)
-            return XENG_EINVAL;
-        if (j.n_samples > 0 && j.row_stride > INT64_MAX / j.n_samples) return XENG_EINVAL;
-        if (!seen.insert({j.ctx, j.slot}).second) return XENG_EINVAL;
-        if (j.n_samples > T_MAX - j.ctx->acc_t[(size_t)j.slot]) return XENG_EOVERFLOW;
-    }
-    // keep only jobs with work
-    std::vector<PlanJob> pj;
-    std::vector<JobDesc> descs;
-    std::vector<int32_t> idx;
-    for (int32_t k = 0; k < n_jobs; ++k) {
-        if (jobs[k].n_samples == 0) continue;
-        pj.push_back(PlanJob{jobs[k].ctx->n, jobs[k].n_samples});
-        descs.push_back(make_job(jobs[k].ctx, jobs[k].slot, jobs[k].d_samples, jobs[k].row_stride));
-        idx.push_back(k);
-    }
-    if (pj.empty()) return XENG_OK;
-
-    DeviceGuard guard(device);
+    JobList jl;
+    int rc = validate_jobs(jobs, n_jobs, 1, &jl);
+    if (rc != XENG_OK || jl.descs.empty()) return rc;
+    DeviceGuard guard(jl.device);
     if (!guard.ok) return XENG_EDEVICE;
-    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    DeviceState *st = jobs[0].ctx->st;
-    uint32_t flags_and = ~0u;
-    for (const JobDesc &jd : descs) flags_and &= jd.flags;
-    const bool dma = use_dma(flags_and);
-    std::lock_guard<std::mutex> lk(st->mu);
-    DevicePlan dp;
-    int rc = get_plan(st, pj.data(), (int)pj.size(), dma ? TileShape::Wide : TileShape::Square, &dp);
+    std::lock_guard<std::mutex> lk(jl.st->mu);
+    const Tuning tu = tuning_for(jl.st, jl.pj.data(), (int)jl.pj.size());
+    rc = run_parts(jl.st, split_by_kernel(jl, tu), tu, static_cast<hipStream_t>(hip_stream));
     if (rc != XENG_OK) return rc;
-
-    // stage the job table through the ring
-    JobTable &tb = st->ring[st->ring_next];
-    st->ring_next = (st->ring_next + 1) % JOB_RING;
-    hipError_t e = hipSuccess;
-    if (tb.pending) {
-        e = hipEventSynchronize(tb.ev);
-        if (e != hipSuccess) return map_err(e);
-        tb.pending = false;
-    }
-    if (!tb.ev && (e = hipEventCreateWithFlags(&tb.ev, hipEventDisableTiming)) != hipSuccess)
-        return map_err(e);
-    if (tb.cap < descs.size()) {
-        if (tb.h) (void)hipHostFree(tb.h);
-        if (tb.d) (void)hipFree(tb.d);
-        tb.h = nullptr;
-        tb.d = nullptr;
-        tb.cap = 0;
-        const size_t cap = std::max<size_t>(descs.size(), 64);
-        if ((e = hipHostMalloc(&tb.h, cap * sizeof(JobDesc), hipHostMallocDefault)) != hipSuccess)
-            return map_err(e);
-        if ((e = hipMalloc(&tb.d, cap * sizeof(JobDesc))) != hipSuccess) {
-            (void)hipHostFree(tb.h);
-            tb.h = nullptr;
-            return map_err(e);
-        }
-        tb.cap = cap;
-    }
-    std::memcpy(tb.h, descs.data(), descs.size() * sizeof(JobDesc));
-    e = hipMemcpyAsync(tb.d, tb.h, descs.size() * sizeof(JobDesc), hipMemcpyHostToDevice, stream);
-    if (e != hipSuccess) return map_err(e);
-    KernelArgs a;
-    std::memset(&a.job0, 0, sizeof a.job0);
-    a.jobs = tb.d;
-    a.zeros = st->d_zeros;
-    a.pieces = dp.d_pieces;
-    a.wg_off = dp.d_off;
-    e = launch(a, dp, dma, flags_and, stream);
-    if (e == hipSuccess) e = hipEventRecord(tb.ev, stream);
-    if (e != hipSuccess) return map_err(e);
-    tb.pending = true;
-    for (int32_t k : idx) jobs[k].ctx->acc_t[(size_t)jobs[k].slot] += jobs[k].n_samples;
+    for (int32_t k : jl.idx) jobs[k].ctx->acc_t[(size_t)jobs[k].slot] += jobs[k].n_samples;
     return XENG_OK;
 }
 
@@ -519,12 +618,206 @@ int64_t xeng_plan_inspect(const int32_t *n_inputs, const int64_t *n_samples, int
     return np;
 }
 
+namespace {
+
+void free_batch(xeng_batch *b)
+{
+    for (auto &l : b->launches) {
+        if (l.d_jobs) (void)hipFree(l.d_jobs);
+        if (l.d_pieces) (void)hipFree(l.d_pieces);
+        if (l.d_off) (void)hipFree(l.d_off);
+    }
+    delete b;
+}
+
+// Guard and counters for `k` more launches of a prepared batch.
+int account_batch(xeng_batch *b, int64_t k)
+{
+    for (const auto &a : b->acct)
+        if (a.n > T_MAX / k || a.n * k > T_MAX - a.ctx->acc_t[(size_t)a.slot]) return XENG_EOVERFLOW;
+    for (const auto &a : b->acct) a.ctx->acc_t[(size_t)a.slot] += a.n * k;
+    return XENG_OK;
+}
+
+}  // namespace
+
+int xeng_batch_create(const xeng_job *jobs, int32_t n_jobs, xeng_batch **out)
+{
+    if (!out) return XENG_EINVAL;
+    *out = nullptr;
+    JobList jl;
+    int rc = validate_jobs(jobs, n_jobs, 0, &jl);
+    if (rc != XENG_OK) return rc;
+    if (n_jobs == 0) return XENG_EINVAL;
+    auto *b = new (std::nothrow) xeng_batch;
+    if (!b) return XENG_ENOMEM;
+    b->device = jobs[0].ctx->device;
+    b->zeros = jobs[0].ctx->st->d_zeros;
+    for (int32_t k : jl.idx) b->acct.push_back({jobs[k].ctx, jobs[k].slot, jobs[k].n_samples});
+    if (jl.descs.empty()) {
+        *out = b;
+        return XENG_OK;
+    }
+    DeviceGuard guard(b->device);
+    if (!guard.ok) {
+        delete b;
+        return XENG_EDEVICE;
+    }
+    Tuning tu;
+    {
+        std::lock_guard<std::mutex> lk(jl.st->mu);
+        tu = tuning_for(jl.st, jl.pj.data(), (int)jl.pj.size());
+    }
+    for (const Part &part : split_by_kernel(jl, tu)) {
+        const TileShape shape = part.dma ? TileShape::Wide : TileShape::Square;
+        const int per_cu = part.dma ? 1 : std::max(1, tu.wgs_per_cu);
+        const Plan plan = make_plan(part.pj.data(), (int)part.pj.size(), jl.st->cu_count * per_cu,
+                                    std::max(1, tu.min_stages), shape);
+        xeng_batch::Launch l{part.dma, part.flags_and, plan.grid, nullptr, nullptr, nullptr};
+        b->launches.push_back(l);
+        xeng_batch::Launch &lb = b->launches.back();
+        const size_t nj = part.descs.size() * sizeof(JobDesc);
+        const size_t np = plan.pieces.size() * sizeof(Piece);
+        const size_t no = plan.wg_off.size() * sizeof(int32_t);
+        hipError_t e = hipMalloc(&lb.d_jobs, nj);
+        if (e == hipSuccess) e = hipMalloc(&lb.d_pieces, std::max<size_t>(np, sizeof(Piece)));
+        if (e == hipSuccess) e = hipMalloc(&lb.d_off, no);
+        // synchronous uploads: a prepared batch is built once
+        if (e == hipSuccess) e = hipMemcpy(lb.d_jobs, part.descs.data(), nj, hipMemcpyHostToDevice);
+        if (e == hipSuccess && np) e = hipMemcpy(lb.d_pieces, plan.pieces.data(), np, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(lb.d_off, plan.wg_off.data(), no, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            free_batch(b);
+            return map_err(e);
+        }
+    }
+    *out = b;
+    return XENG_OK;
+}
+
+int xeng_batch_launch(xeng_batch *b, void *hip_stream)
+{
+    if (!b) return XENG_EINVAL;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    DeviceGuard guard(b->device);
+    if (!guard.ok) return XENG_EDEVICE;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return XENG_EDEVICE;
+    const bool capturing = cap == hipStreamCaptureStatusActive;
+    if (!capturing) {
+        for (const auto &a : b->acct)
+            if (a.n > T_MAX - a.ctx->acc_t[(size_t)a.slot]) return XENG_EOVERFLOW;
+    }
+    for (const auto &l : b->launches) {
+        KernelArgs a;
+        std::memset(&a.job0, 0, sizeof a.job0);
+        a.jobs = l.d_jobs;
+        a.pieces = l.d_pieces;
+        a.wg_off = l.d_off;
+        a.zeros = b->zeros;
+        hipError_t e = launch(a, l.grid, l.dma, l.flags_and, stream);
+        if (e != hipSuccess) return map_err(e);
+    }
+    if (!capturing) (void)account_batch(b, 1);
+    return XENG_OK;
+}
+
+int xeng_batch_note_replays(xeng_batch *b, int64_t n_replays)
+{
+    if (!b || n_replays < 0) return XENG_EINVAL;
+    if (n_replays == 0) return XENG_OK;
+    return account_batch(b, n_replays);
+}
+
+int xeng_batch_destroy(xeng_batch *b)
+{
+    if (!b) return XENG_EINVAL;
+    DeviceGuard guard(b->device);
+    free_batch(b);
+    return XENG_OK;
+}
+
+int xeng_autotune(const xeng_job *jobs, int32_t n_jobs, int32_t iters, void *hip_stream, xeng_tuning *best)
+{
+    if (iters < 1 || iters > 1000) return XENG_EINVAL;
+    JobList jl;
+    int rc = validate_jobs(jobs, n_jobs, 0, &jl);
+    if (rc != XENG_OK) return rc;
+    if (jl.descs.empty()) return XENG_EINVAL;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    DeviceGuard guard(jl.device);
+    if (!guard.ok) return XENG_EDEVICE;
+
+    bool any_dma = false;
+    for (const JobDesc &jd : jl.descs) any_dma = any_dma || (jd.flags & JOB_DMA);
+    std::vector<Tuning> cands;
+    for (int ms : {1, 4, 16, 64}) {
+        if (any_dma) cands.push_back(Tuning{XENG_KERNEL_AUTO, 2, ms});
+        for (int w : {1, 2}) cands.push_back(Tuning{XENG_KERNEL_GENERAL, w, ms});
+    }
+    // the jobs' slots are scratch: zeroed before every candidate, so no
+    // accumulator wraps whatever the number of trial launches
+    auto zero_slots = [&]() -> hipError_t {
+        for (int32_t k : jl.idx) {
+            xeng_ctx *c = jobs[k].ctx;
+            hipError_t e = launch_zero(c->d_acc + (int64_t)jobs[k].slot * c->slot_i32, c->slot_i32, stream);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    Tuning best_t = cands[0];
+    float best_us = -1.0f;
+    std::lock_guard<std::mutex> lk(jl.st->mu);
+    for (const Tuning &tu : cands) {
+        if (e != hipSuccess) break;
+        const std::vector<Part> parts = split_by_kernel(jl, tu);
+        if ((e = zero_slots()) != hipSuccess) break;
+        if ((rc = run_parts(jl.st, parts, tu, stream)) != XENG_OK) break;   // warm-up, plan upload
+        if ((e = hipEventRecord(e0, stream)) != hipSuccess) break;
+        for (int it = 0; it < iters && rc == XENG_OK; ++it) rc = run_parts(jl.st, parts, tu, stream);
+        if (rc != XENG_OK) break;
+        if ((e = hipEventRecord(e1, stream)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.0f;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        const float us = 1000.0f * ms / (float)iters;
+        if (best_us < 0.0f || us < best_us) {
+            best_us = us;
+            best_t = tu;
+        }
+    }
+    if (e == hipSuccess && rc == XENG_OK) e = zero_slots();
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc != XENG_OK) return rc;
+    if (e != hipSuccess) return map_err(e);
+    for (int32_t k : jl.idx) jobs[k].ctx->acc_t[(size_t)jobs[k].slot] = 0;
+    jl.st->tuned[sizes_key(jl.pj.data(), (int)jl.pj.size())] = best_t;
+    if (best) {
+        best->kernel = best_t.kernel;
+        best->wgs_per_cu = best_t.wgs_per_cu;
+        best->min_stages = best_t.min_stages;
+        best->reserved = 0;
+        best->us_per_launch = best_us;
+    }
+    return XENG_OK;
+}
+
 int xeng_set_tuning(int32_t wgs_per_cu, int32_t min_stages, int32_t kernel)
 {
     if (wgs_per_cu > 2 || kernel > XENG_KERNEL_GENERAL) return XENG_EINVAL;
     if (wgs_per_cu > 0) g_wgs_per_cu.store(wgs_per_cu);
     if (min_stages > 0) g_min_stages.store(min_stages);
     if (kernel >= 0) g_kernel.store(kernel);
+    // explicit settings replace what the autotuner chose
+    std::lock_guard<std::mutex> lk(g_states_mu);
+    for (auto &kv : g_states) {
+        std::lock_guard<std::mutex> lk2(kv.second->mu);
+        kv.second->tuned.clear();
+    }
     return XENG_OK;
 }
 

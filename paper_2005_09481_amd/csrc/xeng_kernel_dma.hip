@@ -466,16 +466,17 @@ __global__ __launch_bounds__(256, 1) void xcorr_dma(KernelArgs args)
 
 constexpr int DMA_LDS_BYTES = dma::NSLOT * dma::SLOT;
 
+// Once per device, before any launch (and outside any stream capture): the
+// kernel's LDS ring exceeds the default dynamic-LDS limit.
+hipError_t init_dma_kernel()
+{
+    return hipFuncSetAttribute((const void *)dma::xcorr_dma, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               DMA_LDS_BYTES);
+}
+
 hipError_t launch_correlate_dma(const KernelArgs &a, int grid, hipStream_t stream)
 {
     if (grid <= 0) return hipSuccess;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)dma::xcorr_dma,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, DMA_LDS_BYTES);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
     hipLaunchKernelGGL(dma::xcorr_dma, dim3(grid), dim3(256), DMA_LDS_BYTES, stream, a);
     return hipGetLastError();
 }

@@ -44,6 +44,12 @@ class _Job(ctypes.Structure):
                 ("row_stride", ctypes.c_int64)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
+                ("min_stages", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("us_per_launch", ctypes.c_double)]
+
+
 class _PieceInfo(ctypes.Structure):
     _fields_ = [("job", ctypes.c_int32), ("ti", ctypes.c_int32), ("tj", ctypes.c_int32),
                 ("atomic", ctypes.c_int32), ("t0", ctypes.c_int64), ("t1", ctypes.c_int64),
@@ -80,6 +86,11 @@ def lib() -> ctypes.CDLL:
         "xeng_plan_inspect": (i64, [ctypes.POINTER(i32), ctypes.POINTER(i64), i32, i32, i32, i32,
                                     ctypes.POINTER(_PieceInfo), i64]),
         "xeng_set_tuning": (ctypes.c_int, [i32, i32, i32]),
+        "xeng_batch_create": (ctypes.c_int, [ctypes.POINTER(_Job), i32, ctypes.POINTER(vp)]),
+        "xeng_batch_launch": (ctypes.c_int, [vp, vp]),
+        "xeng_batch_note_replays": (ctypes.c_int, [vp, i64]),
+        "xeng_batch_destroy": (ctypes.c_int, [vp]),
+        "xeng_autotune": (ctypes.c_int, [ctypes.POINTER(_Job), i32, i32, vp, ctypes.POINTER(_Tuning)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -201,19 +212,71 @@ class Correlator:
             pass
 
 
-def correlate_batch(jobs, stream=None):
-    """One persistent launch over ``jobs`` = [(correlator, slot, samples), ...]."""
-    if not jobs:
-        return
+def _job_array(jobs):
     arr = (_Job * len(jobs))()
-    keep = []
-    dev = jobs[0][0].device
     for k, (corr, slot, samples) in enumerate(jobs):
         ptr, t, row_stride = _samples_args(samples, corr.n_inputs, corr.device)
-        keep.append(samples)
         arr[k] = _Job(corr.handle, slot, 0, ptr, t, row_stride)
-    _check(lib().xeng_correlate_batch(arr, len(jobs), _stream_handle(stream, dev)),
+    return arr
+
+
+def correlate_batch(jobs, stream=None):
+    """One persistent launch per kernel kind over ``jobs`` = [(correlator, slot, samples), ...]."""
+    if not jobs:
+        return
+    _check(lib().xeng_correlate_batch(_job_array(jobs), len(jobs),
+                                      _stream_handle(stream, jobs[0][0].device)),
            "xeng_correlate_batch")
+
+
+class Batch:
+    """Prepared batch (``xeng_batch_*``): plan and job table resident on the
+    device, launches that only enqueue kernels (graph-capturable).  The
+    sample tensors named by ``jobs`` are kept alive by the batch."""
+
+    def __init__(self, jobs):
+        self._keep = [j[2] for j in jobs] + [j[0] for j in jobs]
+        self.device = jobs[0][0].device
+        h = ctypes.c_void_p()
+        _check(lib().xeng_batch_create(_job_array(jobs), len(jobs), ctypes.byref(h)),
+               "xeng_batch_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().xeng_batch_launch(self._h, _stream_handle(stream, self.device)),
+               "xeng_batch_launch")
+
+    def note_replays(self, n: int):
+        _check(lib().xeng_batch_note_replays(self._h, n), "xeng_batch_note_replays")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().xeng_batch_destroy(self._h), "xeng_batch_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Tuning:
+    kernel: int
+    wgs_per_cu: int
+    min_stages: int
+    us_per_launch: float
+
+
+def autotune(jobs, iters: int = 5, stream=None) -> Tuning:
+    """Time the candidate launch configurations on ``jobs`` and keep the best
+    for later calls of the same job sizes.  The jobs' slots are zeroed."""
+    t = _Tuning()
+    _check(lib().xeng_autotune(_job_array(jobs), len(jobs), iters,
+                               _stream_handle(stream, jobs[0][0].device), ctypes.byref(t)),
+           "xeng_autotune")
+    return Tuning(t.kernel, t.wgs_per_cu, t.min_stages, t.us_per_launch)
 
 
 def correlate_reference(samples, n_inputs: int | None = None, re_low: bool = False, stream=None):

@@ -1,0 +1,185 @@
+"""GPU parity of batched launches: many channels and sub-arrays of uneven N
+and T in one persistent launch per kernel kind, prepared batches replayed
+from a hipGraph, and the autotuner.  Every result is compared bit for bit
+with the CPU oracle (small cases: every visibility; full-size cases: all
+pairs among sampled inputs) and with the same job launched alone."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def X():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_09481_amd import xeng
+    xeng.lib()
+    return xeng
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def alone(X, x, n=None):
+    c = X.Correlator(x.shape[1] if n is None else n, 1)
+    c.correlate(0, gpu(x))
+    v = c.dump(0)
+    c.close()
+    return v
+
+
+def sampled_pairs_equal(v, x, n, k, seed):
+    """All pairs among k sampled inputs (plus tile edges) against the oracle."""
+    rng = np.random.default_rng(seed)
+    edges = [e for e in (0, 127, 128, 255, 256, n - 1) if e < n]
+    s = np.unique(np.concatenate([rng.choice(n, min(k, n), replace=False), edges]))
+    ref = oracle.correlate(np.ascontiguousarray(x[:, s]))
+    v = v.cpu().numpy().astype(np.int64)
+    idx = [oracle.tri_index(int(s[a]), int(s[b]), n) for a in range(len(s)) for b in range(a, len(s))]
+    np.testing.assert_array_equal(v[idx], ref)
+
+
+def test_mixed_batch_matches_oracle_and_alone(X):
+    # both kernel kinds in one call: N % 256 == 0 jobs take the DMA kernel,
+    # the others the general one
+    shapes = [(256, 700), (100, 333), (512, 64), (64, 4096), (256, 1), (300, 129)]
+    print("mixed batch", shapes, flush=True)
+    xs = [synth.uniform_bytes(n, t, seed=500 + i) for i, (n, t) in enumerate(shapes)]
+    cs = [X.Correlator(n, 2) for n, _ in shapes]
+    X.correlate_batch([(c, 1, gpu(x)) for c, x in zip(cs, xs)])
+    for c, x in zip(cs, xs):
+        v = c.dump(1)
+        np.testing.assert_array_equal(v.cpu().numpy(), oracle.correlate(x))
+        assert torch.equal(v, alone(X, x))
+        assert not c.dump(0).any()      # the other slot is untouched
+        c.close()
+
+
+def test_batch_channels_reduced(X):
+    # batched channels, at N = 256: uneven T, 5% of inputs flagged
+    chans = synth.batched_channels(n_channels=16, n_inputs=256, t_lo=2048, t_hi=4096, seed=3)
+    print("batched channels n=256", [x.shape[0] for x in chans], flush=True)
+    c = X.Correlator(256, 16)
+    X.correlate_batch([(c, k, gpu(x)) for k, x in enumerate(chans)])
+    for k, x in enumerate(chans):
+        np.testing.assert_array_equal(c.dump(k).cpu().numpy(), oracle.correlate(x))
+
+
+def test_subarray_batch_reduced(X):
+    subs = synth.subarray_batch(n_instances=24, n_choices=(256, 512, 100), t_choices=(64, 500, 1024),
+                                seed=4)
+    print("subarray batch", [x.shape for x in subs], flush=True)
+    cs = [X.Correlator(x.shape[1], 1) for x in subs]
+    X.correlate_batch([(c, 0, gpu(x)) for c, x in zip(cs, subs)])
+    for c, x in zip(cs, subs):
+        np.testing.assert_array_equal(c.dump(0).cpu().numpy(), oracle.correlate(x))
+        c.close()
+
+
+def test_batch_channels_full_size(X):
+    # 16 channels x N = 2048, T uniform in [2048, 16384], 5% flagged: one
+    # batched launch against 16 launches alone (bit-exact) and the oracle on
+    # sampled pairs; flagged inputs give zero rows and columns
+    chans = synth.batched_channels(n_channels=16, n_inputs=2048, seed=3)
+    print("batched channels full size", [x.shape[0] for x in chans], flush=True)
+    c = X.Correlator(2048, 16)
+    X.correlate_batch([(c, k, gpu(x)) for k, x in enumerate(chans)])
+    n = 2048
+    for k, x in enumerate(chans):
+        v = c.dump(k)
+        assert torch.equal(v, alone(X, x))
+        sampled_pairs_equal(v, x, n, 24, seed=k)
+        flagged = np.where((x == 0x88).all(axis=0))[0]
+        assert len(flagged) >= 102
+        i = int(flagged[0])
+        row = [oracle.tri_index(min(i, j), max(i, j), n) for j in range(n)]
+        assert not v[row].any()
+
+
+def test_subarray_batch_full_size(X):
+    subs = synth.subarray_batch(n_instances=64, seed=4)
+    print("subarray batch full size", sum(x.nbytes for x in subs) / 1e6, "MB", flush=True)
+    cs = [X.Correlator(x.shape[1], 1) for x in subs]
+    X.correlate_batch([(c, 0, gpu(x)) for c, x in zip(cs, subs)])
+    for k, (c, x) in enumerate(zip(cs, subs)):
+        v = c.dump(0)
+        assert torch.equal(v, alone(X, x))
+        sampled_pairs_equal(v, x, x.shape[1], 16, seed=100 + k)
+        c.close()
+
+
+def test_batch_rejects_bad_jobs(X):
+    c = X.Correlator(64, 2)
+    x = gpu(synth.uniform_bytes(64, 10, seed=1))
+    with pytest.raises(X.XengError) as e:
+        X.correlate_batch([(c, 0, x), (c, 0, x)])          # same slot twice
+    assert e.value.status == X.XENG_EINVAL
+    big = torch.zeros((X.max_integration(), 64), dtype=torch.uint8, device="cuda")
+    X.correlate_batch([(c, 1, big)])
+    with pytest.raises(X.XengError) as e:
+        X.correlate_batch([(c, 0, x), (c, 1, x)])          # slot 1 would overflow
+    assert e.value.status == X.XENG_EOVERFLOW
+    assert c.samples_integrated(0) == 0                     # nothing queued
+    del big
+    c.close()
+
+
+def test_prepared_batch_graph_replays(X):
+    # a prepared batch captured in a hipGraph: every replay integrates the
+    # jobs again; each replay is checked against the oracle, with eager work
+    # and synchronizations between replays
+    shapes = [(256, 300), (512, 129), (100, 77)]
+    xs = [synth.uniform_bytes(n, t, seed=900 + i) for i, (n, t) in enumerate(shapes)]
+    refs = [oracle.correlate(x) for x in xs]
+    cs = [X.Correlator(n, 1) for n, _ in shapes]
+    bufs = [gpu(x) for x in xs]
+    b = X.Batch([(c, 0, t) for c, t in zip(cs, bufs)])
+    b.launch()                                              # eager launch
+    for c, r in zip(cs, refs):
+        np.testing.assert_array_equal(c.dump(0, reset=False).cpu().numpy(), r)
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.launch(stream=s)
+    assert [c.samples_integrated(0) for c in cs] == [t for _, t in shapes]   # capture adds nothing
+    other = X.Correlator(64, 1)
+    y = gpu(synth.uniform_bytes(64, 100, seed=3))
+    for rep in range(1, 4):
+        b.note_replays(1)
+        g.replay()
+        torch.cuda.synchronize()
+        for c, r in zip(cs, refs):
+            np.testing.assert_array_equal(c.dump(0, reset=False).cpu().numpy(), (rep + 1) * r)
+        other.correlate(0, y)                               # eager work between replays
+        torch.cuda.synchronize()
+    assert [c.samples_integrated(0) for c in cs] == [4 * t for _, t in shapes]
+    b.close()
+    for c in cs:
+        c.close()
+
+
+def test_autotune_keeps_results(X):
+    shapes = [(512, 2000), (256, 3000), (128, 1000)]
+    xs = [synth.uniform_bytes(n, t, seed=700 + i) for i, (n, t) in enumerate(shapes)]
+    cs = [X.Correlator(n, 1) for n, _ in shapes]
+    jobs = [(c, 0, gpu(x)) for c, x in zip(cs, xs)]
+    try:
+        best = X.autotune(jobs, iters=2)
+        print("autotuned", best, flush=True)
+        assert best.kernel in (X.XENG_KERNEL_AUTO, X.XENG_KERNEL_GENERAL)
+        assert best.wgs_per_cu in (1, 2) and best.min_stages >= 1 and best.us_per_launch > 0
+        assert all(c.samples_integrated(0) == 0 for c in cs)
+        assert all(not c.dump(0).any() for c in cs)          # scratch slots left zeroed
+        X.correlate_batch(jobs)                               # now with the tuned configuration
+        for c, x in zip(cs, xs):
+            np.testing.assert_array_equal(c.dump(0).cpu().numpy(), oracle.correlate(x))
+    finally:
+        X.set_tuning(2, 4, X.XENG_KERNEL_AUTO)                # defaults; drops the tuned entry
+        for c in cs:
+            c.close()
