@@ -50,6 +50,132 @@ def cpu_baseline(x, n, target_s=12.0):
                       f"({t_s * tri:.3e} CMAC in {dt:.1f} s)"}
 
 
+def bench_serve(args, xeng, synth, torch, np):
+    """Streaming: K channels of N=2048 each release a 256-sample frame every
+    655.36 us (390625 samples/s); exports every 128 frames (83.886 ms).  K is
+    real-time when every released frame is integrated (no drops, no growing
+    backlog) and the p99 frame latency stays below the export period."""
+    n, frame_len, dump = 2048, 256, 128
+    period_ms = dump * frame_len / 390625 * 1e3
+    n_src = 16                                   # distinct frames per channel (8 MiB), cycled
+    base = synth.stream_frames(n, n_src, seed=5)
+    results = []
+
+    def trial(k, host):
+        srv = xeng.Server(n, max_channels=k, dump_frames=dump, launch_period_us=4000.0,
+                          ring_frames=64, max_inflight=2)
+        srcs = []
+        for c in range(k):
+            f = torch.from_numpy(np.roll(base, c, axis=2).copy())     # distinct bytes per channel
+            f = f.pin_memory() if host else f.cuda()
+            srcs.append(f)
+            srv.admit(f, start_s=0.05 + 655.36e-6 * c / k)
+        st = srv.run(args.serve_seconds)
+        srv.close()
+        # real time: nothing dropped, p99 below the export period, and the
+        # frames still queued at the end no more than arrive within the p99
+        # latency plus two launch periods (a server that falls behind sees
+        # its latency grow past the export period within the run)
+        frame_ms = 655.36e-3
+        ok = (st["frames_dropped"] == 0 and st["p99_ms"] < period_ms and
+              st["backlog_frames"] <= k * (st["p99_ms"] + 2 * 4.0) / frame_ms)
+        r = {"k": k, "source": "host" if host else "device", "real_time": bool(ok),
+             "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+             "max_ms": round(st["max_ms"], 3), "tcmacs": round(st["tcmacs"], 2),
+             "frames_done": st["frames_done"], "dropped": st["frames_dropped"],
+             "backlog": st["backlog_frames"], "launches": st["launches"], "dumps": st["dumps"]}
+        print(json.dumps(r), flush=True)
+        return r
+
+    for host, ks in ((False, args.serve_k), (True, args.serve_host_k)):
+        for k in [int(v) for v in ks.split(",") if int(v) > 0]:
+            r = trial(k, host)
+            results.append(r)
+            if not r["real_time"]:
+                break
+    best = {src: max([r["k"] for r in results if r["source"] == src and r["real_time"]], default=0)
+            for src in ("device", "host")}
+    rt = [r for r in results if r["real_time"] and r["source"] == "device"]
+    res = {"metric": "real-time channels/GPU, p99 latency", "value": best["device"],
+           "unit": "channels (N=2048, 390625 samples/s)", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "int8", "data": "synthetic",
+           "config": {"workload": "streaming serve, N=2048, 256-sample frames, export every 128 frames",
+                      "seconds_per_trial": args.serve_seconds},
+           "max_k_host_frames": best["host"],
+           "p99_ms_at_max_k": rt[-1]["p99_ms"] if rt else None,
+           "export_period_ms": round(period_ms, 3)}
+    print(json.dumps(res), flush=True)
+
+
+def bench_batch(args, xeng, synth, torch, np):
+    """Many jobs in one persistent launch (and as a prepared batch replayed
+    from a hipGraph) against the same jobs launched one by one."""
+    if args.workload == "channels16":
+        xs = synth.batched_channels(n_channels=16, n_inputs=2048, seed=3)
+        label = "16 channels x N=2048, T uniform in [2048,16384], 5% of inputs flagged"
+    else:
+        xs = synth.subarray_batch(n_instances=64, seed=4)
+        label = "64 sub-arrays, N in {256,512,1024,2048}, T in {4096,8192,16384}"
+    dev = torch.device("cuda:0")
+    bufs = [torch.from_numpy(x).to(dev) for x in xs]
+    cs = [xeng.Correlator(x.shape[1], 1, device=0) for x in xs]
+    jobs = [(c, 0, b) for c, b in zip(cs, bufs)]
+    cmac = sum(x.shape[0] * x.shape[1] * (x.shape[1] + 1) // 2 for x in xs)
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn, reps):
+        for c in cs:
+            c.reset(0)
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        times = []
+        for _ in range(reps):
+            for c in cs:
+                c.reset(0)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b) / 1e3)
+        return float(np.median(times))
+
+    def plain():
+        for c, b in zip(cs, bufs):
+            c.correlate(0, b, stream=stream)
+
+    def batched():
+        xeng.correlate_batch(jobs, stream=stream)
+
+    t_settle = time.perf_counter() + args.settle_ms / 1e3
+    while time.perf_counter() < t_settle:
+        batched()
+        torch.cuda.synchronize()
+        for c in cs:
+            c.reset(0)
+    t_plain = timed(plain, args.steps)
+    t_batch = timed(batched, args.steps)
+    prepared = xeng.Batch(jobs)
+    t_prep = timed(lambda: prepared.launch(stream=stream), args.steps)
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.graph(g, stream=side):
+        prepared.launch(stream=side)
+    t_graph = timed(g.replay, args.steps)
+    res = {
+        "metric": "Tera-CMAC/s, batched persistent launch vs per-job launches",
+        "value": round(cmac / t_batch / 1e12, 3), "unit": "TCMAC/s", "n_gpus": 1,
+        "steps": args.steps, "higher_is_better": True, "dtype": "int8", "data": "synthetic",
+        "config": {"workload": label, "jobs": len(xs), "cmac": cmac},
+        "batched_ms": round(t_batch * 1e3, 4), "plain_ms": round(t_plain * 1e3, 4),
+        "prepared_ms": round(t_prep * 1e3, 4), "graph_replay_ms": round(t_graph * 1e3, 4),
+        "plain_tcmacs": round(cmac / t_plain / 1e12, 3),
+        "graph_tcmacs": round(cmac / t_graph / 1e12, 3),
+        "speedup_vs_plain": round(t_plain / t_batch, 3),
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +187,15 @@ def main():
                     help="untimed steps for this long before the warm-up steps (clock ramp)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--workload", default="channel", choices=["channel", "channels16", "subarrays64", "serve"],
+                    help="channel: the one-channel step (default, the JSON contract line); "
+                         "channels16 / subarrays64: batched launches against plain launches; "
+                         "serve: streaming channels, largest real-time K")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-k", default="128,192,224,256,288,320,352",
+                    help="channel counts to try (device-sourced frames)")
+    ap.add_argument("--serve-host-k", default="16,32,48,64",
+                    help="channel counts to try with pinned-host frames (0 to skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB "
                          "(reference kernel for scaling hardware byte counters)")
@@ -77,6 +212,11 @@ def main():
 
     import synth
     from paper_2005_09481_amd import xeng
+
+    if args.workload == "serve":
+        return bench_serve(args, xeng, synth, torch, np)
+    if args.workload != "channel":
+        return bench_batch(args, xeng, synth, torch, np)
 
     n, t = args.n, args.t
     tri = n * (n + 1) // 2

@@ -232,6 +232,78 @@ typedef struct {
 int xeng_autotune(const xeng_job *jobs, int32_t n_jobs, int32_t iters, void *hip_stream,
                   xeng_tuning *best);
 
+/*
+ * Streaming server (Sec. 2.1: every channel delivers a sample every 2.56 us
+ * and its integrated visibilities are exported at a chosen cadence).
+ * Channels of N inputs ingest frames of frame_len samples every
+ * frame_period_us; the server keeps their accumulators on the device,
+ * correlates every channel's newly arrived frames in one batched launch
+ * about every launch_period_us (continuous batching: frames that arrive
+ * while launches run join the next one), and exports each channel every
+ * dump_frames frames into a device buffer of its own.
+ */
+typedef struct xeng_server xeng_server;
+typedef struct {
+    int32_t n_inputs;         /* N of every channel */
+    int32_t device;
+    uint32_t flags;           /* XENG_NIBBLE_RE_LOW or 0 */
+    int32_t frame_len;        /* samples per frame (CHIME-shaped: 256) */
+    int32_t dump_frames;      /* frames per export; frame_len * dump_frames <= xeng_max_integration() */
+    int32_t ring_frames;      /* device ring of a host-sourced channel, in frames */
+    int32_t max_inflight;     /* batched launches queued on the device at once, >= 1 */
+    int32_t max_channels;     /* slots; 0 = as many as mem_budget_bytes admits */
+    double frame_period_us;   /* frame cadence per channel (256 samples at 390625/s: 655.36) */
+    double launch_period_us;  /* batching period */
+    int64_t mem_budget_bytes; /* device bytes for channels (0 = none): admission by memory */
+    int32_t reserved;         /* must be 0 */
+} xeng_server_config;
+
+typedef struct {
+    int64_t frames_released;  /* frames whose release time passed during the run */
+    int64_t frames_done;      /* frames integrated */
+    int64_t frames_dropped;   /* host-sourced frames lost to a full ingest ring */
+    int64_t launches;
+    int64_t dumps;
+    int64_t backlog_frames;   /* released, not dropped, not yet integrated at the end */
+    double seconds;           /* wall time of the run */
+    double tcmacs;            /* integrated CMAC / wall time, 1e12/s */
+    double p50_ms, p99_ms, max_ms;   /* frame latency: release -> its launch completed */
+} xeng_server_stats;
+
+typedef struct {
+    int32_t state;            /* 0 waiting for a slot, 1 streaming, 2 finished */
+    int32_t slot;
+    int64_t frames_done;
+    int64_t dumps;
+    int64_t last_dump_first_frame;   /* first frame of the last export, -1 if none */
+} xeng_server_channel;
+
+/* Create a server; XENG_ENOMEM if not even one channel fits the budget. */
+int xeng_server_create(const xeng_server_config *cfg, xeng_server **out);
+int xeng_server_destroy(xeng_server *s);
+/* Slots of the server (channels streaming at once). */
+int32_t xeng_server_max_channels(const xeng_server *s);
+/*
+ * Admit a channel.  Its frames come from `frames`, [n_frames][frame_len][N]
+ * bytes, frame f being frames[f % n_frames]: device memory read in place, or
+ * (host_frames = 1) pinned host memory copied into the channel's device
+ * ring on release.  Caller-owned; must outlive the server.  Frame 0 is
+ * released start_s seconds into the next run; total_frames frames (0 =
+ * unlimited) are streamed.  With every slot in use the channel waits and
+ * takes the first slot freed by a finished channel (its stream then starts).
+ */
+int xeng_server_admit(xeng_server *s, const uint8_t *frames, int64_t n_frames, int32_t host_frames,
+                      double start_s, int64_t total_frames, int32_t *channel);
+/* Run the real-time loop for `seconds`, then wait for queued work; fills `stats`. */
+int xeng_server_run(xeng_server *s, double seconds, xeng_server_stats *stats);
+int xeng_server_channel_info(const xeng_server *s, int32_t channel, xeng_server_channel *info);
+/*
+ * Copy a channel's last export (int32 [N(N+1)/2][2], the frames
+ * [last_dump_first_frame, + dump_frames)) to `out` (device or host memory,
+ * synchronous).  XENG_EBUSY if its slot has since passed to another channel.
+ */
+int xeng_server_last_dump(xeng_server *s, int32_t channel, int32_t *out);
+
 /* Kernel selection for xeng_set_tuning. */
 #define XENG_KERNEL_AUTO 0     /* wide DMA kernel where the job allows it, else general */
 #define XENG_KERNEL_GENERAL 1  /* always the general kernel */

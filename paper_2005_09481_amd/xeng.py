@@ -50,6 +50,28 @@ class _Tuning(ctypes.Structure):
                 ("us_per_launch", ctypes.c_double)]
 
 
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("n_inputs", ctypes.c_int32), ("device", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("frame_len", ctypes.c_int32), ("dump_frames", ctypes.c_int32),
+                ("ring_frames", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("max_channels", ctypes.c_int32), ("frame_period_us", ctypes.c_double),
+                ("launch_period_us", ctypes.c_double), ("mem_budget_bytes", ctypes.c_int64),
+                ("reserved", ctypes.c_int32)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("frames_released", ctypes.c_int64), ("frames_done", ctypes.c_int64),
+                ("frames_dropped", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("dumps", ctypes.c_int64), ("backlog_frames", ctypes.c_int64),
+                ("seconds", ctypes.c_double), ("tcmacs", ctypes.c_double),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
+
+
+class _ServerChannel(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("slot", ctypes.c_int32), ("frames_done", ctypes.c_int64),
+                ("dumps", ctypes.c_int64), ("last_dump_first_frame", ctypes.c_int64)]
+
+
 class _PieceInfo(ctypes.Structure):
     _fields_ = [("job", ctypes.c_int32), ("ti", ctypes.c_int32), ("tj", ctypes.c_int32),
                 ("atomic", ctypes.c_int32), ("t0", ctypes.c_int64), ("t1", ctypes.c_int64),
@@ -91,6 +113,14 @@ def lib() -> ctypes.CDLL:
         "xeng_batch_note_replays": (ctypes.c_int, [vp, i64]),
         "xeng_batch_destroy": (ctypes.c_int, [vp]),
         "xeng_autotune": (ctypes.c_int, [ctypes.POINTER(_Job), i32, i32, vp, ctypes.POINTER(_Tuning)]),
+        "xeng_server_create": (ctypes.c_int, [ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]),
+        "xeng_server_destroy": (ctypes.c_int, [vp]),
+        "xeng_server_max_channels": (i32, [vp]),
+        "xeng_server_admit": (ctypes.c_int, [vp, vp, i64, i32, ctypes.c_double, i64,
+                                             ctypes.POINTER(i32)]),
+        "xeng_server_run": (ctypes.c_int, [vp, ctypes.c_double, ctypes.POINTER(_ServerStats)]),
+        "xeng_server_channel_info": (ctypes.c_int, [vp, i32, ctypes.POINTER(_ServerChannel)]),
+        "xeng_server_last_dump": (ctypes.c_int, [vp, i32, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -318,3 +348,70 @@ def plan_inspect(n_inputs, n_samples, n_workgroups: int, min_stages: int = 0, wi
     assert cnt2 == cnt
     return [PieceInfo(p.job, p.ti, p.tj, bool(p.atomic), p.t0, p.t1, p.workgroup, p.n_tiles)
             for p in out[:cnt]]
+
+
+class Server:
+    """Streaming server (``xeng_server_*``): channels of N inputs ingest
+    frames at a fixed cadence; one batched launch about every
+    ``launch_period_us`` integrates every channel's new frames; each channel
+    is exported every ``dump_frames`` frames."""
+
+    def __init__(self, n_inputs: int, device: int = 0, frame_len: int = 256, dump_frames: int = 128,
+                 ring_frames: int = 64, max_inflight: int = 2, max_channels: int = 0,
+                 frame_period_us: float = 655.36, launch_period_us: float = 5000.0,
+                 mem_budget_bytes: int = 0, re_low: bool = False):
+        cfg = _ServerConfig(n_inputs, device, XENG_NIBBLE_RE_LOW if re_low else 0, frame_len,
+                            dump_frames, ring_frames, max_inflight, max_channels, frame_period_us,
+                            launch_period_us, mem_budget_bytes, 0)
+        h = ctypes.c_void_p()
+        _check(lib().xeng_server_create(ctypes.byref(cfg), ctypes.byref(h)), "xeng_server_create")
+        self._h = h
+        self.n_inputs, self.device, self.frame_len = n_inputs, device, frame_len
+        self._keep = []
+
+    @property
+    def max_channels(self) -> int:
+        return int(lib().xeng_server_max_channels(self._h))
+
+    def admit(self, frames, start_s: float = 0.0, total_frames: int = 0) -> int:
+        """``frames``: uint8 [F][frame_len][N], on the device or in pinned host memory."""
+        import torch
+        if frames.dtype != torch.uint8 or frames.dim() != 3 or not frames.is_contiguous() or \
+                frames.shape[1] != self.frame_len or frames.shape[2] != self.n_inputs:
+            raise ValueError("frames must be contiguous uint8 [F][frame_len][N]")
+        host = 0 if frames.is_cuda else 1
+        if host and not frames.is_pinned():
+            raise ValueError("host frames must be in pinned memory")
+        ch = ctypes.c_int32()
+        _check(lib().xeng_server_admit(self._h, ctypes.c_void_p(frames.data_ptr()), frames.shape[0], host,
+                                       start_s, total_frames, ctypes.byref(ch)), "xeng_server_admit")
+        self._keep.append(frames)
+        return ch.value
+
+    def run(self, seconds: float) -> dict:
+        st = _ServerStats()
+        _check(lib().xeng_server_run(self._h, seconds, ctypes.byref(st)), "xeng_server_run")
+        return {f: getattr(st, f) for f, _ in _ServerStats._fields_}
+
+    def channel_info(self, channel: int) -> dict:
+        ci = _ServerChannel()
+        _check(lib().xeng_server_channel_info(self._h, channel, ctypes.byref(ci)), "xeng_server_channel_info")
+        return {f: getattr(ci, f) for f, _ in _ServerChannel._fields_}
+
+    def last_dump(self, channel: int):
+        import torch
+        out = torch.empty((tri(self.n_inputs), 2), dtype=torch.int32, device=f"cuda:{self.device}")
+        _check(lib().xeng_server_last_dump(self._h, channel, ctypes.c_void_p(out.data_ptr())),
+               "xeng_server_last_dump")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().xeng_server_destroy(self._h), "xeng_server_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,110 @@
+"""GPU tests of the streaming server: real-time frame releases, continuous
+batching over channels, admission as slots free up, exports every
+dump_frames frames.  Each export is compared bit for bit with the oracle on
+the frames it covers, and with the same channel served alone."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N = 256
+DUMP = 32          # frames per export (32 x 256 samples): several exports per run
+
+
+@pytest.fixture(scope="module")
+def X():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_09481_amd import xeng
+    xeng.lib()
+    return xeng
+
+
+def frames_of(seed, n_frames=48, n=N):
+    return synth.stream_frames(n, n_frames, seed=seed)
+
+
+def expected(frames, first, count=DUMP):
+    """Oracle over frames [first, first + count) of a cyclic source."""
+    f = frames[[(first + k) % frames.shape[0] for k in range(count)]]
+    return oracle.correlate(f.reshape(-1, frames.shape[2]))
+
+
+def test_exports_match_oracle_and_alone(X):
+    srcs = [frames_of(seed=[5, c]) for c in range(4)]
+    srv = X.Server(N, dump_frames=DUMP, max_channels=4, launch_period_us=2000.0)
+    chans = [srv.admit(torch.from_numpy(f).cuda(), start_s=0.002 * c, total_frames=3 * DUMP)
+             for c, f in enumerate(srcs)]
+    st = srv.run(0.4)
+    print("serve 4 channels", st, flush=True)
+    assert st["frames_done"] == 4 * 3 * DUMP and st["frames_dropped"] == 0 and st["dumps"] == 12
+    assert st["p99_ms"] > 0
+    got = []
+    for c, f in zip(chans, srcs):
+        info = srv.channel_info(c)
+        assert info["state"] == 2 and info["dumps"] == 3 and info["last_dump_first_frame"] == 2 * DUMP
+        v = srv.last_dump(c)
+        np.testing.assert_array_equal(v.cpu().numpy(), expected(f, 2 * DUMP))
+        got.append(v)
+    srv.close()
+    # channel 0 alone gives the same export
+    solo = X.Server(N, dump_frames=DUMP, max_channels=1, launch_period_us=2000.0)
+    c0 = solo.admit(torch.from_numpy(srcs[0]).cuda(), total_frames=3 * DUMP)
+    solo.run(0.2)
+    assert torch.equal(solo.last_dump(c0), got[0])
+    solo.close()
+
+
+def test_admission_waits_for_a_free_slot(X):
+    # three channels, two slots: the third is admitted when one finishes
+    srcs = [frames_of(seed=[6, c]) for c in range(3)]
+    srv = X.Server(N, dump_frames=DUMP, max_channels=2, launch_period_us=2000.0)
+    chans = [srv.admit(torch.from_numpy(f).cuda(), total_frames=2 * DUMP) for f in srcs]
+    assert srv.channel_info(chans[2])["state"] == 0
+    st = srv.run(0.4)
+    print("admission", st, flush=True)
+    assert st["frames_done"] == 3 * 2 * DUMP
+    infos = [srv.channel_info(c) for c in chans]
+    assert all(i["state"] == 2 and i["dumps"] == 2 for i in infos)
+    reused = infos[2]["slot"]
+    for c, f, i in zip(chans, srcs, infos):
+        if c != chans[2] and i["slot"] == reused:
+            with pytest.raises(X.XengError) as e:      # its slot went to channel 2
+                srv.last_dump(c)
+            assert e.value.status == X.XENG_EBUSY
+            continue
+        np.testing.assert_array_equal(srv.last_dump(c).cpu().numpy(), expected(f, DUMP))
+    srv.close()
+
+
+def test_host_sourced_frames(X):
+    # pinned host frames, copied into each channel's device ring on release
+    srcs = [frames_of(seed=[7, c], n_frames=40) for c in range(2)]
+    srv = X.Server(N, dump_frames=DUMP, max_channels=2, ring_frames=16, launch_period_us=2000.0)
+    hosts = [torch.from_numpy(f).pin_memory() for f in srcs]
+    chans = [srv.admit(h, start_s=0.001 * c, total_frames=2 * DUMP) for c, h in enumerate(hosts)]
+    st = srv.run(0.3)
+    print("host frames", st, flush=True)
+    assert st["frames_dropped"] == 0 and st["frames_done"] == 2 * 2 * DUMP
+    for c, f in zip(chans, srcs):
+        np.testing.assert_array_equal(srv.last_dump(c).cpu().numpy(), expected(f, DUMP))
+    srv.close()
+
+
+def test_server_argument_checks(X):
+    with pytest.raises(X.XengError) as e:
+        X.Server(N, dump_frames=0, max_channels=1)
+    assert e.value.status == X.XENG_EINVAL
+    with pytest.raises(X.XengError) as e:
+        X.Server(N, max_channels=0, mem_budget_bytes=1000)          # not one channel fits
+    assert e.value.status == X.XENG_ENOMEM
+    srv = X.Server(2048, max_channels=0, mem_budget_bytes=3 * (X.slot_bytes(2048) + 2048 * 2049 * 4
+                                                              + 64 * 256 * 2048))
+    assert srv.max_channels == 3                                   # admission by memory
+    with pytest.raises(ValueError):
+        srv.admit(torch.zeros((4, 256, 100), dtype=torch.uint8, device="cuda"))
+    srv.close()
