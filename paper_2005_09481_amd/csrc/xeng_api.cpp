@@ -257,7 +257,10 @@ namespace {
 
 bool slot_ok(const xeng_ctx *c, int32_t slot) { return c && slot >= 0 && slot < c->n_slots; }
 
-JobDesc make_job(const xeng_ctx *c, int32_t slot, const uint8_t *d_samples, int64_t stride)
+// `may_store`: the launch runs once (not a prepared batch), so a slot that
+// holds zeros (nothing integrated since its last reset) may be written by
+// plain stores.
+JobDesc make_job(const xeng_ctx *c, int32_t slot, const uint8_t *d_samples, int64_t stride, bool may_store)
 {
     JobDesc jd;
     jd.samples = d_samples;
@@ -270,6 +273,7 @@ JobDesc make_job(const xeng_ctx *c, int32_t slot, const uint8_t *d_samples, int6
     const uintptr_t addr = reinterpret_cast<uintptr_t>(d_samples);
     if ((stride % 8) == 0 && (addr % 8) == 0 && c->n % 8 == 0) jd.flags |= JOB_ALIGNED8;
     if ((stride % 16) == 0 && (addr % 16) == 0 && c->n % 256 == 0) jd.flags |= JOB_DMA;
+    if (may_store && c->acc_t[(size_t)slot] == 0) jd.flags |= JOB_FRESH;
     jd.pad = 0;
     return jd;
 }
@@ -294,7 +298,7 @@ struct JobList {
 
 // Argument checks shared by the batched calls.  `launches` > 0 also applies
 // the integration guard for that many launches of every job.
-int validate_jobs(const xeng_job *jobs, int32_t n_jobs, int64_t launches, JobList *out)
+int validate_jobs(const xeng_job *jobs, int32_t n_jobs, int64_t launches, bool may_store, JobList *out)
 {
     if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return XENG_EINVAL;
     if (n_jobs == 0) return XENG_OK;
@@ -318,7 +322,7 @@ int validate_jobs(const xeng_job *jobs, int32_t n_jobs, int64_t launches, JobLis
     for (int32_t k = 0; k < n_jobs; ++k) {
         if (jobs[k].n_samples == 0) continue;
         out->pj.push_back(PlanJob{jobs[k].ctx->n, jobs[k].n_samples});
-        out->descs.push_back(make_job(jobs[k].ctx, jobs[k].slot, jobs[k].d_samples, jobs[k].row_stride));
+        out->descs.push_back(make_job(jobs[k].ctx, jobs[k].slot, jobs[k].d_samples, jobs[k].row_stride, may_store));
         out->idx.push_back(k);
     }
     return XENG_OK;
@@ -483,7 +487,7 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_
     PlanJob pj{ctx->n, n_samples};
     DevicePlan dp;
     KernelArgs a;
-    a.job0 = make_job(ctx, slot, d_samples, row_stride);
+    a.job0 = make_job(ctx, slot, d_samples, row_stride, true);
     a.jobs = nullptr;
     a.zeros = ctx->st->d_zeros;
     // held through the launch so that no other thread evicts the plan first
@@ -503,7 +507,7 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_
 int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
 {
     JobList jl;
-    int rc = validate_jobs(jobs, n_jobs, 1, &jl);
+    int rc = validate_jobs(jobs, n_jobs, 1, true, &jl);
     if (rc != XENG_OK || jl.descs.empty()) return rc;
     DeviceGuard guard(jl.device);
     if (!guard.ok) return XENG_EDEVICE;
@@ -646,7 +650,7 @@ int xeng_batch_create(const xeng_job *jobs, int32_t n_jobs, xeng_batch **out)
     if (!out) return XENG_EINVAL;
     *out = nullptr;
     JobList jl;
-    int rc = validate_jobs(jobs, n_jobs, 0, &jl);
+    int rc = validate_jobs(jobs, n_jobs, 0, false, &jl);
     if (rc != XENG_OK) return rc;
     if (n_jobs == 0) return XENG_EINVAL;
     auto *b = new (std::nothrow) xeng_batch;
@@ -741,7 +745,7 @@ int xeng_autotune(const xeng_job *jobs, int32_t n_jobs, int32_t iters, void *hip
 {
     if (iters < 1 || iters > 1000) return XENG_EINVAL;
     JobList jl;
-    int rc = validate_jobs(jobs, n_jobs, 0, &jl);
+    int rc = validate_jobs(jobs, n_jobs, 0, false, &jl);
     if (rc != XENG_OK) return rc;
     if (jl.descs.empty()) return XENG_EINVAL;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);

@@ -370,24 +370,43 @@ __device__ __forceinline__ void run_piece(Acc &acc, uint32_t ring, const Tile &t
 }
 
 // Accumulators hold 256x the stored values (both operands carry 16x the
-// sample parts), so the flush adds acc >> 8; every value is a multiple of
-// 256, so this is exact.
-__device__ __forceinline__ void flush_block(int32_t *blk_, const v16i &re, const v16i &im, bool atomic)
+// sample parts), so a flush adds acc >> 8; every value is a multiple of
+// 256, so this is exact.  A tile shared with other pieces takes atomic adds.
+__device__ __forceinline__ void flush_atomic(gi32 *blk, const v16i &re, const v16i &im)
 {
-    gi32 *blk = (gi32 *)blk_;
-    if (atomic) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            __hip_atomic_fetch_add(blk + r * 64, re[r] >> 8, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(blk + 1024 + r * 64, im[r] >> 8, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-    } else {
+    for (int r = 0; r < 16; ++r) {
+        __hip_atomic_fetch_add(blk + r * 64, re[r] >> 8, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(blk + 1024 + r * 64, im[r] >> 8, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Whole-tile flush of one wave's 2 x 4 blocks: stores if the slot holds
+// zeros, else read-modify-write with the loads of four blocks issued
+// together (one memory latency per four blocks, not one per value).
+__device__ __forceinline__ void flush_owned(gi32 *tb, const Acc &acc, int wa, bool fresh)
+{
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            blk[r * 64] += re[r] >> 8;
-            blk[1024 + r * 64] += im[r] >> 8;
-        }
+    for (int a = 0; a < 2; ++a) {
+        gi32 *blk[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) blk[b] = tb + ((2 * wa + a) * BLKS + b) * BLOCK_I32;
+        int32_t old_re[4][16], old_im[4][16];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                old_re[b][r] = fresh ? 0 : blk[b][r * 64];
+                old_im[b][r] = fresh ? 0 : blk[b][1024 + r * 64];
+            }
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                blk[b][r * 64] = old_re[b][r] + (acc.re[a][b][r] >> 8);
+                blk[b][1024 + r * 64] = old_im[b][r] + (acc.im[a][b][r] >> 8);
+            }
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -448,16 +467,21 @@ __global__ __launch_bounds__(256, 1) void xcorr_dma(KernelArgs args)
 
         if (valid) {
             const int64_t tile_idx = (int64_t)ti * jd.nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);
-            int32_t *tb = jd.acc + tile_idx * TILE_I32 + lane;
+            gi32 *tb = (gi32 *)(jd.acc + tile_idx * TILE_I32 + lane);
+            if (atomic) {
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+                for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    flush_block(tb + ((2 * wa + a) * BLKS + b) * BLOCK_I32, acc.re[a][b], acc.im[a][b],
-                                atomic);
-                    // one block at a time: keeps the register file for the main loop
-                    __builtin_amdgcn_sched_barrier(0);
-                }
+                    for (int b = 0; b < 4; ++b) {
+                        flush_atomic(tb + ((2 * wa + a) * BLKS + b) * BLOCK_I32, acc.re[a][b], acc.im[a][b]);
+                        // one block at a time: keeps the register file for the main loop
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+            } else if (jd.flags & JOB_FRESH) {
+                flush_owned(tb, acc, wa, true);
+            } else {
+                flush_owned(tb, acc, wa, false);
+            }
         }
     }
 }

@@ -220,24 +220,13 @@ __device__ __forceinline__ v4i lds128(const uint8_t *p) { return *(const v4i *)p
 
 // Accumulators hold 16x the stored values (B operands are scaled by 16), so
 // the flush adds acc >> 4; every value is a multiple of 16, so this is exact.
-__device__ __forceinline__ void flush_block(int32_t *blk_, const v16i &re, const v16i &im,
-                                            bool atomic)
+__device__ __forceinline__ void flush_block(int32_t *blk_, const v16i &re, const v16i &im)
 {
     gi32 *blk = (gi32 *)blk_;
-    if (atomic) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            __hip_atomic_fetch_add(blk + r * 64, re[r] >> 4, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(blk + 1024 + r * 64, im[r] >> 4, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-    } else {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            blk[r * 64] += re[r] >> 4;
-            blk[1024 + r * 64] += im[r] >> 4;
-        }
+    for (int r = 0; r < 16; ++r) {
+        __hip_atomic_fetch_add(blk + r * 64, re[r] >> 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(blk + 1024 + r * 64, im[r] >> 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -245,6 +234,35 @@ struct Acc {
     v16i re[2][2];
     v16i im[2][2];
 };
+
+// Whole-tile flush of one wave's 2 x 2 blocks: stores if the slot holds
+// zeros, else read-modify-write with the loads of two blocks issued before
+// their stores (one memory latency per two blocks, not one per value).
+__device__ __forceinline__ void flush_owned(int32_t *tb, const Acc &acc, int wa, int wb, bool fresh)
+{
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        gi32 *blk[2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) blk[b] = (gi32 *)(tb + ((2 * wa + a) * BLKS + (2 * wb + b)) * BLOCK_I32);
+        int32_t old_re[2][16], old_im[2][16];
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                old_re[b][r] = fresh ? 0 : blk[b][r * 64];
+                old_im[b][r] = fresh ? 0 : blk[b][1024 + r * 64];
+            }
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                blk[b][r * 64] = old_re[b][r] + (acc.re[a][b][r] >> 4);
+                blk[b][1024 + r * 64] = old_im[b][r] + (acc.im[a][b][r] >> 4);
+            }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
 
 // The 32 MFMAs of one stage (4 k-steps x 2 x 2 blocks x Re/Im) on `buf`.
 __device__ __forceinline__ void stage_mfma(Acc &acc, const uint8_t *buf, int lane, int wa, int wb)
@@ -365,12 +383,18 @@ __global__ __launch_bounds__(256, 2) void xcorr_mfma(KernelArgs args)
         // integrate into the slot's accumulators
         const int64_t tile_idx = (int64_t)ti * jd.nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);
         int32_t *tb = jd.acc + tile_idx * TILE_I32 + lane;
+        if (atomic) {
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
-                flush_block(tb + ((2 * wa + a) * BLKS + (2 * wb + b)) * BLOCK_I32, acc.re[a][b],
-                            acc.im[a][b], atomic);
+                for (int b = 0; b < 2; ++b)
+                    flush_block(tb + ((2 * wa + a) * BLKS + (2 * wb + b)) * BLOCK_I32, acc.re[a][b],
+                                acc.im[a][b]);
+        } else if (jd.flags & JOB_FRESH) {
+            flush_owned(tb, acc, wa, wb, true);
+        } else {
+            flush_owned(tb, acc, wa, wb, false);
+        }
     }
 }
 
