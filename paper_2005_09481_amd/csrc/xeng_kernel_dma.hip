@@ -26,9 +26,12 @@
 // holds -S_j, and the dump subtracts it.  The general kernel stores the same
 // form.
 //
-// Workgroup tile: 128 rows (A) x 256 columns (B), four waves; wave (wa, wb)
-// computes rows 64wa..64wa+63 against columns 128wb..128wb+127, i.e. 2 x 4
-// MFMA blocks for both Re and Im (256 accumulator registers).
+// Workgroup tile: 128 rows (A) x 256 columns (B), NW waves in two rows of
+// NW / 2; wave (wa, wb) computes rows 64wa..64wa+63 against 256 / (NW / 2)
+// columns, i.e. 2 x BW MFMA blocks for both Re and Im.  Four waves (one per
+// SIMD, 256 accumulator registers each) read the fewest operand bytes per
+// MFMA; eight (two per SIMD, 128 each) let one wave's MFMAs run while the
+// other waits on LDS, a barrier or its DMA issue.
 //
 // LDS stage layout ("chunk-major" in 8-row groups): the A region holds 8
 // groups of 8 time rows x 8 chunks of 16 inputs, chunk c of row r at byte
@@ -61,7 +64,15 @@ constexpr int NSLOT = 6;                    // ring: 144 KB of LDS
 constexpr int AHEAD = NSLOT - 1;            // stages issued ahead
 constexpr int DMA_A = A_STAGE / 1024;       // 1 KB DMA instructions per stage: 8
 constexpr int DMA_B = B_STAGE / 1024;       // 16
-constexpr int DMA_PER_WAVE = (DMA_A + DMA_B) / 4;   // 6
+
+template <int NW> struct Layout {
+    static constexpr int WB_WAVES = NW / 2;                  // waves across the 256 columns
+    static constexpr int BW = 8 / WB_WAVES;                  // B blocks per wave
+    static constexpr int DMA_PER_WAVE = (DMA_A + DMA_B) / NW;
+    static constexpr int MFMA_PER_K = 4 * BW;                // MFMAs per k-step
+    static constexpr int READS_PER_K = 2 + BW;               // transposed reads per k-step
+    static constexpr int VALU_PER_MFMA = NW == 4 ? 3 : 4;    // unpack share between MFMAs
+};
 
 // s_waitcnt immediates: vmcnt in bits 3:0 and 15:14, expcnt 6:4 and
 // lgkmcnt 11:8 at their maxima (no wait on those); and lgkmcnt(0) alone.
@@ -158,44 +169,46 @@ __device__ __forceinline__ void dma_geom(int inst, int lane, int row0, int col0,
     }
 }
 
-// Per-lane byte offsets (row * stride + input) of this wave's six DMA
+// Per-lane byte offsets (row * stride + input) of this wave's DMA
 // instructions from a stage's first row, fixed for a piece.
-struct DmaLane {
-    uint32_t off[DMA_PER_WAVE];
+template <int NW> struct DmaLane {
+    uint32_t off[Layout<NW>::DMA_PER_WAVE];
 };
 
-__device__ __forceinline__ void dma_lane_setup(DmaLane &dl, const Tile &tl, int wave, int lane)
+template <int NW>
+__device__ __forceinline__ void dma_lane_setup(DmaLane<NW> &dl, const Tile &tl, int wave, int lane)
 {
 #pragma unroll
-    for (int k = 0; k < DMA_PER_WAVE; ++k) {
+    for (int k = 0; k < Layout<NW>::DMA_PER_WAVE; ++k) {
         int lds_off, t, in;
-        dma_geom(wave + 4 * k, lane, tl.row0, tl.col0, lds_off, t, in);
+        dma_geom(wave + NW * k, lane, tl.row0, tl.col0, lds_off, t, in);
         dl.off[k] = (uint32_t)((int64_t)t * tl.stride) + (uint32_t)in;
     }
 }
 
-// This wave's share of one stage's DMA: instructions wave, wave+4, ... of the
-// 24.  Rows at or past t1 (the last, partial stage of a piece, and stages
+// This wave's share of one stage's DMA: instructions wave, wave + NW, ... of
+// the 24.  Rows at or past t1 (the last, partial stage of a piece, and stages
 // past its end, issued so that the count of loads in flight stays
 // constant) are read from the zero-sample buffer, so that every stage the
 // compute loop sees is whole.
-__device__ __forceinline__ void issue_stage(uint32_t slot_addr, const Tile &tl, const DmaLane &dl, int stage,
+template <int NW>
+__device__ __forceinline__ void issue_stage(uint32_t slot_addr, const Tile &tl, const DmaLane<NW> &dl, int stage,
                                             int wave, int lane)
 {
     const int ts = tl.t0 + stage * STAGE;
     if (ts + STAGE <= tl.t1) {
         const uint8_t *row = tl.samples + (int64_t)ts * tl.stride;
 #pragma unroll
-        for (int k = 0; k < DMA_PER_WAVE; ++k) {
+        for (int k = 0; k < Layout<NW>::DMA_PER_WAVE; ++k) {
             int lds_off, t, in;
-            dma_geom(wave + 4 * k, lane, tl.row0, tl.col0, lds_off, t, in);
+            dma_geom(wave + NW * k, lane, tl.row0, tl.col0, lds_off, t, in);
             dma16_s(row, dl.off[k], slot_addr + (uint32_t)lds_off);
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < DMA_PER_WAVE; ++k) {
+        for (int k = 0; k < Layout<NW>::DMA_PER_WAVE; ++k) {
             int lds_off, t, in;
-            dma_geom(wave + 4 * k, lane, tl.row0, tl.col0, lds_off, t, in);
+            dma_geom(wave + NW * k, lane, tl.row0, tl.col0, lds_off, t, in);
             const uint8_t *src =
                 ts + t < tl.t1 ? tl.samples + (int64_t)(ts + t) * tl.stride + in : tl.zeros;
             dma16_v(src, slot_addr + (uint32_t)lds_off);
@@ -203,39 +216,40 @@ __device__ __forceinline__ void issue_stage(uint32_t slot_addr, const Tile &tl, 
     }
 }
 
-// Packed operand data of one k-step (2 A blocks, 4 B blocks) and its
+// Packed operand data of one k-step (2 A blocks, BW B blocks) and its
 // unpacked form.
-struct Raw {
+template <int NW> struct Raw {
     v2i a[2];
-    v2i b[4];
+    v2i b[Layout<NW>::BW];
 };
-struct Ops {
+template <int NW> struct Ops {
     v8i a[2];   // {16R, 16R, 16I, 16I, 16~R, 16~R, -, -}: real A = s0123, imaginary A = s2345
-    v4i b[4];   // {16R, 16R, 16I, 16I}
+    v4i b[Layout<NW>::BW];   // {16R, 16R, 16I, 16I}
 };
-struct Acc {
-    v16i re[2][4];
-    v16i im[2][4];
+template <int NW> struct Acc {
+    v16i re[2][Layout<NW>::BW];
+    v16i im[2][Layout<NW>::BW];
 };
 
 // Transposed reads of k-step q: `pa`, `pb` are this lane's bases in the
 // slot's A and B regions (group lane / 32, chunk of the lane's 16-lane
 // group, byte 8 (lane % 16)); k-step q adds 2 groups, block a / b 2 chunks.
-__device__ __forceinline__ void read_k(Raw &r, const lds_u8 *pa, const lds_u8 *pb, int q)
+template <int NW>
+__device__ __forceinline__ void read_k(Raw<NW> &r, const lds_u8 *pa, const lds_u8 *pb, int q)
 {
 #pragma unroll
     for (int a = 0; a < 2; ++a)
         r.a[a] = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i *)(pa + 2 * GRP_A * q + 256 * a));
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < Layout<NW>::BW; ++b)
         r.b[b] = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i *)(pb + 2 * GRP_B * q + 256 * b));
 }
 
 // 16 x (4-bit value) in the high half of each byte: from the high nibbles,
 // (p ^ 0x88) & 0xF0 per byte; from the low nibbles, the same on p << 4.
 // XOR with 0x77 instead of 0x88 gives 16 x the bitwise complement.
-template <bool RE_LOW>
-__device__ __forceinline__ void unpack_k(Ops &o, const Raw &r)
+template <int NW, bool RE_LOW>
+__device__ __forceinline__ void unpack_k(Ops<NW> &o, const Raw<NW> &r)
 {
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
@@ -252,7 +266,7 @@ __device__ __forceinline__ void unpack_k(Ops &o, const Raw &r)
         }
     }
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < Layout<NW>::BW; ++b) {
         const uint32_t x0 = (uint32_t)r.b[b].x, x1 = (uint32_t)r.b[b].y;
         const uint32_t h0 = (x0 ^ 0x88888888u) & 0xF0F0F0F0u, h1 = (x1 ^ 0x88888888u) & 0xF0F0F0F0u;
         const uint32_t l0 = ((x0 << 4) ^ 0x80808080u) & 0xF0F0F0F0u;
@@ -261,10 +275,11 @@ __device__ __forceinline__ void unpack_k(Ops &o, const Raw &r)
     }
 }
 
-__device__ __forceinline__ void mfma_k(Acc &acc, const Ops &o)
+template <int NW>
+__device__ __forceinline__ void mfma_k(Acc<NW> &acc, const Ops<NW> &o)
 {
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < Layout<NW>::BW; ++b)
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
             const v4i re_a = __builtin_shufflevector(o.a[a], o.a[a], 0, 1, 2, 3);
@@ -274,26 +289,29 @@ __device__ __forceinline__ void mfma_k(Acc &acc, const Ops &o)
         }
 }
 
-// Instruction order of a k-step: 16 MFMAs, each followed by a share of the
+// Instruction order of a k-step: the MFMAs, each followed by a share of the
 // unpack of the next k-step (which the matrix core's 32-cycle MFMAs hide)
-// and, after the first six, one of the LDS reads of a later k-step -- spread
+// and, after the first few, one of the LDS reads of a later k-step -- spread
 // out rather than issued as a burst that would stall the wave at issue.
+template <int NW>
 __device__ __forceinline__ void kstep_schedule()
 {
+    using L = Layout<NW>;
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
+    for (int m = 0; m < L::MFMA_PER_K; ++m) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
-        if (m < 6) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read
-        __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);   // VALU
+        if (m < L::READS_PER_K) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read
+        __builtin_amdgcn_sched_group_barrier(0x002, L::VALU_PER_MFMA, 0);   // VALU
     }
 }
 
+template <int NW>
 __device__ __forceinline__ void wait_stage_and_sync()
 {
     // this wave's loads of the next stage have landed (AHEAD - 1 newer
     // stages in flight) and its LDS reads are done; the barrier extends both
     // to the workgroup
-    __builtin_amdgcn_s_waitcnt(XENG_VMCNT((AHEAD - 1) * DMA_PER_WAVE));
+    __builtin_amdgcn_s_waitcnt(XENG_VMCNT((AHEAD - 1) * Layout<NW>::DMA_PER_WAVE));
     __builtin_amdgcn_s_waitcnt(XENG_LGKMCNT0);
     __syncthreads();
 }
@@ -306,62 +324,62 @@ __device__ __forceinline__ void wait_stage_and_sync()
 // the barrier of iteration s - 1; that barrier sits before the first read of
 // stage s.  The last iteration's reads of "stage ns" touch a slot whose
 // contents are never used.
-template <bool RE_LOW>
-__device__ __forceinline__ void run_piece(Acc &acc, uint32_t ring, const Tile &tl, int wave, int lane,
+template <int NW, bool RE_LOW>
+__device__ __forceinline__ void run_piece(Acc<NW> &acc, uint32_t ring, const Tile &tl, int wave, int lane,
                                           uint32_t a_lane, uint32_t b_lane)
 {
     const int ns = (tl.t1 - tl.t0 + STAGE - 1) / STAGE;
-    DmaLane dl;
-    dma_lane_setup(dl, tl, wave, lane);
+    DmaLane<NW> dl;
+    dma_lane_setup<NW>(dl, tl, wave, lane);
     // nothing else in flight: the ring's vmcnt waits then count DMA only
     __builtin_amdgcn_s_waitcnt(XENG_VMCNT(0));
 #pragma unroll
-    for (int d = 0; d < AHEAD; ++d) issue_stage(ring + d * SLOT, tl, dl, d, wave, lane);
-    wait_stage_and_sync();
+    for (int d = 0; d < AHEAD; ++d) issue_stage<NW>(ring + d * SLOT, tl, dl, d, wave, lane);
+    wait_stage_and_sync<NW>();
 
-    Raw r0, r1;
-    Ops u0, u1;
+    Raw<NW> r0, r1;
+    Ops<NW> u0, u1;
     {
         const lds_u8 *pa = (const lds_u8 *)(uintptr_t)(ring + a_lane);
         const lds_u8 *pb = (const lds_u8 *)(uintptr_t)(ring + b_lane);
-        read_k(r0, pa, pb, 0);
-        read_k(r1, pa, pb, 1);
-        unpack_k<RE_LOW>(u0, r0);
+        read_k<NW>(r0, pa, pb, 0);
+        read_k<NW>(r1, pa, pb, 1);
+        unpack_k<NW, RE_LOW>(u0, r0);
     }
     int cur = 0;    // slot of stage s
     for (int s = 0; s < ns; ++s) {
         const int nxt = cur == NSLOT - 1 ? 0 : cur + 1;
         const int iss = cur == 0 ? NSLOT - 1 : cur - 1;   // slot of stage s - 1 = s + AHEAD
-        issue_stage(ring + iss * SLOT, tl, dl, s + AHEAD, wave, lane);
+        issue_stage<NW>(ring + iss * SLOT, tl, dl, s + AHEAD, wave, lane);
         const lds_u8 *pa = (const lds_u8 *)(uintptr_t)(ring + cur * SLOT + a_lane);
         const lds_u8 *pb = (const lds_u8 *)(uintptr_t)(ring + cur * SLOT + b_lane);
         const lds_u8 *qa = (const lds_u8 *)(uintptr_t)(ring + nxt * SLOT + a_lane);
         const lds_u8 *qb = (const lds_u8 *)(uintptr_t)(ring + nxt * SLOT + b_lane);
         __builtin_amdgcn_sched_barrier(0);
         // k-step 0
-        read_k(r0, pa, pb, 2);
-        unpack_k<RE_LOW>(u1, r1);
-        mfma_k(acc, u0);
-        kstep_schedule();
+        read_k<NW>(r0, pa, pb, 2);
+        unpack_k<NW, RE_LOW>(u1, r1);
+        mfma_k<NW>(acc, u0);
+        kstep_schedule<NW>();
         __builtin_amdgcn_sched_barrier(0);
         // k-step 1
-        read_k(r1, pa, pb, 3);
-        unpack_k<RE_LOW>(u0, r0);
-        mfma_k(acc, u1);
-        kstep_schedule();
+        read_k<NW>(r1, pa, pb, 3);
+        unpack_k<NW, RE_LOW>(u0, r0);
+        mfma_k<NW>(acc, u1);
+        kstep_schedule<NW>();
         __builtin_amdgcn_sched_barrier(0);
         // k-step 2: stage s + 1 must be in LDS before its first read
-        wait_stage_and_sync();
-        read_k(r0, qa, qb, 0);
-        unpack_k<RE_LOW>(u1, r1);
-        mfma_k(acc, u0);
-        kstep_schedule();
+        wait_stage_and_sync<NW>();
+        read_k<NW>(r0, qa, qb, 0);
+        unpack_k<NW, RE_LOW>(u1, r1);
+        mfma_k<NW>(acc, u0);
+        kstep_schedule<NW>();
         __builtin_amdgcn_sched_barrier(0);
         // k-step 3
-        read_k(r1, qa, qb, 1);
-        unpack_k<RE_LOW>(u0, r0);
-        mfma_k(acc, u1);
-        kstep_schedule();
+        read_k<NW>(r1, qa, qb, 1);
+        unpack_k<NW, RE_LOW>(u0, r0);
+        mfma_k<NW>(acc, u1);
+        kstep_schedule<NW>();
         __builtin_amdgcn_sched_barrier(0);
         cur = nxt;
     }
@@ -381,26 +399,28 @@ __device__ __forceinline__ void flush_atomic(gi32 *blk, const v16i &re, const v1
     }
 }
 
-// Whole-tile flush of one wave's 2 x 4 blocks: stores if the slot holds
-// zeros, else read-modify-write with the loads of four blocks issued
-// together (one memory latency per four blocks, not one per value).
-__device__ __forceinline__ void flush_owned(gi32 *tb, const Acc &acc, int wa, bool fresh)
+// Whole-tile flush of one wave's 2 x BW blocks (column blocks cb0..): stores
+// if the slot holds zeros, else read-modify-write with the loads of a row of
+// blocks issued together (one memory latency per row, not one per value).
+template <int NW>
+__device__ __forceinline__ void flush_owned(gi32 *tb, const Acc<NW> &acc, int wa, int cb0, bool fresh)
 {
+    constexpr int BW = Layout<NW>::BW;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-        gi32 *blk[4];
+        gi32 *blk[BW];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) blk[b] = tb + ((2 * wa + a) * BLKS + b) * BLOCK_I32;
-        int32_t old_re[4][16], old_im[4][16];
+        for (int b = 0; b < BW; ++b) blk[b] = tb + ((2 * wa + a) * BLKS + cb0 + b) * BLOCK_I32;
+        int32_t old_re[BW][16], old_im[BW][16];
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < BW; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 old_re[b][r] = fresh ? 0 : blk[b][r * 64];
                 old_im[b][r] = fresh ? 0 : blk[b][1024 + r * 64];
             }
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < BW; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 blk[b][r * 64] = old_re[b][r] + (acc.re[a][b][r] >> 8);
@@ -414,8 +434,10 @@ __device__ __forceinline__ void flush_owned(gi32 *tb, const Acc &acc, int wa, bo
 // piece's tile field holds (I, J2): A rows 128 I.., B columns 256 J2.., i.e.
 // accumulator tiles (I, 2 J2) and (I, 2 J2 + 1) where they are in the upper
 // triangle.
-__global__ __launch_bounds__(256, 1) void xcorr_dma(KernelArgs args)
+template <int NW>
+__global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
 {
+    using L = Layout<NW>;
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     // LDS byte address of the ring, wave-uniform (scalar register)
     const uint32_t ring = (uint32_t)__builtin_amdgcn_readfirstlane(
@@ -424,11 +446,11 @@ __global__ __launch_bounds__(256, 1) void xcorr_dma(KernelArgs args)
     const int lane = tid & 63;
     // wave-uniform, so that everything derived from it stays scalar
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wa = wave >> 1, wb = wave & 1;
+    const int wa = wave / L::WB_WAVES, wb = wave % L::WB_WAVES;
     // per-lane parts of the transposed-read addresses (see read_k)
     const int grp = lane >> 4, jl = lane & 15;
     const uint32_t a_lane = GRP_A * (grp >> 1) + 128 * (grp & 1) + 8 * jl + 512 * wa;
-    const uint32_t b_lane = A_STAGE + GRP_B * (grp >> 1) + 128 * (grp & 1) + 8 * jl + 1024 * wb;
+    const uint32_t b_lane = A_STAGE + GRP_B * (grp >> 1) + 128 * (grp & 1) + 8 * jl + 256 * L::BW * wb;
 
     const int p_begin = args.wg_off[blockIdx.x], p_end = args.wg_off[blockIdx.x + 1];
     for (int pi = p_begin; pi < p_end; ++pi) {
@@ -447,23 +469,24 @@ __global__ __launch_bounds__(256, 1) void xcorr_dma(KernelArgs args)
         tl.t1 = __builtin_amdgcn_readfirstlane(pce.t1_atomic & 0x7FFFFFFF);
         // this wave's accumulator tile; a half below the diagonal is
         // computed (the workgroup stays in step) but not stored
-        const int tj = 2 * tj2 + wb;
+        const int tj = 2 * tj2 + wb / (L::WB_WAVES / 2);
+        const int cb0 = (wb % (L::WB_WAVES / 2)) * L::BW;   // first column block in the tile
         const bool valid = tj >= ti && tj < jd.nt;
 
-        Acc acc;
+        Acc<NW> acc;
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
+            for (int b = 0; b < L::BW; ++b)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     acc.re[a][b][r] = 0;
                     acc.im[a][b][r] = 0;
                 }
         if (jd.flags & JOB_RE_LOW)
-            run_piece<true>(acc, ring, tl, wave, lane, a_lane, b_lane);
+            run_piece<NW, true>(acc, ring, tl, wave, lane, a_lane, b_lane);
         else
-            run_piece<false>(acc, ring, tl, wave, lane, a_lane, b_lane);
+            run_piece<NW, false>(acc, ring, tl, wave, lane, a_lane, b_lane);
 
         if (valid) {
             const int64_t tile_idx = (int64_t)ti * jd.nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);
@@ -472,15 +495,15 @@ __global__ __launch_bounds__(256, 1) void xcorr_dma(KernelArgs args)
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        flush_atomic(tb + ((2 * wa + a) * BLKS + b) * BLOCK_I32, acc.re[a][b], acc.im[a][b]);
+                    for (int b = 0; b < L::BW; ++b) {
+                        flush_atomic(tb + ((2 * wa + a) * BLKS + cb0 + b) * BLOCK_I32, acc.re[a][b], acc.im[a][b]);
                         // one block at a time: keeps the register file for the main loop
                         __builtin_amdgcn_sched_barrier(0);
                     }
             } else if (jd.flags & JOB_FRESH) {
-                flush_owned(tb, acc, wa, true);
+                flush_owned<NW>(tb, acc, wa, cb0, true);
             } else {
-                flush_owned(tb, acc, wa, false);
+                flush_owned<NW>(tb, acc, wa, cb0, false);
             }
         }
     }
@@ -490,18 +513,25 @@ __global__ __launch_bounds__(256, 1) void xcorr_dma(KernelArgs args)
 
 constexpr int DMA_LDS_BYTES = dma::NSLOT * dma::SLOT;
 
+// Waves per workgroup of the launched instance (4 or 8).
+#ifndef XENG_DMA_WAVES
+#define XENG_DMA_WAVES 4
+#endif
+static_assert(XENG_DMA_WAVES == 4 || XENG_DMA_WAVES == 8, "4 or 8 waves");
+
 // Once per device, before any launch (and outside any stream capture): the
 // kernel's LDS ring exceeds the default dynamic-LDS limit.
 hipError_t init_dma_kernel()
 {
-    return hipFuncSetAttribute((const void *)dma::xcorr_dma, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               DMA_LDS_BYTES);
+    return hipFuncSetAttribute((const void *)dma::xcorr_dma<XENG_DMA_WAVES>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, DMA_LDS_BYTES);
 }
 
 hipError_t launch_correlate_dma(const KernelArgs &a, int grid, hipStream_t stream)
 {
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(dma::xcorr_dma, dim3(grid), dim3(256), DMA_LDS_BYTES, stream, a);
+    hipLaunchKernelGGL(dma::xcorr_dma<XENG_DMA_WAVES>, dim3(grid), dim3(64 * XENG_DMA_WAVES), DMA_LDS_BYTES,
+                       stream, a);
     return hipGetLastError();
 }
 
