@@ -4,6 +4,8 @@
 
 #include <stdint.h>
 
+#include <hip/hip_runtime.h>
+
 namespace xeng {
 
 // ---------------------------------------------------------------------------
@@ -18,15 +20,30 @@ constexpr int BLKS = TILE / BLK;   // 4 blocks per tile side
 constexpr int STAGE = 64;          // samples per pipeline stage (LDS buffer)
 constexpr int KSTEP = 16;          // samples per MFMA k-step (32 int8 values)
 
-// Accumulator layout of one slot (device, int32): tile-major over the upper
+// Accumulator layout of one slot (device): tile-major over the upper
 // triangle of tiles, tile index ti*nt - ti*(ti-1)/2 + (tj-ti).  Inside a
-// tile: [ca][cb][comp][reg][lane] with ca, cb the 4 x 4 blocks, comp 0 = Re,
-// 1 = Im, and (reg, lane) the MFMA 32 x 32 accumulator register layout:
-// row r of the tile is in block ca = r / 32, column c in block cb = c / 32,
-// and within a block row i, column j sit in register 4*(i/8) + i%4 of lane
-// j + 32*((i/4)%2).
-constexpr int64_t TILE_I32 = (int64_t)BLKS * BLKS * 2 * 16 * 64;   // 32768 int32
-constexpr int64_t BLOCK_I32 = 2 * 16 * 64;                          // 2048 int32
+// tile: [ca][cb][reg][lane] of 64-bit words, with ca, cb the 4 x 4 blocks
+// and (reg, lane) the MFMA 32 x 32 accumulator register layout: row r of the
+// tile is in block ca = r / 32, column c in block cb = c / 32, and within a
+// block row i, column j sit in register 4*(i/8) + i%4 of lane
+// j + 32*((i/4)%2).  A word holds the pair (Re, Im) as Im * 2^32 + Re (Re
+// sign-extended): 64-bit addition of such words adds both parts at once
+// (one atomic per pair), and since each true sum fits in int32, Re is the
+// low half read as int32 and Im = (word - Re) >> 32.
+constexpr int64_t TILE_I32 = (int64_t)BLKS * BLKS * 2 * 16 * 64;   // 32768 int32 = 16384 words
+constexpr int64_t BLOCK_I32 = 2 * 16 * 64;                          // 2048 int32 = 1024 words
+constexpr int64_t TILE_W = TILE_I32 / 2;
+constexpr int64_t BLOCK_W = BLOCK_I32 / 2;
+
+__host__ __device__ inline uint64_t pack_pair(int32_t re, int32_t im)
+{
+    return ((uint64_t)(uint32_t)im << 32) + (uint64_t)(int64_t)re;
+}
+__host__ __device__ inline int32_t pair_re(uint64_t w) { return (int32_t)(uint32_t)w; }
+__host__ __device__ inline int32_t pair_im(uint64_t w)
+{
+    return (int32_t)(uint32_t)((w - (uint64_t)(int64_t)pair_re(w)) >> 32);
+}
 
 inline int64_t tri64(int64_t n) { return n * (n + 1) / 2; }
 inline int n_tiles_side(int n) { return (n + TILE - 1) / TILE; }

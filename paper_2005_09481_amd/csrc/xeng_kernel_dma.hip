@@ -51,7 +51,7 @@ typedef int v8i __attribute__((ext_vector_type(8)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 typedef __attribute__((address_space(3))) v2i lds_v2i;
 typedef __attribute__((address_space(3))) uint8_t lds_u8;
-typedef __attribute__((address_space(1))) int32_t gi32;
+typedef __attribute__((address_space(1))) uint64_t gw64;
 
 constexpr int WA_ROWS = 128;            // A rows per workgroup tile
 constexpr int WB_COLS = 256;            // B columns per workgroup tile
@@ -389,43 +389,39 @@ __device__ __forceinline__ void run_piece(Acc<NW> &acc, uint32_t ring, const Til
 
 // Accumulators hold 256x the stored values (both operands carry 16x the
 // sample parts), so a flush adds acc >> 8; every value is a multiple of
-// 256, so this is exact.  A tile shared with other pieces takes atomic adds.
-__device__ __forceinline__ void flush_atomic(gi32 *blk, const v16i &re, const v16i &im)
+// 256, so this is exact.  Pairs go to the slot as packed 64-bit words (see
+// the layout note): a tile shared with other pieces takes one 64-bit atomic
+// add per pair.
+__device__ __forceinline__ void flush_atomic(gw64 *blk, const v16i &re, const v16i &im)
 {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        __hip_atomic_fetch_add(blk + r * 64, re[r] >> 8, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(blk + 1024 + r * 64, im[r] >> 8, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    for (int r = 0; r < 16; ++r)
+        __hip_atomic_fetch_add(blk + r * 64, pack_pair(re[r] >> 8, im[r] >> 8), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Whole-tile flush of one wave's 2 x BW blocks (column blocks cb0..): stores
 // if the slot holds zeros, else read-modify-write with the loads of a row of
 // blocks issued together (one memory latency per row, not one per value).
 template <int NW>
-__device__ __forceinline__ void flush_owned(gi32 *tb, const Acc<NW> &acc, int wa, int cb0, bool fresh)
+__device__ __forceinline__ void flush_owned(gw64 *tb, const Acc<NW> &acc, int wa, int cb0, bool fresh)
 {
     constexpr int BW = Layout<NW>::BW;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-        gi32 *blk[BW];
+        gw64 *blk[BW];
 #pragma unroll
-        for (int b = 0; b < BW; ++b) blk[b] = tb + ((2 * wa + a) * BLKS + cb0 + b) * BLOCK_I32;
-        int32_t old_re[BW][16], old_im[BW][16];
-#pragma unroll
-        for (int b = 0; b < BW; ++b)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                old_re[b][r] = fresh ? 0 : blk[b][r * 64];
-                old_im[b][r] = fresh ? 0 : blk[b][1024 + r * 64];
-            }
+        for (int b = 0; b < BW; ++b) blk[b] = tb + ((2 * wa + a) * BLKS + cb0 + b) * BLOCK_W;
+        uint64_t old[BW][16];
 #pragma unroll
         for (int b = 0; b < BW; ++b)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                blk[b][r * 64] = old_re[b][r] + (acc.re[a][b][r] >> 8);
-                blk[b][1024 + r * 64] = old_im[b][r] + (acc.im[a][b][r] >> 8);
-            }
+            for (int r = 0; r < 16; ++r) old[b][r] = fresh ? 0 : blk[b][r * 64];
+#pragma unroll
+        for (int b = 0; b < BW; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                blk[b][r * 64] = old[b][r] + pack_pair(acc.re[a][b][r] >> 8, acc.im[a][b][r] >> 8);
         __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -490,13 +486,13 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
 
         if (valid) {
             const int64_t tile_idx = (int64_t)ti * jd.nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);
-            gi32 *tb = (gi32 *)(jd.acc + tile_idx * TILE_I32 + lane);
+            gw64 *tb = (gw64 *)(jd.acc + tile_idx * TILE_I32) + lane;
             if (atomic) {
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
 #pragma unroll
                     for (int b = 0; b < L::BW; ++b) {
-                        flush_atomic(tb + ((2 * wa + a) * BLKS + cb0 + b) * BLOCK_I32, acc.re[a][b], acc.im[a][b]);
+                        flush_atomic(tb + ((2 * wa + a) * BLKS + cb0 + b) * BLOCK_W, acc.re[a][b], acc.im[a][b]);
                         // one block at a time: keeps the register file for the main loop
                         __builtin_amdgcn_sched_barrier(0);
                     }

@@ -83,7 +83,7 @@ __device__ __forceinline__ uint32_t nib_to_not_i8(uint32_t n) { return (0x878787
 // stay in flight while the LDS reads and MFMAs of the current stage run.
 typedef __attribute__((address_space(1))) const u32x2 gcu64;
 typedef __attribute__((address_space(1))) const uint8_t gcu8;
-typedef __attribute__((address_space(1))) int32_t gi32;
+typedef __attribute__((address_space(1))) uint64_t gw64;
 
 // One lane's share of a stage: 8 inputs x 8 consecutive samples of one
 // block (d[k] = the 8 inputs at sample k), as loaded, plus a mask of which
@@ -219,15 +219,15 @@ __device__ __forceinline__ void stage_write(uint8_t *region, const StageRegs &r,
 __device__ __forceinline__ v4i lds128(const uint8_t *p) { return *(const v4i *)p; }
 
 // Accumulators hold 16x the stored values (B operands are scaled by 16), so
-// the flush adds acc >> 4; every value is a multiple of 16, so this is exact.
-__device__ __forceinline__ void flush_block(int32_t *blk_, const v16i &re, const v16i &im)
+// the flush adds acc >> 4; every value is a multiple of 16, so this is
+// exact.  Pairs go to the slot as packed 64-bit words (see the layout note):
+// a shared tile takes one 64-bit atomic add per pair.
+__device__ __forceinline__ void flush_block(gw64 *blk, const v16i &re, const v16i &im)
 {
-    gi32 *blk = (gi32 *)blk_;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        __hip_atomic_fetch_add(blk + r * 64, re[r] >> 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(blk + 1024 + r * 64, im[r] >> 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    for (int r = 0; r < 16; ++r)
+        __hip_atomic_fetch_add(blk + r * 64, pack_pair(re[r] >> 4, im[r] >> 4), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
 }
 
 struct Acc {
@@ -236,30 +236,25 @@ struct Acc {
 };
 
 // Whole-tile flush of one wave's 2 x 2 blocks: stores if the slot holds
-// zeros, else read-modify-write with the loads of two blocks issued before
-// their stores (one memory latency per two blocks, not one per value).
-__device__ __forceinline__ void flush_owned(int32_t *tb, const Acc &acc, int wa, int wb, bool fresh)
+// zeros, else read-modify-write with the loads of a row of blocks issued
+// before their stores (one memory latency per row, not one per value).
+__device__ __forceinline__ void flush_owned(gw64 *tb, const Acc &acc, int wa, int wb, bool fresh)
 {
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-        gi32 *blk[2];
+        gw64 *blk[2];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) blk[b] = (gi32 *)(tb + ((2 * wa + a) * BLKS + (2 * wb + b)) * BLOCK_I32);
-        int32_t old_re[2][16], old_im[2][16];
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                old_re[b][r] = fresh ? 0 : blk[b][r * 64];
-                old_im[b][r] = fresh ? 0 : blk[b][1024 + r * 64];
-            }
+        for (int b = 0; b < 2; ++b) blk[b] = tb + ((2 * wa + a) * BLKS + (2 * wb + b)) * BLOCK_W;
+        uint64_t old[2][16];
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                blk[b][r * 64] = old_re[b][r] + (acc.re[a][b][r] >> 4);
-                blk[b][1024 + r * 64] = old_im[b][r] + (acc.im[a][b][r] >> 4);
-            }
+            for (int r = 0; r < 16; ++r) old[b][r] = fresh ? 0 : blk[b][r * 64];
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                blk[b][r * 64] = old[b][r] + pack_pair(acc.re[a][b][r] >> 4, acc.im[a][b][r] >> 4);
         __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -382,13 +377,13 @@ __global__ __launch_bounds__(256, 2) void xcorr_mfma(KernelArgs args)
 
         // integrate into the slot's accumulators
         const int64_t tile_idx = (int64_t)ti * jd.nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);
-        int32_t *tb = jd.acc + tile_idx * TILE_I32 + lane;
+        gw64 *tb = (gw64 *)(jd.acc + tile_idx * TILE_I32) + lane;
         if (atomic) {
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b)
-                    flush_block(tb + ((2 * wa + a) * BLKS + (2 * wb + b)) * BLOCK_I32, acc.re[a][b],
+                    flush_block(tb + ((2 * wa + a) * BLKS + (2 * wb + b)) * BLOCK_W, acc.re[a][b],
                                 acc.im[a][b]);
         } else if (jd.flags & JOB_FRESH) {
             flush_owned(tb, acc, wa, wb, true);
@@ -398,9 +393,8 @@ __global__ __launch_bounds__(256, 2) void xcorr_mfma(KernelArgs args)
     }
 }
 
-// Position of pair (i <= j) in a slot's tile layout (real part; the
-// imaginary part is 1024 int32 further).
-__device__ __forceinline__ int64_t acc_index(int i, int j, int nt)
+// Word of pair (i <= j) in a slot's tile layout.
+__device__ __forceinline__ int64_t acc_word(int i, int j, int nt)
 {
     const int ti = i >> 7, tj = j >> 7;
     const int ri = i & 127, rj = j & 127;
@@ -408,7 +402,7 @@ __device__ __forceinline__ int64_t acc_index(int i, int j, int nt)
     const int reg = 4 * (ra >> 3) + (ra & 3);
     const int ln = lb + 32 * ((ra >> 2) & 1);
     const int64_t tile = (int64_t)ti * nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);
-    return tile * TILE_I32 + (ca * BLKS + cb) * BLOCK_I32 + reg * 64 + ln;
+    return tile * TILE_W + (ca * BLKS + cb) * BLOCK_W + reg * 64 + ln;
 }
 
 // Stored imaginary parts of the diagonal, d[j] = -S_j (see the operand
@@ -417,15 +411,15 @@ __global__ __launch_bounds__(256) void diag_im(const int32_t *__restrict__ acc, 
                                                int32_t *__restrict__ d)
 {
     const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j < n) d[j] = acc[acc_index(j, j, nt) + 1024];
+    if (j < n) d[j] = pair_im(reinterpret_cast<const uint64_t *>(acc)[acc_word(j, j, nt)]);
 }
 
 // Accumulators (tile layout) -> packed row-major upper triangle of (Re, Im),
 // optionally zeroing the slot in the same pass.  Workgroup (x, y) takes
 // block row ca = x % 4 (32 rows) of tile (ti, tj) = (y, y + x / 4).  Reads:
 // thread t takes row t / 8 of the block row and 16 consecutive columns,
-// 16 * (t % 8).., which are 16 consecutive int32 of one accumulator register
-// row (4 dwordx4 loads per component, coalesced), and stages them in LDS
+// 16 * (t % 8).., which are 16 consecutive words of one accumulator register
+// row (8 dwordx4 loads of packed pairs, coalesced), and stages them in LDS
 // as (Re, Im) pairs.  Writes: consecutive threads take consecutive pairs of
 // an output row, 128 pairs (1 KB contiguous) per row.  The imaginary part of
 // (i, j) is stored as Im V_ij - S_j, so d[j] is subtracted (exact in
@@ -447,27 +441,20 @@ __global__ __launch_bounds__(256) void vis_dump(int32_t *__restrict__ acc, int n
         const int ri = t >> 3, c16 = t & 7;
         const int cb = c16 >> 1, cj0 = 16 * (c16 & 1);
         const int reg = 4 * (ri >> 3) + (ri & 3), half = (ri >> 2) & 1;
-        int32_t *base = acc + tile * TILE_I32 + (ca * BLKS + cb) * BLOCK_I32 + reg * 64 + 32 * half + cj0;
-        int4 *pre = reinterpret_cast<int4 *>(base);
-        int4 *pim = reinterpret_cast<int4 *>(base + 1024);
-        int4 re[4], im[4];
+        uint64_t *base = reinterpret_cast<uint64_t *>(acc) + tile * TILE_W + (ca * BLKS + cb) * BLOCK_W + reg * 64 +
+                         32 * half + cj0;
+        int4 *pw = reinterpret_cast<int4 *>(base);
+        int4 w[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            re[q] = pre[q];
-            im[q] = pim[q];
-        }
+        for (int q = 0; q < 8; ++q) w[q] = pw[q];
         if (reset) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                pre[q] = make_int4(0, 0, 0, 0);
-                pim[q] = make_int4(0, 0, 0, 0);
-            }
+            for (int q = 0; q < 8; ++q) pw[q] = make_int4(0, 0, 0, 0);
         }
-        const int32_t *rv = reinterpret_cast<const int32_t *>(re);
-        const int32_t *iv = reinterpret_cast<const int32_t *>(im);
+        const uint64_t *wv = reinterpret_cast<const uint64_t *>(w);
         int2 *row = stage + ri * DUMP_PITCH + BLK * cb + cj0;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) row[e] = make_int2(rv[e], iv[e]);
+        for (int e = 0; e < 16; ++e) row[e] = make_int2(pair_re(wv[e]), pair_im(wv[e]));
     }
     __syncthreads();
     const int col = t & (TILE - 1);
