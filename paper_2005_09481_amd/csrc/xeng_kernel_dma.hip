@@ -65,10 +65,20 @@ constexpr int AHEAD = NSLOT - 1;            // stages issued ahead
 constexpr int DMA_A = A_STAGE / 1024;       // 1 KB DMA instructions per stage: 8
 constexpr int DMA_B = B_STAGE / 1024;       // 16
 
+// With eight waves, the DMA may be left to one wave per SIMD (the other
+// wave's MFMAs then run while the issuing wave waits to issue).
+#ifndef XENG_DMA_SPLIT
+#define XENG_DMA_SPLIT 1
+#endif
+#ifndef XENG_DMA_SEL
+#define XENG_DMA_SEL 0
+#endif
+
 template <int NW> struct Layout {
     static constexpr int WB_WAVES = NW / 2;                  // waves across the 256 columns
     static constexpr int BW = 8 / WB_WAVES;                  // B blocks per wave
-    static constexpr int DMA_PER_WAVE = (DMA_A + DMA_B) / NW;
+    static constexpr int DMA_WAVES = (NW == 8 && XENG_DMA_SPLIT) ? 4 : NW;   // waves that issue DMA
+    static constexpr int DMA_PER_WAVE = (DMA_A + DMA_B) / DMA_WAVES;
     static constexpr int MFMA_PER_K = 4 * BW;                // MFMAs per k-step
     static constexpr int READS_PER_K = 2 + BW;               // transposed reads per k-step
     static constexpr int VALU_PER_MFMA = NW == 4 ? 3 : 4;    // unpack share between MFMAs
@@ -100,38 +110,17 @@ struct Tile {
     int t0, t1;
 };
 
-// One 16-byte-per-lane DMA into LDS at byte address `lds_addr` + 16 * lane,
+// 16-byte-per-lane DMAs into LDS at byte address `lds_addr` + 16 * lane,
 // written as inline assembly so that the compiler, which cannot tell that
 // reads of other ring slots never alias the slot being filled, does not
 // drain every load in flight before each LDS read; the ring's own vmcnt
-// waits order the accesses.  The instruction has no register result; M0
-// (its LDS base) is saved and restored around it.  Wait states: one between
-// an SALU write of M0 and the DMA; five between a VALU write of an SGPR
-// (readfirstlane) and a memory instruction that reads it as its base, which
-// the scalar-base form covers with s_nop 4 whatever the compiler placed
-// before the statement.
+// waits order the accesses.  The instructions have no register result; M0
+// (their LDS base) is saved and restored around them.  Wait states: one
+// between an SALU write of M0 and the DMA; five between a VALU write of an
+// SGPR (readfirstlane) and a memory instruction that reads it as its base.
+// (readfirstlane is a no-op on values already in scalar registers; it
+// returns a signed int, so each half of a pointer is widened as unsigned.)
 //
-// Scalar-base form: wave-uniform 64-bit base + per-lane 32-bit offset.
-__device__ __forceinline__ void dma16_s(const uint8_t *base, uint32_t lane_off, uint32_t lds_addr)
-{
-    // (no-ops on values already in scalar registers; readfirstlane returns a
-    // signed int: widen each half as unsigned)
-    const uint64_t b = (uint64_t)(uintptr_t)base;
-    const uint32_t b_hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
-    const uint32_t b_lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)b);
-    const uint64_t sb = ((uint64_t)b_hi << 32) | (uint64_t)b_lo;
-    const uint32_t sl = (uint32_t)__builtin_amdgcn_readfirstlane(lds_addr);
-    uint32_t saved;
-    asm volatile("s_mov_b32 %0, m0\n\t"
-                 "s_mov_b32 m0, %3\n\t"
-                 "s_nop 4\n\t"
-                 "global_load_lds_dwordx4 %1, %2\n\t"
-                 "s_mov_b32 m0, %0"
-                 : "=&s"(saved)
-                 : "v"(lane_off), "s"(sb), "s"(sl)
-                 : "memory");
-}
-
 // Vector-address form: a 64-bit address per lane.
 __device__ __forceinline__ void dma16_v(const uint8_t *addr, uint32_t lds_addr)
 {
@@ -145,6 +134,70 @@ __device__ __forceinline__ void dma16_v(const uint8_t *addr, uint32_t lds_addr)
                  : "=&s"(saved)
                  : "v"(addr), "s"(sl)
                  : "memory");
+}
+
+// Scalar-base form, wave-uniform 64-bit base + per-lane 32-bit offsets: a
+// whole stage's share of DMAs (K = 6 or 3) in one statement:
+// M0 saved once, one s_nop 4 ahead of the first instruction (covering a
+// VALU write of any SGPR operand, which the statement's own instructions
+// never make), and between instructions only the one wait state an SALU
+// write of M0 needs before an LDS DMA.
+template <int K>
+__device__ __forceinline__ void dma16_s_stage(const uint8_t *base, const uint32_t (&lane_off)[K],
+                                              const uint32_t (&lds_addr)[K])
+{
+    static_assert(K == 6 || K == 3, "6 or 3 instructions per wave");
+    const uint64_t b = (uint64_t)(uintptr_t)base;
+    const uint32_t b_hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    const uint32_t b_lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint64_t sb = ((uint64_t)b_hi << 32) | (uint64_t)b_lo;
+    uint32_t sl[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) sl[k] = (uint32_t)__builtin_amdgcn_readfirstlane(lds_addr[k]);
+    uint32_t saved;
+    if constexpr (K == 6) {
+        asm volatile("s_mov_b32 %0, m0\n\t"
+                     "s_mov_b32 m0, %8\n\t"
+                     "s_nop 4\n\t"
+                     "global_load_lds_dwordx4 %1, %7\n\t"
+                     "s_mov_b32 m0, %9\n\t"
+                     "s_nop 0\n\t"
+                     "global_load_lds_dwordx4 %2, %7\n\t"
+                     "s_mov_b32 m0, %10\n\t"
+                     "s_nop 0\n\t"
+                     "global_load_lds_dwordx4 %3, %7\n\t"
+                     "s_mov_b32 m0, %11\n\t"
+                     "s_nop 0\n\t"
+                     "global_load_lds_dwordx4 %4, %7\n\t"
+                     "s_mov_b32 m0, %12\n\t"
+                     "s_nop 0\n\t"
+                     "global_load_lds_dwordx4 %5, %7\n\t"
+                     "s_mov_b32 m0, %13\n\t"
+                     "s_nop 0\n\t"
+                     "global_load_lds_dwordx4 %6, %7\n\t"
+                     "s_mov_b32 m0, %0"
+                     : "=&s"(saved)
+                     : "v"(lane_off[0]), "v"(lane_off[1]), "v"(lane_off[2]), "v"(lane_off[3]),
+                       "v"(lane_off[4]), "v"(lane_off[5]), "s"(sb), "s"(sl[0]), "s"(sl[1]), "s"(sl[2]),
+                       "s"(sl[3]), "s"(sl[4]), "s"(sl[5])
+                     : "memory");
+    } else {
+        asm volatile("s_mov_b32 %0, m0\n\t"
+                     "s_mov_b32 m0, %5\n\t"
+                     "s_nop 4\n\t"
+                     "global_load_lds_dwordx4 %1, %4\n\t"
+                     "s_mov_b32 m0, %6\n\t"
+                     "s_nop 0\n\t"
+                     "global_load_lds_dwordx4 %2, %4\n\t"
+                     "s_mov_b32 m0, %7\n\t"
+                     "s_nop 0\n\t"
+                     "global_load_lds_dwordx4 %3, %4\n\t"
+                     "s_mov_b32 m0, %0"
+                     : "=&s"(saved)
+                     : "v"(lane_off[0]), "v"(lane_off[1]), "v"(lane_off[2]), "s"(sb), "s"(sl[0]), "s"(sl[1]),
+                       "s"(sl[2])
+                     : "memory");
+    }
 }
 
 // Geometry of DMA instruction `inst` (0..23) of a stage for this lane: its
@@ -169,6 +222,13 @@ __device__ __forceinline__ void dma_geom(int inst, int lane, int row0, int col0,
     }
 }
 
+// Index of this wave among the DMA-issuing waves, or -1.
+template <int NW> __device__ __forceinline__ int dma_wave(int wave)
+{
+    if (Layout<NW>::DMA_WAVES == NW) return wave;
+    return XENG_DMA_SEL == 0 ? (wave < 4 ? wave : -1) : ((wave & 1) == 0 ? wave >> 1 : -1);
+}
+
 // Per-lane byte offsets (row * stride + input) of this wave's DMA
 // instructions from a stage's first row, fixed for a piece.
 template <int NW> struct DmaLane {
@@ -181,13 +241,14 @@ __device__ __forceinline__ void dma_lane_setup(DmaLane<NW> &dl, const Tile &tl, 
 #pragma unroll
     for (int k = 0; k < Layout<NW>::DMA_PER_WAVE; ++k) {
         int lds_off, t, in;
-        dma_geom(wave + NW * k, lane, tl.row0, tl.col0, lds_off, t, in);
+        dma_geom(dma_wave<NW>(wave) + Layout<NW>::DMA_WAVES * k, lane, tl.row0, tl.col0, lds_off, t, in);
         dl.off[k] = (uint32_t)((int64_t)t * tl.stride) + (uint32_t)in;
     }
 }
 
-// This wave's share of one stage's DMA: instructions wave, wave + NW, ... of
-// the 24.  Rows at or past t1 (the last, partial stage of a piece, and stages
+// This wave's share of one stage's DMA: instructions dw, dw + DMA_WAVES, ...
+// of the 24, dw being the wave's index among the issuing waves (the others
+// issue none).  Rows at or past t1 (the last, partial stage of a piece, and stages
 // past its end, issued so that the count of loads in flight stays
 // constant) are read from the zero-sample buffer, so that every stage the
 // compute loop sees is whole.
@@ -195,20 +256,24 @@ template <int NW>
 __device__ __forceinline__ void issue_stage(uint32_t slot_addr, const Tile &tl, const DmaLane<NW> &dl, int stage,
                                             int wave, int lane)
 {
+    const int dw = dma_wave<NW>(wave);
+    if (dw < 0) return;
     const int ts = tl.t0 + stage * STAGE;
     if (ts + STAGE <= tl.t1) {
         const uint8_t *row = tl.samples + (int64_t)ts * tl.stride;
+        uint32_t lds[Layout<NW>::DMA_PER_WAVE];
 #pragma unroll
         for (int k = 0; k < Layout<NW>::DMA_PER_WAVE; ++k) {
             int lds_off, t, in;
-            dma_geom(wave + NW * k, lane, tl.row0, tl.col0, lds_off, t, in);
-            dma16_s(row, dl.off[k], slot_addr + (uint32_t)lds_off);
+            dma_geom(dw + Layout<NW>::DMA_WAVES * k, lane, tl.row0, tl.col0, lds_off, t, in);
+            lds[k] = slot_addr + (uint32_t)lds_off;
         }
+        dma16_s_stage<Layout<NW>::DMA_PER_WAVE>(row, dl.off, lds);
     } else {
 #pragma unroll
         for (int k = 0; k < Layout<NW>::DMA_PER_WAVE; ++k) {
             int lds_off, t, in;
-            dma_geom(wave + NW * k, lane, tl.row0, tl.col0, lds_off, t, in);
+            dma_geom(dw + Layout<NW>::DMA_WAVES * k, lane, tl.row0, tl.col0, lds_off, t, in);
             const uint8_t *src =
                 ts + t < tl.t1 ? tl.samples + (int64_t)(ts + t) * tl.stride + in : tl.zeros;
             dma16_v(src, slot_addr + (uint32_t)lds_off);
@@ -511,7 +576,7 @@ constexpr int DMA_LDS_BYTES = dma::NSLOT * dma::SLOT;
 
 // Waves per workgroup of the launched instance (4 or 8).
 #ifndef XENG_DMA_WAVES
-#define XENG_DMA_WAVES 4
+#define XENG_DMA_WAVES 8
 #endif
 static_assert(XENG_DMA_WAVES == 4 || XENG_DMA_WAVES == 8, "4 or 8 waves");
 
