@@ -452,6 +452,31 @@ __device__ __forceinline__ void run_piece(Acc<NW> &acc, uint32_t ring, const Til
     __syncthreads();       // the next piece's DMA reuses the slots
 }
 
+// A wave whose accumulator region lies wholly below the diagonal: its
+// products would never be stored, so it computes nothing (which also spares
+// the power that work would draw), but it keeps its share of the
+// workgroup's DMA and passes the same barriers as run_piece.
+template <int NW>
+__device__ __forceinline__ void idle_piece(uint32_t ring, const Tile &tl, int wave, int lane)
+{
+    const int ns = (tl.t1 - tl.t0 + STAGE - 1) / STAGE;
+    DmaLane<NW> dl;
+    dma_lane_setup<NW>(dl, tl, wave, lane);
+    __builtin_amdgcn_s_waitcnt(XENG_VMCNT(0));
+#pragma unroll
+    for (int d = 0; d < AHEAD; ++d) issue_stage<NW>(ring + d * SLOT, tl, dl, d, wave, lane);
+    wait_stage_and_sync<NW>();
+    int cur = 0;
+    for (int s = 0; s < ns; ++s) {
+        const int iss = cur == 0 ? NSLOT - 1 : cur - 1;
+        issue_stage<NW>(ring + iss * SLOT, tl, dl, s + AHEAD, wave, lane);
+        wait_stage_and_sync<NW>();
+        cur = cur == NSLOT - 1 ? 0 : cur + 1;
+    }
+    __builtin_amdgcn_s_waitcnt(XENG_VMCNT(0));
+    __syncthreads();
+}
+
 // Accumulators hold 256x the stored values (both operands carry 16x the
 // sample parts), so a flush adds acc >> 8; every value is a multiple of
 // 256, so this is exact.  Pairs go to the slot as packed 64-bit words (see
@@ -528,11 +553,15 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
         tl.col0 = __builtin_amdgcn_readfirstlane(tj2 * WB_COLS);
         tl.t0 = __builtin_amdgcn_readfirstlane(pce.t0);
         tl.t1 = __builtin_amdgcn_readfirstlane(pce.t1_atomic & 0x7FFFFFFF);
-        // this wave's accumulator tile; a half below the diagonal is
-        // computed (the workgroup stays in step) but not stored
+        // this wave's accumulator tile; a region wholly below the diagonal
+        // is neither computed nor stored (the wave stays in step for the
+        // workgroup's DMA and barriers)
         const int tj = 2 * tj2 + wb / (L::WB_WAVES / 2);
         const int cb0 = (wb % (L::WB_WAVES / 2)) * L::BW;   // first column block in the tile
         const bool valid = tj >= ti && tj < jd.nt;
+        // rows 64 wa.. of tile ti against columns 32 cb0 .. 32 (cb0 + BW) - 1
+        // of tile tj: wholly below the diagonal?
+        const bool below = WA_ROWS * (tj - ti) + BLK * (cb0 + L::BW) <= 64 * wa;
 
         Acc<NW> acc;
 #pragma unroll
@@ -544,12 +573,14 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
                     acc.re[a][b][r] = 0;
                     acc.im[a][b][r] = 0;
                 }
-        if (jd.flags & JOB_RE_LOW)
+        if (below)
+            idle_piece<NW>(ring, tl, wave, lane);
+        else if (jd.flags & JOB_RE_LOW)
             run_piece<NW, true>(acc, ring, tl, wave, lane, a_lane, b_lane);
         else
             run_piece<NW, false>(acc, ring, tl, wave, lane, a_lane, b_lane);
 
-        if (valid) {
+        if (valid && !below) {
             const int64_t tile_idx = (int64_t)ti * jd.nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);
             gw64 *tb = (gw64 *)(jd.acc + tile_idx * TILE_I32) + lane;
             if (atomic) {
