@@ -30,8 +30,8 @@ struct Plan {
 //
 // Square: units are the tiles (ti <= tj) of 128 x 128.  Wide: units are
 // workgroup tiles (I, J2) of 128 rows x 256 columns, i.e. accumulator tiles
-// (I, 2 J2) and (I, 2 J2 + 1), for every I <= 2 J2 + 1 (the half below the
-// diagonal, if any, is computed but not stored).
+// (I, 2 J2) and (I, 2 J2 + 1), for every I <= 2 J2 + 1 (for I = 2 J2 + 1
+// the left tile lies below the diagonal: the DMA kernel leaves it out).
 Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages,
                TileShape shape = TileShape::Square);
 
