@@ -317,6 +317,19 @@ int xeng_server_last_dump(xeng_server *s, int32_t channel, int32_t *out);
  */
 int xeng_set_tuning(int32_t wgs_per_cu, int32_t min_stages, int32_t kernel);
 
+/*
+ * Clock probe, for measurement (results never depend on it).  `dev_buf` is
+ * device memory on `device` of at least 4 int64, or NULL to stop.  While
+ * set, every launch of the wide (DMA) correlation kernel on that device
+ * stores, from its workgroup 0, the shader-clock cycle counter and the
+ * 100 MHz real-time counter at the workgroup's start ([0], [1]) and end
+ * ([2], [3]); the caller derives the shader clock the launch ran at as
+ * ([2] - [0]) / (([3] - [1]) / 1e8).  The buffer stays the caller's and must
+ * outlive the launches that write it.  XENG_EINVAL for a negative device,
+ * XENG_EDEVICE if the device cannot be set up.
+ */
+int xeng_clock_probe(int32_t device, int64_t *dev_buf);
+
 #ifdef __cplusplus
 }
 #endif

@@ -92,6 +92,7 @@ struct DeviceState {
     JobTable ring[JOB_RING];
     int ring_next = 0;
     std::unordered_map<std::string, Tuning> tuned;   // job sizes -> autotuned configuration
+    std::atomic<int64_t *> clock{nullptr};             // xeng_clock_probe buffer
 };
 
 std::mutex g_states_mu;
@@ -395,6 +396,7 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
         std::memset(&a.job0, 0, sizeof a.job0);
         a.jobs = tb.d;
         a.zeros = st->d_zeros;
+        a.clock = st->clock.load();
         a.pieces = dp.d_pieces;
         a.wg_off = dp.d_off;
         e = launch(a, dp.grid, part.dma, part.flags_and, stream);
@@ -490,6 +492,7 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_
     a.job0 = make_job(ctx, slot, d_samples, row_stride, true);
     a.jobs = nullptr;
     a.zeros = ctx->st->d_zeros;
+    a.clock = ctx->st->clock.load();
     // held through the launch so that no other thread evicts the plan first
     std::lock_guard<std::mutex> lk(ctx->st->mu);
     const Tuning tu = tuning_for(ctx->st, &pj, 1);
@@ -719,6 +722,8 @@ int xeng_batch_launch(xeng_batch *b, void *hip_stream)
         a.pieces = l.d_pieces;
         a.wg_off = l.d_off;
         a.zeros = b->zeros;
+        DeviceState *bst = device_state(b->device);
+        a.clock = bst ? bst->clock.load() : nullptr;
         hipError_t e = launch(a, l.grid, l.dma, l.flags_and, stream);
         if (e != hipSuccess) return map_err(e);
     }
@@ -807,6 +812,17 @@ int xeng_autotune(const xeng_job *jobs, int32_t n_jobs, int32_t iters, void *hip
         best->reserved = 0;
         best->us_per_launch = best_us;
     }
+    return XENG_OK;
+}
+
+int xeng_clock_probe(int32_t device, int64_t *dev_buf)
+{
+    if (device < 0) return XENG_EINVAL;
+    DeviceGuard guard(device);
+    if (!guard.ok) return XENG_EDEVICE;
+    DeviceState *st = device_state(device);
+    if (!st) return XENG_EDEVICE;
+    st->clock.store(dev_buf);
     return XENG_OK;
 }
 

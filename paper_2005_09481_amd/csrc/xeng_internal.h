@@ -98,6 +98,7 @@ struct KernelArgs {
     const Piece *pieces;
     const int32_t *wg_off;    // pieces of workgroup w: [wg_off[w], wg_off[w+1])
     const uint8_t *zeros;     // ZERO_BYTES bytes of zero samples (0x88), 16-byte aligned
+    int64_t *clock;           // optional (DMA kernel): workgroup 0 stores {shader cycles, 100 MHz time} at start and end
 };
 constexpr int ZERO_BYTES = 256;
 

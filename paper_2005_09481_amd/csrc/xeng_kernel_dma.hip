@@ -538,6 +538,12 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
     const uint32_t a_lane = GRP_A * (grp >> 1) + 128 * (grp & 1) + 8 * jl + 512 * wa;
     const uint32_t b_lane = A_STAGE + GRP_B * (grp >> 1) + 128 * (grp & 1) + 8 * jl + 256 * L::BW * wb;
 
+    // clock probe (measurement only): workgroup 0's start and end
+    const bool stamp = args.clock != nullptr && blockIdx.x == 0 && tid == 0;
+    if (stamp) {
+        args.clock[0] = (int64_t)__builtin_amdgcn_s_memtime();
+        args.clock[1] = (int64_t)__builtin_amdgcn_s_memrealtime();
+    }
     const int p_begin = args.wg_off[blockIdx.x], p_end = args.wg_off[blockIdx.x + 1];
     for (int pi = p_begin; pi < p_end; ++pi) {
         const Piece pce = args.pieces[pi];
@@ -598,6 +604,10 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
                 flush_owned<NW>(tb, acc, wa, cb0, false);
             }
         }
+    }
+    if (stamp) {
+        args.clock[2] = (int64_t)__builtin_amdgcn_s_memtime();
+        args.clock[3] = (int64_t)__builtin_amdgcn_s_memrealtime();
     }
 }
 

@@ -108,6 +108,7 @@ def lib() -> ctypes.CDLL:
         "xeng_plan_inspect": (i64, [ctypes.POINTER(i32), ctypes.POINTER(i64), i32, i32, i32, i32,
                                     ctypes.POINTER(_PieceInfo), i64]),
         "xeng_set_tuning": (ctypes.c_int, [i32, i32, i32]),
+        "xeng_clock_probe": (ctypes.c_int, [i32, vp]),
         "xeng_batch_create": (ctypes.c_int, [ctypes.POINTER(_Job), i32, ctypes.POINTER(vp)]),
         "xeng_batch_launch": (ctypes.c_int, [vp, vp]),
         "xeng_batch_note_replays": (ctypes.c_int, [vp, i64]),
@@ -156,6 +157,29 @@ def set_tuning(wgs_per_cu: int = 0, min_stages: int = 0, kernel: int = -1):
     per CU, minimum piece length in 64-sample stages, kernel selection
     (XENG_KERNEL_AUTO / XENG_KERNEL_GENERAL; -1 keeps the current one)."""
     _check(lib().xeng_set_tuning(wgs_per_cu, min_stages, kernel), "xeng_set_tuning")
+
+
+def clock_probe(buf=None, device: int = 0):
+    """Clock probe (``xeng_clock_probe``, measurement only): while set, every
+    wide-kernel launch on ``device`` stores, from its workgroup 0, the shader
+    cycle counter and the 100 MHz real-time counter at the workgroup's start
+    and end into ``buf`` (an int64 device tensor of >= 4 elements); None
+    stops it.  ``sclk_ghz(buf)`` turns the four values into a clock."""
+    if buf is not None:
+        import torch
+        if buf.dtype != torch.int64 or buf.numel() < 4 or not buf.is_cuda or not buf.is_contiguous():
+            raise ValueError("clock_probe needs a contiguous int64 device tensor of >= 4 elements")
+        ptr = ctypes.c_void_p(buf.data_ptr())
+    else:
+        ptr = ctypes.c_void_p(0)
+    _check(lib().xeng_clock_probe(device, ptr), "xeng_clock_probe")
+
+
+def sclk_ghz(buf) -> float:
+    """Shader clock of the probed launch from its four counter values."""
+    c = [int(v) for v in buf[:4].tolist()]
+    dt_s = (c[3] - c[1]) / 1e8
+    return (c[2] - c[0]) / dt_s / 1e9 if dt_s > 0 else float("nan")
 
 
 def _stream_handle(stream, device):
