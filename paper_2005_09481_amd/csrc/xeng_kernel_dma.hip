@@ -340,13 +340,22 @@ __device__ __forceinline__ void unpack_k(Ops<NW> &o, const Raw<NW> &r)
     }
 }
 
-template <int NW>
+// DIAG: the wave's 2 x 2 blocks sit on the diagonal (eight waves, rows
+// 64 wa.. against columns 64 wa.. of a diagonal tile); block (1, 0) lies
+// strictly below it and is skipped.
+template <int NW, bool DIAG> __device__ __forceinline__ constexpr bool skip_block(int a, int b)
+{
+    return DIAG && a == 1 && b == 0;
+}
+
+template <int NW, bool DIAG>
 __device__ __forceinline__ void mfma_k(Acc<NW> &acc, const Ops<NW> &o)
 {
 #pragma unroll
     for (int b = 0; b < Layout<NW>::BW; ++b)
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
+            if (skip_block<NW, DIAG>(a, b)) continue;
             const v4i re_a = __builtin_shufflevector(o.a[a], o.a[a], 0, 1, 2, 3);
             const v4i im_a = __builtin_shufflevector(o.a[a], o.a[a], 2, 3, 4, 5);
             acc.re[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(re_a, o.b[b], acc.re[a][b], 0, 0, 0);
@@ -358,15 +367,17 @@ __device__ __forceinline__ void mfma_k(Acc<NW> &acc, const Ops<NW> &o)
 // unpack of the next k-step (which the matrix core's 32-cycle MFMAs hide)
 // and, after the first few, one of the LDS reads of a later k-step -- spread
 // out rather than issued as a burst that would stall the wave at issue.
-template <int NW>
+template <int NW, bool DIAG>
 __device__ __forceinline__ void kstep_schedule()
 {
     using L = Layout<NW>;
+    constexpr int MFMAS = L::MFMA_PER_K - (DIAG ? 2 : 0);
+    constexpr int VALU = DIAG ? (L::VALU_PER_MFMA * L::MFMA_PER_K + MFMAS - 1) / MFMAS : L::VALU_PER_MFMA;
 #pragma unroll
-    for (int m = 0; m < L::MFMA_PER_K; ++m) {
+    for (int m = 0; m < MFMAS; ++m) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
         if (m < L::READS_PER_K) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read
-        __builtin_amdgcn_sched_group_barrier(0x002, L::VALU_PER_MFMA, 0);   // VALU
+        __builtin_amdgcn_sched_group_barrier(0x002, VALU, 0);   // VALU
     }
 }
 
@@ -389,7 +400,7 @@ __device__ __forceinline__ void wait_stage_and_sync()
 // the barrier of iteration s - 1; that barrier sits before the first read of
 // stage s.  The last iteration's reads of "stage ns" touch a slot whose
 // contents are never used.
-template <int NW, bool RE_LOW>
+template <int NW, bool RE_LOW, bool DIAG>
 __device__ __forceinline__ void run_piece(Acc<NW> &acc, uint32_t ring, const Tile &tl, int wave, int lane,
                                           uint32_t a_lane, uint32_t b_lane)
 {
@@ -424,27 +435,27 @@ __device__ __forceinline__ void run_piece(Acc<NW> &acc, uint32_t ring, const Til
         // k-step 0
         read_k<NW>(r0, pa, pb, 2);
         unpack_k<NW, RE_LOW>(u1, r1);
-        mfma_k<NW>(acc, u0);
-        kstep_schedule<NW>();
+        mfma_k<NW, DIAG>(acc, u0);
+        kstep_schedule<NW, DIAG>();
         __builtin_amdgcn_sched_barrier(0);
         // k-step 1
         read_k<NW>(r1, pa, pb, 3);
         unpack_k<NW, RE_LOW>(u0, r0);
-        mfma_k<NW>(acc, u1);
-        kstep_schedule<NW>();
+        mfma_k<NW, DIAG>(acc, u1);
+        kstep_schedule<NW, DIAG>();
         __builtin_amdgcn_sched_barrier(0);
         // k-step 2: stage s + 1 must be in LDS before its first read
         wait_stage_and_sync<NW>();
         read_k<NW>(r0, qa, qb, 0);
         unpack_k<NW, RE_LOW>(u1, r1);
-        mfma_k<NW>(acc, u0);
-        kstep_schedule<NW>();
+        mfma_k<NW, DIAG>(acc, u0);
+        kstep_schedule<NW, DIAG>();
         __builtin_amdgcn_sched_barrier(0);
         // k-step 3
         read_k<NW>(r1, qa, qb, 1);
         unpack_k<NW, RE_LOW>(u0, r0);
-        mfma_k<NW>(acc, u1);
-        kstep_schedule<NW>();
+        mfma_k<NW, DIAG>(acc, u1);
+        kstep_schedule<NW, DIAG>();
         __builtin_amdgcn_sched_barrier(0);
         cur = nxt;
     }
@@ -579,12 +590,21 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
                     acc.re[a][b][r] = 0;
                     acc.im[a][b][r] = 0;
                 }
+        // eight waves: a 64 x 64 region on the diagonal skips its block below it
+        const bool diag = NW == 8 && tj == ti && cb0 == 2 * wa;
         if (below)
             idle_piece<NW>(ring, tl, wave, lane);
-        else if (jd.flags & JOB_RE_LOW)
-            run_piece<NW, true>(acc, ring, tl, wave, lane, a_lane, b_lane);
-        else
-            run_piece<NW, false>(acc, ring, tl, wave, lane, a_lane, b_lane);
+        else if (jd.flags & JOB_RE_LOW) {
+            if (diag)
+                run_piece<NW, true, true>(acc, ring, tl, wave, lane, a_lane, b_lane);
+            else
+                run_piece<NW, true, false>(acc, ring, tl, wave, lane, a_lane, b_lane);
+        } else {
+            if (diag)
+                run_piece<NW, false, true>(acc, ring, tl, wave, lane, a_lane, b_lane);
+            else
+                run_piece<NW, false, false>(acc, ring, tl, wave, lane, a_lane, b_lane);
+        }
 
         if (valid && !below) {
             const int64_t tile_idx = (int64_t)ti * jd.nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);
@@ -594,6 +614,7 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
                 for (int a = 0; a < 2; ++a)
 #pragma unroll
                     for (int b = 0; b < L::BW; ++b) {
+                        if (diag && a == 1 && b == 0) continue;   // below the diagonal, never computed
                         flush_atomic(tb + ((2 * wa + a) * BLKS + cb0 + b) * BLOCK_W, acc.re[a][b], acc.im[a][b]);
                         // one block at a time: keeps the register file for the main loop
                         __builtin_amdgcn_sched_barrier(0);

@@ -64,6 +64,7 @@ def test_argument_checks_without_device(X):
     assert L.xeng_correlate_reference(None, 10, 4, 4, 0, None, None) == X.XENG_EINVAL
     assert L.xeng_set_tuning(3, 0, -1) == X.XENG_EINVAL
     assert L.xeng_set_tuning(0, 0, 7) == X.XENG_EINVAL
+    assert L.xeng_clock_probe(-1, None) == X.XENG_EINVAL
 
 
 def _check_cover(pieces, jobs, grid):

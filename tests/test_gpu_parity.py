@@ -318,3 +318,24 @@ def test_full_size_deterministic(X, full_size):
     c = X.Correlator(2048, 1)
     c.correlate(0, gpu(x))
     np.testing.assert_array_equal(c.dump(0).cpu().numpy(), v)
+
+
+def test_clock_probe_leaves_results_unchanged(X):
+    # the wide kernel's workgroup 0 stamps its start and end; the shader
+    # clock derived from the stamps is plausible, and results are unchanged
+    x = synth.uniform_bytes(512, 3000, seed=77)
+    ref = oracle.correlate(x)
+    buf = torch.zeros(8, dtype=torch.int64, device="cuda")
+    X.clock_probe(buf)
+    try:
+        got = run(X, x)
+    finally:
+        X.clock_probe(None)
+    torch.cuda.synchronize()
+    c = buf.cpu().numpy()
+    print("clock stamps", c[:4].tolist(), "sclk", X.sclk_ghz(buf), flush=True)
+    assert c[2] > c[0] > 0 and c[3] > c[1] > 0 and not c[4:].any()
+    assert 0.3 < X.sclk_ghz(buf) < 3.5
+    np.testing.assert_array_equal(got, ref)
+    with pytest.raises(ValueError):
+        X.clock_probe(torch.zeros(4, dtype=torch.int32, device="cuda"))
