@@ -206,6 +206,8 @@ def main():
     ap.add_argument("--settle-ms", type=float, default=300.0,
                     help="untimed steps for this long before the warm-up steps (clock ramp)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-clock-probe", action="store_true",
+                    help="do not stamp the shader clock of the timed launches")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", default="channel", choices=["channel", "channels16", "subarrays64", "serve"],
                     help="channel: the one-channel step (default, the JSON contract line); "
@@ -269,14 +271,16 @@ def main():
     # shader clock of the timed launches (the wide kernel's workgroup 0
     # stamps its start and end; the last launch's stamps remain)
     clk = torch.zeros(4, dtype=torch.int64, device=dev)
-    xeng.clock_probe(clk, 0)
+    if not args.no_clock_probe:
+        xeng.clock_probe(clk, 0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         step(events[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    xeng.clock_probe(None, 0)
+    if not args.no_clock_probe:
+        xeng.clock_probe(None, 0)
     sclk = xeng.sclk_ghz(clk) if int(clk[0]) != 0 else None
     kern_ms = [a.elapsed_time(b) for a, b in events]
     kern_s = float(np.mean(kern_ms)) / 1e3
