@@ -30,8 +30,11 @@
 // NW / 2; wave (wa, wb) computes rows 64wa..64wa+63 against 256 / (NW / 2)
 // columns, i.e. 2 x BW MFMA blocks for both Re and Im.  Four waves (one per
 // SIMD, 256 accumulator registers each) read the fewest operand bytes per
-// MFMA; eight (two per SIMD, 128 each) let one wave's MFMAs run while the
-// other waits on LDS, a barrier or its DMA issue.
+// MFMA; eight (two per SIMD, 128 each; the default) let one wave's MFMAs run
+// while the other waits on LDS, a barrier or its DMA issue -- with eight,
+// waves 0..3 (one per SIMD) issue all of a stage's DMA, since a burst of DMA
+// instructions holds the issuing wave for tens of cycles per instruction.
+// Regions and blocks wholly below the diagonal are not computed.
 //
 // LDS stage layout ("chunk-major" in 8-row groups): the A region holds 8
 // groups of 8 time rows x 8 chunks of 16 inputs, chunk c of row r at byte
@@ -65,13 +68,11 @@ constexpr int AHEAD = NSLOT - 1;            // stages issued ahead
 constexpr int DMA_A = A_STAGE / 1024;       // 1 KB DMA instructions per stage: 8
 constexpr int DMA_B = B_STAGE / 1024;       // 16
 
-// With eight waves, the DMA may be left to one wave per SIMD (the other
-// wave's MFMAs then run while the issuing wave waits to issue).
+// With eight waves, the DMA is left to one wave per SIMD (the other wave's
+// MFMAs then run while the issuing wave waits to issue); 0 spreads it over
+// all eight.
 #ifndef XENG_DMA_SPLIT
 #define XENG_DMA_SPLIT 1
-#endif
-#ifndef XENG_DMA_SEL
-#define XENG_DMA_SEL 0
 #endif
 
 template <int NW> struct Layout {
@@ -222,11 +223,12 @@ __device__ __forceinline__ void dma_geom(int inst, int lane, int row0, int col0,
     }
 }
 
-// Index of this wave among the DMA-issuing waves, or -1.
+// Index of this wave among the DMA-issuing waves, or -1.  Waves 0..3 sit on
+// SIMDs 0..3 (waves of a workgroup are placed on the SIMDs in turn).
 template <int NW> __device__ __forceinline__ int dma_wave(int wave)
 {
     if (Layout<NW>::DMA_WAVES == NW) return wave;
-    return XENG_DMA_SEL == 0 ? (wave < 4 ? wave : -1) : ((wave & 1) == 0 ? wave >> 1 : -1);
+    return wave < 4 ? wave : -1;
 }
 
 // Per-lane byte offsets (row * stride + input) of this wave's DMA
