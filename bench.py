@@ -77,17 +77,23 @@ def bench_serve(args, xeng, synth, torch, np):
     backlog) and the p99 frame latency stays below the export period."""
     n, frame_len, dump = 2048, 256, 128
     period_ms = dump * frame_len / 390625 * 1e3
-    n_src = 16                                   # distinct frames per channel (8 MiB), cycled
-    base = synth.stream_frames(n, n_src, seed=5)
+    # distinct frames per source, cycled: a device source holds 64 frames
+    # (32 MiB: a server running behind may take up to that many frames of a
+    # channel in one launch), a pinned host source 16
+    n_src_dev, n_src_host = 64, 16
+    base = synth.stream_frames(n, n_src_dev, seed=5)
+    base_dev = torch.from_numpy(base).cuda()
     results = []
 
     def trial(k, host):
-        srv = xeng.Server(n, max_channels=k, dump_frames=dump, launch_period_us=4000.0,
-                          ring_frames=64, max_inflight=2)
+        srv = xeng.Server(n, max_channels=k, dump_frames=dump, launch_period_us=args.serve_launch_us,
+                          ring_frames=64, max_inflight=2, stagger_exports=bool(args.serve_stagger))
         srcs = []
         for c in range(k):
-            f = torch.from_numpy(np.roll(base, c, axis=2).copy())     # distinct bytes per channel
-            f = f.pin_memory() if host else f.cuda()
+            if host:                                 # distinct bytes per channel
+                f = torch.from_numpy(np.roll(base[:n_src_host], c, axis=2).copy()).pin_memory()
+            else:
+                f = torch.roll(base_dev, c, dims=2)
             srcs.append(f)
             srv.admit(f, start_s=0.05 + 655.36e-6 * c / k)
         st = srv.run(args.serve_seconds)
@@ -97,8 +103,9 @@ def bench_serve(args, xeng, synth, torch, np):
         # latency plus two launch periods (a server that falls behind sees
         # its latency grow past the export period within the run)
         frame_ms = 655.36e-3
+        launch_ms = args.serve_launch_us / 1e3
         ok = (st["frames_dropped"] == 0 and st["p99_ms"] < period_ms and
-              st["backlog_frames"] <= k * (st["p99_ms"] + 2 * 4.0) / frame_ms)
+              st["backlog_frames"] <= k * (st["p99_ms"] + 2 * launch_ms) / frame_ms)
         r = {"k": k, "source": "host" if host else "device", "real_time": bool(ok),
              "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
              "max_ms": round(st["max_ms"], 3), "tcmacs": round(st["tcmacs"], 2),
@@ -120,7 +127,9 @@ def bench_serve(args, xeng, synth, torch, np):
            "unit": "channels (N=2048, 390625 samples/s)", "n_gpus": 1, "higher_is_better": True,
            "dtype": "int8", "data": "synthetic",
            "config": {"workload": "streaming serve, N=2048, 256-sample frames, export every 128 frames",
-                      "seconds_per_trial": args.serve_seconds},
+                      "seconds_per_trial": args.serve_seconds,
+                      "launch_period_us": args.serve_launch_us,
+                      "staggered_exports": bool(args.serve_stagger)},
            "max_k_host_frames": best["host"],
            "p99_ms_at_max_k": rt[-1]["p99_ms"] if rt else None,
            "export_period_ms": round(period_ms, 3)}
@@ -214,6 +223,11 @@ def main():
                          "channels16 / subarrays64: batched launches against plain launches; "
                          "serve: streaming channels, largest real-time K")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-launch-us", type=float, default=4000.0,
+                    help="launch period of the streaming server (frames per launch per channel)")
+    ap.add_argument("--serve-stagger", type=int, choices=(0, 1), default=1,
+                    help="1: each slot exports at its own phase of the export period "
+                         "(XENG_SERVER_STAGGER_EXPORTS); 0: every channel exports in the same launch")
     ap.add_argument("--serve-k", default="128,192,224,256,288,320,352",
                     help="channel counts to try (device-sourced frames)")
     ap.add_argument("--serve-host-k", default="16,32,48,64",

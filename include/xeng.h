@@ -115,7 +115,11 @@ typedef struct {
  * call lets one GPU serve many).  Every result equals what xeng_correlate
  * would give for that job alone.  All contexts must be on one device; a
  * (ctx, slot) pair may appear at most once per batch.  Checks every job
- * before queuing anything.
+ * before queuing anything.  Each call copies its job table and its plan
+ * (recurring job sizes are planned once; the plans are kept on the host) to
+ * the device on hip_stream through a pinned staging ring, and never
+ * synchronizes the device, so that a loop of calls with changing sizes
+ * keeps the GPU busy.  For graph capture use xeng_batch_* below.
  */
 int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream);
 
@@ -243,10 +247,20 @@ int xeng_autotune(const xeng_job *jobs, int32_t n_jobs, int32_t iters, void *hip
  * dump_frames frames into a device buffer of its own.
  */
 typedef struct xeng_server xeng_server;
+
+/*
+ * Server flag: stagger the exports.  The channel in slot s is exported when
+ * its frame count reaches m * dump_frames - phase(s), m = 1, 2, ..., with
+ * phase(s) = s * dump_frames / max_channels (so its first export covers
+ * fewer frames, every later one dump_frames).  The channels' exports then
+ * spread over the export period instead of all falling in one launch.
+ */
+#define XENG_SERVER_STAGGER_EXPORTS 2u
+
 typedef struct {
     int32_t n_inputs;         /* N of every channel */
     int32_t device;
-    uint32_t flags;           /* XENG_NIBBLE_RE_LOW or 0 */
+    uint32_t flags;           /* XENG_NIBBLE_RE_LOW, XENG_SERVER_STAGGER_EXPORTS, or 0 */
     int32_t frame_len;        /* samples per frame (CHIME-shaped: 256) */
     int32_t dump_frames;      /* frames per export; frame_len * dump_frames <= xeng_max_integration() */
     int32_t ring_frames;      /* device ring of a host-sourced channel, in frames */

@@ -69,12 +69,13 @@ struct DevicePlan {
     int32_t grid = 0;
 };
 
-// A device buffer for job tables of batched launches, reused once the
-// event recorded after its last launch has completed.
+// Staging of one batched launch: its job table and its plan, in one pinned
+// host buffer copied to one device buffer; reused once the event recorded
+// after its launch has completed.
 struct JobTable {
-    JobDesc *h = nullptr;   // pinned host staging
-    JobDesc *d = nullptr;
-    size_t cap = 0;
+    uint8_t *h = nullptr;   // pinned host staging
+    uint8_t *d = nullptr;
+    size_t cap = 0;         // bytes
     hipEvent_t ev = nullptr;
     bool pending = false;
 };
@@ -89,6 +90,11 @@ struct DeviceState {
     std::mutex mu;
     std::unordered_map<std::string, DevicePlan> plans;
     std::list<std::string> lru;
+    // plans of batched calls, kept on the host only: every batched launch
+    // copies its plan to the device with its job table, so that nothing in
+    // that path allocates, frees or copies synchronously
+    std::unordered_map<std::string, std::shared_ptr<const Plan>> host_plans;
+    std::list<std::string> host_lru;
     JobTable ring[JOB_RING];
     int ring_next = 0;
     std::unordered_map<std::string, Tuning> tuned;   // job sizes -> autotuned configuration
@@ -159,25 +165,31 @@ Tuning tuning_for(DeviceState *st, const PlanJob *jobs, int n_jobs)
     return global_tuning();
 }
 
-// Look up (or build and upload) the plan for these job sizes.  Called with
-// st->mu held and the device current.
-int get_plan(DeviceState *st, const PlanJob *jobs, int n_jobs, TileShape shape, const Tuning &tu,
-             DevicePlan *out)
+// Planner limits for a launch: workgroups and the minimum piece length.
+// The DMA kernel holds one workgroup per CU (its LDS ring fills most of the
+// CU); the general kernel fits two.
+void plan_limits(const DeviceState *st, TileShape shape, const Tuning &tu, int *max_wgs, int *min_stages)
 {
-    // the DMA kernel holds one 256-thread workgroup per CU (its LDS ring
-    // fills most of the CU); the general kernel fits two
     const int per_cu = shape == TileShape::Wide ? 1 : std::max(1, tu.wgs_per_cu);
-    const int max_wgs = st->cu_count * per_cu;
-    const int min_stages = std::max(1, tu.min_stages);
-    const std::string key = plan_key(jobs, n_jobs, max_wgs, min_stages, shape);
+    *max_wgs = st->cu_count * per_cu;
+    *min_stages = std::max(1, tu.min_stages);
+}
+
+// The cached plan for this key, if any.  Called with st->mu held.
+bool find_plan(DeviceState *st, const std::string &key, DevicePlan *out)
+{
     auto it = st->plans.find(key);
-    if (it != st->plans.end()) {
-        st->lru.remove(key);
-        st->lru.push_front(key);
-        *out = it->second;
-        return XENG_OK;
-    }
-    Plan plan = make_plan(jobs, n_jobs, max_wgs, min_stages, shape);
+    if (it == st->plans.end()) return false;
+    st->lru.remove(key);
+    st->lru.push_front(key);
+    *out = it->second;
+    return true;
+}
+
+// Upload `plan` and cache it under `key`.  Called with st->mu held and the
+// device current.
+int cache_plan(DeviceState *st, const std::string &key, const Plan &plan, DevicePlan *out)
+{
     DevicePlan dp;
     dp.grid = plan.grid;
     if (plan.grid > 0) {
@@ -210,6 +222,18 @@ int get_plan(DeviceState *st, const PlanJob *jobs, int n_jobs, TileShape shape, 
     st->lru.push_front(key);
     *out = dp;
     return XENG_OK;
+}
+
+// Look up (or build, upload and cache) the plan for these job sizes.
+// Called with st->mu held and the device current.
+int get_plan(DeviceState *st, const PlanJob *jobs, int n_jobs, TileShape shape, const Tuning &tu,
+             DevicePlan *out)
+{
+    int max_wgs, min_stages;
+    plan_limits(st, shape, tu, &max_wgs, &min_stages);
+    const std::string key = plan_key(jobs, n_jobs, max_wgs, min_stages, shape);
+    if (find_plan(st, key, out)) return XENG_OK;
+    return cache_plan(st, key, make_plan(jobs, n_jobs, max_wgs, min_stages, shape), out);
 }
 
 int map_err(hipError_t e)
@@ -358,10 +382,27 @@ std::vector<Part> split_by_kernel(const JobList &jl, const Tuning &tu)
 int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu, hipStream_t stream)
 {
     for (const Part &part : parts) {
-        DevicePlan dp;
-        int rc = get_plan(st, part.pj.data(), (int)part.pj.size(),
-                          part.dma ? TileShape::Wide : TileShape::Square, tu, &dp);
-        if (rc != XENG_OK) return rc;
+        const TileShape shape = part.dma ? TileShape::Wide : TileShape::Square;
+        int max_wgs, min_stages;
+        plan_limits(st, shape, tu, &max_wgs, &min_stages);
+        const std::string key = plan_key(part.pj.data(), (int)part.pj.size(), max_wgs, min_stages, shape);
+        std::shared_ptr<const Plan> plan;
+        auto it = st->host_plans.find(key);
+        if (it != st->host_plans.end()) {
+            plan = it->second;
+            st->host_lru.remove(key);
+            st->host_lru.push_front(key);
+        } else {
+            plan = std::make_shared<const Plan>(
+                make_plan(part.pj.data(), (int)part.pj.size(), max_wgs, min_stages, shape));
+            if ((int)st->host_plans.size() >= PLAN_CACHE_MAX) {
+                st->host_plans.erase(st->host_lru.back());
+                st->host_lru.pop_back();
+            }
+            st->host_plans.emplace(key, plan);
+            st->host_lru.push_front(key);
+        }
+        if (plan->grid <= 0) continue;
         JobTable &tb = st->ring[st->ring_next];
         st->ring_next = (st->ring_next + 1) % JOB_RING;
         hipError_t e = hipSuccess;
@@ -372,34 +413,41 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
         }
         if (!tb.ev && (e = hipEventCreateWithFlags(&tb.ev, hipEventDisableTiming)) != hipSuccess)
             return map_err(e);
-        const size_t nd = part.descs.size();
-        if (tb.cap < nd) {
+        // [job descriptors | pieces | workgroup offsets], 16-byte aligned parts
+        auto up16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
+        const size_t b_jobs = part.descs.size() * sizeof(JobDesc);
+        const size_t b_pieces = plan->pieces.size() * sizeof(Piece);
+        const size_t b_off = plan->wg_off.size() * sizeof(int32_t);
+        const size_t o_pieces = up16(b_jobs), o_off = o_pieces + up16(b_pieces);
+        const size_t bytes = o_off + b_off;
+        if (tb.cap < bytes) {
             if (tb.h) (void)hipHostFree(tb.h);
             if (tb.d) (void)hipFree(tb.d);
             tb.h = nullptr;
             tb.d = nullptr;
             tb.cap = 0;
-            const size_t cap = std::max<size_t>(nd, 64);
-            if ((e = hipHostMalloc(&tb.h, cap * sizeof(JobDesc), hipHostMallocDefault)) != hipSuccess)
-                return map_err(e);
-            if ((e = hipMalloc(&tb.d, cap * sizeof(JobDesc))) != hipSuccess) {
+            const size_t cap = std::max<size_t>(bytes + bytes / 2, 64 * sizeof(JobDesc));
+            if ((e = hipHostMalloc(&tb.h, cap, hipHostMallocDefault)) != hipSuccess) return map_err(e);
+            if ((e = hipMalloc(&tb.d, cap)) != hipSuccess) {
                 (void)hipHostFree(tb.h);
                 tb.h = nullptr;
                 return map_err(e);
             }
             tb.cap = cap;
         }
-        std::memcpy(tb.h, part.descs.data(), nd * sizeof(JobDesc));
-        e = hipMemcpyAsync(tb.d, tb.h, nd * sizeof(JobDesc), hipMemcpyHostToDevice, stream);
+        std::memcpy(tb.h, part.descs.data(), b_jobs);
+        std::memcpy(tb.h + o_pieces, plan->pieces.data(), b_pieces);
+        std::memcpy(tb.h + o_off, plan->wg_off.data(), b_off);
+        e = hipMemcpyAsync(tb.d, tb.h, bytes, hipMemcpyHostToDevice, stream);
         if (e != hipSuccess) return map_err(e);
         KernelArgs a;
         std::memset(&a.job0, 0, sizeof a.job0);
-        a.jobs = tb.d;
+        a.jobs = reinterpret_cast<const JobDesc *>(tb.d);
         a.zeros = st->d_zeros;
         a.clock = st->clock.load();
-        a.pieces = dp.d_pieces;
-        a.wg_off = dp.d_off;
-        e = launch(a, dp.grid, part.dma, part.flags_and, stream);
+        a.pieces = reinterpret_cast<const Piece *>(tb.d + o_pieces);
+        a.wg_off = reinterpret_cast<const int32_t *>(tb.d + o_off);
+        e = launch(a, plan->grid, part.dma, part.flags_and, stream);
         if (e == hipSuccess) e = hipEventRecord(tb.ev, stream);
         if (e != hipSuccess) return map_err(e);
         tb.pending = true;

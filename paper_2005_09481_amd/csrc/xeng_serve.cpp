@@ -11,7 +11,9 @@
 //     correlates every channel's available frames (up to its next dump
 //     boundary), while earlier launches may still run on the device;
 //   * exports: a channel reaching a dump boundary is dumped (with reset)
-//     into its own device buffer right after the launch that completed it;
+//     into its own device buffer right after the launch that completed it
+//     (boundaries every dump_frames frames, offset per slot with
+//     XENG_SERVER_STAGGER_EXPORTS);
 //   * admission: a channel admitted while every slot is in use waits and
 //     takes the first slot released by a channel that has finished;
 //   * latency of a frame: from its release time to the host observing the
@@ -46,6 +48,7 @@ struct Chan {
     int64_t done = 0;              // frames whose launch has completed
     int64_t dumps = 0;
     int64_t last_dump_first = -1;  // first frame of the last exported integration
+    int64_t phase = 0;             // exports at frame counts m * dump_frames - phase
     uint8_t *ring = nullptr;       // device ring for a host source
     std::deque<std::pair<int64_t, hipEvent_t>> copies;   // (frames copied up to, event)
 };
@@ -84,6 +87,13 @@ hipEvent_t get_event(xeng_server *s)
     return e;
 }
 
+// Export phase of a slot (XENG_SERVER_STAGGER_EXPORTS), else 0.
+int64_t export_phase(const xeng_server *s, int32_t slot)
+{
+    if (!(s->cfg.flags & XENG_SERVER_STAGGER_EXPORTS)) return 0;
+    return (int64_t)slot * s->cfg.dump_frames / (int64_t)s->slot_owner.size();
+}
+
 double release_time(const xeng_server *s, const Chan &c, int64_t f)
 {
     return c.start_s + (double)f * s->cfg.frame_period_us * 1e-6;
@@ -116,6 +126,7 @@ int xeng_server_create(const xeng_server_config *cfg, xeng_server **out)
     if (cfg->n_inputs < 1 || cfg->n_inputs > 65535 || cfg->frame_len < 1 || cfg->dump_frames < 1 ||
         cfg->ring_frames < 1 || cfg->frame_period_us <= 0 || cfg->launch_period_us < 0 || cfg->max_inflight < 1 ||
         cfg->max_channels < 0 || cfg->mem_budget_bytes < 0 || cfg->reserved != 0 ||
+        (cfg->flags & ~(XENG_NIBBLE_RE_LOW | XENG_SERVER_STAGGER_EXPORTS)) ||
         (int64_t)cfg->frame_len * cfg->dump_frames > xeng_max_integration())
         return XENG_EINVAL;
     const int64_t n = cfg->n_inputs;
@@ -135,7 +146,7 @@ int xeng_server_create(const xeng_server_config *cfg, xeng_server **out)
     s->cfg.max_channels = (int32_t)chans;
     s->frame_bytes = frame_bytes;
     s->out_i32 = out_bytes / 4;
-    xeng_config c{cfg->n_inputs, (int32_t)chans, cfg->device, cfg->flags, 0};
+    xeng_config c{cfg->n_inputs, (int32_t)chans, cfg->device, cfg->flags & XENG_NIBBLE_RE_LOW, 0};
     int rc = xeng_create(&c, &s->ctx);
     if (rc != XENG_OK) {
         delete s;
@@ -183,6 +194,7 @@ int xeng_server_admit(xeng_server *s, const uint8_t *frames, int64_t n_frames, i
         c.slot = s->free_slots.back();
         s->free_slots.pop_back();
         c.state = 1;
+        c.phase = export_phase(s, c.slot);
         s->slot_owner[(size_t)c.slot] = (int32_t)s->chans.size();
     }
     s->chans.push_back(c);
@@ -242,6 +254,7 @@ int xeng_server_run(xeng_server *s, double seconds, xeng_server_stats *stats)
                 c.slot = s->free_slots.back();
                 s->free_slots.pop_back();
                 c.state = 1;
+                c.phase = export_phase(s, c.slot);
                 s->slot_owner[(size_t)c.slot] = (int32_t)k;
                 if (c.start_s < t) c.start_s = t;   // its stream starts once admitted
             }
@@ -297,7 +310,7 @@ int xeng_server_run(xeng_server *s, double seconds, xeng_server_stats *stats)
                 Chan &c = s->chans[k];
                 if (c.state != 1 || c.available <= c.launched) continue;
                 const int64_t f0 = c.launched;
-                const int64_t boundary = (f0 / cf.dump_frames + 1) * cf.dump_frames;
+                const int64_t boundary = ((f0 + c.phase) / cf.dump_frames + 1) * cf.dump_frames - c.phase;
                 const int64_t wrap_n = c.src_host ? cf.ring_frames : c.src_frames;
                 const int64_t wrap = (f0 / wrap_n + 1) * wrap_n;
                 const int64_t f1 = std::min({c.available, boundary, wrap});
@@ -321,7 +334,7 @@ int xeng_server_run(xeng_server *s, double seconds, xeng_server_stats *stats)
                     Chan &c = s->chans[(size_t)k];
                     rc = xeng_dump(s->ctx, c.slot, s->d_out + (int64_t)c.slot * s->out_i32, 1, s->compute);
                     if (rc != XENG_OK) break;
-                    c.last_dump_first = c.launched - cf.dump_frames;
+                    c.last_dump_first = std::max<int64_t>(0, c.launched - cf.dump_frames);
                     ++c.dumps;
                 }
                 if (rc != XENG_OK) break;

@@ -22,6 +22,7 @@ XENG_EDEVICE = -4
 XENG_EBUSY = -5
 XENG_ENOTSUP = -6
 XENG_NIBBLE_RE_LOW = 1
+XENG_SERVER_STAGGER_EXPORTS = 2
 XENG_KERNEL_AUTO = 0
 XENG_KERNEL_GENERAL = 1
 
@@ -378,13 +379,16 @@ class Server:
     """Streaming server (``xeng_server_*``): channels of N inputs ingest
     frames at a fixed cadence; one batched launch about every
     ``launch_period_us`` integrates every channel's new frames; each channel
-    is exported every ``dump_frames`` frames."""
+    is exported every ``dump_frames`` frames (``stagger_exports``: at frame
+    counts offset per slot, XENG_SERVER_STAGGER_EXPORTS)."""
 
     def __init__(self, n_inputs: int, device: int = 0, frame_len: int = 256, dump_frames: int = 128,
                  ring_frames: int = 64, max_inflight: int = 2, max_channels: int = 0,
                  frame_period_us: float = 655.36, launch_period_us: float = 5000.0,
-                 mem_budget_bytes: int = 0, re_low: bool = False):
-        cfg = _ServerConfig(n_inputs, device, XENG_NIBBLE_RE_LOW if re_low else 0, frame_len,
+                 mem_budget_bytes: int = 0, re_low: bool = False, stagger_exports: bool = False):
+        flags = (XENG_NIBBLE_RE_LOW if re_low else 0) | (XENG_SERVER_STAGGER_EXPORTS if stagger_exports else 0)
+        self.dump_frames = dump_frames
+        cfg = _ServerConfig(n_inputs, device, flags, frame_len,
                             dump_frames, ring_frames, max_inflight, max_channels, frame_period_us,
                             launch_period_us, mem_budget_bytes, 0)
         h = ctypes.c_void_p()

@@ -65,6 +65,11 @@ def test_argument_checks_without_device(X):
     assert L.xeng_set_tuning(3, 0, -1) == X.XENG_EINVAL
     assert L.xeng_set_tuning(0, 0, 7) == X.XENG_EINVAL
     assert L.xeng_clock_probe(-1, None) == X.XENG_EINVAL
+    # server configurations are checked before any device call: unknown flag
+    # bits, a zero export cadence and a nonzero reserved field are refused
+    for flags, dump, reserved in ((4, 8, 0), (1 << 31, 8, 0), (0, 0, 0), (X.XENG_SERVER_STAGGER_EXPORTS, 8, 1)):
+        sc = X._ServerConfig(64, 0, flags, 256, dump, 16, 2, 4, 655.36, 1000.0, 0, reserved)
+        assert L.xeng_server_create(ctypes.byref(sc), ctypes.byref(h)) == X.XENG_EINVAL
 
 
 def _check_cover(pieces, jobs, grid):

@@ -59,6 +59,33 @@ def test_exports_match_oracle_and_alone(X):
     solo.close()
 
 
+def test_staggered_exports(X):
+    # XENG_SERVER_STAGGER_EXPORTS: slot s exports at frame counts
+    # m * DUMP - s * DUMP / slots; every export still equals the oracle over
+    # the frames it covers
+    srcs = [frames_of(seed=[8, c]) for c in range(4)]
+    srv = X.Server(N, dump_frames=DUMP, max_channels=4, launch_period_us=2000.0, stagger_exports=True)
+    chans = [srv.admit(torch.from_numpy(f).cuda(), start_s=0.001 * c, total_frames=3 * DUMP)
+             for c, f in enumerate(srcs)]
+    st = srv.run(0.4)
+    print("staggered exports", st, flush=True)
+    assert st["frames_done"] == 4 * 3 * DUMP and st["frames_dropped"] == 0
+    firsts = set()
+    for c, f in zip(chans, srcs):
+        info = srv.channel_info(c)
+        phase = info["slot"] * DUMP // 4
+        assert info["dumps"] == 3
+        # exports after DUMP - phase, 2 DUMP - phase, 3 DUMP - phase frames
+        # (the first integration is the short one); the frames past the last
+        # export are dropped when the channel finishes
+        first = info["last_dump_first_frame"]
+        assert first == 2 * DUMP - phase
+        np.testing.assert_array_equal(srv.last_dump(c).cpu().numpy(), expected(f, first))
+        firsts.add(first)
+    assert len(firsts) == 4                      # four different phases
+    srv.close()
+
+
 def test_admission_waits_for_a_free_slot(X):
     # three channels, two slots: the third is admitted when one finishes
     srcs = [frames_of(seed=[6, c]) for c in range(3)]
