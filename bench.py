@@ -225,10 +225,10 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-launch-us", type=float, default=4000.0,
                     help="launch period of the streaming server (frames per launch per channel)")
-    ap.add_argument("--serve-stagger", type=int, choices=(0, 1), default=1,
+    ap.add_argument("--serve-stagger", type=int, choices=(0, 1), default=0,
                     help="1: each slot exports at its own phase of the export period "
                          "(XENG_SERVER_STAGGER_EXPORTS); 0: every channel exports in the same launch")
-    ap.add_argument("--serve-k", default="128,192,224,256,288,320,352",
+    ap.add_argument("--serve-k", default="256,288,320,336,352",
                     help="channel counts to try (device-sourced frames)")
     ap.add_argument("--serve-host-k", default="16,32,48,64",
                     help="channel counts to try with pinned-host frames (0 to skip)")

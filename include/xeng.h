@@ -132,6 +132,31 @@ int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
  */
 int xeng_dump(xeng_ctx *ctx, int32_t slot, int32_t *out, int32_t reset, void *hip_stream);
 
+typedef struct {
+    xeng_ctx *ctx;
+    int32_t slot;
+    int32_t reset;             /* 0 or 1, as in xeng_dump */
+    int32_t *out;              /* int32 [N(N+1)/2][2] of this ctx's N, as in xeng_dump */
+    int32_t reserved;          /* must be 0 */
+    int32_t pad;
+} xeng_dump_job;
+
+/*
+ * Export many slots at once (the exports of Sec. 2.1 for every channel that
+ * reaches its cadence together): each job's output equals what xeng_dump
+ * would write for it, and reset jobs zero their slot and sample counter.
+ * Two launches cover the whole batch (diagonal staging, then the export),
+ * where one xeng_dump per slot runs each export as its own small launch.
+ * All contexts must be on one device; a (ctx, slot) pair may appear at most
+ * once; the outputs must not overlap one another or any accumulator.
+ * Checks every job before queuing anything (XENG_EINVAL, nothing queued).
+ * Asynchronous on hip_stream: the job table is copied to the device through
+ * the same pinned staging ring as xeng_correlate_batch (the host waits only
+ * when the launch that used a ring buffer eight calls earlier is still
+ * running).  n_jobs == 0 is a no-op.
+ */
+int xeng_dump_batch(const xeng_dump_job *jobs, int32_t n_jobs, void *hip_stream);
+
 /* Zero one slot's accumulators and sample counter (asynchronous). */
 int xeng_reset(xeng_ctx *ctx, int32_t slot, void *hip_stream);
 

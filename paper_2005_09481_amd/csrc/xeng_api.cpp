@@ -25,6 +25,7 @@ hipError_t launch_correlate_dma(const KernelArgs &a, int grid, hipStream_t strea
 hipError_t init_dma_kernel();
 hipError_t launch_dump(int32_t *acc, int32_t *diag, int n, int nt, int32_t *out, bool reset,
                        hipStream_t stream);
+hipError_t launch_dump_batch(const DumpDesc *d_jobs, int n_jobs, int n_max, int nt_max, hipStream_t stream);
 hipError_t launch_zero(int32_t *p, int64_t n_i32, hipStream_t stream);
 hipError_t launch_reference(const uint8_t *s, int64_t n_samples, int n, int64_t stride,
                             uint32_t re_low, int32_t *out, hipStream_t stream);
@@ -377,6 +378,39 @@ std::vector<Part> split_by_kernel(const JobList &jl, const Tuning &tu)
     return parts;
 }
 
+// The next staging buffer of the ring, at least `bytes` long, once the
+// launch that last used it has completed.  Called with st->mu held and the
+// device current.
+int ring_acquire(DeviceState *st, size_t bytes, JobTable **out)
+{
+    JobTable &tb = st->ring[st->ring_next];
+    st->ring_next = (st->ring_next + 1) % JOB_RING;
+    hipError_t e = hipSuccess;
+    if (tb.pending) {
+        e = hipEventSynchronize(tb.ev);
+        if (e != hipSuccess) return map_err(e);
+        tb.pending = false;
+    }
+    if (!tb.ev && (e = hipEventCreateWithFlags(&tb.ev, hipEventDisableTiming)) != hipSuccess) return map_err(e);
+    if (tb.cap < bytes) {
+        if (tb.h) (void)hipHostFree(tb.h);
+        if (tb.d) (void)hipFree(tb.d);
+        tb.h = nullptr;
+        tb.d = nullptr;
+        tb.cap = 0;
+        const size_t cap = std::max<size_t>(bytes + bytes / 2, 64 * sizeof(JobDesc));
+        if ((e = hipHostMalloc(&tb.h, cap, hipHostMallocDefault)) != hipSuccess) return map_err(e);
+        if ((e = hipMalloc(&tb.d, cap)) != hipSuccess) {
+            (void)hipHostFree(tb.h);
+            tb.h = nullptr;
+            return map_err(e);
+        }
+        tb.cap = cap;
+    }
+    *out = &tb;
+    return XENG_OK;
+}
+
 // Launch the parts of a batch, staging each job table through the ring.
 // Called with st->mu held and the device current.
 int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu, hipStream_t stream)
@@ -403,16 +437,6 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
             st->host_lru.push_front(key);
         }
         if (plan->grid <= 0) continue;
-        JobTable &tb = st->ring[st->ring_next];
-        st->ring_next = (st->ring_next + 1) % JOB_RING;
-        hipError_t e = hipSuccess;
-        if (tb.pending) {
-            e = hipEventSynchronize(tb.ev);
-            if (e != hipSuccess) return map_err(e);
-            tb.pending = false;
-        }
-        if (!tb.ev && (e = hipEventCreateWithFlags(&tb.ev, hipEventDisableTiming)) != hipSuccess)
-            return map_err(e);
         // [job descriptors | pieces | workgroup offsets], 16-byte aligned parts
         auto up16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
         const size_t b_jobs = part.descs.size() * sizeof(JobDesc);
@@ -420,21 +444,11 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
         const size_t b_off = plan->wg_off.size() * sizeof(int32_t);
         const size_t o_pieces = up16(b_jobs), o_off = o_pieces + up16(b_pieces);
         const size_t bytes = o_off + b_off;
-        if (tb.cap < bytes) {
-            if (tb.h) (void)hipHostFree(tb.h);
-            if (tb.d) (void)hipFree(tb.d);
-            tb.h = nullptr;
-            tb.d = nullptr;
-            tb.cap = 0;
-            const size_t cap = std::max<size_t>(bytes + bytes / 2, 64 * sizeof(JobDesc));
-            if ((e = hipHostMalloc(&tb.h, cap, hipHostMallocDefault)) != hipSuccess) return map_err(e);
-            if ((e = hipMalloc(&tb.d, cap)) != hipSuccess) {
-                (void)hipHostFree(tb.h);
-                tb.h = nullptr;
-                return map_err(e);
-            }
-            tb.cap = cap;
-        }
+        JobTable *tbp = nullptr;
+        const int rc = ring_acquire(st, bytes, &tbp);
+        if (rc != XENG_OK) return rc;
+        JobTable &tb = *tbp;
+        hipError_t e = hipSuccess;
         std::memcpy(tb.h, part.descs.data(), b_jobs);
         std::memcpy(tb.h + o_pieces, plan->pieces.data(), b_pieces);
         std::memcpy(tb.h + o_off, plan->wg_off.data(), b_off);
@@ -581,6 +595,58 @@ int xeng_dump(xeng_ctx *ctx, int32_t slot, int32_t *out, int32_t reset, void *hi
     hipError_t e = launch_dump(acc, diag, ctx->n, ctx->nt, out, reset != 0, stream);
     if (e != hipSuccess) return map_err(e);
     if (reset) ctx->acc_t[(size_t)slot] = 0;
+    return XENG_OK;
+}
+
+int xeng_dump_batch(const xeng_dump_job *jobs, int32_t n_jobs, void *hip_stream)
+{
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return XENG_EINVAL;
+    if (n_jobs == 0) return XENG_OK;
+    if (!jobs[0].ctx) return XENG_EINVAL;
+    const int device = jobs[0].ctx->device;
+    std::set<std::pair<const xeng_ctx *, int32_t>> seen;
+    std::vector<DumpDesc> descs((size_t)n_jobs);
+    for (int32_t k = 0; k < n_jobs; ++k) {
+        const xeng_dump_job &j = jobs[k];
+        if (!slot_ok(j.ctx, j.slot) || !j.out || (j.reset != 0 && j.reset != 1) || j.reserved != 0 ||
+            j.ctx->device != device || !seen.insert({j.ctx, j.slot}).second)
+            return XENG_EINVAL;
+        DumpDesc &d = descs[(size_t)k];
+        d.acc = j.ctx->d_acc + (int64_t)j.slot * j.ctx->slot_i32;
+        d.diag = j.ctx->d_diag + (int64_t)j.slot * diag_i32(j.ctx->n);
+        d.out = j.out;
+        d.n = j.ctx->n;
+        d.nt = j.ctx->nt;
+        d.reset = j.reset;
+        d.pad = 0;
+    }
+    DeviceGuard guard(device);
+    if (!guard.ok) return XENG_EDEVICE;
+    DeviceState *st = jobs[0].ctx->st;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    std::lock_guard<std::mutex> lk(st->mu);
+    constexpr int32_t CHUNK = 65535;   // grid z limit
+    for (int32_t k0 = 0; k0 < n_jobs; k0 += CHUNK) {
+        const int32_t m = std::min(CHUNK, n_jobs - k0);
+        int n_max = 0, nt_max = 0;
+        for (int32_t k = k0; k < k0 + m; ++k) {
+            n_max = std::max(n_max, (int)descs[(size_t)k].n);
+            nt_max = std::max(nt_max, (int)descs[(size_t)k].nt);
+        }
+        const size_t bytes = (size_t)m * sizeof(DumpDesc);
+        JobTable *tb = nullptr;
+        int rc = ring_acquire(st, bytes, &tb);
+        if (rc != XENG_OK) return rc;
+        std::memcpy(tb->h, descs.data() + k0, bytes);
+        hipError_t e = hipMemcpyAsync(tb->d, tb->h, bytes, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = launch_dump_batch(reinterpret_cast<const DumpDesc *>(tb->d), m, n_max, nt_max, stream);
+        if (e == hipSuccess) e = hipEventRecord(tb->ev, stream);
+        if (e != hipSuccess) return map_err(e);
+        tb->pending = true;
+    }
+    for (int32_t k = 0; k < n_jobs; ++k)
+        if (jobs[k].reset) jobs[k].ctx->acc_t[(size_t)jobs[k].slot] = 0;
     return XENG_OK;
 }
 

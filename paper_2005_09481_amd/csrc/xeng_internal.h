@@ -102,4 +102,16 @@ struct KernelArgs {
 };
 constexpr int ZERO_BYTES = 256;
 
+// One export of a batched dump: a slot's accumulators, its diagonal staging
+// (n int32) and the caller's output, [n(n+1)/2][2] int32.
+struct DumpDesc {
+    int32_t *acc;
+    int32_t *diag;
+    int32_t *out;
+    int32_t n;
+    int32_t nt;
+    int32_t reset;
+    int32_t pad;
+};
+
 }  // namespace xeng

@@ -426,15 +426,14 @@ __global__ __launch_bounds__(256) void diag_im(const int32_t *__restrict__ acc, 
 // wrapping int32 arithmetic, since Im V_ij itself fits).
 constexpr int DUMP_PITCH = TILE + 1;   // int2 per staged row (padding spreads banks)
 
-__global__ __launch_bounds__(256) void vis_dump(int32_t *__restrict__ acc, int n, int nt,
-                                                const int32_t *__restrict__ d,
-                                                int32_t *__restrict__ out, int reset)
+__device__ __forceinline__ void dump_block_row(int32_t *__restrict__ acc, int n, int nt,
+                                               const int32_t *__restrict__ d, int32_t *__restrict__ out,
+                                               int reset, int bx, int by, int2 *stage)
 {
-    __shared__ int2 stage[BLK * DUMP_PITCH];
-    const int ti = blockIdx.y;
-    const int tj = ti + (blockIdx.x >> 2);
+    const int ti = by;
+    const int tj = ti + (bx >> 2);
     if (tj >= nt) return;
-    const int ca = blockIdx.x & 3;
+    const int ca = bx & 3;
     const int t = threadIdx.x;
     const int64_t tile = (int64_t)ti * nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);
     {
@@ -470,6 +469,34 @@ __global__ __launch_bounds__(256) void vis_dump(int32_t *__restrict__ acc, int n
         const int2 v = stage[r * DUMP_PITCH + col];
         o[k] = make_int2(v.x, (int32_t)((uint32_t)v.y - dj));
     }
+}
+
+__global__ __launch_bounds__(256) void vis_dump(int32_t *__restrict__ acc, int n, int nt,
+                                                const int32_t *__restrict__ d,
+                                                int32_t *__restrict__ out, int reset)
+{
+    __shared__ int2 stage[BLK * DUMP_PITCH];
+    dump_block_row(acc, n, nt, d, out, reset, blockIdx.x, blockIdx.y, stage);
+}
+
+// Batched export: job blockIdx.z of the descriptor table, the grid sized
+// for the largest job (workgroups past a smaller job's tiles return).  One
+// launch keeps enough block rows in flight to run at memory speed, where one
+// export per launch leaves most of the chip waiting on a single wave of
+// workgroups.
+__global__ __launch_bounds__(256) void diag_im_batch(const DumpDesc *__restrict__ jobs)
+{
+    const DumpDesc jd = jobs[blockIdx.y];
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j < jd.n) jd.diag[j] = pair_im(reinterpret_cast<const uint64_t *>(jd.acc)[acc_word(j, j, jd.nt)]);
+}
+
+__global__ __launch_bounds__(256) void vis_dump_batch(const DumpDesc *__restrict__ jobs)
+{
+    __shared__ int2 stage[BLK * DUMP_PITCH];
+    const DumpDesc jd = jobs[blockIdx.z];
+    if ((int)blockIdx.y >= jd.nt || (int)blockIdx.x >= 4 * jd.nt) return;
+    dump_block_row(jd.acc, jd.n, jd.nt, jd.diag, jd.out, jd.reset, blockIdx.x, blockIdx.y, stage);
 }
 
 __global__ __launch_bounds__(256) void fill_zero(int4 *__restrict__ p, int64_t n4)
@@ -530,6 +557,16 @@ hipError_t launch_dump(int32_t *acc, int32_t *diag, int n, int nt, int32_t *out,
     hipLaunchKernelGGL(diag_im, dim3((n + 255) / 256), dim3(256), 0, stream, acc, n, nt, diag);
     hipLaunchKernelGGL(vis_dump, dim3(4 * nt, nt), dim3(256), 0, stream, acc, n, nt, diag, out,
                        reset ? 1 : 0);
+    return hipGetLastError();
+}
+
+// `d_jobs`: n_jobs descriptors in device memory (n_jobs <= 65535); n_max and
+// nt_max: the largest n and nt among them.
+hipError_t launch_dump_batch(const DumpDesc *d_jobs, int n_jobs, int n_max, int nt_max, hipStream_t stream)
+{
+    if (n_jobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(diag_im_batch, dim3((n_max + 255) / 256, n_jobs), dim3(256), 0, stream, d_jobs);
+    hipLaunchKernelGGL(vis_dump_batch, dim3(4 * nt_max, nt_max, n_jobs), dim3(256), 0, stream, d_jobs);
     return hipGetLastError();
 }
 

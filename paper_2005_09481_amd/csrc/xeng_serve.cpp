@@ -51,11 +51,18 @@ struct Chan {
     int64_t phase = 0;             // exports at frame counts m * dump_frames - phase
     uint8_t *ring = nullptr;       // device ring for a host source
     std::deque<std::pair<int64_t, hipEvent_t>> copies;   // (frames copied up to, event)
+    std::deque<int64_t> gaps;      // frames dropped at ingest, in order: never integrated
+};
+
+struct Range {
+    int32_t chan;
+    int64_t f0, f1;     // frames [f0, f1)
+    bool skipped;       // dropped frames passed over: neither integrated nor counted as done work
 };
 
 struct InFlight {
-    hipEvent_t ev;
-    std::vector<std::pair<int32_t, std::pair<int64_t, int64_t>>> ranges;   // channel, [f0, f1)
+    hipEvent_t ev = nullptr;
+    std::vector<Range> ranges;
 };
 
 }  // namespace
@@ -224,12 +231,14 @@ int xeng_server_run(xeng_server *s, double seconds, xeng_server_stats *stats)
             if (q == hipErrorNotReady) return XENG_OK;
             if (q != hipSuccess) return XENG_EDEVICE;
             const double t = now_s();
-            for (auto &r : f.ranges) {
-                Chan &c = s->chans[(size_t)r.first];
-                for (int64_t fr = r.second.first; fr < r.second.second; ++fr)
-                    lat.push_back((float)(1e3 * (t - release_time(s, c, fr))));
-                c.done = r.second.second;
-                frames_done += r.second.second - r.second.first;
+            for (const Range &r : f.ranges) {
+                Chan &c = s->chans[(size_t)r.chan];
+                if (!r.skipped) {
+                    for (int64_t fr = r.f0; fr < r.f1; ++fr)
+                        lat.push_back((float)(1e3 * (t - release_time(s, c, fr))));
+                    frames_done += r.f1 - r.f0;
+                }
+                c.done = r.f1;
                 if (c.state == 1 && c.total_frames > 0 && c.done >= c.total_frames) {
                     // finished: zero what it integrated past its last export
                     // (queued behind that export) and free the slot
@@ -270,8 +279,10 @@ int xeng_server_run(xeng_server *s, double seconds, xeng_server_stats *stats)
                     continue;
                 }
                 if (f - c.done >= cf.ring_frames) {
-                    // the ring still holds frames not yet integrated: lost
+                    // the ring still holds frames not yet integrated: lost,
+                    // and passed over by the launches
                     ++dropped;
+                    c.gaps.push_back(f);
                     continue;
                 }
                 const int64_t r = f % cf.ring_frames;
@@ -308,12 +319,28 @@ int xeng_server_run(xeng_server *s, double seconds, xeng_server_stats *stats)
             std::vector<int32_t> dump_now;
             for (size_t k = 0; k < s->chans.size(); ++k) {
                 Chan &c = s->chans[k];
-                if (c.state != 1 || c.available <= c.launched) continue;
-                const int64_t f0 = c.launched;
+                if (c.state != 1) continue;
+                int64_t f0 = c.launched;
                 const int64_t boundary = ((f0 + c.phase) / cf.dump_frames + 1) * cf.dump_frames - c.phase;
+                // pass over dropped frames at the front, up to the export boundary
+                int64_t g = f0;
+                while (!c.gaps.empty() && c.gaps.front() == g && g < boundary) {
+                    c.gaps.pop_front();
+                    ++g;
+                }
+                if (g > f0) {
+                    f.ranges.push_back({(int32_t)k, f0, g, true});
+                    c.launched = f0 = g;
+                    if (g == boundary) {
+                        dump_now.push_back((int32_t)k);
+                        continue;
+                    }
+                }
+                if (c.available <= f0) continue;
                 const int64_t wrap_n = c.src_host ? cf.ring_frames : c.src_frames;
                 const int64_t wrap = (f0 / wrap_n + 1) * wrap_n;
-                const int64_t f1 = std::min({c.available, boundary, wrap});
+                const int64_t next_gap = c.gaps.empty() ? INT64_MAX : c.gaps.front();
+                const int64_t f1 = std::min({c.available, boundary, wrap, next_gap});
                 const uint8_t *base = c.src_host ? c.ring + (f0 % cf.ring_frames) * s->frame_bytes
                                                  : c.src + (f0 % c.src_frames) * s->frame_bytes;
                 xeng_job j;
@@ -324,27 +351,34 @@ int xeng_server_run(xeng_server *s, double seconds, xeng_server_stats *stats)
                 j.n_samples = (f1 - f0) * cf.frame_len;
                 j.row_stride = n;
                 jobs.push_back(j);
-                f.ranges.push_back({(int32_t)k, {f0, f1}});
+                f.ranges.push_back({(int32_t)k, f0, f1, false});
                 c.launched = f1;
                 if (f1 == boundary) dump_now.push_back((int32_t)k);
             }
-            if (!jobs.empty()) {
-                if ((rc = xeng_correlate_batch(jobs.data(), (int32_t)jobs.size(), s->compute)) != XENG_OK) break;
+            if (!f.ranges.empty()) {
+                if (!jobs.empty() &&
+                    (rc = xeng_correlate_batch(jobs.data(), (int32_t)jobs.size(), s->compute)) != XENG_OK)
+                    break;
+                // every export due after this launch, in two launches
+                std::vector<xeng_dump_job> dj;
+                dj.reserve(dump_now.size());
+                for (int32_t k : dump_now) {
+                    const Chan &c = s->chans[(size_t)k];
+                    dj.push_back({s->ctx, c.slot, 1, s->d_out + (int64_t)c.slot * s->out_i32, 0, 0});
+                }
+                if ((rc = xeng_dump_batch(dj.data(), (int32_t)dj.size(), s->compute)) != XENG_OK) break;
                 for (int32_t k : dump_now) {
                     Chan &c = s->chans[(size_t)k];
-                    rc = xeng_dump(s->ctx, c.slot, s->d_out + (int64_t)c.slot * s->out_i32, 1, s->compute);
-                    if (rc != XENG_OK) break;
                     c.last_dump_first = std::max<int64_t>(0, c.launched - cf.dump_frames);
                     ++c.dumps;
                 }
-                if (rc != XENG_OK) break;
                 f.ev = get_event(s);
                 if (!f.ev || hipEventRecord(f.ev, s->compute) != hipSuccess) {
                     rc = XENG_EDEVICE;
                     break;
                 }
                 inflight.push_back(std::move(f));
-                ++launches;
+                if (!jobs.empty()) ++launches;
                 next_launch = t + cf.launch_period_us * 1e-6;
             }
         }

@@ -45,6 +45,11 @@ class _Job(ctypes.Structure):
                 ("row_stride", ctypes.c_int64)]
 
 
+class _DumpJob(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("slot", ctypes.c_int32), ("reset", ctypes.c_int32),
+                ("out", ctypes.c_void_p), ("reserved", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 class _Tuning(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
                 ("min_stages", ctypes.c_int32), ("reserved", ctypes.c_int32),
@@ -98,6 +103,7 @@ def lib() -> ctypes.CDLL:
         "xeng_correlate": (ctypes.c_int, [vp, i32, vp, i64, i64, vp]),
         "xeng_correlate_batch": (ctypes.c_int, [ctypes.POINTER(_Job), i32, vp]),
         "xeng_dump": (ctypes.c_int, [vp, i32, vp, i32, vp]),
+        "xeng_dump_batch": (ctypes.c_int, [ctypes.POINTER(_DumpJob), i32, vp]),
         "xeng_reset": (ctypes.c_int, [vp, i32, vp]),
         "xeng_samples_integrated": (i64, [vp, i32]),
         "xeng_max_integration": (i64, []),
@@ -233,14 +239,18 @@ class Correlator:
         _check(lib().xeng_correlate(self.handle, slot, ptr, t, row_stride,
                                     _stream_handle(stream, self.device)), "xeng_correlate")
 
-    def dump(self, slot: int, out=None, reset: bool = True, stream=None):
-        """Integrated visibilities int32 [N(N+1)/2, 2] (Re, Im), upper triangle row-major."""
+    def _dump_out(self, out):
         import torch
         if out is None:
             out = torch.empty((tri(self.n_inputs), 2), dtype=torch.int32,
                               device=f"cuda:{self.device}")
         if out.dtype != torch.int32 or out.numel() != 2 * tri(self.n_inputs) or not out.is_contiguous():
             raise ValueError("out must be a contiguous int32 tensor of N(N+1)/2 x 2")
+        return out
+
+    def dump(self, slot: int, out=None, reset: bool = True, stream=None):
+        """Integrated visibilities int32 [N(N+1)/2, 2] (Re, Im), upper triangle row-major."""
+        out = self._dump_out(out)
         _check(lib().xeng_dump(self.handle, slot, ctypes.c_void_p(out.data_ptr()), int(bool(reset)),
                                _stream_handle(stream, self.device)), "xeng_dump")
         return out
@@ -282,6 +292,25 @@ def correlate_batch(jobs, stream=None):
     _check(lib().xeng_correlate_batch(_job_array(jobs), len(jobs),
                                       _stream_handle(stream, jobs[0][0].device)),
            "xeng_correlate_batch")
+
+
+def dump_batch(jobs, stream=None):
+    """Export many slots in two launches: ``jobs`` = [(correlator, slot), ...]
+    or [(correlator, slot, out, reset), ...] (out None: allocated; reset
+    default True).  Returns the output tensors in job order."""
+    if not jobs:
+        return []
+    arr = (_DumpJob * len(jobs))()
+    outs = []
+    for k, j in enumerate(jobs):
+        c, slot = j[0], j[1]
+        out = c._dump_out(j[2] if len(j) > 2 else None)
+        reset = bool(j[3]) if len(j) > 3 else True
+        arr[k] = _DumpJob(c.handle, slot, int(reset), out.data_ptr(), 0, 0)
+        outs.append(out)
+    _check(lib().xeng_dump_batch(arr, len(jobs), _stream_handle(stream, jobs[0][0].device)),
+           "xeng_dump_batch")
+    return outs
 
 
 class Batch:

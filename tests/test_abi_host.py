@@ -65,6 +65,10 @@ def test_argument_checks_without_device(X):
     assert L.xeng_set_tuning(3, 0, -1) == X.XENG_EINVAL
     assert L.xeng_set_tuning(0, 0, 7) == X.XENG_EINVAL
     assert L.xeng_clock_probe(-1, None) == X.XENG_EINVAL
+    assert L.xeng_dump_batch(None, 1, None) == X.XENG_EINVAL
+    assert L.xeng_dump_batch(None, 0, None) == X.XENG_OK
+    no_ctx = (X._DumpJob * 1)()
+    assert L.xeng_dump_batch(no_ctx, 1, None) == X.XENG_EINVAL
     # server configurations are checked before any device call: unknown flag
     # bits, a zero export cadence and a nonzero reserved field are refused
     for flags, dump, reserved in ((4, 8, 0), (1 << 31, 8, 0), (0, 0, 0), (X.XENG_SERVER_STAGGER_EXPORTS, 8, 1)):

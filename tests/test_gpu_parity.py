@@ -339,3 +339,70 @@ def test_clock_probe_leaves_results_unchanged(X):
     np.testing.assert_array_equal(got, ref)
     with pytest.raises(ValueError):
         X.clock_probe(torch.zeros(4, dtype=torch.int32, device="cuda"))
+
+
+def test_dump_batch_matches_single_dumps_and_oracle(X):
+    # several contexts of different N (one with N a multiple of 256, which
+    # the DMA kernel integrates) and several slots each; one batched export
+    # with resets on some jobs only
+    print("dump batch: N in {1, 129, 300, 512}", flush=True)
+    cases = [(1, 2, 33), (129, 3, 300), (300, 2, 257), (512, 2, 1024)]
+    corrs, data = [], {}
+    for n, slots, t in cases:
+        c = X.Correlator(n, slots)
+        for s in range(slots):
+            x = synth.uniform_bytes(n, t + 17 * s, seed=[40, n, s])
+            c.correlate(s, gpu(x))
+            data[(n, s)] = x
+        corrs.append(c)
+    jobs, want = [], []
+    for c in corrs:
+        for s in range(c.n_slots):
+            reset = (s + c.n_inputs) % 2 == 0
+            jobs.append((c, s, None, reset))
+            want.append(oracle.correlate(data[(c.n_inputs, s)]))
+    outs = X.dump_batch(jobs)
+    for (c, s, _, reset), got, w in zip(jobs, outs, want):
+        np.testing.assert_array_equal(got.cpu().numpy().astype(np.int64), w)
+        # reset jobs zeroed their slot and counter; the others kept both
+        if reset:
+            assert c.samples_integrated(s) == 0
+            assert not c.dump(s, reset=False).any()
+        else:
+            assert c.samples_integrated(s) > 0
+            np.testing.assert_array_equal(c.dump(s, reset=False).cpu().numpy().astype(np.int64), w)
+    # a second batch over a subset, after more data, into caller buffers
+    c = corrs[1]
+    x = synth.uniform_bytes(129, 64, seed=41)
+    c.correlate(0, gpu(x))
+    bufs = [torch.full((X.tri(n), 2), -7, dtype=torch.int32, device="cuda") for n in (129, 300)]
+    X.dump_batch([(c, 0, bufs[0], True), (corrs[2], 1, bufs[1], True)])
+    s0 = oracle.correlate(x) + (0 if (0 + 129) % 2 == 0 else oracle.correlate(data[(129, 0)]))
+    np.testing.assert_array_equal(bufs[0].cpu().numpy().astype(np.int64), s0)
+    np.testing.assert_array_equal(bufs[1].cpu().numpy().astype(np.int64), oracle.correlate(data[(300, 1)]))
+    assert X.dump_batch([]) == []
+    for cc in corrs:
+        cc.close()
+
+
+def test_dump_batch_argument_errors(X):
+    c = X.Correlator(64, 2)
+    d = X.Correlator(128, 1)
+    with pytest.raises(X.XengError):
+        X.dump_batch([(c, 0), (c, 0)])              # one slot twice
+    with pytest.raises(X.XengError):
+        X.dump_batch([(c, 2)])                      # no such slot
+    with pytest.raises(ValueError):
+        X.dump_batch([(c, 0, torch.empty(5, dtype=torch.int32, device="cuda"))])
+    L = X.lib()
+    arr = (X._DumpJob * 2)()
+    out = torch.empty((X.tri(64), 2), dtype=torch.int32, device="cuda")
+    arr[0] = X._DumpJob(c.handle, 0, 1, out.data_ptr(), 0, 0)
+    arr[1] = X._DumpJob(d.handle, 0, 2, out.data_ptr(), 0, 0)   # reset must be 0 or 1
+    assert L.xeng_dump_batch(arr, 2, None) == X.XENG_EINVAL
+    arr[1] = X._DumpJob(d.handle, 0, 1, None, 0, 0)             # no output
+    assert L.xeng_dump_batch(arr, 2, None) == X.XENG_EINVAL
+    arr[1] = X._DumpJob(d.handle, 0, 1, out.data_ptr(), 1, 0)   # reserved must be 0
+    assert L.xeng_dump_batch(arr, 2, None) == X.XENG_EINVAL
+    c.close()
+    d.close()

@@ -122,6 +122,33 @@ def test_host_sourced_frames(X):
     srv.close()
 
 
+def test_dropped_frames_are_never_integrated(X):
+    # a host source whose ring (3 frames) overflows while the server waits
+    # out a long launch period: the frames it drops must be passed over, not
+    # integrated from the ring's stale contents, and still count towards the
+    # export boundaries and the channel's end.  Every frame of the source is
+    # the same, so each export is m x V(frame) for the m frames it integrated.
+    frame = frames_of(seed=[9, 0], n_frames=1)
+    host = torch.from_numpy(frame).pin_memory()
+    srv = X.Server(N, dump_frames=16, max_channels=1, ring_frames=3, max_inflight=1,
+                   frame_period_us=200.0, launch_period_us=20000.0)
+    ch = srv.admit(host, total_frames=32)
+    st = srv.run(0.2)
+    print("dropping host source", st, flush=True)
+    assert st["frames_released"] == 32 and st["frames_dropped"] > 0
+    assert st["backlog_frames"] == 0
+    assert st["frames_done"] + st["frames_dropped"] == 32
+    info = srv.channel_info(ch)
+    assert info["state"] == 2 and info["dumps"] == 2 and info["last_dump_first_frame"] == 16
+    v1 = oracle.correlate(frame.reshape(-1, N)).astype(np.int64)
+    got = srv.last_dump(ch).cpu().numpy().astype(np.int64)
+    k = int(np.flatnonzero(v1)[0])
+    m = got.flat[k] // v1.flat[k]
+    np.testing.assert_array_equal(got, m * v1)
+    assert 0 <= m <= 16 and 0 <= st["frames_done"] - m <= 16
+    srv.close()
+
+
 def test_server_argument_checks(X):
     with pytest.raises(X.XengError) as e:
         X.Server(N, dump_frames=0, max_channels=1)
