@@ -415,45 +415,49 @@ __global__ __launch_bounds__(256) void diag_im(const int32_t *__restrict__ acc, 
 }
 
 // Accumulators (tile layout) -> packed row-major upper triangle of (Re, Im),
-// optionally zeroing the slot in the same pass.  Workgroup (x, y) takes
-// block row ca = x % 4 (32 rows) of tile (ti, tj) = (y, y + x / 4).  Reads:
-// thread t takes row t / 8 of the block row and 16 consecutive columns,
-// 16 * (t % 8).., which are 16 consecutive words of one accumulator register
-// row (8 dwordx4 loads of packed pairs, coalesced), and stages them in LDS
-// as (Re, Im) pairs.  Writes: consecutive threads take consecutive pairs of
-// an output row, 128 pairs (1 KB contiguous) per row.  The imaginary part of
-// (i, j) is stored as Im V_ij - S_j, so d[j] is subtracted (exact in
-// wrapping int32 arithmetic, since Im V_ij itself fits).
+// optionally zeroing the slot in the same pass.  A workgroup takes DUMP_ROWS
+// rows of one 32-row block row of tile (ti, tj): blockIdx.y = ti and
+// blockIdx.x = (tj - ti) * DUMP_PARTS_PER_TILE + ca * DUMP_PARTS + part.
+// Reads: row r of the part is 64 threads, thread c taking the 16 bytes of
+// columns 32 (c / 16) + 2 (c % 16) .. + 1 (two consecutive words of one
+// accumulator register row, so a row is read as four coalesced 256-byte
+// runs), staged in LDS as (Re, Im) pairs.  Writes: consecutive threads take
+// consecutive pairs of an output row, 128 pairs (1 KB contiguous) per row.
+// Few rows per workgroup keep many small workgroups in flight: the export
+// is a single pass over memory, and this form measured twice as fast as
+// 32-row workgroups.  The imaginary part of (i, j) is stored as Im V_ij -
+// S_j, so d[j] is subtracted (exact in wrapping int32 arithmetic, since
+// Im V_ij itself fits).
 constexpr int DUMP_PITCH = TILE + 1;   // int2 per staged row (padding spreads banks)
+constexpr int DUMP_ROWS = 4;
+constexpr int DUMP_PARTS = BLK / DUMP_ROWS;
+constexpr int DUMP_PARTS_PER_TILE = 4 * DUMP_PARTS;   // workgroups per tile
 
 __device__ __forceinline__ void dump_block_row(int32_t *__restrict__ acc, int n, int nt,
                                                const int32_t *__restrict__ d, int32_t *__restrict__ out,
                                                int reset, int bx, int by, int2 *stage)
 {
     const int ti = by;
-    const int tj = ti + (bx >> 2);
+    const int tj = ti + bx / DUMP_PARTS_PER_TILE;
     if (tj >= nt) return;
-    const int ca = bx & 3;
+    const int ca = (bx / DUMP_PARTS) & 3, part = bx % DUMP_PARTS;
     const int t = threadIdx.x;
     const int64_t tile = (int64_t)ti * nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);
     {
-        const int ri = t >> 3, c16 = t & 7;
-        const int cb = c16 >> 1, cj0 = 16 * (c16 & 1);
-        const int reg = 4 * (ri >> 3) + (ri & 3), half = (ri >> 2) & 1;
+        const int ri = t >> 6, c = t & 63;
+        const int ra = DUMP_ROWS * part + ri;
+        const int cb = c >> 4, cj0 = 2 * (c & 15);
+        const int reg = 4 * (ra >> 3) + (ra & 3), half = (ra >> 2) & 1;
         uint64_t *base = reinterpret_cast<uint64_t *>(acc) + tile * TILE_W + (ca * BLKS + cb) * BLOCK_W + reg * 64 +
                          32 * half + cj0;
         int4 *pw = reinterpret_cast<int4 *>(base);
-        int4 w[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) w[q] = pw[q];
-        if (reset) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) pw[q] = make_int4(0, 0, 0, 0);
-        }
-        const uint64_t *wv = reinterpret_cast<const uint64_t *>(w);
+        const int4 w = *pw;
+        if (reset) *pw = make_int4(0, 0, 0, 0);
+        const uint64_t w0 = (uint64_t)(uint32_t)w.x | ((uint64_t)(uint32_t)w.y << 32);
+        const uint64_t w1 = (uint64_t)(uint32_t)w.z | ((uint64_t)(uint32_t)w.w << 32);
         int2 *row = stage + ri * DUMP_PITCH + BLK * cb + cj0;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) row[e] = make_int2(pair_re(wv[e]), pair_im(wv[e]));
+        row[0] = make_int2(pair_re(w0), pair_im(w0));
+        row[1] = make_int2(pair_re(w1), pair_im(w1));
     }
     __syncthreads();
     const int col = t & (TILE - 1);
@@ -461,9 +465,9 @@ __device__ __forceinline__ void dump_block_row(int32_t *__restrict__ acc, int n,
     if (j >= n) return;
     const uint32_t dj = (uint32_t)d[j];
     int2 *o = reinterpret_cast<int2 *>(out);
-#pragma unroll 4
-    for (int r = t >> 7; r < BLK; r += 2) {
-        const int i = TILE * ti + BLK * ca + r;
+#pragma unroll
+    for (int r = t >> 7; r < DUMP_ROWS; r += 2) {
+        const int i = TILE * ti + BLK * ca + DUMP_ROWS * part + r;
         if (i >= n || j < i) continue;
         const int64_t k = (int64_t)i * n - (int64_t)i * (i - 1) / 2 + (j - i);
         const int2 v = stage[r * DUMP_PITCH + col];
@@ -475,7 +479,7 @@ __global__ __launch_bounds__(256) void vis_dump(int32_t *__restrict__ acc, int n
                                                 const int32_t *__restrict__ d,
                                                 int32_t *__restrict__ out, int reset)
 {
-    __shared__ int2 stage[BLK * DUMP_PITCH];
+    __shared__ int2 stage[DUMP_ROWS * DUMP_PITCH];
     dump_block_row(acc, n, nt, d, out, reset, blockIdx.x, blockIdx.y, stage);
 }
 
@@ -493,9 +497,9 @@ __global__ __launch_bounds__(256) void diag_im_batch(const DumpDesc *__restrict_
 
 __global__ __launch_bounds__(256) void vis_dump_batch(const DumpDesc *__restrict__ jobs)
 {
-    __shared__ int2 stage[BLK * DUMP_PITCH];
+    __shared__ int2 stage[DUMP_ROWS * DUMP_PITCH];
     const DumpDesc jd = jobs[blockIdx.z];
-    if ((int)blockIdx.y >= jd.nt || (int)blockIdx.x >= 4 * jd.nt) return;
+    if ((int)blockIdx.y >= jd.nt || (int)blockIdx.x >= DUMP_PARTS_PER_TILE * jd.nt) return;
     dump_block_row(jd.acc, jd.n, jd.nt, jd.diag, jd.out, jd.reset, blockIdx.x, blockIdx.y, stage);
 }
 
@@ -555,7 +559,7 @@ hipError_t launch_dump(int32_t *acc, int32_t *diag, int n, int nt, int32_t *out,
                        hipStream_t stream)
 {
     hipLaunchKernelGGL(diag_im, dim3((n + 255) / 256), dim3(256), 0, stream, acc, n, nt, diag);
-    hipLaunchKernelGGL(vis_dump, dim3(4 * nt, nt), dim3(256), 0, stream, acc, n, nt, diag, out,
+    hipLaunchKernelGGL(vis_dump, dim3(DUMP_PARTS_PER_TILE * nt, nt), dim3(256), 0, stream, acc, n, nt, diag, out,
                        reset ? 1 : 0);
     return hipGetLastError();
 }
@@ -566,7 +570,8 @@ hipError_t launch_dump_batch(const DumpDesc *d_jobs, int n_jobs, int n_max, int 
 {
     if (n_jobs <= 0) return hipSuccess;
     hipLaunchKernelGGL(diag_im_batch, dim3((n_max + 255) / 256, n_jobs), dim3(256), 0, stream, d_jobs);
-    hipLaunchKernelGGL(vis_dump_batch, dim3(4 * nt_max, nt_max, n_jobs), dim3(256), 0, stream, d_jobs);
+    hipLaunchKernelGGL(vis_dump_batch, dim3(DUMP_PARTS_PER_TILE * nt_max, nt_max, n_jobs), dim3(256), 0, stream,
+                       d_jobs);
     return hipGetLastError();
 }
 
