@@ -128,7 +128,10 @@ int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
  * integrated visibilities are exported at a chosen cadence).
  * out: int32 [N(N+1)/2][2], device memory or host memory from
  *   hipHostMalloc; owned by the caller.  reset != 0 zeroes the slot and its
- *   sample counter after the export.  Asynchronous on hip_stream.
+ *   sample counter after the export.  Asynchronous on hip_stream.  Exports
+ *   of one slot must not run concurrently on different streams (they share
+ *   the slot's diagonal staging, and a reset export writes the accumulators
+ *   the other reads).
  */
 int xeng_dump(xeng_ctx *ctx, int32_t slot, int32_t *out, int32_t reset, void *hip_stream);
 
