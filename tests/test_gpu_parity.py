@@ -406,3 +406,30 @@ def test_dump_batch_argument_errors(X):
     assert L.xeng_dump_batch(arr, 2, None) == X.XENG_EINVAL
     c.close()
     d.close()
+
+
+def test_library_int8_gemm_cross_check(X):
+    # an independent GPU path: unpack the samples into int8 matrices with
+    # plain tensor ops and form the products with the vendor int8 GEMM
+    # (torch._int_mm, int32 accumulation, exact at these sizes):
+    #   U = [Re | Im] (N x 2T), W = [-Im | Re];  Re V = U U^T, Im V = U W^T
+    # (V_ij = sum x_i conj(x_j): Im = Im_i Re_j - Re_i Im_j)
+    n, t = 512, 4096
+    print(f"library int8 GEMM cross-check n={n} t={t}", flush=True)
+    x = synth.uniform_bytes(n, t, seed=4242)
+    xd = gpu(x)
+    try:
+        hi = (xd >> 4).to(torch.int16) - 8
+        lo = (xd & 15).to(torch.int16) - 8
+        re, im = hi.to(torch.int8).t(), lo.to(torch.int8).t()          # [n, t]
+        u = torch.cat([re, im], dim=1).contiguous()                     # [n, 2t]
+        w = torch.cat([-im, re], dim=1).contiguous()
+        vr = torch._int_mm(u, u.t().contiguous())
+        vi = torch._int_mm(u, w.t().contiguous())
+        torch.cuda.synchronize()
+    except (RuntimeError, NotImplementedError) as e:
+        pytest.skip(f"int8 GEMM not available in this torch build: {e}")
+    iu = torch.triu_indices(n, n, device="cuda")
+    lib_out = torch.stack([vr[iu[0], iu[1]], vi[iu[0], iu[1]]], dim=1).cpu().numpy().astype(np.int64)
+    got = run(X, x)
+    np.testing.assert_array_equal(got, lib_out)
