@@ -247,3 +247,18 @@ def test_host_ring_sustained_overload_interleaves_drops(sim_lib):
     assert set(g.tolist()) == copies
     assert sim.chan(0)["state"] == 2
     sim.close()
+
+
+def test_core_under_sanitizers(tmp_path):
+    # the scheduling core and the harness built with AddressSanitizer and
+    # UndefinedBehaviorSanitizer, every scenario kind run in one process
+    exe = str(tmp_path / "sched_sim_asan")
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_2005_09481_amd", "csrc"),
+           os.path.join(ROOT, "tests", "sched_sim_main.cpp"), os.path.join(ROOT, "tests", "sched_sim.cpp"),
+           os.path.join(ROOT, "paper_2005_09481_amd", "csrc", "xeng_sched.cpp"), "-o", exe]
+    subprocess.run(cmd, check=True, capture_output=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "ERROR" not in r.stderr and "runtime error" not in r.stderr, r.stderr
+    assert r.stdout.count("rc=0") == 4
