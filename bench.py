@@ -84,6 +84,8 @@ def bench_serve(args, xeng, synth, torch, np):
     base = synth.stream_frames(n, n_src_dev, seed=5)
     base_dev = torch.from_numpy(base).cuda()
     results = []
+    # shader clock stamped by workgroup 0 of the last correlation launch of a trial
+    clock_buf = None if args.no_clock_probe else torch.zeros(4, dtype=torch.int64, device="cuda")
 
     def trial(k, host):
         srv = xeng.Server(n, max_channels=k, dump_frames=dump, launch_period_us=args.serve_launch_us,
@@ -96,7 +98,14 @@ def bench_serve(args, xeng, synth, torch, np):
                 f = torch.roll(base_dev, c, dims=2)
             srcs.append(f)
             srv.admit(f, start_s=0.05 + 655.36e-6 * c / k)
+        if clock_buf is not None:
+            xeng.clock_probe(clock_buf)
         st = srv.run(args.serve_seconds)
+        sclk = None
+        if clock_buf is not None:
+            torch.cuda.synchronize()
+            sclk = round(xeng.sclk_ghz(clock_buf), 3)
+            xeng.clock_probe(None)
         srv.close()
         # real time: nothing dropped, p99 below the export period, and the
         # frames still queued at the end no more than arrive within the p99
@@ -110,7 +119,8 @@ def bench_serve(args, xeng, synth, torch, np):
              "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
              "max_ms": round(st["max_ms"], 3), "tcmacs": round(st["tcmacs"], 2),
              "frames_done": st["frames_done"], "dropped": st["frames_dropped"],
-             "backlog": st["backlog_frames"], "launches": st["launches"], "dumps": st["dumps"]}
+             "backlog": st["backlog_frames"], "launches": st["launches"], "dumps": st["dumps"],
+             "sclk_ghz": sclk}
         print(json.dumps(r), flush=True)
         return r
 
@@ -228,7 +238,7 @@ def main():
     ap.add_argument("--serve-stagger", type=int, choices=(0, 1), default=0,
                     help="1: each slot exports at its own phase of the export period "
                          "(XENG_SERVER_STAGGER_EXPORTS); 0: every channel exports in the same launch")
-    ap.add_argument("--serve-k", default="256,288,320,336,352",
+    ap.add_argument("--serve-k", default="256,288,320,336,352,368,384",
                     help="channel counts to try (device-sourced frames)")
     ap.add_argument("--serve-host-k", default="16,32,48,64",
                     help="channel counts to try with pinned-host frames (0 to skip)")
