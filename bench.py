@@ -232,7 +232,8 @@ def main():
                     help="channel: the one-channel step (default, the JSON contract line); "
                          "channels16 / subarrays64: batched launches against plain launches; "
                          "serve: streaming channels, largest real-time K")
-    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of each streaming trial (real time)")
     ap.add_argument("--serve-launch-us", type=float, default=4000.0,
                     help="launch period of the streaming server (frames per launch per channel)")
     ap.add_argument("--serve-stagger", type=int, choices=(0, 1), default=0,
