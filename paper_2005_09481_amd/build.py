@@ -22,7 +22,9 @@ def build(verbose: bool = False) -> str:
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Wall", "-Wno-unused-result", *DEVICE_FLAGS,
            "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           "-o", tmp, *[os.path.join(CSRC, s) for s in SOURCES]]
+           "-o", tmp, *[os.path.join(CSRC, s) for s in SOURCES],
+           # roctx ranges of the streaming server (for rocprofv3 --marker-trace)
+           "-L", "/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     noise = "is not a recognized feature for this target"
     msgs = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if noise not in l)

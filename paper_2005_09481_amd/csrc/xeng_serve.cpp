@@ -11,6 +11,7 @@
 // (xeng_correlate_batch), the exports due after each (xeng_dump_batch, into
 // one device buffer per slot) and slot resets, and events for completion.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <chrono>
@@ -24,6 +25,15 @@
 namespace {
 
 using Clock = std::chrono::steady_clock;
+
+// A roctx range over a scope: the server's phases show up in a
+// rocprofv3 --marker-trace beside the kernels they queue.
+struct Range {
+    explicit Range(const char *what) { roctxRangePush(what); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 // Device-side state of a channel (its scheduling state lives in the core).
 struct ChanMem {
@@ -58,6 +68,7 @@ public:
 
     int copy(const xeng::sched::Chan &c, int32_t chan, int64_t frame, int64_t *token) override
     {
+        Range r("xeng server: ingest copy");
         const ChanMem &m = s_->mem[(size_t)chan];
         uint8_t *dst = m.ring + (frame % s_->cfg.ring_frames) * s_->frame_bytes;
         const uint8_t *src = m.src + (frame % c.src_frames) * s_->frame_bytes;
@@ -69,6 +80,7 @@ public:
     int launch(const std::vector<xeng::sched::Job> &jobs, const std::vector<xeng::sched::Job> &exports,
                int64_t *token) override
     {
+        Range r("xeng server: launch + exports");
         const xeng::sched::Config &cf = s_->sch->config();
         int rc = XENG_OK;
         if (!jobs.empty()) {
@@ -100,7 +112,11 @@ public:
         return record(s_->compute, token);
     }
 
-    int reset(int32_t slot) override { return xeng_reset(s_->ctx, slot, s_->compute); }
+    int reset(int32_t slot) override
+    {
+        Range r("xeng server: slot reset");
+        return xeng_reset(s_->ctx, slot, s_->compute);
+    }
 
     int poll(int64_t token, bool wait) override
     {
@@ -263,7 +279,11 @@ int xeng_server_run(xeng_server *s, double seconds, xeng_server_stats *stats)
     if (hipSetDevice(s->cfg.device) != hipSuccess) return XENG_EDEVICE;
     HipExec ex(s);
     xeng::sched::Stats st;
-    const int rc = s->sch->run(ex, seconds, &st);
+    int rc;
+    {
+        Range r("xeng server: run");
+        rc = s->sch->run(ex, seconds, &st);
+    }
     stats->frames_released = st.frames_released;
     stats->frames_done = st.frames_done;
     stats->frames_dropped = st.frames_dropped;
