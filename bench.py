@@ -241,7 +241,7 @@ def main():
                          "(XENG_SERVER_STAGGER_EXPORTS); 0: every channel exports in the same launch")
     ap.add_argument("--serve-k", default="256,288,320,336,352,368,384",
                     help="channel counts to try (device-sourced frames)")
-    ap.add_argument("--serve-host-k", default="16,32,48,64",
+    ap.add_argument("--serve-host-k", default="16,24,32,40,48",
                     help="channel counts to try with pinned-host frames (0 to skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB "
