@@ -109,14 +109,15 @@ def test_admission_waits_for_a_free_slot(X):
 
 
 def test_host_sourced_frames(X):
-    # pinned host frames, copied into each channel's device ring on release
-    srcs = [frames_of(seed=[7, c], n_frames=40) for c in range(2)]
-    srv = X.Server(N, dump_frames=DUMP, max_channels=2, ring_frames=16, launch_period_us=2000.0)
+    # pinned host frames, copied into each channel's device ring on release;
+    # five channels over the server's four copy streams, so two share one
+    srcs = [frames_of(seed=[7, c], n_frames=40) for c in range(5)]
+    srv = X.Server(N, dump_frames=DUMP, max_channels=5, ring_frames=16, launch_period_us=2000.0)
     hosts = [torch.from_numpy(f).pin_memory() for f in srcs]
-    chans = [srv.admit(h, start_s=0.001 * c, total_frames=2 * DUMP) for c, h in enumerate(hosts)]
+    chans = [srv.admit(h, start_s=0.0005 * c, total_frames=2 * DUMP) for c, h in enumerate(hosts)]
     st = srv.run(0.3)
     print("host frames", st, flush=True)
-    assert st["frames_dropped"] == 0 and st["frames_done"] == 2 * 2 * DUMP
+    assert st["frames_dropped"] == 0 and st["frames_done"] == 5 * 2 * DUMP
     for c, f in zip(chans, srcs):
         np.testing.assert_array_equal(srv.last_dump(c).cpu().numpy(), expected(f, DUMP))
     srv.close()
