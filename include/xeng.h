@@ -196,7 +196,7 @@ int xeng_correlate_reference(const uint8_t *d_samples, int64_t n_samples, int32_
  * a contiguous range of samples, each piece run by one workgroup of the
  * persistent launch.  Tiles cut into several pieces are flushed with integer
  * atomic adds, the others with a plain add.  Jobs whose samples pointer and
- * row stride are multiples of 16 bytes and whose N is a multiple of 256 use
+ * row stride are multiples of 16 bytes and whose N is a multiple of 16 use
  * workgroup tiles of 128 x 256 inputs ("wide"), others 128 x 128.
  */
 typedef struct {

@@ -298,7 +298,7 @@ JobDesc make_job(const xeng_ctx *c, int32_t slot, const uint8_t *d_samples, int6
     if (c->flags & XENG_NIBBLE_RE_LOW) jd.flags |= JOB_RE_LOW;
     const uintptr_t addr = reinterpret_cast<uintptr_t>(d_samples);
     if ((stride % 8) == 0 && (addr % 8) == 0 && c->n % 8 == 0) jd.flags |= JOB_ALIGNED8;
-    if ((stride % 16) == 0 && (addr % 16) == 0 && c->n % 256 == 0) jd.flags |= JOB_DMA;
+    if ((stride % 16) == 0 && (addr % 16) == 0 && c->n % 16 == 0) jd.flags |= JOB_DMA;
     if (may_store && c->acc_t[(size_t)slot] == 0) jd.flags |= JOB_FRESH;
     jd.pad = 0;
     return jd;

@@ -77,7 +77,7 @@ struct JobDesc {
 };
 constexpr uint32_t JOB_RE_LOW = 1u;    // real part in the low nibble
 constexpr uint32_t JOB_ALIGNED8 = 2u;   // samples, stride and N are multiples of 8 bytes
-constexpr uint32_t JOB_DMA = 4u;        // samples, stride multiples of 16, N of 256: DMA kernel
+constexpr uint32_t JOB_DMA = 4u;        // samples and stride multiples of 16 bytes, N of 16: DMA kernel
 constexpr uint32_t JOB_FRESH = 8u;      // the slot holds zeros: whole-tile flushes store instead of add
 
 // Work decomposition shapes: 128 x 128 tiles (general kernel) or

@@ -1,5 +1,5 @@
-// gfx950 correlation kernel for 16-byte-aligned sample arrays of N a
-// multiple of 256.
+// gfx950 correlation kernel for 16-byte-aligned sample arrays (base and row
+// stride) of N a multiple of 16.
 //
 // Same product as the general kernel -- for a tile of the upper triangle,
 //   V_ij = sum_t x_i(t) conj(x_j(t))                      (Sec. 2.2, eta)
@@ -107,6 +107,7 @@ struct Tile {
     const uint8_t *samples;
     const uint8_t *zeros;   // 16 bytes of zero samples (0x88)
     int64_t stride;
+    int n;                  // inputs (a multiple of 16)
     int row0, col0;         // first A input, first B input
     int t0, t1;
 };
@@ -207,7 +208,11 @@ __device__ __forceinline__ void dma16_s_stage(const uint8_t *base, const uint32_
 // `inst`; 8..23 fill half h of B group g.  Lane l fetches chunk l / 8 of
 // the instruction's 8 chunks at time row l % 8 of the group, which lands at
 // byte 16 l = 128 (l / 8) + 16 (l % 8) of the instruction's kilobyte.
-__device__ __forceinline__ void dma_geom(int inst, int lane, int row0, int col0, int &lds_off, int &t,
+// A chunk at or past input n (the edge tiles of an N that is not a multiple
+// of the tile) is fetched from inputs n - 16.. instead: every load stays in
+// its row, and what lands in those rows or columns of the tile only reaches
+// accumulator entries (i, j) with i or j >= n, which are never exported.
+__device__ __forceinline__ void dma_geom(int inst, int lane, int n, int row0, int col0, int &lds_off, int &t,
                                          int &in)
 {
     const int r = lane & 7, c = lane >> 3;
@@ -221,6 +226,7 @@ __device__ __forceinline__ void dma_geom(int inst, int lane, int row0, int col0,
         t = 8 * g + r;
         in = col0 + 16 * (8 * h + c);
     }
+    in = min(in, n - 16);
 }
 
 // Index of this wave among the DMA-issuing waves, or -1.  Waves 0..3 sit on
@@ -243,7 +249,7 @@ __device__ __forceinline__ void dma_lane_setup(DmaLane<NW> &dl, const Tile &tl, 
 #pragma unroll
     for (int k = 0; k < Layout<NW>::DMA_PER_WAVE; ++k) {
         int lds_off, t, in;
-        dma_geom(dma_wave<NW>(wave) + Layout<NW>::DMA_WAVES * k, lane, tl.row0, tl.col0, lds_off, t, in);
+        dma_geom(dma_wave<NW>(wave) + Layout<NW>::DMA_WAVES * k, lane, tl.n, tl.row0, tl.col0, lds_off, t, in);
         dl.off[k] = (uint32_t)((int64_t)t * tl.stride) + (uint32_t)in;
     }
 }
@@ -267,7 +273,7 @@ __device__ __forceinline__ void issue_stage(uint32_t slot_addr, const Tile &tl, 
 #pragma unroll
         for (int k = 0; k < Layout<NW>::DMA_PER_WAVE; ++k) {
             int lds_off, t, in;
-            dma_geom(dw + Layout<NW>::DMA_WAVES * k, lane, tl.row0, tl.col0, lds_off, t, in);
+            dma_geom(dw + Layout<NW>::DMA_WAVES * k, lane, tl.n, tl.row0, tl.col0, lds_off, t, in);
             lds[k] = slot_addr + (uint32_t)lds_off;
         }
         dma16_s_stage<Layout<NW>::DMA_PER_WAVE>(row, dl.off, lds);
@@ -275,7 +281,7 @@ __device__ __forceinline__ void issue_stage(uint32_t slot_addr, const Tile &tl, 
 #pragma unroll
         for (int k = 0; k < Layout<NW>::DMA_PER_WAVE; ++k) {
             int lds_off, t, in;
-            dma_geom(dw + Layout<NW>::DMA_WAVES * k, lane, tl.row0, tl.col0, lds_off, t, in);
+            dma_geom(dw + Layout<NW>::DMA_WAVES * k, lane, tl.n, tl.row0, tl.col0, lds_off, t, in);
             const uint8_t *src =
                 ts + t < tl.t1 ? tl.samples + (int64_t)(ts + t) * tl.stride + in : tl.zeros;
             dma16_v(src, slot_addr + (uint32_t)lds_off);
@@ -577,6 +583,7 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
         tl.samples = uniform(jd.samples);
         tl.zeros = uniform(args.zeros);
         tl.stride = uniform(jd.stride);
+        tl.n = __builtin_amdgcn_readfirstlane(jd.n);
         tl.row0 = __builtin_amdgcn_readfirstlane(ti * WA_ROWS);
         tl.col0 = __builtin_amdgcn_readfirstlane(tj2 * WB_COLS);
         tl.t0 = __builtin_amdgcn_readfirstlane(pce.t0);
@@ -603,7 +610,9 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
                 }
         // eight waves: a 64 x 64 region on the diagonal skips its block below it
         const bool diag = NW == 8 && tj == ti && cb0 == 2 * wa;
-        if (below)
+        // a wave whose tile lies past the last tile column (odd tile count)
+        // has nothing to compute either
+        if (below || tj >= jd.nt)
             idle_piece<NW>(ring, tl, wave, lane);
         else if (jd.flags & JOB_RE_LOW) {
             if (diag)

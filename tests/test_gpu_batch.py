@@ -46,7 +46,7 @@ def sampled_pairs_equal(v, x, n, k, seed):
 
 
 def test_mixed_batch_matches_oracle_and_alone(X):
-    # both kernel kinds in one call: N % 256 == 0 jobs take the DMA kernel,
+    # both kernel kinds in one call: N % 16 == 0 jobs take the DMA kernel,
     # the others the general one
     shapes = [(256, 700), (100, 333), (512, 64), (64, 4096), (256, 1), (300, 129)]
     print("mixed batch", shapes, flush=True)

@@ -197,10 +197,14 @@ def test_tuning_does_not_change_results(X):
     np.testing.assert_array_equal(outs[0], oracle.correlate(x))
 
 
-# N a multiple of 256 with aligned arrays takes the DMA kernel; the sample
-# counts straddle its 64-sample stages and the pieces' boundaries.
+# N a multiple of 16 with aligned arrays takes the DMA kernel; the sample
+# counts straddle its 64-sample stages and the pieces' boundaries, and N
+# that is not a multiple of its 256-input workgroup tile leaves edge tiles
+# (272 and 1904: an odd number of 128-input tiles, so the last workgroup
+# tile has no right half).
 @pytest.mark.parametrize("n,t", [(256, 1), (256, 63), (256, 64), (256, 65), (512, 1000),
-                                 (768, 4097), (1024, 333)])
+                                 (768, 4097), (1024, 333), (16, 1), (48, 65), (144, 300),
+                                 (272, 129), (400, 1000), (1008, 333), (1904, 64), (2000, 200)])
 @pytest.mark.parametrize("kernel", ["auto", "general"])
 def test_both_kernels_match_oracle(X, n, t, kernel):
     print(f"kernel={kernel} n={n} t={t}", flush=True)
