@@ -95,6 +95,12 @@ int xeng_destroy(xeng_ctx *ctx);
  *   N <= row_stride <= 2^26.
  * Asynchronous on hip_stream.  Refuses with XENG_EOVERFLOW if the slot
  * would integrate more than xeng_max_integration() samples.
+ * Samples whose base and row stride are multiples of 16 bytes with N a
+ * multiple of 16 are read in place; otherwise, for N >= 256, the call first
+ * copies them (in chunks of at most 256 MiB) into rows of N rounded up to
+ * 16 bytes, in stream-ordered scratch from a pool the library keeps per
+ * device (up to 1 GiB retained), and correlates the copy; XENG_ENOMEM if
+ * that scratch cannot be had.
  */
 int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples,
                    int64_t n_samples, int64_t row_stride, void *hip_stream);

@@ -27,6 +27,8 @@ hipError_t launch_dump(int32_t *acc, int32_t *diag, int n, int nt, int32_t *out,
                        hipStream_t stream);
 hipError_t launch_dump_batch(const DumpDesc *d_jobs, int n_jobs, int n_max, int nt_max, hipStream_t stream);
 hipError_t launch_zero(int32_t *p, int64_t n_i32, hipStream_t stream);
+hipError_t launch_pad_rows(const uint8_t *src, int64_t stride, int n, int64_t rows, int n16, uint8_t *dst,
+                           hipStream_t stream);
 hipError_t launch_reference(const uint8_t *s, int64_t n_samples, int n, int64_t stride,
                             uint32_t re_low, int32_t *out, hipStream_t stream);
 }  // namespace xeng
@@ -100,6 +102,7 @@ struct DeviceState {
     int ring_next = 0;
     std::unordered_map<std::string, Tuning> tuned;   // job sizes -> autotuned configuration
     std::atomic<int64_t *> clock{nullptr};             // xeng_clock_probe buffer
+    hipMemPool_t pad_pool = nullptr;   // scratch of padded single-channel calls (keeps up to 1 GiB)
 };
 
 std::mutex g_states_mu;
@@ -311,6 +314,75 @@ hipError_t launch(const KernelArgs &a, int32_t grid, bool dma, uint32_t flags_an
 {
     if (dma) return launch_correlate_dma(a, grid, stream);
     return launch_correlate(a, grid, (flags_and & JOB_ALIGNED8) != 0, stream);
+}
+
+// A single-channel call the DMA kernel cannot read in place (N not a
+// multiple of 16, or a base or stride not a multiple of 16 bytes) with N of
+// at least PAD_MIN_N: the samples are copied, in chunks of time rows, into
+// stream-ordered scratch with rows of N rounded up to 16 bytes padded with
+// zero samples, and each chunk is correlated from there by the DMA kernel
+// (about twice the general kernel's rate for a copy that moves each sample
+// twice).  Below PAD_MIN_N the general kernel's 128 x 128 tiles waste less.
+constexpr int PAD_MIN_N = 256;
+constexpr int64_t PAD_SCRATCH_BYTES = INT64_C(256) << 20;
+
+// Called with st->mu held and the device current; updates acc_t per chunk.
+int correlate_padded(xeng_ctx *ctx, int32_t slot, const uint8_t *samples, int64_t n_samples, int64_t stride,
+                     const Tuning &tu, hipStream_t stream)
+{
+    const int n16 = (ctx->n + 15) / 16 * 16;
+    const int64_t rows = std::min<int64_t>(n_samples, std::max<int64_t>(STAGE, PAD_SCRATCH_BYTES / n16 / STAGE * STAGE));
+    DeviceState *st = ctx->st;
+    hipError_t e = hipSuccess;
+    if (!st->pad_pool) {
+        // a pool of the library's own that keeps its memory between calls
+        // (the default pool returns it at every synchronization, and mapping
+        // it again costs more than the copy)
+        hipMemPoolProps props = {};
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = st->device;
+        if ((e = hipMemPoolCreate(&st->pad_pool, &props)) != hipSuccess) {
+            st->pad_pool = nullptr;
+            return map_err(e);
+        }
+        uint64_t keep = UINT64_C(1) << 30;
+        if ((e = hipMemPoolSetAttribute(st->pad_pool, hipMemPoolAttrReleaseThreshold, &keep)) != hipSuccess)
+            return map_err(e);
+    }
+    uint8_t *scratch = nullptr;
+    e = hipMallocFromPoolAsync(reinterpret_cast<void **>(&scratch), (size_t)(rows * n16), st->pad_pool, stream);
+    if (e != hipSuccess) return map_err(e);
+    int rc = XENG_OK;
+    for (int64_t t0 = 0; t0 < n_samples; t0 += rows) {
+        const int64_t tc = std::min(rows, n_samples - t0);
+        e = launch_pad_rows(samples + t0 * stride, stride, ctx->n, tc, n16, scratch, stream);
+        if (e != hipSuccess) {
+            rc = map_err(e);
+            break;
+        }
+        KernelArgs a;
+        a.job0 = make_job(ctx, slot, scratch, n16, true);
+        a.job0.n = n16;                 // the padded inputs hold zero samples
+        a.job0.flags |= JOB_DMA;
+        a.jobs = nullptr;
+        a.zeros = ctx->st->d_zeros;
+        a.clock = ctx->st->clock.load();
+        PlanJob pj{ctx->n, tc};
+        DevicePlan dp;
+        if ((rc = get_plan(ctx->st, &pj, 1, TileShape::Wide, tu, &dp)) != XENG_OK) break;
+        a.pieces = dp.d_pieces;
+        a.wg_off = dp.d_off;
+        if ((e = launch(a, dp.grid, true, a.job0.flags, stream)) != hipSuccess) {
+            rc = map_err(e);
+            break;
+        }
+        ctx->acc_t[(size_t)slot] += tc;
+    }
+    e = hipFreeAsync(scratch, stream);
+    if (rc == XENG_OK && e != hipSuccess) rc = map_err(e);
+    return rc;
 }
 
 // Validated jobs of a batch that have work, in input order.
@@ -559,6 +631,8 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_
     std::lock_guard<std::mutex> lk(ctx->st->mu);
     const Tuning tu = tuning_for(ctx->st, &pj, 1);
     const bool dma = use_dma(a.job0.flags, tu);
+    if (!dma && tu.kernel != XENG_KERNEL_GENERAL && ctx->n >= PAD_MIN_N)
+        return correlate_padded(ctx, slot, d_samples, n_samples, row_stride, tu, stream);
     int rc = get_plan(ctx->st, &pj, 1, dma ? TileShape::Wide : TileShape::Square, tu, &dp);
     if (rc != XENG_OK) return rc;
     a.pieces = dp.d_pieces;

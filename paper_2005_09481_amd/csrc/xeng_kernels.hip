@@ -503,6 +503,41 @@ __global__ __launch_bounds__(256) void vis_dump_batch(const DumpDesc *__restrict
     dump_block_row(jd.acc, jd.n, jd.nt, jd.diag, jd.out, jd.reset, blockIdx.x, blockIdx.y, stage);
 }
 
+// Rows of n samples (any stride and alignment) copied into rows of n16 = n
+// rounded up to 16 bytes, padded with zero samples (0x88): a layout the DMA
+// kernel reads.  Workgroup t copies row t, one output dword per thread and
+// step, consecutive threads on consecutive dwords, so the reads coalesce.
+// A dword's four source bytes are read as the one or two aligned dwords that
+// hold them (joined by a byte funnel shift); the second is read only when it
+// holds a byte of the row, so every load touches an aligned dword with at
+// least one byte of the caller's row in it.
+__global__ __launch_bounds__(256) void pad_rows(const uint8_t *__restrict__ src, int64_t stride, int n, int n16,
+                                                uint8_t *__restrict__ dst)
+{
+    const int64_t t = blockIdx.x;
+    const uint8_t *row = src + t * stride;
+    uint32_t *out_row = reinterpret_cast<uint32_t *>(dst + t * n16);
+    for (int c0 = 4 * (int)threadIdx.x; c0 < n16; c0 += 4 * 256) {
+        uint32_t out = 0x88888888u;
+        if (c0 < n) {
+            const uintptr_t a = reinterpret_cast<uintptr_t>(row + c0);
+            const uint32_t sh = (uint32_t)(a & 3);
+            const uint32_t *p = reinterpret_cast<const uint32_t *>(a - sh);
+            const int last = min(c0 + 3, n - 1);        // last byte of the row in this dword
+            const uint32_t lo = p[0];
+            const uint32_t hi = (sh != 0 && c0 + 4 - (int)sh <= last) ? p[1] : 0u;
+            uint32_t v = sh ? __builtin_amdgcn_alignbyte(hi, lo, sh) : lo;
+            const int valid = last - c0 + 1;
+            if (valid < 4) {
+                const uint32_t m = 0xFFFFFFFFu >> (8 * (4 - valid));
+                v = (v & m) | (0x88888888u & ~m);
+            }
+            out = v;
+        }
+        out_row[c0 >> 2] = out;
+    }
+}
+
 __global__ __launch_bounds__(256) void fill_zero(int4 *__restrict__ p, int64_t n4)
 {
     for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n4;
@@ -572,6 +607,15 @@ hipError_t launch_dump_batch(const DumpDesc *d_jobs, int n_jobs, int n_max, int 
     hipLaunchKernelGGL(diag_im_batch, dim3((n_max + 255) / 256, n_jobs), dim3(256), 0, stream, d_jobs);
     hipLaunchKernelGGL(vis_dump_batch, dim3(DUMP_PARTS_PER_TILE * nt_max, nt_max, n_jobs), dim3(256), 0, stream,
                        d_jobs);
+    return hipGetLastError();
+}
+
+// `dst`: rows * n16 bytes, 16-byte aligned; n16 a multiple of 16, >= n.
+hipError_t launch_pad_rows(const uint8_t *src, int64_t stride, int n, int64_t rows, int n16, uint8_t *dst,
+                           hipStream_t stream)
+{
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pad_rows, dim3((unsigned)rows), dim3(256), 0, stream, src, stride, n, n16, dst);
     return hipGetLastError();
 }
 

@@ -78,7 +78,8 @@ def test_re_low_order(X):
     np.testing.assert_array_equal(run(X, x, re_low=True), oracle.correlate(x, re_low=True))
 
 
-@pytest.mark.parametrize("n,stride,offset", [(100, 101, 0), (100, 128, 1), (61, 67, 3), (128, 130, 2)])
+@pytest.mark.parametrize("n,stride,offset", [(100, 101, 0), (100, 128, 1), (61, 67, 3), (128, 130, 2),
+                                             (256, 261, 3), (400, 400, 5), (1000, 1001, 1)])
 def test_strides_and_misaligned_base(X, n, stride, offset):
     t = 77
     big = synth.uniform_bytes(stride + offset, t, seed=4 + n)
@@ -437,3 +438,36 @@ def test_library_int8_gemm_cross_check(X):
     lib_out = torch.stack([vr[iu[0], iu[1]], vi[iu[0], iu[1]]], dim=1).cpu().numpy().astype(np.int64)
     got = run(X, x)
     np.testing.assert_array_equal(got, lib_out)
+
+
+# N >= 256 that the DMA kernel cannot read in place (N not a multiple of 16,
+# or an odd stride or base) is copied into zero-padded rows first; long
+# integrations go in chunks of time rows
+@pytest.mark.parametrize("n,t", [(1000, 3000), (2047, 129), (260, 65), (300, 5)])
+def test_padded_path_matches_oracle_and_general_kernel(X, n, t):
+    print(f"padded path n={n} t={t}", flush=True)
+    x = synth.uniform_bytes(n, t, seed=[61, n, t])
+    got = run(X, x)
+    np.testing.assert_array_equal(got, oracle.correlate(x))
+    try:
+        X.set_tuning(0, 0, X.XENG_KERNEL_GENERAL)
+        gen = run(X, x)
+    finally:
+        X.set_tuning(0, 0, X.XENG_KERNEL_AUTO)
+    np.testing.assert_array_equal(got, gen)
+
+
+def test_padded_path_accumulates_and_resets(X):
+    # two calls into one slot (the second not into a fresh slot), then a
+    # reset and a third call
+    n = 1000
+    xs = [synth.uniform_bytes(n, t, seed=[62, t]) for t in (200, 333, 64)]
+    c = X.Correlator(n, 1)
+    c.correlate(0, gpu(xs[0]))
+    c.correlate(0, gpu(xs[1]))
+    assert c.samples_integrated(0) == 533
+    got = c.dump(0).cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(got, oracle.correlate(np.concatenate(xs[:2])))
+    c.correlate(0, gpu(xs[2]))
+    np.testing.assert_array_equal(c.dump(0).cpu().numpy().astype(np.int64), oracle.correlate(xs[2]))
+    c.close()
