@@ -125,7 +125,11 @@ typedef struct {
  * (recurring job sizes are planned once; the plans are kept on the host) to
  * the device on hip_stream through a pinned staging ring, and never
  * synchronizes the device, so that a loop of calls with changing sizes
- * keeps the GPU busy.  For graph capture use xeng_batch_* below.
+ * keeps the GPU busy.  Jobs with N >= 256 that the wide kernel cannot read
+ * in place (see xeng_correlate) are copied into padded rows in scratch from
+ * the library's pool first, up to 256 MiB of them per call; the rest run
+ * the 128 x 128 kernel.  For graph capture use xeng_batch_* below (which
+ * reads every job in place).
  */
 int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream);
 

@@ -326,33 +326,43 @@ hipError_t launch(const KernelArgs &a, int32_t grid, bool dma, uint32_t flags_an
 constexpr int PAD_MIN_N = 256;
 constexpr int64_t PAD_SCRATCH_BYTES = INT64_C(256) << 20;
 
+// The device's scratch pool for padded jobs, created on first use: a pool
+// of the library's own that keeps up to 1 GiB between calls (the default
+// pool returns its memory at every synchronization, and mapping it again
+// costs more than the copy).  Called with st->mu held, device current.
+int pad_pool(DeviceState *st, hipMemPool_t *out)
+{
+    if (!st->pad_pool) {
+        hipMemPoolProps props = {};
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = st->device;
+        hipMemPool_t pool = nullptr;
+        hipError_t e = hipMemPoolCreate(&pool, &props);
+        if (e != hipSuccess) return map_err(e);
+        uint64_t keep = UINT64_C(1) << 30;
+        if ((e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep)) != hipSuccess) {
+            (void)hipMemPoolDestroy(pool);
+            return map_err(e);
+        }
+        st->pad_pool = pool;
+    }
+    *out = st->pad_pool;
+    return XENG_OK;
+}
+
 // Called with st->mu held and the device current; updates acc_t per chunk.
 int correlate_padded(xeng_ctx *ctx, int32_t slot, const uint8_t *samples, int64_t n_samples, int64_t stride,
                      const Tuning &tu, hipStream_t stream)
 {
     const int n16 = (ctx->n + 15) / 16 * 16;
     const int64_t rows = std::min<int64_t>(n_samples, std::max<int64_t>(STAGE, PAD_SCRATCH_BYTES / n16 / STAGE * STAGE));
-    DeviceState *st = ctx->st;
-    hipError_t e = hipSuccess;
-    if (!st->pad_pool) {
-        // a pool of the library's own that keeps its memory between calls
-        // (the default pool returns it at every synchronization, and mapping
-        // it again costs more than the copy)
-        hipMemPoolProps props = {};
-        props.allocType = hipMemAllocationTypePinned;
-        props.handleTypes = hipMemHandleTypeNone;
-        props.location.type = hipMemLocationTypeDevice;
-        props.location.id = st->device;
-        if ((e = hipMemPoolCreate(&st->pad_pool, &props)) != hipSuccess) {
-            st->pad_pool = nullptr;
-            return map_err(e);
-        }
-        uint64_t keep = UINT64_C(1) << 30;
-        if ((e = hipMemPoolSetAttribute(st->pad_pool, hipMemPoolAttrReleaseThreshold, &keep)) != hipSuccess)
-            return map_err(e);
-    }
+    hipMemPool_t pool = nullptr;
+    int prc = pad_pool(ctx->st, &pool);
+    if (prc != XENG_OK) return prc;
     uint8_t *scratch = nullptr;
-    e = hipMallocFromPoolAsync(reinterpret_cast<void **>(&scratch), (size_t)(rows * n16), st->pad_pool, stream);
+    hipError_t e = hipMallocFromPoolAsync(reinterpret_cast<void **>(&scratch), (size_t)(rows * n16), pool, stream);
     if (e != hipSuccess) return map_err(e);
     int rc = XENG_OK;
     for (int64_t t0 = 0; t0 < n_samples; t0 += rows) {
@@ -433,6 +443,50 @@ struct Part {
     std::vector<PlanJob> pj;
     std::vector<JobDesc> descs;
 };
+
+// Batched jobs the DMA kernel cannot read in place, with N >= PAD_MIN_N, are
+// copied into one pooled scratch buffer (as many as fit in PAD_SCRATCH_BYTES,
+// in job order; the rest keep the general kernel) and their descriptors
+// point at the copy.  The caller frees *scratch on the stream after the
+// launches.  Called with st->mu held and the device current.
+int pad_batch_jobs(JobList &jl, const Tuning &tu, hipStream_t stream, uint8_t **scratch)
+{
+    *scratch = nullptr;
+    if (tu.kernel == XENG_KERNEL_GENERAL) return XENG_OK;
+    std::vector<size_t> pick;
+    std::vector<int64_t> off;
+    int64_t total = 0;
+    for (size_t k = 0; k < jl.descs.size(); ++k) {
+        const JobDesc &d = jl.descs[k];
+        if ((d.flags & JOB_DMA) || d.n < PAD_MIN_N || jl.pj[k].t <= 0) continue;
+        const int64_t bytes = jl.pj[k].t * (int64_t)((d.n + 15) / 16 * 16);
+        if (total + bytes > PAD_SCRATCH_BYTES) continue;
+        pick.push_back(k);
+        off.push_back(total);
+        total += (bytes + 255) / 256 * 256;
+    }
+    if (pick.empty()) return XENG_OK;
+    hipMemPool_t pool = nullptr;
+    int rc = pad_pool(jl.st, &pool);
+    if (rc != XENG_OK) return rc;
+    hipError_t e = hipMallocFromPoolAsync(reinterpret_cast<void **>(scratch), (size_t)total, pool, stream);
+    if (e != hipSuccess) {
+        *scratch = nullptr;
+        return map_err(e);
+    }
+    for (size_t i = 0; i < pick.size(); ++i) {
+        JobDesc &d = jl.descs[pick[i]];
+        const int n16 = (d.n + 15) / 16 * 16;
+        uint8_t *dst = *scratch + off[i];
+        if ((e = launch_pad_rows(d.samples, d.stride, d.n, jl.pj[pick[i]].t, n16, dst, stream)) != hipSuccess)
+            return map_err(e);
+        d.samples = dst;
+        d.stride = n16;
+        d.n = n16;   // the padded inputs hold zero samples
+        d.flags |= JOB_DMA;
+    }
+    return XENG_OK;
+}
 
 std::vector<Part> split_by_kernel(const JobList &jl, const Tuning &tu)
 {
@@ -652,7 +706,14 @@ int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
     if (!guard.ok) return XENG_EDEVICE;
     std::lock_guard<std::mutex> lk(jl.st->mu);
     const Tuning tu = tuning_for(jl.st, jl.pj.data(), (int)jl.pj.size());
-    rc = run_parts(jl.st, split_by_kernel(jl, tu), tu, static_cast<hipStream_t>(hip_stream));
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    uint8_t *scratch = nullptr;
+    rc = pad_batch_jobs(jl, tu, stream, &scratch);
+    if (rc == XENG_OK) rc = run_parts(jl.st, split_by_kernel(jl, tu), tu, stream);
+    if (scratch) {
+        const hipError_t e = hipFreeAsync(scratch, stream);
+        if (rc == XENG_OK && e != hipSuccess) rc = map_err(e);
+    }
     if (rc != XENG_OK) return rc;
     for (int32_t k : jl.idx) jobs[k].ctx->acc_t[(size_t)jobs[k].slot] += jobs[k].n_samples;
     return XENG_OK;

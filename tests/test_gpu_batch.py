@@ -183,3 +183,21 @@ def test_autotune_keeps_results(X):
         X.set_tuning(2, 4, X.XENG_KERNEL_AUTO)                # defaults; drops the tuned entry
         for c in cs:
             c.close()
+
+
+def test_batch_pads_jobs_the_dma_kernel_cannot_read(X):
+    # N >= 256 that the DMA kernel cannot read in place (N not a multiple of
+    # 16, or an odd stride or base) is copied into padded rows for the batched
+    # launch; a DMA-ready job and a small general-kernel job ride along
+    shapes = [(1000, 700), (2047, 129), (300, 64), (256, 100), (100, 50)]
+    print("padded batch", shapes, flush=True)
+    xs = [synth.uniform_bytes(n, t, seed=[700, n, t]) for n, t in shapes]
+    # one more job: a misaligned view with an odd row stride
+    big = synth.uniform_bytes(523, 257, seed=701)
+    view = gpu(big)[:, 3:3 + 512]
+    cs = [X.Correlator(n, 1) for n, _ in shapes] + [X.Correlator(512, 1)]
+    X.correlate_batch([(c, 0, gpu(x)) for c, x in zip(cs, xs)] + [(cs[-1], 0, view)])
+    for c, x in zip(cs, xs + [big[:, 3:3 + 512]]):
+        v = c.dump(0)
+        np.testing.assert_array_equal(v.cpu().numpy(), oracle.correlate(np.ascontiguousarray(x)))
+        c.close()
