@@ -100,7 +100,9 @@ int xeng_destroy(xeng_ctx *ctx);
  * copies them (in chunks of at most 256 MiB) into rows of N rounded up to
  * 16 bytes, in stream-ordered scratch from a pool the library keeps per
  * device (up to 1 GiB retained), and correlates the copy; XENG_ENOMEM if
- * that scratch cannot be had.
+ * that scratch cannot be had (nothing queued).  A device error in a later
+ * chunk leaves the chunks already queued integrated and counted in
+ * xeng_samples_integrated.
  */
 int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples,
                    int64_t n_samples, int64_t row_stride, void *hip_stream);
