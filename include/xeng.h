@@ -39,6 +39,13 @@
  * is queued asynchronously; buffers passed in must stay valid until the
  * stream reaches the queued work.  Calls on one slot must be ordered on one
  * stream.  One context is not thread-safe; distinct contexts are.
+ *
+ * Graph capture: xeng_batch_launch is the one call that may be captured
+ * into a hipGraph.  xeng_correlate, xeng_correlate_batch, xeng_dump,
+ * xeng_dump_batch and xeng_reset keep host-side bookkeeping (the
+ * integration counter, staging buffers, pooled scratch) that a replay would
+ * not repeat, so they return XENG_ENOTSUP, queuing nothing, while their
+ * stream is capturing.
  */
 #ifndef XENG_H
 #define XENG_H
@@ -75,7 +82,8 @@ typedef struct {
 } xeng_config;
 
 /*
- * Create a correlator context: allocates n_slots zeroed int32 accumulators
+ * Create a correlator context (the channels a node serves, Sec. 2.3: each
+ * slot integrates one channel's visibilities): allocates n_slots zeroed int32 accumulators
  * of xeng_slot_bytes(n_inputs) bytes each on `device`.  The library owns
  * them until xeng_destroy.  Returns XENG_EINVAL for bad fields,
  * XENG_ENOMEM if the accumulators exceed mem_budget_bytes or hipMalloc
@@ -94,7 +102,9 @@ int xeng_destroy(xeng_ctx *ctx);
  *   owned by the caller.  n_samples >= 0 (0 is a no-op).
  *   N <= row_stride <= 2^26.
  * Asynchronous on hip_stream.  Refuses with XENG_EOVERFLOW if the slot
- * would integrate more than xeng_max_integration() samples.
+ * would integrate more than xeng_max_integration() samples.  On a slot
+ * named by a live prepared batch (xeng_batch_create) the call first waits
+ * for the device to read the slot's true count.
  * Samples whose base and row stride are multiples of 16 bytes with N a
  * multiple of 16 are read in place; otherwise, for N >= 256, the call first
  * copies them (in chunks of at most 256 MiB) into rows of N rounded up to
@@ -175,7 +185,10 @@ int xeng_dump_batch(const xeng_dump_job *jobs, int32_t n_jobs, void *hip_stream)
 /* Zero one slot's accumulators and sample counter (asynchronous). */
 int xeng_reset(xeng_ctx *ctx, int32_t slot, void *hip_stream);
 
-/* Samples integrated in a slot since its last reset; -1 on bad arguments. */
+/* Samples integrated in a slot since its last reset (the integration length
+ * the overflow bound of Sec. 2.2's 4+4-bit products limits); -1 on bad
+ * arguments.  For a slot named by a live prepared batch the count lives on
+ * the device: the call waits for the device and reads it. */
 int64_t xeng_samples_integrated(const xeng_ctx *ctx, int32_t slot);
 
 /* Largest number of samples a slot may integrate between resets. */
@@ -189,7 +202,8 @@ int64_t xeng_slot_bytes(int32_t n_inputs);
 int32_t xeng_n_inputs(const xeng_ctx *ctx);
 int32_t xeng_n_slots(const xeng_ctx *ctx);
 
-/* Human-readable text for a status code (static storage). */
+/* Human-readable text for a status code (static storage); the codes are
+ * those of enum xeng_status above. */
 const char *xeng_strerror(int status);
 
 /*
@@ -241,18 +255,26 @@ int64_t xeng_plan_inspect(const int32_t *n_inputs, const int64_t *n_samples, int
  * sample pointers are fixed: each launch reads whatever those buffers hold
  * when it runs.  The contexts must outlive the batch.
  *
- * xeng_batch_launch enqueues one kernel launch per kernel kind (at most
- * two) and nothing else -- no copy, no memset, no allocation -- so it may be
- * captured into a hipGraph.  Outside a capture it applies the integration
- * guard and advances the slots' sample counters.  While hip_stream is
- * capturing it does neither: each replay of the graph integrates again, and
- * its caller reports replays with xeng_batch_note_replays (which applies the
- * guard first, XENG_EOVERFLOW leaving the counters unchanged).
+ * xeng_batch_launch enqueues kernels only -- a one-thread guard kernel,
+ * then one correlation launch per kernel kind (at most two); no copy, no
+ * memset, no allocation -- so it may be captured into a hipGraph, and every
+ * replay integrates again.  The integration bound is enforced on the
+ * device: each slot named by a live batch keeps its sample counter in
+ * device memory, and the guard kernel of every launch or replay advances
+ * the counters of all the batch's slots only if none would pass
+ * xeng_max_integration(); otherwise the launch integrates nothing at all
+ * (counters and accumulators unchanged) and is counted as refused.
+ * xeng_batch_check waits for the device and returns XENG_EOVERFLOW if any
+ * launch or replay of the batch was refused since the previous check.
+ * While a slot is named by a live batch, xeng_samples_integrated and the
+ * calls that integrate into it wait for the device to read its counter,
+ * and it is never treated as holding zeros.  xeng_batch_destroy (which
+ * synchronizes the device) hands the count back to the host.
  */
 typedef struct xeng_batch xeng_batch;
 int xeng_batch_create(const xeng_job *jobs, int32_t n_jobs, xeng_batch **out);
 int xeng_batch_launch(xeng_batch *b, void *hip_stream);
-int xeng_batch_note_replays(xeng_batch *b, int64_t n_replays);
+int xeng_batch_check(xeng_batch *b);
 int xeng_batch_destroy(xeng_batch *b);
 
 /* A launch configuration chosen by xeng_autotune. */
@@ -358,6 +380,21 @@ int xeng_server_channel_info(const xeng_server *s, int32_t channel, xeng_server_
  */
 int xeng_server_last_dump(xeng_server *s, int32_t channel, int32_t *out);
 
+/*
+ * Export ring of a channel (where its integrated visibilities go at every
+ * export, Sec. 2.1: visibilities leave the node at a chosen cadence):
+ * export k of the channel (k = 0, 1, ... in export order) is written to
+ * ring + (k % n_entries) * N(N+1)/2 * 2 int32, in device memory or pinned
+ * host memory, caller-owned, valid until the server is destroyed.  The
+ * exports land in stream order; read them after xeng_server_run returns.
+ * Without a ring (the default) each export goes to the slot's own buffer
+ * and only the last is kept (xeng_server_last_dump).  Must be set before
+ * the channel's first export (XENG_EBUSY after); ring NULL with
+ * n_entries 0 sets none.  xeng_server_last_dump then reads the ring's
+ * latest entry.
+ */
+int xeng_server_export_ring(xeng_server *s, int32_t channel, int32_t *ring, int32_t n_entries);
+
 /* Kernel selection for xeng_set_tuning. */
 #define XENG_KERNEL_AUTO 0     /* wide DMA kernel where the job allows it, else general */
 #define XENG_KERNEL_GENERAL 1  /* always the general kernel */
@@ -370,6 +407,16 @@ int xeng_server_last_dump(xeng_server *s, int32_t channel, int32_t *out);
  * never depend on these settings.
  */
 int xeng_set_tuning(int32_t wgs_per_cu, int32_t min_stages, int32_t kernel);
+
+/*
+ * Scratch of the padded path: the single-channel calls that copy their
+ * samples into padded rows (see xeng_correlate) go in chunks of at most
+ * `bytes` of scratch, and a batched call pads at most `bytes` of its jobs.
+ * 0 restores the default (256 MiB).  Applies to later calls on every
+ * device; results never depend on it (smaller chunks only mean more
+ * launches).  XENG_EINVAL if bytes < 0.
+ */
+int xeng_set_pad_chunk_bytes(int64_t bytes);
 
 /*
  * Clock probe, for measurement (results never depend on it).  `dev_buf` is

@@ -31,6 +31,9 @@ hipError_t launch_pad_rows(const uint8_t *src, int64_t stride, int n, int64_t ro
                            hipStream_t stream);
 hipError_t launch_reference(const uint8_t *s, int64_t n_samples, int n, int64_t stride,
                             uint32_t re_low, int32_t *out, hipStream_t stream);
+hipError_t launch_batch_guard(const GuardJob *d_jobs, int n_jobs, int32_t *d_skip, int64_t *d_skipped,
+                              hipStream_t stream);
+hipError_t launch_set_count(int64_t *p, int64_t v, hipStream_t stream);
 }  // namespace xeng
 
 using namespace xeng;
@@ -40,6 +43,9 @@ namespace {
 std::atomic<int> g_wgs_per_cu{2};      // general kernel
 std::atomic<int> g_min_stages{4};
 std::atomic<int> g_kernel{XENG_KERNEL_AUTO};
+// Scratch bytes per padded chunk (single calls) and per batched call.
+constexpr int64_t PAD_SCRATCH_DEFAULT = INT64_C(256) << 20;
+std::atomic<int64_t> g_pad_bytes{PAD_SCRATCH_DEFAULT};
 
 // Launch configuration of one call: the global settings, or what the
 // autotuner found best for calls of the same job sizes.
@@ -255,6 +261,14 @@ struct xeng_batch {
         int32_t slot;
         int64_t n;
     };
+    // device: the guard table (one GuardJob per job with samples), then the
+    // skip flag (int32) and the count of refused launches (int64)
+    uint8_t *d_guard = nullptr;
+    GuardJob *d_gjobs = nullptr;
+    int32_t *d_skip = nullptr;
+    int64_t *d_skipped = nullptr;
+    int64_t skipped_seen = 0;
+    bool bound = false;          // the jobs' slots count this batch in ctx->bound
     struct Launch {
         bool dma;
         uint32_t flags_and;
@@ -278,13 +292,50 @@ struct xeng_ctx {
     int64_t slot_i32 = 0;
     int32_t *d_acc = nullptr;    // n_slots accumulators, then n_slots diagonal stagings
     int32_t *d_diag = nullptr;
+    int64_t *d_count = nullptr;  // per slot: samples integrated, kept on the device for prepared batches
     std::vector<int64_t> acc_t;
+    // live prepared batches naming each slot; while > 0 the slot's device
+    // counter (advanced by the batches' device guard) is the true count and
+    // acc_t is refreshed from it before any host-side check
+    std::vector<int32_t> bound;
     DeviceState *st = nullptr;
 };
 
 namespace {
 
 bool slot_ok(const xeng_ctx *c, int32_t slot) { return c && slot >= 0 && slot < c->n_slots; }
+
+// Calls that queue work with host-side bookkeeping (the integration counter,
+// staging buffers, pooled scratch) are refused while their stream is being
+// captured: a replay would repeat the work without the bookkeeping.  Only
+// xeng_batch_launch may be captured.
+int refuse_capture(hipStream_t stream)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return XENG_EDEVICE;
+    return cs == hipStreamCaptureStatusNone ? XENG_OK : XENG_ENOTSUP;
+}
+
+// A slot named by a live prepared batch: wait for the device and take the
+// device counter (which the batches' guard advances on every launch and
+// replay) as the host's count.  Device current.
+int refresh_count(xeng_ctx *c, int32_t slot)
+{
+    if (c->bound[(size_t)slot] == 0) return XENG_OK;
+    if (hipDeviceSynchronize() != hipSuccess) return XENG_EDEVICE;
+    int64_t v = 0;
+    if (hipMemcpy(&v, c->d_count + slot, sizeof v, hipMemcpyDeviceToHost) != hipSuccess) return XENG_EDEVICE;
+    c->acc_t[(size_t)slot] = v;
+    return XENG_OK;
+}
+
+// After an eager call changed a bound slot's count: the new value goes to
+// the device counter in stream order.
+hipError_t publish_count(xeng_ctx *c, int32_t slot, hipStream_t stream)
+{
+    if (c->bound[(size_t)slot] == 0) return hipSuccess;
+    return launch_set_count(c->d_count + slot, c->acc_t[(size_t)slot], stream);
+}
 
 // `may_store`: the launch runs once (not a prepared batch), so a slot that
 // holds zeros (nothing integrated since its last reset) may be written by
@@ -302,7 +353,7 @@ JobDesc make_job(const xeng_ctx *c, int32_t slot, const uint8_t *d_samples, int6
     const uintptr_t addr = reinterpret_cast<uintptr_t>(d_samples);
     if ((stride % 8) == 0 && (addr % 8) == 0 && c->n % 8 == 0) jd.flags |= JOB_ALIGNED8;
     if ((stride % 16) == 0 && (addr % 16) == 0 && c->n % 16 == 0) jd.flags |= JOB_DMA;
-    if (may_store && c->acc_t[(size_t)slot] == 0) jd.flags |= JOB_FRESH;
+    if (may_store && c->acc_t[(size_t)slot] == 0 && c->bound[(size_t)slot] == 0) jd.flags |= JOB_FRESH;
     jd.pad = 0;
     return jd;
 }
@@ -324,7 +375,6 @@ hipError_t launch(const KernelArgs &a, int32_t grid, bool dma, uint32_t flags_an
 // (about twice the general kernel's rate for a copy that moves each sample
 // twice).  Below PAD_MIN_N the general kernel's 128 x 128 tiles waste less.
 constexpr int PAD_MIN_N = 256;
-constexpr int64_t PAD_SCRATCH_BYTES = INT64_C(256) << 20;
 
 // The device's scratch pool for padded jobs, created on first use: a pool
 // of the library's own that keeps up to 1 GiB between calls (the default
@@ -357,7 +407,7 @@ int correlate_padded(xeng_ctx *ctx, int32_t slot, const uint8_t *samples, int64_
                      const Tuning &tu, hipStream_t stream)
 {
     const int n16 = (ctx->n + 15) / 16 * 16;
-    const int64_t rows = std::min<int64_t>(n_samples, std::max<int64_t>(STAGE, PAD_SCRATCH_BYTES / n16 / STAGE * STAGE));
+    const int64_t rows = std::min<int64_t>(n_samples, std::max<int64_t>(STAGE, g_pad_bytes.load() / n16 / STAGE * STAGE));
     hipMemPool_t pool = nullptr;
     int prc = pad_pool(ctx->st, &pool);
     if (prc != XENG_OK) return prc;
@@ -372,7 +422,7 @@ int correlate_padded(xeng_ctx *ctx, int32_t slot, const uint8_t *samples, int64_
             rc = map_err(e);
             break;
         }
-        KernelArgs a;
+        KernelArgs a{};
         a.job0 = make_job(ctx, slot, scratch, n16, true);
         a.job0.n = n16;                 // the padded inputs hold zero samples
         a.job0.flags |= JOB_DMA;
@@ -391,6 +441,8 @@ int correlate_padded(xeng_ctx *ctx, int32_t slot, const uint8_t *samples, int64_
         ctx->acc_t[(size_t)slot] += tc;
     }
     e = hipFreeAsync(scratch, stream);
+    if (rc == XENG_OK && e != hipSuccess) rc = map_err(e);
+    e = publish_count(ctx, slot, stream);
     if (rc == XENG_OK && e != hipSuccess) rc = map_err(e);
     return rc;
 }
@@ -460,7 +512,7 @@ int pad_batch_jobs(JobList &jl, const Tuning &tu, hipStream_t stream, uint8_t **
         const JobDesc &d = jl.descs[k];
         if ((d.flags & JOB_DMA) || d.n < PAD_MIN_N || jl.pj[k].t <= 0) continue;
         const int64_t bytes = jl.pj[k].t * (int64_t)((d.n + 15) / 16 * 16);
-        if (total + bytes > PAD_SCRATCH_BYTES) continue;
+        if (total + bytes > g_pad_bytes.load()) continue;
         pick.push_back(k);
         off.push_back(total);
         total += (bytes + 255) / 256 * 256;
@@ -538,9 +590,22 @@ int ring_acquire(DeviceState *st, size_t bytes, JobTable **out)
 }
 
 // Launch the parts of a batch, staging each job table through the ring.
+// Every plan and staging buffer is obtained, and every table written into
+// its pinned buffer, before the first copy or launch is queued: a host-side
+// failure (ENOMEM, a failed wait for a ring buffer) queues nothing.
 // Called with st->mu held and the device current.
 int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu, hipStream_t stream)
 {
+    struct Staged {
+        JobTable *tb;
+        size_t bytes;
+        KernelArgs a;
+        int32_t grid;
+        bool dma;
+        uint32_t flags_and;
+    };
+    std::vector<Staged> staged;
+    staged.reserve(parts.size());
     for (const Part &part : parts) {
         const TileShape shape = part.dma ? TileShape::Wide : TileShape::Square;
         int max_wgs, min_stages;
@@ -573,24 +638,29 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
         JobTable *tbp = nullptr;
         const int rc = ring_acquire(st, bytes, &tbp);
         if (rc != XENG_OK) return rc;
-        JobTable &tb = *tbp;
-        hipError_t e = hipSuccess;
-        std::memcpy(tb.h, part.descs.data(), b_jobs);
-        std::memcpy(tb.h + o_pieces, plan->pieces.data(), b_pieces);
-        std::memcpy(tb.h + o_off, plan->wg_off.data(), b_off);
-        e = hipMemcpyAsync(tb.d, tb.h, bytes, hipMemcpyHostToDevice, stream);
+        std::memcpy(tbp->h, part.descs.data(), b_jobs);
+        std::memcpy(tbp->h + o_pieces, plan->pieces.data(), b_pieces);
+        std::memcpy(tbp->h + o_off, plan->wg_off.data(), b_off);
+        Staged sg;
+        sg.tb = tbp;
+        sg.bytes = bytes;
+        sg.a = KernelArgs{};
+        sg.a.jobs = reinterpret_cast<const JobDesc *>(tbp->d);
+        sg.a.zeros = st->d_zeros;
+        sg.a.clock = st->clock.load();
+        sg.a.pieces = reinterpret_cast<const Piece *>(tbp->d + o_pieces);
+        sg.a.wg_off = reinterpret_cast<const int32_t *>(tbp->d + o_off);
+        sg.grid = plan->grid;
+        sg.dma = part.dma;
+        sg.flags_and = part.flags_and;
+        staged.push_back(sg);
+    }
+    for (Staged &sg : staged) {
+        hipError_t e = hipMemcpyAsync(sg.tb->d, sg.tb->h, sg.bytes, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = launch(sg.a, sg.grid, sg.dma, sg.flags_and, stream);
+        if (e == hipSuccess) e = hipEventRecord(sg.tb->ev, stream);
         if (e != hipSuccess) return map_err(e);
-        KernelArgs a;
-        std::memset(&a.job0, 0, sizeof a.job0);
-        a.jobs = reinterpret_cast<const JobDesc *>(tb.d);
-        a.zeros = st->d_zeros;
-        a.clock = st->clock.load();
-        a.pieces = reinterpret_cast<const Piece *>(tb.d + o_pieces);
-        a.wg_off = reinterpret_cast<const int32_t *>(tb.d + o_off);
-        e = launch(a, plan->grid, part.dma, part.flags_and, stream);
-        if (e == hipSuccess) e = hipEventRecord(tb.ev, stream);
-        if (e != hipSuccess) return map_err(e);
-        tb.pending = true;
+        sg.tb->pending = true;
     }
     return XENG_OK;
 }
@@ -630,17 +700,25 @@ int xeng_create(const xeng_config *cfg, xeng_ctx **out)
     c->nt = n_tiles_side(cfg->n_inputs);
     c->slot_i32 = slot_i32(cfg->n_inputs);
     c->acc_t.assign((size_t)cfg->n_slots, 0);
+    c->bound.assign((size_t)cfg->n_slots, 0);
     c->st = st;
     hipError_t e = hipMalloc(&c->d_acc, (size_t)bytes);
     if (e != hipSuccess) {
         delete c;
         return map_err(e);
     }
+    if ((e = hipMalloc(&c->d_count, (size_t)cfg->n_slots * sizeof(int64_t))) != hipSuccess) {
+        (void)hipFree(c->d_acc);
+        delete c;
+        return map_err(e);
+    }
     c->d_diag = c->d_acc + (int64_t)cfg->n_slots * c->slot_i32;
     e = launch_zero(c->d_acc, bytes / 4, nullptr);
+    if (e == hipSuccess) e = hipMemset(c->d_count, 0, (size_t)cfg->n_slots * sizeof(int64_t));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         (void)hipFree(c->d_acc);
+        (void)hipFree(c->d_count);
         delete c;
         return map_err(e);
     }
@@ -655,6 +733,7 @@ int xeng_destroy(xeng_ctx *ctx)
     {
         DeviceGuard guard(ctx->device);
         if (ctx->d_acc && hipFree(ctx->d_acc) != hipSuccess) rc = XENG_EDEVICE;
+        if (ctx->d_count && hipFree(ctx->d_count) != hipSuccess) rc = XENG_EDEVICE;
     }
     delete ctx;
     return rc;
@@ -666,17 +745,20 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_
     if (!slot_ok(ctx, slot) || n_samples < 0 || row_stride < ctx->n || row_stride > MAX_STRIDE)
         return XENG_EINVAL;
     if (n_samples > 0 && !d_samples) return XENG_EINVAL;
-    if (n_samples > T_MAX - ctx->acc_t[(size_t)slot]) return XENG_EOVERFLOW;
-    if (n_samples == 0) return XENG_OK;
     // sample offsets t * row_stride must stay addressable
-    if (row_stride > INT64_MAX / n_samples) return XENG_EINVAL;
-
+    if (n_samples > 0 && row_stride > INT64_MAX / n_samples) return XENG_EINVAL;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     DeviceGuard guard(ctx->device);
     if (!guard.ok) return XENG_EDEVICE;
-    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    int rc = refuse_capture(stream);
+    if (rc != XENG_OK) return rc;
+    if ((rc = refresh_count(ctx, slot)) != XENG_OK) return rc;
+    if (n_samples > T_MAX - ctx->acc_t[(size_t)slot]) return XENG_EOVERFLOW;
+    if (n_samples == 0) return XENG_OK;
+
     PlanJob pj{ctx->n, n_samples};
     DevicePlan dp;
-    KernelArgs a;
+    KernelArgs a{};
     a.job0 = make_job(ctx, slot, d_samples, row_stride, true);
     a.jobs = nullptr;
     a.zeros = ctx->st->d_zeros;
@@ -687,26 +769,36 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_
     const bool dma = use_dma(a.job0.flags, tu);
     if (!dma && tu.kernel != XENG_KERNEL_GENERAL && ctx->n >= PAD_MIN_N)
         return correlate_padded(ctx, slot, d_samples, n_samples, row_stride, tu, stream);
-    int rc = get_plan(ctx->st, &pj, 1, dma ? TileShape::Wide : TileShape::Square, tu, &dp);
+    rc = get_plan(ctx->st, &pj, 1, dma ? TileShape::Wide : TileShape::Square, tu, &dp);
     if (rc != XENG_OK) return rc;
     a.pieces = dp.d_pieces;
     a.wg_off = dp.d_off;
     hipError_t e = launch(a, dp.grid, dma, a.job0.flags, stream);
     if (e != hipSuccess) return map_err(e);
     ctx->acc_t[(size_t)slot] += n_samples;
-    return XENG_OK;
+    return map_err(publish_count(ctx, slot, stream));
 }
 
 int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
 {
-    JobList jl;
-    int rc = validate_jobs(jobs, n_jobs, 1, true, &jl);
-    if (rc != XENG_OK || jl.descs.empty()) return rc;
-    DeviceGuard guard(jl.device);
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return XENG_EINVAL;
+    if (n_jobs == 0) return XENG_OK;
+    if (!jobs[0].ctx) return XENG_EINVAL;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    DeviceGuard guard(jobs[0].ctx->device);
     if (!guard.ok) return XENG_EDEVICE;
+    int rc = refuse_capture(stream);
+    if (rc != XENG_OK) return rc;
+    // slots of live prepared batches: their true counts first
+    for (int32_t k = 0; k < n_jobs; ++k)
+        if (slot_ok(jobs[k].ctx, jobs[k].slot) && jobs[k].ctx->device == jobs[0].ctx->device &&
+            (rc = refresh_count(jobs[k].ctx, jobs[k].slot)) != XENG_OK)
+            return rc;
+    JobList jl;
+    rc = validate_jobs(jobs, n_jobs, 1, true, &jl);
+    if (rc != XENG_OK || jl.descs.empty()) return rc;
     std::lock_guard<std::mutex> lk(jl.st->mu);
     const Tuning tu = tuning_for(jl.st, jl.pj.data(), (int)jl.pj.size());
-    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     uint8_t *scratch = nullptr;
     rc = pad_batch_jobs(jl, tu, stream, &scratch);
     if (rc == XENG_OK) rc = run_parts(jl.st, split_by_kernel(jl, tu), tu, stream);
@@ -715,7 +807,11 @@ int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
         if (rc == XENG_OK && e != hipSuccess) rc = map_err(e);
     }
     if (rc != XENG_OK) return rc;
-    for (int32_t k : jl.idx) jobs[k].ctx->acc_t[(size_t)jobs[k].slot] += jobs[k].n_samples;
+    for (int32_t k : jl.idx) {
+        jobs[k].ctx->acc_t[(size_t)jobs[k].slot] += jobs[k].n_samples;
+        const hipError_t e = publish_count(jobs[k].ctx, jobs[k].slot, stream);
+        if (e != hipSuccess) return map_err(e);
+    }
     return XENG_OK;
 }
 
@@ -725,11 +821,16 @@ int xeng_dump(xeng_ctx *ctx, int32_t slot, int32_t *out, int32_t reset, void *hi
     DeviceGuard guard(ctx->device);
     if (!guard.ok) return XENG_EDEVICE;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int rc = refuse_capture(stream);
+    if (rc != XENG_OK) return rc;
     int32_t *acc = ctx->d_acc + (int64_t)slot * ctx->slot_i32;
     int32_t *diag = ctx->d_diag + (int64_t)slot * diag_i32(ctx->n);
     hipError_t e = launch_dump(acc, diag, ctx->n, ctx->nt, out, reset != 0, stream);
     if (e != hipSuccess) return map_err(e);
-    if (reset) ctx->acc_t[(size_t)slot] = 0;
+    if (reset) {
+        ctx->acc_t[(size_t)slot] = 0;
+        return map_err(publish_count(ctx, slot, stream));
+    }
     return XENG_OK;
 }
 
@@ -759,6 +860,8 @@ int xeng_dump_batch(const xeng_dump_job *jobs, int32_t n_jobs, void *hip_stream)
     if (!guard.ok) return XENG_EDEVICE;
     DeviceState *st = jobs[0].ctx->st;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int crc = refuse_capture(stream);
+    if (crc != XENG_OK) return crc;
     std::lock_guard<std::mutex> lk(st->mu);
     constexpr int32_t CHUNK = 65535;   // grid z limit
     for (int32_t k0 = 0; k0 < n_jobs; k0 += CHUNK) {
@@ -781,7 +884,11 @@ int xeng_dump_batch(const xeng_dump_job *jobs, int32_t n_jobs, void *hip_stream)
         tb->pending = true;
     }
     for (int32_t k = 0; k < n_jobs; ++k)
-        if (jobs[k].reset) jobs[k].ctx->acc_t[(size_t)jobs[k].slot] = 0;
+        if (jobs[k].reset) {
+            jobs[k].ctx->acc_t[(size_t)jobs[k].slot] = 0;
+            const hipError_t e = publish_count(jobs[k].ctx, jobs[k].slot, stream);
+            if (e != hipSuccess) return map_err(e);
+        }
     return XENG_OK;
 }
 
@@ -790,17 +897,25 @@ int xeng_reset(xeng_ctx *ctx, int32_t slot, void *hip_stream)
     if (!slot_ok(ctx, slot)) return XENG_EINVAL;
     DeviceGuard guard(ctx->device);
     if (!guard.ok) return XENG_EDEVICE;
-    hipError_t e = launch_zero(ctx->d_acc + (int64_t)slot * ctx->slot_i32, ctx->slot_i32,
-                               static_cast<hipStream_t>(hip_stream));
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int rc = refuse_capture(stream);
+    if (rc != XENG_OK) return rc;
+    hipError_t e = launch_zero(ctx->d_acc + (int64_t)slot * ctx->slot_i32, ctx->slot_i32, stream);
     if (e != hipSuccess) return map_err(e);
     ctx->acc_t[(size_t)slot] = 0;
-    return XENG_OK;
+    return map_err(publish_count(ctx, slot, stream));
 }
 
 int64_t xeng_samples_integrated(const xeng_ctx *ctx, int32_t slot)
 {
     if (!slot_ok(ctx, slot)) return -1;
-    return ctx->acc_t[(size_t)slot];
+    if (ctx->bound[(size_t)slot] == 0) return ctx->acc_t[(size_t)slot];
+    DeviceGuard guard(ctx->device);
+    int64_t v = -1;
+    if (!guard.ok || hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(&v, ctx->d_count + slot, sizeof v, hipMemcpyDeviceToHost) != hipSuccess)
+        return -1;
+    return v;
 }
 
 int64_t xeng_max_integration(void) { return T_MAX; }
@@ -876,23 +991,38 @@ int64_t xeng_plan_inspect(const int32_t *n_inputs, const int64_t *n_samples, int
 
 namespace {
 
+// Releases the batch's slots: a slot no other live batch names takes its
+// device counter's value as the host's count again.  Device current.
+void unbind_slots(xeng_batch *b)
+{
+    if (!b->bound) return;
+    bool synced = false;
+    for (const auto &a : b->acct) {
+        int32_t &bd = a.ctx->bound[(size_t)a.slot];
+        if (bd == 1) {
+            if (!synced) {
+                (void)hipDeviceSynchronize();
+                synced = true;
+            }
+            int64_t v = 0;
+            if (hipMemcpy(&v, a.ctx->d_count + a.slot, sizeof v, hipMemcpyDeviceToHost) == hipSuccess)
+                a.ctx->acc_t[(size_t)a.slot] = v;
+        }
+        if (bd > 0) --bd;
+    }
+    b->bound = false;
+}
+
 void free_batch(xeng_batch *b)
 {
+    unbind_slots(b);
     for (auto &l : b->launches) {
         if (l.d_jobs) (void)hipFree(l.d_jobs);
         if (l.d_pieces) (void)hipFree(l.d_pieces);
         if (l.d_off) (void)hipFree(l.d_off);
     }
+    if (b->d_guard) (void)hipFree(b->d_guard);
     delete b;
-}
-
-// Guard and counters for `k` more launches of a prepared batch.
-int account_batch(xeng_batch *b, int64_t k)
-{
-    for (const auto &a : b->acct)
-        if (a.n > T_MAX / k || a.n * k > T_MAX - a.ctx->acc_t[(size_t)a.slot]) return XENG_EOVERFLOW;
-    for (const auto &a : b->acct) a.ctx->acc_t[(size_t)a.slot] += a.n * k;
-    return XENG_OK;
 }
 
 }  // namespace
@@ -947,6 +1077,32 @@ int xeng_batch_create(const xeng_job *jobs, int32_t n_jobs, xeng_batch **out)
             return map_err(e);
         }
     }
+    // the device guard: [GuardJob per job | skip flag | refused launches]
+    std::vector<GuardJob> gj;
+    for (const auto &a : b->acct) gj.push_back(GuardJob{a.ctx->d_count + a.slot, a.n});
+    const size_t gbytes = (gj.size() * sizeof(GuardJob) + 15) / 16 * 16;
+    hipError_t e = hipMalloc(&b->d_guard, gbytes + 16);
+    if (e == hipSuccess) e = hipMemcpy(b->d_guard, gj.data(), gj.size() * sizeof(GuardJob), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(b->d_guard + gbytes, 0, 16);
+    if (e != hipSuccess) {
+        free_batch(b);
+        return map_err(e);
+    }
+    b->d_gjobs = reinterpret_cast<GuardJob *>(b->d_guard);
+    b->d_skip = reinterpret_cast<int32_t *>(b->d_guard + gbytes);
+    b->d_skipped = reinterpret_cast<int64_t *>(b->d_guard + gbytes + 8);
+    // bind the slots: a slot no live batch names yet starts its device
+    // counter from the host's count (which includes work already queued)
+    for (const auto &a : b->acct) {
+        if (a.ctx->bound[(size_t)a.slot] == 0 &&
+            (e = hipMemcpy(a.ctx->d_count + a.slot, &a.ctx->acc_t[(size_t)a.slot], sizeof(int64_t),
+                           hipMemcpyHostToDevice)) != hipSuccess) {
+            free_batch(b);
+            return map_err(e);
+        }
+        a.ctx->bound[(size_t)a.slot]++;
+        b->bound = true;
+    }
     *out = b;
     return XENG_OK;
 }
@@ -954,37 +1110,41 @@ int xeng_batch_create(const xeng_job *jobs, int32_t n_jobs, xeng_batch **out)
 int xeng_batch_launch(xeng_batch *b, void *hip_stream)
 {
     if (!b) return XENG_EINVAL;
+    if (b->launches.empty()) return XENG_OK;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     DeviceGuard guard(b->device);
     if (!guard.ok) return XENG_EDEVICE;
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return XENG_EDEVICE;
-    const bool capturing = cap == hipStreamCaptureStatusActive;
-    if (!capturing) {
-        for (const auto &a : b->acct)
-            if (a.n > T_MAX - a.ctx->acc_t[(size_t)a.slot]) return XENG_EOVERFLOW;
-    }
+    DeviceState *bst = device_state(b->device);
+    hipError_t e = launch_batch_guard(b->d_gjobs, (int)b->acct.size(), b->d_skip, b->d_skipped, stream);
+    if (e != hipSuccess) return map_err(e);
     for (const auto &l : b->launches) {
-        KernelArgs a;
-        std::memset(&a.job0, 0, sizeof a.job0);
+        KernelArgs a{};
         a.jobs = l.d_jobs;
         a.pieces = l.d_pieces;
         a.wg_off = l.d_off;
         a.zeros = b->zeros;
-        DeviceState *bst = device_state(b->device);
         a.clock = bst ? bst->clock.load() : nullptr;
-        hipError_t e = launch(a, l.grid, l.dma, l.flags_and, stream);
-        if (e != hipSuccess) return map_err(e);
+        a.skip = b->d_skip;
+        if ((e = launch(a, l.grid, l.dma, l.flags_and, stream)) != hipSuccess) return map_err(e);
     }
-    if (!capturing) (void)account_batch(b, 1);
     return XENG_OK;
 }
 
-int xeng_batch_note_replays(xeng_batch *b, int64_t n_replays)
+int xeng_batch_check(xeng_batch *b)
 {
-    if (!b || n_replays < 0) return XENG_EINVAL;
-    if (n_replays == 0) return XENG_OK;
-    return account_batch(b, n_replays);
+    if (!b) return XENG_EINVAL;
+    if (!b->d_skipped) return XENG_OK;
+    DeviceGuard guard(b->device);
+    if (!guard.ok) return XENG_EDEVICE;
+    int64_t v = 0;
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(&v, b->d_skipped, sizeof v, hipMemcpyDeviceToHost) != hipSuccess)
+        return XENG_EDEVICE;
+    if (v > b->skipped_seen) {
+        b->skipped_seen = v;
+        return XENG_EOVERFLOW;
+    }
+    return XENG_OK;
 }
 
 int xeng_batch_destroy(xeng_batch *b)
@@ -1087,6 +1247,13 @@ int xeng_set_tuning(int32_t wgs_per_cu, int32_t min_stages, int32_t kernel)
         std::lock_guard<std::mutex> lk2(kv.second->mu);
         kv.second->tuned.clear();
     }
+    return XENG_OK;
+}
+
+int xeng_set_pad_chunk_bytes(int64_t bytes)
+{
+    if (bytes < 0) return XENG_EINVAL;
+    g_pad_bytes.store(bytes == 0 ? PAD_SCRATCH_DEFAULT : bytes);
     return XENG_OK;
 }
 

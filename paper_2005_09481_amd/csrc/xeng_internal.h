@@ -99,6 +99,14 @@ struct KernelArgs {
     const int32_t *wg_off;    // pieces of workgroup w: [wg_off[w], wg_off[w+1])
     const uint8_t *zeros;     // ZERO_BYTES bytes of zero samples (0x88), 16-byte aligned
     int64_t *clock;           // optional (DMA kernel): workgroup 0 stores {shader cycles, 100 MHz time} at start and end
+    const int32_t *skip;      // optional: nonzero at launch time -> the launch integrates nothing
+};
+
+// Device-side integration guard of a prepared batch: one entry per job,
+// the slot's device sample counter and the samples one launch adds.
+struct GuardJob {
+    int64_t *count;
+    int64_t n;
 };
 constexpr int ZERO_BYTES = 256;
 

@@ -553,6 +553,8 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
 {
     using L = Layout<NW>;
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    // a prepared batch's device guard refused this launch
+    if (args.skip != nullptr && *args.skip != 0) return;
     // LDS byte address of the ring, wave-uniform (scalar register)
     const uint32_t ring = (uint32_t)__builtin_amdgcn_readfirstlane(
         (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)lds);

@@ -323,6 +323,8 @@ template <bool ALIGNED>
 __global__ __launch_bounds__(256, 2) void xcorr_mfma(KernelArgs args)
 {
     __shared__ __attribute__((aligned(16))) uint8_t smem[NBUF * STAGE_BYTES];
+    // a prepared batch's device guard refused this launch
+    if (args.skip != nullptr && *args.skip != 0) return;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -545,6 +547,30 @@ __global__ __launch_bounds__(256) void fill_zero(int4 *__restrict__ p, int64_t n
         p[k] = make_int4(0, 0, 0, 0);
 }
 
+// Integration guard of a prepared batch, run ahead of its correlation
+// launches: if every job's slot can take its samples without passing T_MAX,
+// the counters advance and *skip = 0; otherwise nothing changes, *skip = 1
+// (the correlation launches then return at once) and *skipped counts the
+// refusal.  One thread: a batch holds few jobs, and the check must see all
+// of them before any counter moves.
+__global__ void batch_guard(const GuardJob *__restrict__ jobs, int n_jobs, int32_t *skip, int64_t *skipped)
+{
+    if (threadIdx.x != 0) return;
+    bool ok = true;
+    for (int k = 0; k < n_jobs; ++k) ok = ok && jobs[k].n <= T_MAX - *jobs[k].count;
+    if (ok)
+        for (int k = 0; k < n_jobs; ++k) *jobs[k].count += jobs[k].n;
+    else
+        *skipped += 1;
+    *skip = ok ? 0 : 1;
+}
+
+// Stores one value into a device sample counter, in stream order.
+__global__ void set_count(int64_t *p, int64_t v)
+{
+    if (threadIdx.x == 0) *p = v;
+}
+
 // Scalar reference: one thread per pair (i <= j), int32 sums over t.
 __global__ __launch_bounds__(256) void xcorr_scalar(const uint8_t *__restrict__ s, int64_t n_samples,
                                                     int n, int64_t stride, uint32_t re_low,
@@ -627,6 +653,19 @@ hipError_t launch_zero(int32_t *p, int64_t n_i32, hipStream_t stream)
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(fill_zero, dim3((unsigned)blocks), dim3(256), 0, stream,
                        reinterpret_cast<int4 *>(p), n4);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_guard(const GuardJob *d_jobs, int n_jobs, int32_t *d_skip, int64_t *d_skipped,
+                              hipStream_t stream)
+{
+    hipLaunchKernelGGL(batch_guard, dim3(1), dim3(64), 0, stream, d_jobs, n_jobs, d_skip, d_skipped);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_count(int64_t *p, int64_t v, hipStream_t stream)
+{
+    hipLaunchKernelGGL(set_count, dim3(1), dim3(64), 0, stream, p, v);
     return hipGetLastError();
 }
 

@@ -45,6 +45,9 @@ struct Range {
 struct ChanMem {
     const uint8_t *src = nullptr;  // [src_frames][frame_len][N], device or pinned host
     uint8_t *ring = nullptr;       // device ring of a host source
+    int32_t *exports = nullptr;    // caller's export ring ([n_exports][N(N+1)/2][2]) or null
+    int32_t n_exports = 0;
+    int64_t issued = 0;            // exports queued into the caller's ring
 };
 
 }  // namespace
@@ -113,8 +116,12 @@ public:
         if (!exports.empty()) {
             std::vector<xeng_dump_job> dj;
             dj.reserve(exports.size());
-            for (const xeng::sched::Job &e : exports)
-                dj.push_back({s_->ctx, e.slot, 1, s_->d_out + (int64_t)e.slot * s_->out_i32, 0, 0});
+            for (const xeng::sched::Job &e : exports) {
+                ChanMem &m = s_->mem[(size_t)e.chan];
+                int32_t *dst = s_->d_out + (int64_t)e.slot * s_->out_i32;
+                if (m.exports) dst = m.exports + (m.issued++ % m.n_exports) * s_->out_i32;
+                dj.push_back({s_->ctx, e.slot, 1, dst, 0, 0});
+            }
             if ((rc = xeng_dump_batch(dj.data(), (int32_t)dj.size(), s_->compute)) != XENG_OK) return rc;
         }
         return record(s_->compute, token);
@@ -330,13 +337,30 @@ int xeng_server_last_dump(xeng_server *s, int32_t channel, int32_t *out)
 {
     if (!s || !out || channel < 0 || channel >= (int32_t)s->sch->chans().size()) return XENG_EINVAL;
     const xeng::sched::Chan &c = s->sch->chans()[(size_t)channel];
+    const ChanMem &m = s->mem[(size_t)channel];
     if (c.slot < 0 || c.dumps == 0) return XENG_EINVAL;
-    if (s->sch->slot_owner(c.slot) != channel) return XENG_EBUSY;   // slot reused since
+    const int32_t *src = nullptr;
+    if (m.exports) {
+        src = m.exports + ((m.issued - 1) % m.n_exports) * s->out_i32;
+    } else {
+        if (s->sch->slot_owner(c.slot) != channel) return XENG_EBUSY;   // slot reused since
+        src = s->d_out + (int64_t)c.slot * s->out_i32;
+    }
     if (hipSetDevice(s->cfg.device) != hipSuccess) return XENG_EDEVICE;
     if (hipStreamSynchronize(s->compute) != hipSuccess) return XENG_EDEVICE;
-    if (hipMemcpy(out, s->d_out + (int64_t)c.slot * s->out_i32, (size_t)(s->out_i32 * 4), hipMemcpyDefault) !=
-        hipSuccess)
-        return XENG_EDEVICE;
+    if (hipMemcpy(out, src, (size_t)(s->out_i32 * 4), hipMemcpyDefault) != hipSuccess) return XENG_EDEVICE;
+    return XENG_OK;
+}
+
+int xeng_server_export_ring(xeng_server *s, int32_t channel, int32_t *ring, int32_t n_entries)
+{
+    if (!s || channel < 0 || channel >= (int32_t)s->sch->chans().size() || (ring && n_entries < 1) ||
+        (!ring && n_entries != 0))
+        return XENG_EINVAL;
+    ChanMem &m = s->mem[(size_t)channel];
+    if (m.issued != 0 || s->sch->chans()[(size_t)channel].dumps != 0) return XENG_EBUSY;
+    m.exports = ring;
+    m.n_exports = n_entries;
     return XENG_OK;
 }
 

@@ -118,7 +118,9 @@ def lib() -> ctypes.CDLL:
         "xeng_clock_probe": (ctypes.c_int, [i32, vp]),
         "xeng_batch_create": (ctypes.c_int, [ctypes.POINTER(_Job), i32, ctypes.POINTER(vp)]),
         "xeng_batch_launch": (ctypes.c_int, [vp, vp]),
-        "xeng_batch_note_replays": (ctypes.c_int, [vp, i64]),
+        "xeng_batch_check": (ctypes.c_int, [vp]),
+        "xeng_set_pad_chunk_bytes": (ctypes.c_int, [i64]),
+        "xeng_server_export_ring": (ctypes.c_int, [vp, i32, vp, i32]),
         "xeng_batch_destroy": (ctypes.c_int, [vp]),
         "xeng_autotune": (ctypes.c_int, [ctypes.POINTER(_Job), i32, i32, vp, ctypes.POINTER(_Tuning)]),
         "xeng_server_create": (ctypes.c_int, [ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]),
@@ -164,6 +166,11 @@ def set_tuning(wgs_per_cu: int = 0, min_stages: int = 0, kernel: int = -1):
     per CU, minimum piece length in 64-sample stages, kernel selection
     (XENG_KERNEL_AUTO / XENG_KERNEL_GENERAL; -1 keeps the current one)."""
     _check(lib().xeng_set_tuning(wgs_per_cu, min_stages, kernel), "xeng_set_tuning")
+
+
+def set_pad_chunk_bytes(nbytes: int = 0):
+    """Scratch bytes per padded chunk / per batched call (0: the default)."""
+    _check(lib().xeng_set_pad_chunk_bytes(nbytes), "xeng_set_pad_chunk_bytes")
 
 
 def clock_probe(buf=None, device: int = 0):
@@ -330,8 +337,11 @@ class Batch:
         _check(lib().xeng_batch_launch(self._h, _stream_handle(stream, self.device)),
                "xeng_batch_launch")
 
-    def note_replays(self, n: int):
-        _check(lib().xeng_batch_note_replays(self._h, n), "xeng_batch_note_replays")
+    def check(self) -> int:
+        """Wait for the device; XENG_EOVERFLOW if a launch or replay since
+        the previous check was refused by the device-side integration guard
+        (it then integrated nothing), else XENG_OK."""
+        return int(lib().xeng_batch_check(self._h))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -454,6 +464,19 @@ class Server:
         ci = _ServerChannel()
         _check(lib().xeng_server_channel_info(self._h, channel, ctypes.byref(ci)), "xeng_server_channel_info")
         return {f: getattr(ci, f) for f, _ in _ServerChannel._fields_}
+
+    def export_ring(self, channel: int, ring):
+        """Every export of ``channel`` goes to ``ring`` [n][N(N+1)/2][2] int32
+        (device or pinned host), entry k % n for its k-th export."""
+        import torch
+        if ring.dtype != torch.int32 or ring.dim() != 3 or not ring.is_contiguous() or \
+                ring.shape[1] != tri(self.n_inputs) or ring.shape[2] != 2:
+            raise ValueError("ring must be contiguous int32 [n][N(N+1)/2][2]")
+        if not ring.is_cuda and not ring.is_pinned():
+            raise ValueError("a host ring must be in pinned memory")
+        _check(lib().xeng_server_export_ring(self._h, channel, ctypes.c_void_p(ring.data_ptr()), ring.shape[0]),
+               "xeng_server_export_ring")
+        self._keep.append(ring)
 
     def last_dump(self, channel: int):
         import torch

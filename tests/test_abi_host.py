@@ -160,3 +160,4 @@ def test_plan_caps_piece_length(X, wide, cap):
     # units of N = 256: tiles (0,0), (0,1), (1,1); wide tiles (0,0), (1,0)
     assert len(pieces) == (2 if wide else 3) * per_unit
     assert all(p.atomic for p in pieces)
+

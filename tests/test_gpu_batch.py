@@ -1,8 +1,9 @@
 """GPU parity of batched launches: many channels and sub-arrays of uneven N
 and T in one persistent launch per kernel kind, prepared batches replayed
-from a hipGraph, and the autotuner.  Every result is compared bit for bit
-with the CPU oracle (small cases: every visibility; full-size cases: all
-pairs among sampled inputs) and with the same job launched alone."""
+from a hipGraph (with their device-side integration guard), and the
+autotuner.  Every result is compared bit for bit with the CPU oracle (small
+cases: run in the test; full-size cases: every visibility against the
+oracle's recorded digest) and with the same job launched alone."""
 import numpy as np
 import pytest
 
@@ -32,17 +33,6 @@ def alone(X, x, n=None):
     v = c.dump(0)
     c.close()
     return v
-
-
-def sampled_pairs_equal(v, x, n, k, seed):
-    """All pairs among k sampled inputs (plus tile edges) against the oracle."""
-    rng = np.random.default_rng(seed)
-    edges = [e for e in (0, 127, 128, 255, 256, n - 1) if e < n]
-    s = np.unique(np.concatenate([rng.choice(n, min(k, n), replace=False), edges]))
-    ref = oracle.correlate(np.ascontiguousarray(x[:, s]))
-    v = v.cpu().numpy().astype(np.int64)
-    idx = [oracle.tri_index(int(s[a]), int(s[b]), n) for a in range(len(s)) for b in range(a, len(s))]
-    np.testing.assert_array_equal(v[idx], ref)
 
 
 def test_mixed_batch_matches_oracle_and_alone(X):
@@ -84,17 +74,19 @@ def test_subarray_batch_reduced(X):
 
 def test_batch_channels_full_size(X):
     # 16 channels x N = 2048, T uniform in [2048, 16384], 5% flagged: one
-    # batched launch against 16 launches alone (bit-exact) and the oracle on
-    # sampled pairs; flagged inputs give zero rows and columns
-    chans = synth.batched_channels(n_channels=16, n_inputs=2048, seed=3)
+    # batched launch; every channel's complete output against the oracle's
+    # recorded digest and against the channel launched alone; flagged
+    # inputs give zero rows and columns
+    import parity_util as pu
+    chans = pu.fc.channels16()
     print("batched channels full size", [x.shape[0] for x in chans], flush=True)
     c = X.Correlator(2048, 16)
     X.correlate_batch([(c, k, gpu(x)) for k, x in enumerate(chans)])
     n = 2048
     for k, x in enumerate(chans):
         v = c.dump(k)
+        pu.assert_matches_oracle_digest(f"channels16_c{k}", v, x)
         assert torch.equal(v, alone(X, x))
-        sampled_pairs_equal(v, x, n, 24, seed=k)
         flagged = np.where((x == 0x88).all(axis=0))[0]
         assert len(flagged) >= 102
         i = int(flagged[0])
@@ -103,14 +95,18 @@ def test_batch_channels_full_size(X):
 
 
 def test_subarray_batch_full_size(X):
-    subs = synth.subarray_batch(n_instances=64, seed=4)
+    # 64 sub-arrays of uneven N and T in one batched launch: every
+    # instance's complete output against the oracle's recorded digest and
+    # against the instance launched alone
+    import parity_util as pu
+    subs = pu.fc.subarrays64()
     print("subarray batch full size", sum(x.nbytes for x in subs) / 1e6, "MB", flush=True)
     cs = [X.Correlator(x.shape[1], 1) for x in subs]
     X.correlate_batch([(c, 0, gpu(x)) for c, x in zip(cs, subs)])
     for k, (c, x) in enumerate(zip(cs, subs)):
         v = c.dump(0)
+        pu.assert_matches_oracle_digest(f"subarrays64_k{k}", v, x)
         assert torch.equal(v, alone(X, x))
-        sampled_pairs_equal(v, x, x.shape[1], 16, seed=100 + k)
         c.close()
 
 
@@ -132,8 +128,9 @@ def test_batch_rejects_bad_jobs(X):
 
 def test_prepared_batch_graph_replays(X):
     # a prepared batch captured in a hipGraph: every replay integrates the
-    # jobs again; each replay is checked against the oracle, with eager work
-    # and synchronizations between replays
+    # jobs again and advances the slots' device counters; each replay is
+    # checked against the oracle, with eager work and synchronizations
+    # between replays
     shapes = [(256, 300), (512, 129), (100, 77)]
     xs = [synth.uniform_bytes(n, t, seed=900 + i) for i, (n, t) in enumerate(shapes)]
     refs = [oracle.correlate(x) for x in xs]
@@ -151,17 +148,73 @@ def test_prepared_batch_graph_replays(X):
     other = X.Correlator(64, 1)
     y = gpu(synth.uniform_bytes(64, 100, seed=3))
     for rep in range(1, 4):
-        b.note_replays(1)
         g.replay()
         torch.cuda.synchronize()
         for c, r in zip(cs, refs):
             np.testing.assert_array_equal(c.dump(0, reset=False).cpu().numpy(), (rep + 1) * r)
+        assert [c.samples_integrated(0) for c in cs] == [(rep + 1) * t for _, t in shapes]
         other.correlate(0, y)                               # eager work between replays
         torch.cuda.synchronize()
-    assert [c.samples_integrated(0) for c in cs] == [4 * t for _, t in shapes]
+    assert b.check() == X.XENG_OK
     b.close()
+    # the count is the host's again after the batch is gone
+    assert [c.samples_integrated(0) for c in cs] == [4 * t for _, t in shapes]
     for c in cs:
         c.close()
+
+
+def test_prepared_batch_guard_refuses_replay_past_bound(X):
+    # a slot brought within one job of the integration bound: a replay that
+    # fits integrates, the next (which would pass the bound) is refused on
+    # the device -- accumulators and counter unchanged, reported by check()
+    # -- and an eager call into the slot afterwards still adds to what the
+    # replays integrated (the slot is never taken for an empty one)
+    n, job = 64, 64
+    tmax = X.max_integration()
+    zeros = torch.zeros((1 << 20, n), dtype=torch.uint8, device="cuda")   # every sample -8-8j
+    c = X.Correlator(n, 1)
+    done, target = 0, tmax - job - 10
+    while done < target:
+        k = min(zeros.shape[0], target - done)
+        c.correlate(0, zeros[:k])
+        done += k
+    x = gpu(np.zeros((job, n), dtype=np.uint8))
+    b = X.Batch([(c, 0, x)])
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.launch(stream=s)
+    g.replay()                                          # fits: tmax - 10
+    torch.cuda.synchronize()
+    assert c.samples_integrated(0) == tmax - 10
+    assert b.check() == X.XENG_OK
+    g.replay()                                          # would pass the bound
+    torch.cuda.synchronize()
+    assert b.check() == X.XENG_EOVERFLOW
+    assert b.check() == X.XENG_OK                       # reported once
+    assert c.samples_integrated(0) == tmax - 10
+    v = c.dump(0, reset=False).cpu().numpy().astype(np.int64)
+    assert (v[:, 0] == 128 * (tmax - 10)).all() and not v[:, 1].any()
+    # eager call on the bound slot: guard from the device count, adds
+    with pytest.raises(X.XengError) as e:
+        c.correlate(0, zeros[:11])
+    assert e.value.status == X.XENG_EOVERFLOW
+    u = synth.uniform_bytes(n, 10, seed=91)
+    c.correlate(0, gpu(u))
+    assert c.samples_integrated(0) == tmax
+    v = c.dump(0, reset=False).cpu().numpy().astype(np.int64)
+    ref = oracle.correlate(u)
+    np.testing.assert_array_equal(v[:, 0], 128 * (tmax - 10) + ref[:, 0])
+    np.testing.assert_array_equal(v[:, 1], ref[:, 1])
+    # after a reset the replays fit again
+    c.reset(0)
+    g.replay()
+    torch.cuda.synchronize()
+    assert b.check() == X.XENG_OK and c.samples_integrated(0) == job
+    assert (c.dump(0, reset=False).cpu().numpy()[:, 0] == 128 * job).all()
+    b.close()
+    assert c.samples_integrated(0) == job
+    c.close()
 
 
 def test_autotune_keeps_results(X):

@@ -1,9 +1,10 @@
 """GPU parity: the gfx950 correlator against the CPU oracle, bit for bit.
 
-Integer work, so the bar is exact equality.  Small cases compare every
-visibility; the full-size N=2048 workload compares sampled pairs computed by
-the oracle plus properties that hold at any size (diagonal power, a rank-1
-tone's closed form)."""
+Integer work, so the bar is exact equality, and every visibility is
+compared: small and ragged cases against the oracle run in the test, the
+full-size N=2048 channel against the oracle run in the test and its recorded
+digest.  Properties that hold at any size (diagonal power, a rank-1 tone's
+closed form) are checked beside them."""
 import ctypes
 
 import numpy as np
@@ -269,8 +270,9 @@ def test_kernels_mixed_on_one_slot(X):
 
 @pytest.fixture(scope="module")
 def full_size(X):
+    import parity_util as pu
     print("full-size n=2048 t=32768: generating", flush=True)
-    x = synth.chime_channel(2048, 32768, seed=2)
+    x = pu.fc.channel_n2048()
     c = X.Correlator(2048, 1)
     c.correlate(0, gpu(x))
     v = c.dump(0).cpu().numpy().astype(np.int64)
@@ -278,19 +280,17 @@ def full_size(X):
     return x, v
 
 
-def test_full_size_sampled_pairs(X, full_size):
+def test_full_size_matches_oracle(X, full_size):
+    """Every one of the N(N+1)/2 = 2,098,176 visibilities of the N=2048,
+    T=32768 channel, in the launch configuration the benchmark times, equals
+    the oracle's (computed here on the host's cores, and its recorded digest)."""
+    import parity_util as pu
     x, v = full_size
-    n = 2048
-    rng = np.random.default_rng(123)
-    # 96 random inputs plus the tile edges: all their pairs, by the oracle
-    s = np.unique(np.concatenate([rng.choice(n, 96, replace=False),
-                                  [0, 1, 127, 128, 1023, 1024, 2046, 2047]]))
-    ref = oracle.correlate(x[:, s])
-    k = 0
-    for a in range(len(s)):
-        for b in range(a, len(s)):
-            np.testing.assert_array_equal(v[oracle.tri_index(int(s[a]), int(s[b]), n)], ref[k])
-            k += 1
+    print("full-size n=2048 t=32768: oracle", flush=True)
+    ref = oracle.correlate(x)
+    if not np.array_equal(v, ref):
+        raise AssertionError(pu.first_difference(v, ref, 2048))
+    pu.assert_matches_oracle_digest("channel_n2048_t32768", v, x)
 
 
 def test_full_size_diagonal_is_power(X, full_size):
@@ -470,4 +470,65 @@ def test_padded_path_accumulates_and_resets(X):
     np.testing.assert_array_equal(got, oracle.correlate(np.concatenate(xs[:2])))
     c.correlate(0, gpu(xs[2]))
     np.testing.assert_array_equal(c.dump(0).cpu().numpy().astype(np.int64), oracle.correlate(xs[2]))
+    c.close()
+
+
+def test_padded_path_in_chunks(X):
+    # the padded path's scratch lowered so that T = 3000 at N = 1000 runs in
+    # three chunks of 1472, 1472 and 56 rows (a tail shorter than one
+    # 64-sample stage): scratch reused across chunks, the later chunks
+    # adding into a slot that already holds the earlier ones, a plan per
+    # chunk; then a second call into the same slot
+    n, t = 1000, 3000
+    print(f"padded path in chunks n={n} t={t}", flush=True)
+    xs = [synth.uniform_bytes(n, t, seed=[63, k]) for k in range(2)]
+    try:
+        X.set_pad_chunk_bytes(1472 * 1008)
+        c = X.Correlator(n, 1)
+        c.correlate(0, gpu(xs[0]))
+        np.testing.assert_array_equal(c.dump(0, reset=False).cpu().numpy().astype(np.int64),
+                                      oracle.correlate(xs[0]))
+        c.correlate(0, gpu(xs[1]))
+        assert c.samples_integrated(0) == 2 * t
+        np.testing.assert_array_equal(c.dump(0).cpu().numpy().astype(np.int64),
+                                      oracle.correlate(np.concatenate(xs)))
+        c.close()
+    finally:
+        X.set_pad_chunk_bytes(0)
+
+
+def test_calls_refused_while_capturing(X):
+    # only xeng_batch_launch may be captured: the others return
+    # XENG_ENOTSUP while their stream captures, queue nothing and leave the
+    # counters alone
+    n = 64
+    L = X.lib()
+    c = X.Correlator(n, 2)
+    x = gpu(synth.uniform_bytes(n, 100, seed=64))
+    c.correlate(0, x)
+    torch.cuda.synchronize()
+    out = torch.zeros((X.tri(n), 2), dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    p = ctypes.c_void_p(x.data_ptr())
+    codes = {}
+    with torch.cuda.graph(g, stream=s):
+        h = ctypes.c_void_p(s.cuda_stream)
+        codes["correlate"] = L.xeng_correlate(c.handle, 1, p, 100, n, h)
+        codes["dump"] = L.xeng_dump(c.handle, 0, ctypes.c_void_p(out.data_ptr()), 1, h)
+        codes["reset"] = L.xeng_reset(c.handle, 0, h)
+        arr = (X._Job * 1)()
+        arr[0] = X._Job(c.handle, 1, 0, p, 100, n)
+        codes["batch"] = L.xeng_correlate_batch(arr, 1, h)
+        darr = (X._DumpJob * 1)()
+        darr[0] = X._DumpJob(c.handle, 0, 1, out.data_ptr(), 0, 0)
+        codes["dump_batch"] = L.xeng_dump_batch(darr, 1, h)
+    assert all(v == X.XENG_ENOTSUP for v in codes.values()), codes
+    assert c.samples_integrated(0) == 100 and c.samples_integrated(1) == 0
+    g.replay()
+    torch.cuda.synchronize()
+    assert not out.any()
+    ref = oracle.correlate(x.cpu().numpy())
+    np.testing.assert_array_equal(c.dump(0).cpu().numpy(), ref)
+    assert not c.dump(1).any()
     c.close()

@@ -163,3 +163,42 @@ def test_server_argument_checks(X):
     with pytest.raises(ValueError):
         srv.admit(torch.zeros((4, 256, 100), dtype=torch.uint8, device="cuda"))
     srv.close()
+
+
+def test_full_size_n2048_every_export(X):
+    # four device-sourced channels of N = 2048 (each cycling 48 distinct
+    # frames), three exports each into an export ring: every export equals
+    # the oracle over the frames it covers (recorded digests), and channel
+    # 0 served alone gives the same exports as in the mix
+    import parity_util as pu
+    fc = pu.fc
+    n, d = fc.SERVE_N, fc.SERVE_DUMP
+    srcs = [fc.serve_source(c) for c in range(fc.SERVE_CHANNELS)]
+    print(f"serve n={n}: {fc.SERVE_CHANNELS} channels x {fc.SERVE_EXPORTS} exports", flush=True)
+
+    def serve(channels):
+        srv = X.Server(n, dump_frames=d, max_channels=len(channels), launch_period_us=2000.0)
+        rings = []
+        for k, c in enumerate(channels):
+            ch = srv.admit(torch.from_numpy(srcs[c]).cuda(), start_s=0.001 * k,
+                           total_frames=fc.SERVE_EXPORTS * d)
+            ring = torch.full((fc.SERVE_EXPORTS, X.tri(n), 2), -1, dtype=torch.int32, device="cuda")
+            srv.export_ring(ch, ring)
+            rings.append((ch, ring))
+        st = srv.run(0.5)
+        print("serve", channels, st, flush=True)
+        assert st["frames_done"] == len(channels) * fc.SERVE_EXPORTS * d and st["frames_dropped"] == 0
+        for ch, _ in rings:
+            info = srv.channel_info(ch)
+            assert info["state"] == 2 and info["dumps"] == fc.SERVE_EXPORTS
+        out = [ring.cpu() for _, ring in rings]
+        srv.close()
+        return out
+
+    mix = serve(list(range(fc.SERVE_CHANNELS)))
+    for c, ring in enumerate(mix):
+        for m in range(fc.SERVE_EXPORTS):
+            pu.assert_matches_oracle_digest(f"serve_n2048_c{c}_e{m}", ring[m].numpy(),
+                                            fc.serve_window(srcs[c], m))
+    solo = serve([0])
+    assert torch.equal(solo[0], mix[0])
