@@ -117,6 +117,26 @@ int xeng_destroy(xeng_ctx *ctx);
 int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples,
                    int64_t n_samples, int64_t row_stride, void *hip_stream);
 
+/*
+ * Allocation-free variant of xeng_correlate, for callers that cannot
+ * allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc): the same result and the same checks, but nothing is
+ * allocated, freed or pooled -- no cached plan, no padded copy.  The call's
+ * work plan is written on the device, by a one-thread kernel queued ahead
+ * of the correlation, into a fixed array of XENG_STATIC_SCRATCH_BYTES that
+ * each GPU holds from the library's set-up until the process ends.  Every
+ * call on a GPU shares that array (and each call overwrites it), so calls
+ * that may overlap on one GPU -- on different streams, from different
+ * threads -- race; calls ordered on one stream do not.  Samples the wide
+ * kernel cannot read in place take the 128 x 128 kernel directly.
+ * XENG_ENOMEM, nothing queued, if the plan would not fit the array (about
+ * 65000 pieces: N = 2048 fits at any T up to xeng_max_integration()).
+ * XENG_ENOTSUP while hip_stream is capturing, like xeng_correlate.
+ */
+#define XENG_STATIC_SCRATCH_BYTES (1 << 20)
+int xeng_correlate_static(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples,
+                          int64_t n_samples, int64_t row_stride, void *hip_stream);
+
 /* One unit of a batched correlation: correlate d_samples into ctx/slot. */
 typedef struct {
     xeng_ctx *ctx;
@@ -246,6 +266,16 @@ typedef struct {
 int64_t xeng_plan_inspect(const int32_t *n_inputs, const int64_t *n_samples, int32_t n_jobs,
                           int32_t n_workgroups, int32_t min_stages, int32_t wide,
                           xeng_piece_info *out, int64_t cap);
+
+/*
+ * The pieces xeng_correlate_static would launch for one job of n_inputs x
+ * n_samples on n_workgroups workgroups (host only; same conventions and
+ * return value as xeng_plan_inspect, job index 0).  The static path's
+ * device planner emits exactly these, and they equal xeng_plan_inspect's
+ * for that single job.
+ */
+int64_t xeng_plan_inspect_static(int32_t n_inputs, int64_t n_samples, int32_t n_workgroups, int32_t min_stages,
+                                 int32_t wide, xeng_piece_info *out, int64_t cap);
 
 /*
  * Prepared batch, for repeated launches of the same jobs (a streaming loop,

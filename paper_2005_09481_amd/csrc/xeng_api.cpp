@@ -34,6 +34,10 @@ hipError_t launch_reference(const uint8_t *s, int64_t n_samples, int n, int64_t 
 hipError_t launch_batch_guard(const GuardJob *d_jobs, int n_jobs, int32_t *d_skip, int64_t *d_skipped,
                               hipStream_t stream);
 hipError_t launch_set_count(int64_t *p, int64_t v, hipStream_t stream);
+hipError_t static_scratch_address(void **ptr);
+hipError_t launch_static_plan(const SinglePlanArgs &a, Piece *pieces, int32_t *wg_off, int32_t used,
+                              hipStream_t stream);
+constexpr int64_t STATIC_SCRATCH_BYTES = INT64_C(1) << 20;
 }  // namespace xeng
 
 using namespace xeng;
@@ -109,6 +113,7 @@ struct DeviceState {
     std::unordered_map<std::string, Tuning> tuned;   // job sizes -> autotuned configuration
     std::atomic<int64_t *> clock{nullptr};             // xeng_clock_probe buffer
     hipMemPool_t pad_pool = nullptr;   // scratch of padded single-channel calls (keeps up to 1 GiB)
+    uint8_t *static_scratch = nullptr;  // this device's copy of the fixed plan array (xeng_correlate_static)
 };
 
 std::mutex g_states_mu;
@@ -129,11 +134,13 @@ DeviceState *device_state(int device)
     // zero samples that the DMA kernel reads in place of rows past a
     // piece's end; written once, before any launch that could read them
     if (hipMalloc(&st->d_zeros, ZERO_BYTES) != hipSuccess) return nullptr;
+    void *scr = nullptr;
     if (hipMemset(st->d_zeros, 0x88, ZERO_BYTES) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
-        init_dma_kernel() != hipSuccess) {
+        init_dma_kernel() != hipSuccess || static_scratch_address(&scr) != hipSuccess || !scr) {
         (void)hipFree(st->d_zeros);
         return nullptr;
     }
+    st->static_scratch = static_cast<uint8_t *>(scr);
     DeviceState *p = st.get();
     g_states[device] = std::move(st);
     return p;
@@ -779,6 +786,49 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_
     return map_err(publish_count(ctx, slot, stream));
 }
 
+int xeng_correlate_static(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_t n_samples,
+                          int64_t row_stride, void *hip_stream)
+{
+    if (!slot_ok(ctx, slot) || n_samples < 0 || row_stride < ctx->n || row_stride > MAX_STRIDE)
+        return XENG_EINVAL;
+    if (n_samples > 0 && !d_samples) return XENG_EINVAL;
+    if (n_samples > 0 && row_stride > INT64_MAX / n_samples) return XENG_EINVAL;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return XENG_EDEVICE;
+    int rc = refuse_capture(stream);
+    if (rc != XENG_OK) return rc;
+    if ((rc = refresh_count(ctx, slot)) != XENG_OK) return rc;
+    if (n_samples > T_MAX - ctx->acc_t[(size_t)slot]) return XENG_EOVERFLOW;
+    if (n_samples == 0) return XENG_OK;
+
+    DeviceState *st = ctx->st;
+    const Tuning tu = global_tuning();   // no tuned-table lookup: it builds a key string
+    KernelArgs a{};
+    a.job0 = make_job(ctx, slot, d_samples, row_stride, true);
+    const bool dma = use_dma(a.job0.flags, tu);
+    const TileShape shape = dma ? TileShape::Wide : TileShape::Square;
+    int max_wgs, min_stages;
+    plan_limits(st, shape, tu, &max_wgs, &min_stages);
+    int64_t np = 0, used = 0;
+    const SinglePlanArgs pa = single_plan(ctx->n, n_samples, shape, max_wgs, min_stages, &np, &used);
+    // [pieces | workgroup offsets] in the fixed array
+    const int64_t off_at = (np * (int64_t)sizeof(Piece) + 255) / 256 * 256;
+    if (off_at + (used + 1) * (int64_t)sizeof(int32_t) > STATIC_SCRATCH_BYTES) return XENG_ENOMEM;
+    Piece *pieces = reinterpret_cast<Piece *>(st->static_scratch);
+    int32_t *wg_off = reinterpret_cast<int32_t *>(st->static_scratch + off_at);
+    hipError_t e = launch_static_plan(pa, pieces, wg_off, (int32_t)used, stream);
+    if (e != hipSuccess) return map_err(e);
+    a.jobs = nullptr;
+    a.zeros = st->d_zeros;
+    a.clock = st->clock.load();
+    a.pieces = pieces;
+    a.wg_off = wg_off;
+    if ((e = launch(a, (int32_t)used, dma, a.job0.flags, stream)) != hipSuccess) return map_err(e);
+    ctx->acc_t[(size_t)slot] += n_samples;
+    return map_err(publish_count(ctx, slot, stream));
+}
+
 int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
 {
     if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return XENG_EINVAL;
@@ -986,6 +1036,43 @@ int64_t xeng_plan_inspect(const int32_t *n_inputs, const int64_t *n_samples, int
         o.workgroup = plan.piece_wg[(size_t)k];
         o.n_tiles = wide ? 2 : 1;
     }
+    return np;
+}
+
+int64_t xeng_plan_inspect_static(int32_t n_inputs, int64_t n_samples, int32_t n_workgroups, int32_t min_stages,
+                                 int32_t wide, xeng_piece_info *out, int64_t cap)
+{
+    if (n_inputs < 1 || n_samples < 1 || n_samples > T_MAX || n_workgroups < 1 || cap < 0 || (cap > 0 && !out) ||
+        (wide != 0 && wide != 1))
+        return XENG_EINVAL;
+    if (min_stages <= 0) min_stages = g_min_stages.load();
+    int64_t np = 0, used = 0;
+    const SinglePlanArgs pa = single_plan(n_inputs, n_samples, wide ? TileShape::Wide : TileShape::Square,
+                                          n_workgroups, min_stages, &np, &used);
+    // the device kernel's emission, run on the host: pieces in order, a
+    // unit cut into several pieces flagged atomic
+    int64_t k = 0, unit_first = 0;
+    auto close_unit = [&]() {
+        if (k - unit_first > 1)
+            for (int64_t q = unit_first; q < k && q < cap; ++q) out[q].atomic = 1;
+        unit_first = k;
+    };
+    single_fill(pa, [&](int64_t w, int32_t ti, int32_t tj, int64_t s0, int64_t s1, int64_t kk) {
+        if (kk == 0) close_unit();
+        if (k < cap) {
+            xeng_piece_info &o = out[k];
+            o.job = 0;
+            o.ti = ti;
+            o.tj = wide ? 2 * tj : tj;
+            o.atomic = 0;
+            o.t0 = s0 * STAGE;
+            o.t1 = std::min<int64_t>(s1 * STAGE, n_samples);
+            o.workgroup = (int32_t)w;
+            o.n_tiles = wide ? 2 : 1;
+        }
+        ++k;
+    });
+    close_unit();
     return np;
 }
 

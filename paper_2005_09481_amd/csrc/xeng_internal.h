@@ -46,6 +46,7 @@ __host__ __device__ inline int32_t pair_im(uint64_t w)
 }
 
 inline int64_t tri64(int64_t n) { return n * (n + 1) / 2; }
+__host__ __device__ inline int n_tiles_side_hd(int n) { return (n + TILE - 1) / TILE; }
 inline int n_tiles_side(int n) { return (n + TILE - 1) / TILE; }
 inline int64_t slot_i32(int n) { return tri64(n_tiles_side(n)) * TILE_I32; }
 // Per-slot staging of the diagonal's imaginary parts for the dump.

@@ -20,13 +20,13 @@ std::vector<std::pair<int, int>> plan_units(int n, TileShape shape)
     return u;
 }
 
-namespace {
-
 // Cost of a piece beyond its stages, in stage units: its prologue (the
 // first stages' loads are not yet overlapped) and its flush of the tile's
 // accumulators to memory.  Measured on the DMA kernel's 128 x 256 tiles at
 // about 16 stage times; a 128 x 128 tile flushes half as much.
 int64_t piece_overhead(TileShape shape) { return shape == TileShape::Wide ? 16 : 8; }
+
+namespace {
 
 struct UnitRef {
     int job, ti, tj;
@@ -129,6 +129,40 @@ Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, Til
     }
     for (size_t w = 0; w < (size_t)used; ++w) plan.wg_off[w + 1] += plan.wg_off[w];
     return plan;
+}
+
+SinglePlanArgs single_plan(int32_t n, int64_t t, TileShape shape, int max_wgs, int min_stages, int64_t *n_pieces,
+                          int64_t *used)
+{
+    SinglePlanArgs a;
+    a.n = n;
+    a.t = t;
+    a.wide = shape == TileShape::Wide ? 1 : 0;
+    a.overhead = piece_overhead(shape);
+    a.cap = shape == TileShape::Wide ? MAX_PIECE_STAGES_WIDE : MAX_PIECE_STAGES;
+    if (min_stages < 1) min_stages = 1;
+    if (max_wgs < 1) max_wgs = 1;
+    const int64_t units = single_units(a);
+    const int64_t total = units * single_stages(a);
+    a.grid = std::max<int64_t>(1, std::min<int64_t>(max_wgs, (total + min_stages - 1) / min_stages));
+    auto none = [](int64_t, int32_t, int32_t, int64_t, int64_t, int64_t) {};
+    // the budget search of make_plan, over the same unit order
+    int64_t lo = a.overhead + 1, hi = a.overhead + total + 1;
+    hi = std::max(hi, (total + a.grid - 1) / a.grid + a.overhead * (units + 1) + 1);
+    a.budget = hi;
+    while (single_fill(a, none) > a.grid) a.budget = (hi *= 2);
+    while (lo < hi) {
+        a.budget = lo + (hi - lo) / 2;
+        if (single_fill(a, none) <= a.grid)
+            hi = a.budget;
+        else
+            lo = a.budget + 1;
+    }
+    a.budget = lo;
+    int64_t np = 0;
+    *used = single_fill(a, [&np](int64_t, int32_t, int32_t, int64_t, int64_t, int64_t) { ++np; });
+    *n_pieces = np;
+    return a;
 }
 
 }  // namespace xeng

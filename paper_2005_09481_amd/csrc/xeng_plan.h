@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "xeng_internal.h"
+#include "xeng_plan_single.h"
 
 namespace xeng {
 
@@ -38,5 +39,14 @@ Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages,
 // Units of one job in the plan's order: pairs (row index, column index)
 // in the shape's own units.
 std::vector<std::pair<int, int>> plan_units(int n, TileShape shape);
+
+// Stage-equivalents charged per piece (prologue and flush) by the planners.
+int64_t piece_overhead(TileShape shape);
+
+// Plan parameters of one job as make_plan would choose them (grid and
+// budget), for the container-free planner of xeng_plan_single.h; also the
+// number of pieces and of workgroups used.  Host only, allocates nothing.
+SinglePlanArgs single_plan(int32_t n, int64_t t, TileShape shape, int max_wgs, int min_stages, int64_t *n_pieces,
+                          int64_t *used);
 
 }  // namespace xeng

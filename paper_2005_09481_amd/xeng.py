@@ -120,6 +120,8 @@ def lib() -> ctypes.CDLL:
         "xeng_batch_launch": (ctypes.c_int, [vp, vp]),
         "xeng_batch_check": (ctypes.c_int, [vp]),
         "xeng_set_pad_chunk_bytes": (ctypes.c_int, [i64]),
+        "xeng_correlate_static": (ctypes.c_int, [vp, i32, vp, i64, i64, vp]),
+        "xeng_plan_inspect_static": (i64, [i32, i64, i32, i32, i32, ctypes.POINTER(_PieceInfo), i64]),
         "xeng_server_export_ring": (ctypes.c_int, [vp, i32, vp, i32]),
         "xeng_batch_destroy": (ctypes.c_int, [vp]),
         "xeng_autotune": (ctypes.c_int, [ctypes.POINTER(_Job), i32, i32, vp, ctypes.POINTER(_Tuning)]),
@@ -409,6 +411,19 @@ def plan_inspect(n_inputs, n_samples, n_workgroups: int, min_stages: int = 0, wi
         raise XengError(int(cnt), "xeng_plan_inspect")
     out = (_PieceInfo * max(cnt, 1))()
     cnt2 = lib().xeng_plan_inspect(ni, ns, n, n_workgroups, min_stages, int(wide), out, cnt)
+    assert cnt2 == cnt
+    return [PieceInfo(p.job, p.ti, p.tj, bool(p.atomic), p.t0, p.t1, p.workgroup, p.n_tiles)
+            for p in out[:cnt]]
+
+
+def plan_inspect_static(n_inputs: int, n_samples: int, n_workgroups: int, min_stages: int = 0,
+                        wide: bool = False):
+    """Pieces of the allocation-free path's device planner (host copy)."""
+    cnt = lib().xeng_plan_inspect_static(n_inputs, n_samples, n_workgroups, min_stages, int(wide), None, 0)
+    if cnt < 0:
+        raise XengError(int(cnt), "xeng_plan_inspect_static")
+    out = (_PieceInfo * max(cnt, 1))()
+    cnt2 = lib().xeng_plan_inspect_static(n_inputs, n_samples, n_workgroups, min_stages, int(wide), out, cnt)
     assert cnt2 == cnt
     return [PieceInfo(p.job, p.ti, p.tj, bool(p.atomic), p.t0, p.t1, p.workgroup, p.n_tiles)
             for p in out[:cnt]]

@@ -161,3 +161,27 @@ def test_plan_caps_piece_length(X, wide, cap):
     assert len(pieces) == (2 if wide else 3) * per_unit
     assert all(p.atomic for p in pieces)
 
+
+@pytest.mark.parametrize("wide", [False, True])
+@pytest.mark.parametrize("n,t,grid,min_st", [
+    (2048, 32768, 256, 4), (2048, 32768, 512, 8), (64, 4096, 256, 4), (1, 1, 256, 4),
+    (129, 33, 7, 1), (1000, 3000, 256, 4), (256, 3_000_000, 1, 1), (2048, 16_777_215, 256, 4),
+])
+def test_static_planner_equals_cached_plan(X, n, t, grid, min_st, wide):
+    # the allocation-free path's planner (written without containers, run by
+    # a one-thread kernel) emits the same pieces as the cached planner for a
+    # single job, and they cover every (pair, sample) exactly once
+    want = X.plan_inspect([n], [t], grid, min_st, wide)
+    got = X.plan_inspect_static(n, t, grid, min_st, wide)
+    assert got == want
+    _check_cover(got, [(n, t)], grid)
+
+
+def test_static_planner_rejects_bad_arguments(X):
+    L = X.lib()
+    assert L.xeng_plan_inspect_static(0, 10, 1, 1, 0, None, 0) == X.XENG_EINVAL
+    assert L.xeng_plan_inspect_static(10, 0, 1, 1, 0, None, 0) == X.XENG_EINVAL
+    assert L.xeng_plan_inspect_static(10, 10, 0, 1, 0, None, 0) == X.XENG_EINVAL
+    assert L.xeng_plan_inspect_static(10, 10, 1, 1, 2, None, 0) == X.XENG_EINVAL
+    assert L.xeng_plan_inspect_static(10, X.max_integration() + 1, 1, 1, 0, None, 0) == X.XENG_EINVAL
+    assert L.xeng_correlate_static(None, 0, None, 10, 10, None) == X.XENG_EINVAL
