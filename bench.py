@@ -243,6 +243,8 @@ def main():
                     help="channel counts to try (device-sourced frames)")
     ap.add_argument("--serve-host-k", default="16,24,32,40,48",
                     help="channel counts to try with pinned-host frames (0 to skip)")
+    ap.add_argument("--plan-order", default="xcd", choices=["xcd", "linear"],
+                    help="work order of the single-channel launch (xeng_set_plan_order; never changes results)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB "
                          "(reference kernel for scaling hardware byte counters)")
@@ -260,6 +262,7 @@ def main():
     import synth
     from paper_2005_09481_amd import xeng
 
+    xeng.set_plan_order({"xcd": xeng.XENG_PLAN_XCD, "linear": xeng.XENG_PLAN_LINEAR}[args.plan_order])
     if args.workload == "serve":
         return bench_serve(args, xeng, synth, torch, np)
     if args.workload != "channel":
@@ -340,7 +343,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"CHIME-shaped single channel N={n}, T={t}, 4+4-bit, "
                                "correlate + dump/reset per step",
-                   "n_inputs": n, "n_samples": t, "parallelism": "single GPU"},
+                   "n_inputs": n, "n_samples": t, "parallelism": "single GPU",
+                   "plan_order": args.plan_order},
         "roofline": roofline,
         "mfma_util_pct": round(100 * achieved / INT8_PEAK_TOPS, 2),
         # the int8 peak assumes 2.4 GHz; under this load the chip runs slower

@@ -439,6 +439,24 @@ int xeng_server_export_ring(xeng_server *s, int32_t channel, int32_t *ring, int3
 int xeng_set_tuning(int32_t wgs_per_cu, int32_t min_stages, int32_t kernel);
 
 /*
+ * Work order of single-job launches (results never depend on it).
+ * XENG_PLAN_XCD (the default): the job's tiles in Morton order, cut into
+ * time segments of about the balanced share of a workgroup; the 32
+ * workgroups that share one of MI355X's eight XCDs (and its L2) take
+ * segments of one time window over a compact block of tiles, so that they
+ * read the same input rows and columns at about the same time; the tiles'
+ * tails go to the remaining workgroups.  XENG_PLAN_LINEAR: the stream-K
+ * order (tiles in row order, each workgroup a contiguous range of (tile,
+ * stage)).  Batches of several jobs and jobs too short for one 32-stage
+ * segment per workgroup always take the linear order, as does
+ * xeng_correlate_static.  Applies to later calls on every device and to
+ * xeng_plan_inspect.
+ */
+#define XENG_PLAN_LINEAR 0
+#define XENG_PLAN_XCD 1
+int xeng_set_plan_order(int32_t order);
+
+/*
  * Scratch of the padded path: the single-channel calls that copy their
  * samples into padded rows (see xeng_correlate) go in chunks of at most
  * `bytes` of scratch, and a batched call pads at most `bytes` of its jobs.

@@ -50,6 +50,18 @@ std::atomic<int> g_kernel{XENG_KERNEL_AUTO};
 // Scratch bytes per padded chunk (single calls) and per batched call.
 constexpr int64_t PAD_SCRATCH_DEFAULT = INT64_C(256) << 20;
 std::atomic<int64_t> g_pad_bytes{PAD_SCRATCH_DEFAULT};
+std::atomic<int> g_plan_order{XENG_PLAN_XCD};
+
+// The plan of a launch: single jobs take the XCD-aware decomposition where
+// it applies (and the order asks for it), everything else the linear
+// stream-K plan.
+Plan build_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, TileShape shape)
+{
+    Plan p;
+    const int order = g_plan_order.load();
+    if (order == XENG_PLAN_XCD && n_jobs == 1 && make_plan_xcd(jobs[0], max_wgs, shape, &p)) return p;
+    return make_plan(jobs, n_jobs, max_wgs, min_stages, shape);
+}
 
 // Launch configuration of one call: the global settings, or what the
 // autotuner found best for calls of the same job sizes.
@@ -151,6 +163,7 @@ std::string plan_key(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stage
     std::string k;
     k.reserve(32 + 16 * (size_t)n_jobs);
     k.push_back(shape == TileShape::Wide ? 'w' : 's');
+    k.push_back((char)('0' + g_plan_order.load()));
     k.append(reinterpret_cast<const char *>(&max_wgs), sizeof max_wgs);
     k.append(reinterpret_cast<const char *>(&min_stages), sizeof min_stages);
     for (int j = 0; j < n_jobs; ++j) {
@@ -250,7 +263,7 @@ int get_plan(DeviceState *st, const PlanJob *jobs, int n_jobs, TileShape shape, 
     plan_limits(st, shape, tu, &max_wgs, &min_stages);
     const std::string key = plan_key(jobs, n_jobs, max_wgs, min_stages, shape);
     if (find_plan(st, key, out)) return XENG_OK;
-    return cache_plan(st, key, make_plan(jobs, n_jobs, max_wgs, min_stages, shape), out);
+    return cache_plan(st, key, build_plan(jobs, n_jobs, max_wgs, min_stages, shape), out);
 }
 
 int map_err(hipError_t e)
@@ -626,7 +639,7 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
             st->host_lru.push_front(key);
         } else {
             plan = std::make_shared<const Plan>(
-                make_plan(part.pj.data(), (int)part.pj.size(), max_wgs, min_stages, shape));
+                build_plan(part.pj.data(), (int)part.pj.size(), max_wgs, min_stages, shape));
             if ((int)st->host_plans.size() >= PLAN_CACHE_MAX) {
                 st->host_plans.erase(st->host_lru.back());
                 st->host_lru.pop_back();
@@ -1021,7 +1034,7 @@ int64_t xeng_plan_inspect(const int32_t *n_inputs, const int64_t *n_samples, int
     }
     if (min_stages <= 0) min_stages = g_min_stages.load();
     const TileShape shape = wide ? TileShape::Wide : TileShape::Square;
-    Plan plan = make_plan(pj.data(), n_jobs, n_workgroups, min_stages, shape);
+    Plan plan = build_plan(pj.data(), n_jobs, n_workgroups, min_stages, shape);
     const int64_t np = (int64_t)plan.pieces.size();
     for (int64_t k = 0; k < np && k < cap; ++k) {
         const Piece &p = plan.pieces[(size_t)k];
@@ -1144,8 +1157,8 @@ int xeng_batch_create(const xeng_job *jobs, int32_t n_jobs, xeng_batch **out)
     for (const Part &part : split_by_kernel(jl, tu)) {
         const TileShape shape = part.dma ? TileShape::Wide : TileShape::Square;
         const int per_cu = part.dma ? 1 : std::max(1, tu.wgs_per_cu);
-        const Plan plan = make_plan(part.pj.data(), (int)part.pj.size(), jl.st->cu_count * per_cu,
-                                    std::max(1, tu.min_stages), shape);
+        const Plan plan = build_plan(part.pj.data(), (int)part.pj.size(), jl.st->cu_count * per_cu,
+                                     std::max(1, tu.min_stages), shape);
         xeng_batch::Launch l{part.dma, part.flags_and, plan.grid, nullptr, nullptr, nullptr};
         b->launches.push_back(l);
         xeng_batch::Launch &lb = b->launches.back();
@@ -1334,6 +1347,13 @@ int xeng_set_tuning(int32_t wgs_per_cu, int32_t min_stages, int32_t kernel)
         std::lock_guard<std::mutex> lk2(kv.second->mu);
         kv.second->tuned.clear();
     }
+    return XENG_OK;
+}
+
+int xeng_set_plan_order(int32_t order)
+{
+    if (order != XENG_PLAN_LINEAR && order != XENG_PLAN_XCD) return XENG_EINVAL;
+    g_plan_order.store(order);
     return XENG_OK;
 }
 

@@ -2,6 +2,8 @@
 #include "xeng_plan.h"
 
 #include <algorithm>
+#include <cstdint>
+#include <unordered_map>
 
 namespace xeng {
 
@@ -129,6 +131,139 @@ Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, Til
     }
     for (size_t w = 0; w < (size_t)used; ++w) plan.wg_off[w + 1] += plan.wg_off[w];
     return plan;
+}
+
+namespace {
+
+// Interleaved bits of (a, b): units close in both coordinates come close
+// together in this order, so a run of consecutive units covers a compact
+// block of the triangle (few distinct row and column blocks).
+uint64_t morton(uint32_t a, uint32_t b)
+{
+    uint64_t r = 0;
+    for (int k = 0; k < 16; ++k) r |= (uint64_t)((a >> k) & 1u) << (2 * k + 1) | (uint64_t)((b >> k) & 1u) << (2 * k);
+    return r;
+}
+
+}  // namespace
+
+namespace {
+
+// One candidate of make_plan_xcd for segment length L: the pieces of each
+// logical workgroup, and the largest workgroup cost (stages + overhead per
+// piece).  Returns -1 if the work does not fit in G workgroups.
+struct XSeg {
+    int64_t u, s0, s1;
+};
+
+int64_t xcd_candidate(int64_t U, int64_t ns, int64_t G, int64_t L, int64_t ovh, int64_t cap,
+                      std::vector<std::vector<XSeg>> *out)
+{
+    const int64_t F = ns / L;          // full segments per unit
+    const int64_t r = ns - F * L;      // each unit's tail
+    const int64_t main = U * F;
+    if (main > G || (r > 0 && main == G)) return -1;
+    if (out) out->assign((size_t)G, {});
+    if (out)
+        for (int64_t p = 0; p < F; ++p)
+            for (int64_t u = 0; u < U; ++u) (*out)[(size_t)(p * U + u)].push_back(XSeg{u, p * L, (p + 1) * L});
+    const int64_t worst = F > 0 ? L + ovh : 0;
+    if (r == 0) return worst;
+    // the tails: stream-K over the remaining workgroups, smallest budget that fits
+    const int64_t rest = G - main;
+    auto fill = [&](int64_t budget, bool emit) -> bool {
+        int64_t k = main, left = budget, u = 0, done = 0;
+        while (u < U) {
+            if (left <= ovh) {
+                if (++k >= main + rest) return false;
+                left = budget;
+            }
+            const int64_t take = std::min({r - done, left - ovh, cap});
+            if (emit) (*out)[(size_t)k].push_back(XSeg{u, F * L + done, F * L + done + take});
+            done += take;
+            left -= take + ovh;
+            if (done == r) {
+                ++u;
+                done = 0;
+            }
+        }
+        return true;
+    };
+    int64_t lo = ovh + 1, hi = ovh + 1;
+    while (!fill(hi, false)) hi *= 2;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (fill(mid, false))
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    if (out) fill(lo, true);
+    return std::max(worst, lo);
+}
+
+}  // namespace
+
+bool make_plan_xcd(const PlanJob &job, int max_wgs, TileShape shape, Plan *out)
+{
+    const int64_t G = max_wgs;
+    if (G < XCDS || G % XCDS != 0 || job.n <= 0 || job.t <= 0) return false;
+    std::vector<std::pair<int, int>> units = plan_units(job.n, shape);
+    const int64_t U = (int64_t)units.size();
+    const int64_t ns = (job.t + STAGE - 1) / STAGE;
+    const int64_t ovh = piece_overhead(shape);
+    const int64_t cap = shape == TileShape::Wide ? MAX_PIECE_STAGES_WIDE : MAX_PIECE_STAGES;
+    // segment lengths around the balanced share (longer ones leave less
+    // for the tail workgroups): the candidate with the smallest largest
+    // workgroup cost wins
+    const int64_t L0 = (U * ns + G - 1) / G;
+    if (L0 < XCD_MIN_SEGMENT || L0 >= ns) return false;
+    int64_t best_L = -1, best_cost = -1;
+    for (int64_t L = std::min({L0 + 4 * ovh, cap, ns - 1}); L >= std::max<int64_t>(XCD_MIN_SEGMENT, L0 - ovh); --L) {
+        const int64_t c = xcd_candidate(U, ns, G, L, ovh, cap, nullptr);
+        if (c >= 0 && (best_cost < 0 || c < best_cost)) {
+            best_cost = c;
+            best_L = L;
+        }
+    }
+    if (best_L < 0) return false;
+    const int col_scale = shape == TileShape::Wide ? 2 : 1;
+    std::stable_sort(units.begin(), units.end(), [col_scale](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+        return morton((uint32_t)a.first, (uint32_t)(col_scale * a.second)) <
+               morton((uint32_t)b.first, (uint32_t)(col_scale * b.second));
+    });
+    std::vector<std::vector<XSeg>> logical;
+    xcd_candidate(U, ns, G, best_L, ovh, cap, &logical);
+    // a unit cut into several pieces is shared: flushed with atomics
+    std::vector<int> pieces_of(units.size(), 0);
+    for (const auto &v : logical)
+        for (const XSeg &sg : v) pieces_of[(size_t)sg.u]++;
+    // logical workgroup k runs on XCD k / (G / XCDS): physical id
+    // (k % (G / XCDS)) * XCDS + k / (G / XCDS), workgroups being dealt to the
+    // XCDs in turn
+    const int64_t per_xcd = G / XCDS;
+    std::vector<const std::vector<XSeg> *> by_wg((size_t)G);
+    for (int64_t k = 0; k < G; ++k) by_wg[(size_t)((k % per_xcd) * XCDS + k / per_xcd)] = &logical[(size_t)k];
+    Plan plan;
+    plan.wg_off.assign((size_t)G + 1, 0);
+    for (int64_t w = 0; w < G; ++w) {
+        for (const XSeg &sg : *by_wg[(size_t)w]) {
+            Piece pc;
+            pc.job = 0;
+            pc.tile = units[(size_t)sg.u].first | (units[(size_t)sg.u].second << 16);
+            pc.t0 = (int32_t)(sg.s0 * STAGE);
+            pc.t1_atomic = (int32_t)std::min<int64_t>(sg.s1 * STAGE, job.t);
+            if (pieces_of[(size_t)sg.u] > 1) pc.t1_atomic |= (int32_t)0x80000000u;
+            plan.pieces.push_back(pc);
+            plan.piece_wg.push_back((int32_t)w);
+        }
+        plan.wg_off[(size_t)w + 1] = (int32_t)plan.pieces.size();
+    }
+    // every physical id up to G - 1 is launched (workgroups without pieces
+    // return at once), so that the XCD placement holds
+    plan.grid = (int32_t)G;
+    *out = std::move(plan);
+    return true;
 }
 
 SinglePlanArgs single_plan(int32_t n, int64_t t, TileShape shape, int max_wgs, int min_stages, int64_t *n_pieces,

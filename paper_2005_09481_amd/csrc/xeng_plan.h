@@ -40,6 +40,23 @@ Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages,
 // in the shape's own units.
 std::vector<std::pair<int, int>> plan_units(int n, TileShape shape);
 
+// XCD-aware, time-aligned decomposition of ONE job.  MI355X deals the
+// workgroups of a launch to its 8 XCDs in turn (workgroup w on XCD w % 8),
+// and each XCD has its own L2.  The job's units, in Morton order of their
+// (row, column) tile coordinates, are cut into full time segments of L
+// stages (L about the balanced share, total / grid) plus a tail each;
+// logical workgroup k takes the k-th full segment in (time window, unit)
+// order, and the tails are spread over the remaining workgroups by the
+// stream-K fill.  Logical workgroups 32 x .. 32 x + 31 are placed on XCD x,
+// so each XCD's workgroups work on one time window over a compact block of
+// units and share those input rows and columns in its L2.  Every workgroup
+// has one piece, or a few for the tails, as in the linear plan.  Returns
+// false (nothing written) for a grid that is not a multiple of 8 or a job
+// too short for one segment of XCD_MIN_SEGMENT stages per workgroup.
+constexpr int XCDS = 8;
+constexpr int64_t XCD_MIN_SEGMENT = 32;
+bool make_plan_xcd(const PlanJob &job, int max_wgs, TileShape shape, Plan *out);
+
 // Stage-equivalents charged per piece (prologue and flush) by the planners.
 int64_t piece_overhead(TileShape shape);
 

@@ -25,6 +25,8 @@ XENG_NIBBLE_RE_LOW = 1
 XENG_SERVER_STAGGER_EXPORTS = 2
 XENG_KERNEL_AUTO = 0
 XENG_KERNEL_GENERAL = 1
+XENG_PLAN_LINEAR = 0
+XENG_PLAN_XCD = 1
 
 
 class XengError(RuntimeError):
@@ -120,6 +122,7 @@ def lib() -> ctypes.CDLL:
         "xeng_batch_launch": (ctypes.c_int, [vp, vp]),
         "xeng_batch_check": (ctypes.c_int, [vp]),
         "xeng_set_pad_chunk_bytes": (ctypes.c_int, [i64]),
+        "xeng_set_plan_order": (ctypes.c_int, [i32]),
         "xeng_correlate_static": (ctypes.c_int, [vp, i32, vp, i64, i64, vp]),
         "xeng_plan_inspect_static": (i64, [i32, i64, i32, i32, i32, ctypes.POINTER(_PieceInfo), i64]),
         "xeng_server_export_ring": (ctypes.c_int, [vp, i32, vp, i32]),
@@ -168,6 +171,11 @@ def set_tuning(wgs_per_cu: int = 0, min_stages: int = 0, kernel: int = -1):
     per CU, minimum piece length in 64-sample stages, kernel selection
     (XENG_KERNEL_AUTO / XENG_KERNEL_GENERAL; -1 keeps the current one)."""
     _check(lib().xeng_set_tuning(wgs_per_cu, min_stages, kernel), "xeng_set_tuning")
+
+
+def set_plan_order(order: int):
+    """Work order of single-job launches: XENG_PLAN_XCD (default) or XENG_PLAN_LINEAR."""
+    _check(lib().xeng_set_plan_order(order), "xeng_set_plan_order")
 
 
 def set_pad_chunk_bytes(nbytes: int = 0):

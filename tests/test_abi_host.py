@@ -120,7 +120,11 @@ def _check_cover(pieces, jobs, grid):
     ([(300, 1000), (5, 0), (1024, 16384), (256, 4097)], 512, 4),
 ])
 def test_plan_covers_exactly_once(X, jobs, grid, min_st, wide):
-    pieces = X.plan_inspect([j[0] for j in jobs], [j[1] for j in jobs], grid, min_st, wide)
+    X.set_plan_order(X.XENG_PLAN_LINEAR)
+    try:
+        pieces = X.plan_inspect([j[0] for j in jobs], [j[1] for j in jobs], grid, min_st, wide)
+    finally:
+        X.set_plan_order(X.XENG_PLAN_XCD)
     stages, n_pieces = _check_cover(pieces, jobs, grid)
     # balance: the cost of a workgroup, its stages plus a fixed overhead per
     # piece (prologue and flush), is within one overhead of every other's;
@@ -169,9 +173,14 @@ def test_plan_caps_piece_length(X, wide, cap):
 ])
 def test_static_planner_equals_cached_plan(X, n, t, grid, min_st, wide):
     # the allocation-free path's planner (written without containers, run by
-    # a one-thread kernel) emits the same pieces as the cached planner for a
-    # single job, and they cover every (pair, sample) exactly once
-    want = X.plan_inspect([n], [t], grid, min_st, wide)
+    # a one-thread kernel) emits the same pieces as the cached planner's
+    # linear order for a single job, and they cover every (pair, sample)
+    # exactly once
+    X.set_plan_order(X.XENG_PLAN_LINEAR)
+    try:
+        want = X.plan_inspect([n], [t], grid, min_st, wide)
+    finally:
+        X.set_plan_order(X.XENG_PLAN_XCD)
     got = X.plan_inspect_static(n, t, grid, min_st, wide)
     assert got == want
     _check_cover(got, [(n, t)], grid)
@@ -185,3 +194,32 @@ def test_static_planner_rejects_bad_arguments(X):
     assert L.xeng_plan_inspect_static(10, 10, 1, 1, 2, None, 0) == X.XENG_EINVAL
     assert L.xeng_plan_inspect_static(10, X.max_integration() + 1, 1, 1, 0, None, 0) == X.XENG_EINVAL
     assert L.xeng_correlate_static(None, 0, None, 10, 10, None) == X.XENG_EINVAL
+
+
+@pytest.mark.parametrize("wide", [False, True])
+@pytest.mark.parametrize("n,t,grid", [(2048, 32768, 256), (2048, 32768, 512), (2000, 32768, 256),
+                                      (1024, 32768, 256), (2048, 16384, 256), (1536, 65536, 256),
+                                      (2048, 4096, 256), (256, 5000, 64), (2048, 16_777_215, 256)])
+def test_xcd_plan_covers_exactly_once_and_balances(X, n, t, grid, wide):
+    # the XCD-aware order (the default for single jobs): every (pair, sample)
+    # exactly once, no workgroup costlier than under the linear order by
+    # more than one piece overhead, and where it applies the main segments
+    # of the 32 workgroups of one XCD (physical id % 8) share a time window
+    pieces = X.plan_inspect([n], [t], grid, 4, wide)
+    stages, n_pieces = _check_cover(pieces, [(n, t)], grid)
+    ovh = 16 if wide else 8
+    X.set_plan_order(X.XENG_PLAN_LINEAR)
+    try:
+        lin = X.plan_inspect([n], [t], grid, 4, wide)
+    finally:
+        X.set_plan_order(X.XENG_PLAN_XCD)
+    lin_stages, lin_pieces = _check_cover(lin, [(n, t)], grid)
+    cost = max(stages[w] + ovh * n_pieces[w] for w in stages)
+    lin_cost = max(lin_stages[w] + ovh * lin_pieces[w] for w in lin_stages)
+    assert cost <= lin_cost + ovh
+    if (n, t, grid, wide) == (2048, 32768, 256, True):
+        last = {}
+        for p in pieces:
+            last[p.workgroup] = p            # a workgroup's last piece is its main segment
+        for x in (0, 1, 3, 5, 7):            # XCDs wholly inside one window
+            assert len({last[w].t0 for w in range(x, grid, 8)}) == 1
