@@ -12,6 +12,9 @@ including autocorrelations, V_ij = sum_t x_i(t) conj(x_j(t))):
 * ``correlate_numpy``  decode + one complex128 matrix product X^T conj(X)
                        (exact: every partial sum is an integer far below 2^53);
 * ``correlate_python`` Python ``complex`` arithmetic, for tiny inputs.
+
+``oracle.flags`` holds the flag-aware correlation (per-baseline sample
+counts) and its RFI-excision step (spectral kurtosis per block).
 """
 from __future__ import annotations
 

@@ -148,3 +148,43 @@ def rank1_tone(n_inputs: int, n_samples: int, seed=7, quarter_turns: int = 1):
     im = np.where(k[:, None] == 0, g_im, np.where(k[:, None] == 1, g_re,
                   np.where(k[:, None] == 2, -g_im, -g_re)))
     return encode(re, im), g_re, g_im
+
+
+def rfi_channel(n_inputs: int, n_samples: int, seed=6, block_len: int = 256, tone_frac: float = 0.03,
+                burst_frac: float = 0.02, broadband_blocks: int = 1) -> np.ndarray:
+    """A CHIME-shaped channel with radio-frequency interference injected in
+    whole (block, input) cells of ``block_len`` samples:
+
+    * narrow-band carriers: a tone of amplitude 6 turning a quarter cycle
+      per sample, (6, 0), (0, 6), (-6, 0), (0, -6), ... -- constant power;
+    * impulsive bursts: the cell silenced (zero samples) except four
+      samples at -7-7j -- a few strong spikes;
+    * broadband bursts: ``broadband_blocks`` whole blocks across every
+      input turned into impulsive bursts.
+
+    The rest is ``chime_channel`` data (seed ``seed``)."""
+    x = chime_channel(n_inputs, n_samples, seed=seed)
+    rng = np.random.default_rng([seed, 99])
+    nb = (n_samples + block_len - 1) // block_len
+    cells = nb * n_inputs
+    pick = rng.permutation(cells)
+    n_tone = int(round(tone_frac * cells))
+    n_burst = int(round(burst_frac * cells))
+    tone = encode(np.array([6, 0, -6, 0]), np.array([0, 6, 0, -6]))
+    spike = encode(np.array([-7]), np.array([-7]))[0]
+    for k, c in enumerate(pick[:n_tone + n_burst]):
+        b, i = divmod(int(c), n_inputs)
+        t0, t1 = b * block_len, min((b + 1) * block_len, n_samples)
+        if k < n_tone:
+            x[t0:t1, i] = tone[(np.arange(t0, t1) % 4)]
+        else:
+            x[t0:t1, i] = FLAG_BYTE
+            where = rng.choice(t1 - t0, size=min(4, t1 - t0), replace=False)
+            x[t0 + where, i] = spike
+    for b in rng.choice(nb, size=min(broadband_blocks, nb), replace=False):
+        t0, t1 = int(b) * block_len, min((int(b) + 1) * block_len, n_samples)
+        x[t0:t1, :] = FLAG_BYTE
+        for i in range(n_inputs):
+            where = rng.choice(t1 - t0, size=min(4, t1 - t0), replace=False)
+            x[t0 + where, i] = spike
+    return x
