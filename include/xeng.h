@@ -72,6 +72,7 @@ enum xeng_status {
 
 /* config flags */
 #define XENG_NIBBLE_RE_LOW 0x1u   /* real part in the low nibble */
+#define XENG_COUNTS 0x4u          /* keep per-pair sample counts (xeng_correlate_flagged, xeng_dump_counts) */
 
 typedef struct {
     int32_t n_inputs;          /* 1 <= N <= 65535 receiver-polarizations per channel */
@@ -136,6 +137,64 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples,
 #define XENG_STATIC_SCRATCH_BYTES (1 << 20)
 int xeng_correlate_static(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples,
                           int64_t n_samples, int64_t row_stride, void *hip_stream);
+
+/*
+ * Flags and RFI excision (Sec. 2.2: every block of samples travels with
+ * flags and metadata; Table tab:computing: an "RFI Excision" task runs on
+ * the GPU ahead of the correlation).  A flag covers one input over a block
+ * of block_len consecutive samples of a call (the last block may be
+ * shorter): flags[b * N + i] != 0 means input i is flagged over samples
+ * [b * block_len, (b + 1) * block_len).
+ */
+typedef struct {
+    int32_t block_len;  /* samples per block, 2 .. XENG_RFI_MAX_BLOCK */
+    int32_t den;        /* thresholds lo = lo_num / den, hi = hi_num / den; 1 <= den <= 1024 */
+    int32_t lo_num;     /* 0 <= lo_num <= hi_num <= 16 * den */
+    int32_t hi_num;
+    int32_t reserved;   /* must be 0 */
+} xeng_rfi_config;
+#define XENG_RFI_MAX_BLOCK 1024
+
+/*
+ * RFI excision by spectral kurtosis (the estimator of Nita and Gary 2010;
+ * the paper names the task, not the method): for each block of M samples
+ * of each input, with P = |x|^2, S1 = sum P and S2 = sum P^2,
+ *     SK = (M + 1) / (M - 1) * (M S2 / S1^2 - 1)
+ * (expectation 1 for Gaussian noise; a steady carrier gives about 0,
+ * impulsive interference much more than 1).  d_flags[b * N + i] = 1 where
+ * SK < lo or SK > hi or S1 = 0, else 0; blocks of one sample are never
+ * flagged.  The comparison is exact (integer arithmetic).  d_samples as in
+ * xeng_correlate (N = n_inputs, `flags` = XENG_NIBBLE_RE_LOW or 0);
+ * d_flags: device, ceil(n_samples / block_len) * N bytes, owned by the
+ * caller.  Asynchronous on hip_stream; XENG_EINVAL for bad arguments (at
+ * most 65535 blocks per call), XENG_ENOTSUP while capturing.
+ */
+int xeng_rfi_flags(const uint8_t *d_samples, int64_t n_samples, int32_t n_inputs, int64_t row_stride,
+                   uint32_t flags, const xeng_rfi_config *cfg, uint8_t *d_flags, void *hip_stream);
+
+/*
+ * Flag-aware correlation into a context created with XENG_COUNTS:
+ *   acc[slot]    += sum_t w_i(t) w_j(t) x_i(t) conj(x_j(t))
+ *   counts[slot] += sum_t w_i(t) w_j(t)          (n_ij, per pair)
+ * with w = 0 where the flag array marks the sample's (block, input), else
+ * 1.  Flagged samples never enter a visibility; n_ij counts the samples
+ * that did, so V_ij / n_ij is the mean over them.  The samples are copied
+ * into padded rows with flagged samples set to zero (scratch from the
+ * library's pool, in chunks as the padded path of xeng_correlate) and
+ * correlated by the wide kernel.  Same checks and integration bound as
+ * xeng_correlate; XENG_EINVAL without XENG_COUNTS or with block_len < 1.
+ */
+int xeng_correlate_flagged(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_t n_samples,
+                           int64_t row_stride, const uint8_t *d_flags, int32_t block_len, void *hip_stream);
+
+/*
+ * Per-pair sample counts of a slot (XENG_COUNTS): out[k], int32
+ * [N(N+1)/2] in the pair order of xeng_dump, = the samples integrated into
+ * pair k since the slot's last reset (every sample of an unflagged call
+ * counts for every pair).  Asynchronous; call it before the xeng_dump that
+ * resets the slot (a reset clears the counts with the visibilities).
+ */
+int xeng_dump_counts(xeng_ctx *ctx, int32_t slot, int32_t *out, void *hip_stream);
 
 /* One unit of a batched correlation: correlate d_samples into ctx/slot. */
 typedef struct {
@@ -215,7 +274,8 @@ int64_t xeng_samples_integrated(const xeng_ctx *ctx, int32_t slot);
 int64_t xeng_max_integration(void);
 
 /* Device bytes of one slot for N inputs: its int32 accumulators plus the
- * staging the dump uses (admission control); -1 if N < 1. */
+ * staging the dump uses (admission control); -1 if N < 1.  A context
+ * created with XENG_COUNTS holds 4 * N(N+1)/2 bytes more per slot. */
 int64_t xeng_slot_bytes(int32_t n_inputs);
 
 /* N and slot count of a context (-1 on NULL). */

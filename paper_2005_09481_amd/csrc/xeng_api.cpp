@@ -35,6 +35,15 @@ hipError_t launch_batch_guard(const GuardJob *d_jobs, int n_jobs, int32_t *d_ski
                               hipStream_t stream);
 hipError_t launch_set_count(int64_t *p, int64_t v, hipStream_t stream);
 hipError_t static_scratch_address(void **ptr);
+hipError_t launch_sk_flags(const uint8_t *s, int64_t n_samples, int n, int64_t stride, uint32_t re_low,
+                           int block_len, int64_t lo_num, int64_t hi_num, int64_t den, uint8_t *flags,
+                           hipStream_t stream);
+hipError_t launch_mask_rows(const uint8_t *src, int64_t stride, int n, int64_t rows, int n16, uint8_t *dst,
+                            const uint8_t *flags, int block_len, int64_t t_first, hipStream_t stream);
+hipError_t launch_counts(const uint8_t *flags, int nb, int n, int block_len, int last_len, uint32_t *bits,
+                         int32_t *counts, hipStream_t stream);
+hipError_t launch_counts_export(const int32_t *counts, int64_t npairs, int32_t base, int32_t *out,
+                                hipStream_t stream);
 hipError_t launch_static_plan(const SinglePlanArgs &a, Piece *pieces, int32_t *wg_off, int32_t used,
                               hipStream_t stream);
 constexpr int64_t STATIC_SCRATCH_BYTES = INT64_C(1) << 20;
@@ -313,7 +322,10 @@ struct xeng_ctx {
     int32_t *d_acc = nullptr;    // n_slots accumulators, then n_slots diagonal stagings
     int32_t *d_diag = nullptr;
     int64_t *d_count = nullptr;  // per slot: samples integrated, kept on the device for prepared batches
+    int32_t *d_counts = nullptr; // XENG_COUNTS: per slot, int32 [count_i32]: samples per pair from flagged calls
+    int64_t count_i32 = 0;       // N(N+1)/2 rounded up to a multiple of 4
     std::vector<int64_t> acc_t;
+    std::vector<int64_t> flagged_t;   // samples integrated by flagged calls (their counts are in d_counts)
     // live prepared batches naming each slot; while > 0 the slot's device
     // counter (advanced by the batches' device guard) is the true count and
     // acc_t is refreshed from it before any host-side check
@@ -347,6 +359,14 @@ int refresh_count(xeng_ctx *c, int32_t slot)
     if (hipMemcpy(&v, c->d_count + slot, sizeof v, hipMemcpyDeviceToHost) != hipSuccess) return XENG_EDEVICE;
     c->acc_t[(size_t)slot] = v;
     return XENG_OK;
+}
+
+// A reset of a slot also clears its per-pair sample counts (XENG_COUNTS).
+hipError_t reset_counts(xeng_ctx *c, int32_t slot, hipStream_t stream)
+{
+    if (!c->d_counts || c->flagged_t[(size_t)slot] == 0) return hipSuccess;
+    c->flagged_t[(size_t)slot] = 0;
+    return launch_zero(c->d_counts + (int64_t)slot * c->count_i32, c->count_i32, stream);
 }
 
 // After an eager call changed a bound slot's count: the new value goes to
@@ -423,8 +443,10 @@ int pad_pool(DeviceState *st, hipMemPool_t *out)
 }
 
 // Called with st->mu held and the device current; updates acc_t per chunk.
+// With `flags` ([n_blocks][N], block_len samples per block), flagged samples
+// become the zero sample in the copy.
 int correlate_padded(xeng_ctx *ctx, int32_t slot, const uint8_t *samples, int64_t n_samples, int64_t stride,
-                     const Tuning &tu, hipStream_t stream)
+                     const Tuning &tu, hipStream_t stream, const uint8_t *flags = nullptr, int block_len = 0)
 {
     const int n16 = (ctx->n + 15) / 16 * 16;
     const int64_t rows = std::min<int64_t>(n_samples, std::max<int64_t>(STAGE, g_pad_bytes.load() / n16 / STAGE * STAGE));
@@ -437,7 +459,9 @@ int correlate_padded(xeng_ctx *ctx, int32_t slot, const uint8_t *samples, int64_
     int rc = XENG_OK;
     for (int64_t t0 = 0; t0 < n_samples; t0 += rows) {
         const int64_t tc = std::min(rows, n_samples - t0);
-        e = launch_pad_rows(samples + t0 * stride, stride, ctx->n, tc, n16, scratch, stream);
+        e = flags ? launch_mask_rows(samples + t0 * stride, stride, ctx->n, tc, n16, scratch, flags, block_len, t0,
+                                     stream)
+                  : launch_pad_rows(samples + t0 * stride, stride, ctx->n, tc, n16, scratch, stream);
         if (e != hipSuccess) {
             rc = map_err(e);
             break;
@@ -445,16 +469,18 @@ int correlate_padded(xeng_ctx *ctx, int32_t slot, const uint8_t *samples, int64_
         KernelArgs a{};
         a.job0 = make_job(ctx, slot, scratch, n16, true);
         a.job0.n = n16;                 // the padded inputs hold zero samples
-        a.job0.flags |= JOB_DMA;
+        a.job0.flags |= JOB_DMA | JOB_ALIGNED8;
         a.jobs = nullptr;
         a.zeros = ctx->st->d_zeros;
         a.clock = ctx->st->clock.load();
+        // the wide kernel, unless the tuning asks for the general one
+        const bool dma = tu.kernel != XENG_KERNEL_GENERAL;
         PlanJob pj{ctx->n, tc};
         DevicePlan dp;
-        if ((rc = get_plan(ctx->st, &pj, 1, TileShape::Wide, tu, &dp)) != XENG_OK) break;
+        if ((rc = get_plan(ctx->st, &pj, 1, dma ? TileShape::Wide : TileShape::Square, tu, &dp)) != XENG_OK) break;
         a.pieces = dp.d_pieces;
         a.wg_off = dp.d_off;
-        if ((e = launch(a, dp.grid, true, a.job0.flags, stream)) != hipSuccess) {
+        if ((e = launch(a, dp.grid, dma, a.job0.flags, stream)) != hipSuccess) {
             rc = map_err(e);
             break;
         }
@@ -694,9 +720,10 @@ int xeng_create(const xeng_config *cfg, xeng_ctx **out)
     if (!cfg || !out) return XENG_EINVAL;
     *out = nullptr;
     if (cfg->n_inputs < 1 || cfg->n_inputs > 65535 || cfg->n_slots < 1 ||
-        cfg->device < 0 || (cfg->flags & ~XENG_NIBBLE_RE_LOW) || cfg->mem_budget_bytes < 0)
+        cfg->device < 0 || (cfg->flags & ~(XENG_NIBBLE_RE_LOW | XENG_COUNTS)) || cfg->mem_budget_bytes < 0)
         return XENG_EINVAL;
-    const int64_t slot_bytes = (slot_i32(cfg->n_inputs) + diag_i32(cfg->n_inputs)) * 4;
+    const int64_t count_i32 = (cfg->flags & XENG_COUNTS) ? (tri64(cfg->n_inputs) + 3) / 4 * 4 : 0;
+    const int64_t slot_bytes = (slot_i32(cfg->n_inputs) + diag_i32(cfg->n_inputs) + count_i32) * 4;
     if (slot_bytes > INT64_MAX / cfg->n_slots) return XENG_ENOMEM;
     const int64_t bytes = slot_bytes * cfg->n_slots;
     if (cfg->mem_budget_bytes > 0 && bytes > cfg->mem_budget_bytes) return XENG_ENOMEM;
@@ -720,7 +747,9 @@ int xeng_create(const xeng_config *cfg, xeng_ctx **out)
     c->nt = n_tiles_side(cfg->n_inputs);
     c->slot_i32 = slot_i32(cfg->n_inputs);
     c->acc_t.assign((size_t)cfg->n_slots, 0);
+    c->flagged_t.assign((size_t)cfg->n_slots, 0);
     c->bound.assign((size_t)cfg->n_slots, 0);
+    c->count_i32 = count_i32;
     c->st = st;
     hipError_t e = hipMalloc(&c->d_acc, (size_t)bytes);
     if (e != hipSuccess) {
@@ -733,6 +762,7 @@ int xeng_create(const xeng_config *cfg, xeng_ctx **out)
         return map_err(e);
     }
     c->d_diag = c->d_acc + (int64_t)cfg->n_slots * c->slot_i32;
+    if (count_i32) c->d_counts = c->d_diag + (int64_t)cfg->n_slots * diag_i32(cfg->n_inputs);
     e = launch_zero(c->d_acc, bytes / 4, nullptr);
     if (e == hipSuccess) e = hipMemset(c->d_count, 0, (size_t)cfg->n_slots * sizeof(int64_t));
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -797,6 +827,83 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_
     if (e != hipSuccess) return map_err(e);
     ctx->acc_t[(size_t)slot] += n_samples;
     return map_err(publish_count(ctx, slot, stream));
+}
+
+int xeng_rfi_flags(const uint8_t *d_samples, int64_t n_samples, int32_t n_inputs, int64_t row_stride,
+                   uint32_t flags, const xeng_rfi_config *cfg, uint8_t *d_flags, void *hip_stream)
+{
+    if (!cfg || n_inputs < 1 || n_samples < 0 || row_stride < n_inputs || row_stride > MAX_STRIDE ||
+        (flags & ~XENG_NIBBLE_RE_LOW) || cfg->block_len < 2 || cfg->block_len > XENG_RFI_MAX_BLOCK ||
+        cfg->den < 1 || cfg->den > 1024 || cfg->lo_num < 0 || cfg->hi_num < cfg->lo_num ||
+        cfg->hi_num > 16 * cfg->den || cfg->reserved != 0)
+        return XENG_EINVAL;
+    if (n_samples == 0) return XENG_OK;
+    if (!d_samples || !d_flags || row_stride > INT64_MAX / n_samples) return XENG_EINVAL;
+    if ((n_samples + cfg->block_len - 1) / cfg->block_len > 65535) return XENG_EINVAL;   // grid y
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int rc = refuse_capture(stream);
+    if (rc != XENG_OK) return rc;
+    return map_err(launch_sk_flags(d_samples, n_samples, n_inputs, row_stride, (flags & XENG_NIBBLE_RE_LOW) ? 1u : 0u,
+                                   cfg->block_len, cfg->lo_num, cfg->hi_num, cfg->den, d_flags, stream));
+}
+
+int xeng_correlate_flagged(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_t n_samples,
+                           int64_t row_stride, const uint8_t *d_flags, int32_t block_len, void *hip_stream)
+{
+    if (!slot_ok(ctx, slot) || n_samples < 0 || row_stride < ctx->n || row_stride > MAX_STRIDE || block_len < 1 ||
+        !ctx->d_counts)
+        return XENG_EINVAL;
+    if (n_samples > 0 && (!d_samples || !d_flags || row_stride > INT64_MAX / n_samples)) return XENG_EINVAL;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return XENG_EDEVICE;
+    int rc = refuse_capture(stream);
+    if (rc != XENG_OK) return rc;
+    if ((rc = refresh_count(ctx, slot)) != XENG_OK) return rc;
+    if (n_samples > T_MAX - ctx->acc_t[(size_t)slot]) return XENG_EOVERFLOW;
+    if (n_samples == 0) return XENG_OK;
+    const int64_t nb = (n_samples + block_len - 1) / block_len;
+    if (nb > INT32_MAX / 32) return XENG_EINVAL;
+    const int last_len = (int)(n_samples - (nb - 1) * block_len);
+    std::lock_guard<std::mutex> lk(ctx->st->mu);
+    PlanJob pj{ctx->n, n_samples};
+    const Tuning tu = tuning_for(ctx->st, &pj, 1);
+    // the counts' bit masks first (scratch), so that a failure to get it
+    // queues nothing
+    hipMemPool_t pool = nullptr;
+    if ((rc = pad_pool(ctx->st, &pool)) != XENG_OK) return rc;
+    uint32_t *bits = nullptr;
+    const size_t bits_bytes = (size_t)ctx->n * (size_t)((nb + 31) / 32) * sizeof(uint32_t);
+    hipError_t e = hipMallocFromPoolAsync(reinterpret_cast<void **>(&bits), bits_bytes, pool, stream);
+    if (e != hipSuccess) return map_err(e);
+    // visibilities of the masked samples (acc_t advances per chunk), then
+    // the pair counts; after a device error the slot's contents are not
+    // defined (reset it)
+    rc = correlate_padded(ctx, slot, d_samples, n_samples, row_stride, tu, stream, d_flags, block_len);
+    if (rc == XENG_OK) {
+        e = launch_counts(d_flags, (int)nb, ctx->n, block_len, last_len, bits,
+                          ctx->d_counts + (int64_t)slot * ctx->count_i32, stream);
+        if (e == hipSuccess) ctx->flagged_t[(size_t)slot] += n_samples;
+        rc = map_err(e);
+    }
+    e = hipFreeAsync(bits, stream);
+    if (rc == XENG_OK && e != hipSuccess) rc = map_err(e);
+    return rc;
+}
+
+int xeng_dump_counts(xeng_ctx *ctx, int32_t slot, int32_t *out, void *hip_stream)
+{
+    if (!slot_ok(ctx, slot) || !out || !ctx->d_counts) return XENG_EINVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return XENG_EDEVICE;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    int rc = refuse_capture(stream);
+    if (rc != XENG_OK) return rc;
+    if ((rc = refresh_count(ctx, slot)) != XENG_OK) return rc;
+    // samples integrated without flags count for every pair
+    const int64_t base = ctx->acc_t[(size_t)slot] - ctx->flagged_t[(size_t)slot];
+    return map_err(launch_counts_export(ctx->d_counts + (int64_t)slot * ctx->count_i32, tri64(ctx->n), (int32_t)base,
+                                        out, stream));
 }
 
 int xeng_correlate_static(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_t n_samples,
@@ -892,6 +999,7 @@ int xeng_dump(xeng_ctx *ctx, int32_t slot, int32_t *out, int32_t reset, void *hi
     if (e != hipSuccess) return map_err(e);
     if (reset) {
         ctx->acc_t[(size_t)slot] = 0;
+        if ((e = reset_counts(ctx, slot, stream)) != hipSuccess) return map_err(e);
         return map_err(publish_count(ctx, slot, stream));
     }
     return XENG_OK;
@@ -949,7 +1057,8 @@ int xeng_dump_batch(const xeng_dump_job *jobs, int32_t n_jobs, void *hip_stream)
     for (int32_t k = 0; k < n_jobs; ++k)
         if (jobs[k].reset) {
             jobs[k].ctx->acc_t[(size_t)jobs[k].slot] = 0;
-            const hipError_t e = publish_count(jobs[k].ctx, jobs[k].slot, stream);
+            hipError_t e = reset_counts(jobs[k].ctx, jobs[k].slot, stream);
+            if (e == hipSuccess) e = publish_count(jobs[k].ctx, jobs[k].slot, stream);
             if (e != hipSuccess) return map_err(e);
         }
     return XENG_OK;
@@ -964,6 +1073,7 @@ int xeng_reset(xeng_ctx *ctx, int32_t slot, void *hip_stream)
     const int rc = refuse_capture(stream);
     if (rc != XENG_OK) return rc;
     hipError_t e = launch_zero(ctx->d_acc + (int64_t)slot * ctx->slot_i32, ctx->slot_i32, stream);
+    if (e == hipSuccess) e = reset_counts(ctx, slot, stream);
     if (e != hipSuccess) return map_err(e);
     ctx->acc_t[(size_t)slot] = 0;
     return map_err(publish_count(ctx, slot, stream));

@@ -22,6 +22,8 @@ XENG_EDEVICE = -4
 XENG_EBUSY = -5
 XENG_ENOTSUP = -6
 XENG_NIBBLE_RE_LOW = 1
+XENG_COUNTS = 4
+XENG_RFI_MAX_BLOCK = 1024
 XENG_SERVER_STAGGER_EXPORTS = 2
 XENG_KERNEL_AUTO = 0
 XENG_KERNEL_GENERAL = 1
@@ -39,6 +41,11 @@ class _Config(ctypes.Structure):
     _fields_ = [("n_inputs", ctypes.c_int32), ("n_slots", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("mem_budget_bytes", ctypes.c_int64)]
+
+
+class _RfiConfig(ctypes.Structure):
+    _fields_ = [("block_len", ctypes.c_int32), ("den", ctypes.c_int32), ("lo_num", ctypes.c_int32),
+                ("hi_num", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _Job(ctypes.Structure):
@@ -123,6 +130,9 @@ def lib() -> ctypes.CDLL:
         "xeng_batch_check": (ctypes.c_int, [vp]),
         "xeng_set_pad_chunk_bytes": (ctypes.c_int, [i64]),
         "xeng_set_plan_order": (ctypes.c_int, [i32]),
+        "xeng_rfi_flags": (ctypes.c_int, [vp, i64, i32, i64, u32, ctypes.POINTER(_RfiConfig), vp, vp]),
+        "xeng_correlate_flagged": (ctypes.c_int, [vp, i32, vp, i64, i64, vp, i32, vp]),
+        "xeng_dump_counts": (ctypes.c_int, [vp, i32, vp, vp]),
         "xeng_correlate_static": (ctypes.c_int, [vp, i32, vp, i64, i64, vp]),
         "xeng_plan_inspect_static": (i64, [i32, i64, i32, i32, i32, ctypes.POINTER(_PieceInfo), i64]),
         "xeng_server_export_ring": (ctypes.c_int, [vp, i32, vp, i32]),
@@ -233,11 +243,11 @@ class Correlator:
     """N-input correlator with ``n_slots`` device-resident int32 accumulators."""
 
     def __init__(self, n_inputs: int, n_slots: int = 1, device: int | None = None,
-                 re_low: bool = False, mem_budget_bytes: int = 0):
+                 re_low: bool = False, mem_budget_bytes: int = 0, counts: bool = False):
         import torch
         self.device = torch.cuda.current_device() if device is None else int(device)
-        cfg = _Config(n_inputs, n_slots, self.device, XENG_NIBBLE_RE_LOW if re_low else 0,
-                      mem_budget_bytes)
+        flags = (XENG_NIBBLE_RE_LOW if re_low else 0) | (XENG_COUNTS if counts else 0)
+        cfg = _Config(n_inputs, n_slots, self.device, flags, mem_budget_bytes)
         h = ctypes.c_void_p()
         _check(lib().xeng_create(ctypes.byref(cfg), ctypes.byref(h)), "xeng_create")
         self._h = h
@@ -255,6 +265,30 @@ class Correlator:
         ptr, t, row_stride = _samples_args(samples, self.n_inputs, self.device)
         _check(lib().xeng_correlate(self.handle, slot, ptr, t, row_stride,
                                     _stream_handle(stream, self.device)), "xeng_correlate")
+
+    def correlate_flagged(self, slot: int, samples, flags, block_len: int, stream=None):
+        """acc[slot] += V over unflagged samples, counts[slot] += n_ij;
+        ``flags`` uint8 [ceil(T / block_len), N] on the device (nonzero = flagged)."""
+        import torch
+        ptr, t, row_stride = _samples_args(samples, self.n_inputs, self.device)
+        nb = -(-t // block_len) if block_len > 0 else 0
+        if not isinstance(flags, torch.Tensor) or flags.dtype != torch.uint8 or not flags.is_contiguous() \
+                or (t > 0 and (tuple(flags.shape) != (nb, self.n_inputs) or not flags.is_cuda)):
+            raise ValueError("flags must be a contiguous uint8 device tensor [ceil(T/block_len), N]")
+        fptr = ctypes.c_void_p(flags.data_ptr()) if t > 0 else None
+        _check(lib().xeng_correlate_flagged(self.handle, slot, ptr, t, row_stride, fptr, block_len,
+                                            _stream_handle(stream, self.device)), "xeng_correlate_flagged")
+
+    def dump_counts(self, slot: int, out=None, stream=None):
+        """Per-pair sample counts int32 [N(N+1)/2] (pairs in the order of dump)."""
+        import torch
+        if out is None:
+            out = torch.empty(tri(self.n_inputs), dtype=torch.int32, device=f"cuda:{self.device}")
+        if out.dtype != torch.int32 or out.numel() != tri(self.n_inputs) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int32 tensor of N(N+1)/2")
+        _check(lib().xeng_dump_counts(self.handle, slot, ctypes.c_void_p(out.data_ptr()),
+                                      _stream_handle(stream, self.device)), "xeng_dump_counts")
+        return out
 
     def _dump_out(self, out):
         import torch
@@ -381,6 +415,24 @@ def autotune(jobs, iters: int = 5, stream=None) -> Tuning:
                                _stream_handle(stream, jobs[0][0].device), ctypes.byref(t)),
            "xeng_autotune")
     return Tuning(t.kernel, t.wgs_per_cu, t.min_stages, t.us_per_launch)
+
+
+def rfi_flags(samples, n_inputs: int | None = None, block_len: int = 256, lo_num: int = 625,
+              hi_num: int = 1375, den: int = 1000, re_low: bool = False, out=None, stream=None):
+    """Spectral-kurtosis RFI flags uint8 [ceil(T / block_len), N] (1 = flagged)."""
+    import torch
+    n = samples.shape[1] if n_inputs is None else n_inputs
+    dev = samples.device.index if samples.device.type == "cuda" else torch.cuda.current_device()
+    ptr, t, row_stride = _samples_args(samples, n, dev)
+    nb = -(-t // block_len)
+    if out is None:
+        out = torch.empty((nb, n), dtype=torch.uint8, device=f"cuda:{dev}")
+    if out.dtype != torch.uint8 or tuple(out.shape) != (nb, n) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous uint8 tensor [ceil(T/block_len), N]")
+    cfg = _RfiConfig(block_len, den, lo_num, hi_num, 0)
+    _check(lib().xeng_rfi_flags(ptr, t, n, row_stride, XENG_NIBBLE_RE_LOW if re_low else 0, ctypes.byref(cfg),
+                                ctypes.c_void_p(out.data_ptr()), _stream_handle(stream, dev)), "xeng_rfi_flags")
+    return out
 
 
 def correlate_reference(samples, n_inputs: int | None = None, re_low: bool = False, stream=None):

@@ -48,7 +48,7 @@ def test_argument_checks_without_device(X):
     h = ctypes.c_void_p()
     assert L.xeng_create(None, ctypes.byref(h)) == X.XENG_EINVAL
     for bad in (X._Config(0, 1, 0, 0, 0), X._Config(8, 0, 0, 0, 0),
-                X._Config(8, 1, -1, 0, 0), X._Config(8, 1, 0, 4, 0),
+                X._Config(8, 1, -1, 0, 0), X._Config(8, 1, 0, 8, 0),
                 X._Config(8, 1, 0, 0, -5)):
         assert L.xeng_create(ctypes.byref(bad), ctypes.byref(h)) == X.XENG_EINVAL
     # a memory budget below one slot is refused before any allocation
