@@ -274,6 +274,48 @@ def bench_flagged(args, xeng, synth, torch, np):
     print(json.dumps(res), flush=True)
 
 
+def bench_presum(args, xeng, synth, torch, np):
+    """The unsigned-nibble form with pre-sums (xeng_correlate_presum) on the
+    CHIME-shaped channel: pre-sum pass, the 128 x 128 kernel on the stored
+    nibbles, the correction pass; timed with HIP events on its stream, next
+    to xeng_correlate on the same data."""
+    n, t = args.n, args.t
+    tri = n * (n + 1) // 2
+    x = torch.from_numpy(synth.chime_channel(n, t, seed=2)).cuda()
+    corr = xeng.Correlator(n, 1, device=0)
+    out = torch.empty((tri, 2), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        t_settle = time.perf_counter() + args.settle_ms / 1e3
+        while time.perf_counter() < t_settle:
+            fn()
+            corr.dump(0, out=out, stream=stream)
+            torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        for a, b in evs:
+            a.record(stream)
+            fn()
+            b.record(stream)
+            corr.dump(0, out=out, stream=stream)
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in evs])) / 1e3
+
+    t_presum = timed(lambda: corr.correlate_presum(0, x, stream=stream))
+    t_plain = timed(lambda: corr.correlate(0, x, stream=stream))
+    cmac = t * tri
+    res = {"metric": "Tera-CMAC/s at N=2048, unsigned-nibble form with pre-sums",
+           "value": round(cmac / t_presum / 1e12, 3), "unit": "TCMAC/s", "n_gpus": 1, "steps": args.steps,
+           "higher_is_better": True, "dtype": "int8", "data": "synthetic",
+           "config": {"workload": f"CHIME-shaped single channel N={n}, T={t}, xeng_correlate_presum"},
+           "presum_call_us": round(t_presum * 1e6, 2), "correlate_call_us": round(t_plain * 1e6, 2),
+           "roofline": {"bound": "mfma", "achieved": round(8.0 * cmac / t_presum / 1e12, 2),
+                        "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
+                        "frac": round(8.0 * cmac / t_presum / 1e12 / INT8_PEAK_TOPS, 4), "traffic": None}}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -288,7 +330,7 @@ def main():
                     help="do not stamp the shader clock of the timed launches")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", default="channel",
-                    choices=["channel", "channels16", "subarrays64", "serve", "flagged"],
+                    choices=["channel", "channels16", "subarrays64", "serve", "flagged", "presum"],
                     help="channel: the one-channel step (default, the JSON contract line); "
                          "channels16 / subarrays64: batched launches against plain launches; "
                          "serve: streaming channels, largest real-time K")
@@ -327,6 +369,8 @@ def main():
         return bench_serve(args, xeng, synth, torch, np)
     if args.workload == "flagged":
         return bench_flagged(args, xeng, synth, torch, np)
+    if args.workload == "presum":
+        return bench_presum(args, xeng, synth, torch, np)
     if args.workload != "channel":
         return bench_batch(args, xeng, synth, torch, np)
 

@@ -196,6 +196,23 @@ int xeng_correlate_flagged(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples
  */
 int xeng_dump_counts(xeng_ctx *ctx, int32_t slot, int32_t *out, void *hip_stream);
 
+/*
+ * The same integration as xeng_correlate (same result, checks and bound),
+ * computed in the paper's unsigned form (Sec. 2.3, "GPUs": low-bit
+ * products at the cost of O(N) bookkeeping; Table tab:computing, "Re-Order
+ * and Pre-Sum"): the int8 matrix cores multiply the stored nibbles
+ * u = x + 8 (0..15) themselves, a pre-sum pass forms SR_i = sum_t uR_i and
+ * SI_i = sum_t uI_i, and a correction pass adds, per pair,
+ *   Re: -8 (SR_i + SI_i + SR_j + SI_j) + 128 T,
+ *   Im:  8 (SR_i - SI_i) - 8 (SR_j - SI_j).
+ * A second, independent route to the same integers on the GPU (it takes
+ * the 128 x 128 kernel for any alignment).  Pre-sum scratch (8 N bytes)
+ * comes from the library's pool; XENG_ENOMEM, nothing queued, if it
+ * cannot be had.
+ */
+int xeng_correlate_presum(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_t n_samples,
+                          int64_t row_stride, void *hip_stream);
+
 /* One unit of a batched correlation: correlate d_samples into ctx/slot. */
 typedef struct {
     xeng_ctx *ctx;

@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxeng.so")
-SOURCES = ["xeng_kernels.hip", "xeng_kernel_dma.hip", "xeng_static.hip", "xeng_flags.hip", "xeng_plan.cpp",
+SOURCES = ["xeng_kernels.hip", "xeng_kernel_dma.hip", "xeng_static.hip", "xeng_flags.hip", "xeng_presum.hip",
+           "xeng_plan.cpp",
            "xeng_api.cpp", "xeng_sched.cpp", "xeng_serve.cpp"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

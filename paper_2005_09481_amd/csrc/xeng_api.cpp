@@ -21,6 +21,11 @@
 
 namespace xeng {
 hipError_t launch_correlate(const KernelArgs &a, int grid, bool aligned, hipStream_t stream);
+hipError_t launch_correlate_unsigned(const KernelArgs &a, int grid, bool aligned, hipStream_t stream);
+hipError_t launch_presum(const uint8_t *s, int64_t n_samples, int n, int64_t stride, uint32_t re_low, int32_t *sr,
+                         int32_t *si, hipStream_t stream);
+hipError_t launch_presum_correct(int32_t *acc, int n, int nt, int64_t n_samples, const int32_t *sr,
+                                 const int32_t *si, hipStream_t stream);
 hipError_t launch_correlate_dma(const KernelArgs &a, int grid, hipStream_t stream);
 hipError_t init_dma_kernel();
 hipError_t launch_dump(int32_t *acc, int32_t *diag, int n, int nt, int32_t *out, bool reset,
@@ -64,8 +69,9 @@ std::atomic<int> g_plan_order{XENG_PLAN_XCD};
 // The plan of a launch: single jobs take the XCD-aware decomposition where
 // it applies (and the order asks for it), everything else the linear
 // stream-K plan.
-Plan build_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, TileShape shape)
+Plan build_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, TileShape shape, int64_t cap = 0)
 {
+    if (cap > 0) return make_plan(jobs, n_jobs, max_wgs, min_stages, shape, cap);
     Plan p;
     const int order = g_plan_order.load();
     if (order == XENG_PLAN_XCD && n_jobs == 1 && make_plan_xcd(jobs[0], max_wgs, shape, &p)) return p;
@@ -167,10 +173,12 @@ DeviceState *device_state(int device)
     return p;
 }
 
-std::string plan_key(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, TileShape shape)
+std::string plan_key(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, TileShape shape,
+                     int64_t cap = 0)
 {
     std::string k;
-    k.reserve(32 + 16 * (size_t)n_jobs);
+    k.reserve(40 + 16 * (size_t)n_jobs);
+    k.append(reinterpret_cast<const char *>(&cap), sizeof cap);
     k.push_back(shape == TileShape::Wide ? 'w' : 's');
     k.push_back((char)('0' + g_plan_order.load()));
     k.append(reinterpret_cast<const char *>(&max_wgs), sizeof max_wgs);
@@ -266,13 +274,13 @@ int cache_plan(DeviceState *st, const std::string &key, const Plan &plan, Device
 // Look up (or build, upload and cache) the plan for these job sizes.
 // Called with st->mu held and the device current.
 int get_plan(DeviceState *st, const PlanJob *jobs, int n_jobs, TileShape shape, const Tuning &tu,
-             DevicePlan *out)
+             DevicePlan *out, int64_t cap = 0)
 {
     int max_wgs, min_stages;
     plan_limits(st, shape, tu, &max_wgs, &min_stages);
-    const std::string key = plan_key(jobs, n_jobs, max_wgs, min_stages, shape);
+    const std::string key = plan_key(jobs, n_jobs, max_wgs, min_stages, shape, cap);
     if (find_plan(st, key, out)) return XENG_OK;
-    return cache_plan(st, key, build_plan(jobs, n_jobs, max_wgs, min_stages, shape), out);
+    return cache_plan(st, key, build_plan(jobs, n_jobs, max_wgs, min_stages, shape, cap), out);
 }
 
 int map_err(hipError_t e)
@@ -888,6 +896,54 @@ int xeng_correlate_flagged(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples
     }
     e = hipFreeAsync(bits, stream);
     if (rc == XENG_OK && e != hipSuccess) rc = map_err(e);
+    return rc;
+}
+
+int xeng_correlate_presum(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_t n_samples,
+                          int64_t row_stride, void *hip_stream)
+{
+    if (!slot_ok(ctx, slot) || n_samples < 0 || row_stride < ctx->n || row_stride > MAX_STRIDE)
+        return XENG_EINVAL;
+    if (n_samples > 0 && (!d_samples || row_stride > INT64_MAX / n_samples)) return XENG_EINVAL;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return XENG_EDEVICE;
+    int rc = refuse_capture(stream);
+    if (rc != XENG_OK) return rc;
+    if ((rc = refresh_count(ctx, slot)) != XENG_OK) return rc;
+    if (n_samples > T_MAX - ctx->acc_t[(size_t)slot]) return XENG_EOVERFLOW;
+    if (n_samples == 0) return XENG_OK;
+    std::lock_guard<std::mutex> lk(ctx->st->mu);
+    hipMemPool_t pool = nullptr;
+    if ((rc = pad_pool(ctx->st, &pool)) != XENG_OK) return rc;
+    const int64_t n4 = ((int64_t)ctx->n + 3) / 4 * 4;
+    int32_t *sums = nullptr;   // [SR | SI], n4 each
+    hipError_t e = hipMallocFromPoolAsync(reinterpret_cast<void **>(&sums), (size_t)(2 * n4 * 4), pool, stream);
+    if (e != hipSuccess) return map_err(e);
+    PlanJob pj{ctx->n, n_samples};
+    DevicePlan dp;
+    const Tuning tu = tuning_for(ctx->st, &pj, 1);
+    rc = get_plan(ctx->st, &pj, 1, TileShape::Square, tu, &dp, MAX_PIECE_STAGES_UNSIGNED);
+    if (rc == XENG_OK) {
+        KernelArgs a{};
+        a.job0 = make_job(ctx, slot, d_samples, row_stride, true);
+        a.zeros = ctx->st->d_zeros;
+        a.pieces = dp.d_pieces;
+        a.wg_off = dp.d_off;
+        const uint32_t re_low = (ctx->flags & XENG_NIBBLE_RE_LOW) ? 1u : 0u;
+        e = launch_zero(sums, 2 * n4, stream);
+        if (e == hipSuccess) e = launch_presum(d_samples, n_samples, ctx->n, row_stride, re_low, sums, sums + n4, stream);
+        if (e == hipSuccess)
+            e = launch_correlate_unsigned(a, dp.grid, (a.job0.flags & JOB_ALIGNED8) != 0, stream);
+        if (e == hipSuccess)
+            e = launch_presum_correct(ctx->d_acc + (int64_t)slot * ctx->slot_i32, ctx->n, ctx->nt, n_samples, sums,
+                                      sums + n4, stream);
+        if (e == hipSuccess) ctx->acc_t[(size_t)slot] += n_samples;
+        rc = map_err(e);
+    }
+    e = hipFreeAsync(sums, stream);
+    if (rc == XENG_OK && e != hipSuccess) rc = map_err(e);
+    if (rc == XENG_OK) rc = map_err(publish_count(ctx, slot, stream));
     return rc;
 }
 

@@ -58,6 +58,9 @@ inline int64_t diag_i32(int n) { return ((int64_t)n + 63) / 64 * 64; }
 // below 2^16 samples).
 constexpr int MAX_PIECE_STAGES = ((1 << 20) - 1) / STAGE;       // 16383 stages
 constexpr int MAX_PIECE_STAGES_WIDE = ((1 << 16) - 1) / STAGE;  // 1023 stages
+// The general kernel on unsigned nibbles: at most 8 x 450 per sample, so
+// pieces below 2^19 samples keep the sums in int32.
+constexpr int MAX_PIECE_STAGES_UNSIGNED = ((1 << 19) - 1) / STAGE;   // 8191 stages
 
 // Largest row stride: lane offsets inside a stage (up to 31 rows) stay 32-bit.
 constexpr int64_t MAX_STRIDE = INT64_C(1) << 26;

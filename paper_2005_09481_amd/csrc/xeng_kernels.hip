@@ -25,6 +25,13 @@
 // The paper's own design packed several low-bit products into 24-bit
 // multiply-adds on GCN3 (Sec. 2.3, "GPUs"); on CDNA4 the int8 matrix cores
 // do this work instead (Sec. 4.1 anticipates low-bit matrix units).
+//
+// UNSIGNED instances multiply the stored nibbles u = x + 8 themselves (the
+// paper's unsigned form, whose O(N) bookkeeping is the pre-sum correction
+// of xeng_presum.hip): A = [uR | uI] and [uI | -uR], B = [8 uR | 8 uI], so
+// the sums are 8 x sum (uR_i uR_j + uI_i uI_j) and 8 x sum (uI_i uR_j -
+// uR_i uI_j), flushed with a shift of 3.  At most 3600 per sample, so such
+// pieces stay below 2^19 samples (int32 register sums).
 #include <hip/hip_runtime.h>
 
 #include "xeng_internal.h"
@@ -170,7 +177,7 @@ __device__ __forceinline__ void load_stage(StageRegs &r, const PieceCtx &pc, int
 // Unpack one lane's share of a stage into the stage buffer.  `slot` is the
 // byte offset of this lane's (first input, half) in a component region;
 // input c of the lane sits 16 * c bytes further.
-template <bool ROLE_A, bool RE_LOW>
+template <bool ROLE_A, bool RE_LOW, bool UNSIGNED>
 __device__ __forceinline__ void stage_write(uint8_t *region, const StageRegs &r, int slot)
 {
     uint32_t lo[8], hi[8];
@@ -180,11 +187,15 @@ __device__ __forceinline__ void stage_write(uint8_t *region, const StageRegs &r,
         hi[k] = r.d[k].y;
     }
     if (r.valid != ALL_VALID) {     // uniform in the steady state
+        // samples past the piece's end (or past N) become the zero sample;
+        // in the unsigned form the zero sample u = 8 would add 64 per
+        // product, so there they become u = 0, which adds nothing
+        const uint32_t fill = UNSIGNED ? 0u : 0x88888888u;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const bool ok = (r.valid >> k) & 1u;
-            lo[k] = ok ? lo[k] : 0x88888888u;
-            hi[k] = ok ? hi[k] : 0x88888888u;
+            lo[k] = ok ? lo[k] : fill;
+            hi[k] = ok ? hi[k] : fill;
         }
     }
     // p[c][h]: input c, samples 4h..4h+3
@@ -196,6 +207,25 @@ __device__ __forceinline__ void stage_write(uint8_t *region, const StageRegs &r,
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         uint8_t *dst = region + slot + 16 * c;
+        if (UNSIGNED) {
+            // the stored nibbles u in 0..15, no offset removed: A rows keep
+            // uR, uI and -uR (per byte (0x80 - u) ^ 0x80, no borrows); B
+            // rows 8 uR, 8 uI (at most 120: int8)
+            const uint32_t h0 = (p[c][0] >> 4) & 0x0F0F0F0Fu, l0 = p[c][0] & 0x0F0F0F0Fu;
+            const uint32_t h1 = (p[c][1] >> 4) & 0x0F0F0F0Fu, l1 = p[c][1] & 0x0F0F0F0Fu;
+            const uint32_t re0 = RE_LOW ? l0 : h0, im0 = RE_LOW ? h0 : l0;
+            const uint32_t re1 = RE_LOW ? l1 : h1, im1 = RE_LOW ? h1 : l1;
+            if (ROLE_A) {
+                *(uint2 *)(dst) = make_uint2(re0, re1);
+                *(uint2 *)(dst + CH) = make_uint2(im0, im1);
+                *(uint2 *)(dst + 2 * CH) =
+                    make_uint2((0x80808080u - re0) ^ 0x80808080u, (0x80808080u - re1) ^ 0x80808080u);
+            } else {
+                *(uint2 *)(dst) = make_uint2(re0 << 3, re1 << 3);
+                *(uint2 *)(dst + CH) = make_uint2(im0 << 3, im1 << 3);
+            }
+            continue;
+        }
         if (ROLE_A) {
             const uint32_t h0 = (p[c][0] >> 4) & 0x0F0F0F0Fu, l0 = p[c][0] & 0x0F0F0F0Fu;
             const uint32_t h1 = (p[c][1] >> 4) & 0x0F0F0F0Fu, l1 = p[c][1] & 0x0F0F0F0Fu;
@@ -222,11 +252,12 @@ __device__ __forceinline__ v4i lds128(const uint8_t *p) { return *(const v4i *)p
 // the flush adds acc >> 4; every value is a multiple of 16, so this is
 // exact.  Pairs go to the slot as packed 64-bit words (see the layout note):
 // a shared tile takes one 64-bit atomic add per pair.
+template <int SHIFT>
 __device__ __forceinline__ void flush_block(gw64 *blk, const v16i &re, const v16i &im)
 {
 #pragma unroll
     for (int r = 0; r < 16; ++r)
-        __hip_atomic_fetch_add(blk + r * 64, pack_pair(re[r] >> 4, im[r] >> 4), __ATOMIC_RELAXED,
+        __hip_atomic_fetch_add(blk + r * 64, pack_pair(re[r] >> SHIFT, im[r] >> SHIFT), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -238,6 +269,7 @@ struct Acc {
 // Whole-tile flush of one wave's 2 x 2 blocks: stores if the slot holds
 // zeros, else read-modify-write with the loads of a row of blocks issued
 // before their stores (one memory latency per row, not one per value).
+template <int SHIFT>
 __device__ __forceinline__ void flush_owned(gw64 *tb, const Acc &acc, int wa, int wb, bool fresh)
 {
 #pragma unroll
@@ -254,7 +286,7 @@ __device__ __forceinline__ void flush_owned(gw64 *tb, const Acc &acc, int wa, in
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                blk[b][r * 64] = old[b][r] + pack_pair(acc.re[a][b][r] >> 4, acc.im[a][b][r] >> 4);
+                blk[b][r * 64] = old[b][r] + pack_pair(acc.re[a][b][r] >> SHIFT, acc.im[a][b][r] >> SHIFT);
         __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -288,7 +320,7 @@ __device__ __forceinline__ void stage_mfma(Acc &acc, const uint8_t *buf, int lan
 // other LDS buffer and stage s+2 loads from memory.  Steps run in pairs with
 // no early exit: a stage past the end of the piece holds zero samples and
 // adds exactly nothing.
-template <bool ALIGNED, bool ROLE_A, bool RE_LOW>
+template <bool ALIGNED, bool ROLE_A, bool RE_LOW, bool UNSIGNED>
 __device__ __forceinline__ void run_piece(Acc &acc, uint8_t *smem, const PieceCtx &pc, int lane,
                                           int wa, int wb, int wslot)
 {
@@ -298,17 +330,17 @@ __device__ __forceinline__ void run_piece(Acc &acc, uint8_t *smem, const PieceCt
 
     load_stage<ALIGNED>(r0, pc, 0);
     load_stage<ALIGNED>(r1, pc, 1);
-    stage_write<ROLE_A, RE_LOW>(buf0, r0, wslot);
+    stage_write<ROLE_A, RE_LOW, UNSIGNED>(buf0, r0, wslot);
     __syncthreads();
 
     for (int s = 0; s < nst; s += NBUF) {
         load_stage<ALIGNED>(r0, pc, s + 2);
         stage_mfma(acc, buf0, lane, wa, wb);
-        stage_write<ROLE_A, RE_LOW>(buf1, r1, wslot);
+        stage_write<ROLE_A, RE_LOW, UNSIGNED>(buf1, r1, wslot);
         __syncthreads();
         load_stage<ALIGNED>(r1, pc, s + 3);
         stage_mfma(acc, buf1, lane, wa, wb);
-        stage_write<ROLE_A, RE_LOW>(buf0, r0, wslot);
+        stage_write<ROLE_A, RE_LOW, UNSIGNED>(buf0, r0, wslot);
         __syncthreads();
     }
 }
@@ -319,7 +351,7 @@ __device__ __forceinline__ void run_piece(Acc &acc, uint8_t *smem, const PieceCt
 // waves 0-1 unpack the A (row) block, waves 2-3 the B (column) block; a lane
 // takes 8 inputs x 8 samples (lane bits 0-2 and 4 pick the 8-input group,
 // bit 3 the half of a k-step, bit 5 and the wave the k-step).
-template <bool ALIGNED>
+template <bool ALIGNED, bool UNSIGNED>
 __global__ __launch_bounds__(256, 2) void xcorr_mfma(KernelArgs args)
 {
     __shared__ __attribute__((aligned(16))) uint8_t smem[NBUF * STAGE_BYTES];
@@ -370,11 +402,11 @@ __global__ __launch_bounds__(256, 2) void xcorr_mfma(KernelArgs args)
 
         const bool re_low = (jd.flags & JOB_RE_LOW) != 0;
         if (role_a) {
-            if (re_low) run_piece<ALIGNED, true, true>(acc, smem, pc, lane, wa, wb, wslot);
-            else run_piece<ALIGNED, true, false>(acc, smem, pc, lane, wa, wb, wslot);
+            if (re_low) run_piece<ALIGNED, true, true, UNSIGNED>(acc, smem, pc, lane, wa, wb, wslot);
+            else run_piece<ALIGNED, true, false, UNSIGNED>(acc, smem, pc, lane, wa, wb, wslot);
         } else {
-            if (re_low) run_piece<ALIGNED, false, true>(acc, smem, pc, lane, wa, wb, wslot);
-            else run_piece<ALIGNED, false, false>(acc, smem, pc, lane, wa, wb, wslot);
+            if (re_low) run_piece<ALIGNED, false, true, UNSIGNED>(acc, smem, pc, lane, wa, wb, wslot);
+            else run_piece<ALIGNED, false, false, UNSIGNED>(acc, smem, pc, lane, wa, wb, wslot);
         }
 
         // integrate into the slot's accumulators
@@ -385,12 +417,12 @@ __global__ __launch_bounds__(256, 2) void xcorr_mfma(KernelArgs args)
             for (int a = 0; a < 2; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b)
-                    flush_block(tb + ((2 * wa + a) * BLKS + (2 * wb + b)) * BLOCK_W, acc.re[a][b],
+                    flush_block<UNSIGNED ? 3 : 4>(tb + ((2 * wa + a) * BLKS + (2 * wb + b)) * BLOCK_W, acc.re[a][b],
                                 acc.im[a][b]);
         } else if (jd.flags & JOB_FRESH) {
-            flush_owned(tb, acc, wa, wb, true);
+            flush_owned<UNSIGNED ? 3 : 4>(tb, acc, wa, wb, true);
         } else {
-            flush_owned(tb, acc, wa, wb, false);
+            flush_owned<UNSIGNED ? 3 : 4>(tb, acc, wa, wb, false);
         }
     }
 }
@@ -610,9 +642,21 @@ hipError_t launch_correlate(const KernelArgs &a, int grid, bool aligned, hipStre
 {
     if (grid <= 0) return hipSuccess;
     if (aligned)
-        hipLaunchKernelGGL(xcorr_mfma<true>, dim3(grid), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL((xcorr_mfma<true, false>), dim3(grid), dim3(256), 0, stream, a);
     else
-        hipLaunchKernelGGL(xcorr_mfma<false>, dim3(grid), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL((xcorr_mfma<false, false>), dim3(grid), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+// The unsigned-nibble form (xeng_correlate_presum): the same kernel on the
+// stored nibbles; its sums need the pre-sum correction below.
+hipError_t launch_correlate_unsigned(const KernelArgs &a, int grid, bool aligned, hipStream_t stream)
+{
+    if (grid <= 0) return hipSuccess;
+    if (aligned)
+        hipLaunchKernelGGL((xcorr_mfma<true, true>), dim3(grid), dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL((xcorr_mfma<false, true>), dim3(grid), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 

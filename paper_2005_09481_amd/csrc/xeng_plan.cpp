@@ -63,12 +63,13 @@ int64_t fill(const std::vector<UnitRef> &units, int64_t budget, int64_t overhead
 
 }  // namespace
 
-Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, TileShape shape)
+Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, TileShape shape, int64_t cap_override)
 {
     Plan plan;
     if (min_stages < 1) min_stages = 1;
     if (max_wgs < 1) max_wgs = 1;
-    const int64_t cap = shape == TileShape::Wide ? MAX_PIECE_STAGES_WIDE : MAX_PIECE_STAGES;
+    const int64_t cap = cap_override > 0 ? cap_override
+                                         : (shape == TileShape::Wide ? MAX_PIECE_STAGES_WIDE : MAX_PIECE_STAGES);
     const int64_t ovh = piece_overhead(shape);
 
     std::vector<UnitRef> units;

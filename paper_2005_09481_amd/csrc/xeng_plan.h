@@ -33,8 +33,9 @@ struct Plan {
 // workgroup tiles (I, J2) of 128 rows x 256 columns, i.e. accumulator tiles
 // (I, 2 J2) and (I, 2 J2 + 1), for every I <= 2 J2 + 1 (for I = 2 J2 + 1
 // the left tile lies below the diagonal: the DMA kernel leaves it out).
+// `cap` (stages), when positive, replaces the shape's longest piece.
 Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages,
-               TileShape shape = TileShape::Square);
+               TileShape shape = TileShape::Square, int64_t cap = 0);
 
 // Units of one job in the plan's order: pairs (row index, column index)
 // in the shape's own units.

@@ -133,6 +133,7 @@ def lib() -> ctypes.CDLL:
         "xeng_rfi_flags": (ctypes.c_int, [vp, i64, i32, i64, u32, ctypes.POINTER(_RfiConfig), vp, vp]),
         "xeng_correlate_flagged": (ctypes.c_int, [vp, i32, vp, i64, i64, vp, i32, vp]),
         "xeng_dump_counts": (ctypes.c_int, [vp, i32, vp, vp]),
+        "xeng_correlate_presum": (ctypes.c_int, [vp, i32, vp, i64, i64, vp]),
         "xeng_correlate_static": (ctypes.c_int, [vp, i32, vp, i64, i64, vp]),
         "xeng_plan_inspect_static": (i64, [i32, i64, i32, i32, i32, ctypes.POINTER(_PieceInfo), i64]),
         "xeng_server_export_ring": (ctypes.c_int, [vp, i32, vp, i32]),
@@ -265,6 +266,12 @@ class Correlator:
         ptr, t, row_stride = _samples_args(samples, self.n_inputs, self.device)
         _check(lib().xeng_correlate(self.handle, slot, ptr, t, row_stride,
                                     _stream_handle(stream, self.device)), "xeng_correlate")
+
+    def correlate_presum(self, slot: int, samples, stream=None):
+        """acc[slot] += V(samples) by the unsigned-nibble form with pre-sums."""
+        ptr, t, row_stride = _samples_args(samples, self.n_inputs, self.device)
+        _check(lib().xeng_correlate_presum(self.handle, slot, ptr, t, row_stride,
+                                           _stream_handle(stream, self.device)), "xeng_correlate_presum")
 
     def correlate_flagged(self, slot: int, samples, flags, block_len: int, stream=None):
         """acc[slot] += V over unflagged samples, counts[slot] += n_ij;

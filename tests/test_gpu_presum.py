@@ -1,0 +1,106 @@
+"""GPU parity of the unsigned-nibble form with pre-sums
+(xeng_correlate_presum): every visibility against the oracle -- small and
+ragged shapes, both nibble orders, unaligned arrays, pieces split at the
+unsigned form's register bound, accumulation with the other kernels in one
+slot, the full integration bound where the unsigned sums pass int32, and the
+full-size N=2048 channel against the oracle's recorded digest."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.presum as OP
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def X():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_09481_amd import xeng
+    xeng.lib()
+    return xeng
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def run(X, x, re_low=False):
+    c = X.Correlator(x.shape[1], 1, re_low=re_low)
+    c.correlate_presum(0, gpu(x))
+    v = c.dump(0).cpu().numpy().astype(np.int64)
+    c.close()
+    return v
+
+
+@pytest.mark.parametrize("n,t", [(1, 1), (2, 33), (5, 64), (64, 4096), (100, 1000), (128, 129), (129, 300),
+                                 (256, 65), (513, 129), (1000, 777)])
+def test_presum_matches_oracle(X, n, t):
+    print(f"presum n={n} t={t}", flush=True)
+    x = synth.uniform_bytes(n, t, seed=[41, n, t])
+    got = run(X, x)
+    np.testing.assert_array_equal(got, oracle.correlate(x))
+    np.testing.assert_array_equal(got, OP.correlate_presum(x))
+
+
+def test_presum_re_low_and_unaligned(X):
+    x = synth.uniform_bytes(70, 300, seed=42)
+    np.testing.assert_array_equal(run(X, x, re_low=True), oracle.correlate(x, re_low=True))
+    big = synth.uniform_bytes(105, 200, seed=43)
+    c = X.Correlator(100, 1)
+    c.correlate_presum(0, gpu(big)[:, 3:103])
+    np.testing.assert_array_equal(c.dump(0).cpu().numpy(), oracle.correlate(big[:, 3:103]))
+    c.close()
+
+
+def test_presum_pieces_past_register_bound(X):
+    # T = 600,000 > 2^19: every tile cut into pieces; extreme nibbles
+    # maximise the unsigned sums
+    n, t = 64, 600_000
+    rng = np.random.default_rng(44)
+    x = rng.choice(np.array([0x00, 0x0F, 0xF0, 0xFF, 0x88], dtype=np.uint8), size=(t, n))
+    print(f"presum long pieces n={n} t={t}", flush=True)
+    np.testing.assert_array_equal(run(X, x), oracle.correlate(x))
+
+
+def test_presum_mixed_with_other_kernels(X):
+    n = 512
+    xs = [synth.uniform_bytes(n, t, seed=[45, t]) for t in (300, 1000, 77)]
+    c = X.Correlator(n, 1)
+    c.correlate(0, gpu(xs[0]))                  # wide kernel
+    c.correlate_presum(0, gpu(xs[1]))           # unsigned form
+    c.correlate(0, gpu(xs[2]))
+    assert c.samples_integrated(0) == 1377
+    np.testing.assert_array_equal(c.dump(0).cpu().numpy(), oracle.correlate(np.concatenate(xs)))
+    c.close()
+
+
+def test_presum_at_the_integration_bound(X):
+    # every sample 7+7j (u = 15): the unsigned sums reach 450 T, past int32,
+    # and the corrections bring every pair back to Re = 98 T, Im = 0
+    n = 64
+    tmax = X.max_integration()
+    chunk = 1 << 21
+    ones = torch.full((chunk, n), 0xFF, dtype=torch.uint8, device="cuda")
+    c = X.Correlator(n, 1)
+    done = 0
+    while done < tmax:
+        k = min(chunk, tmax - done)
+        c.correlate_presum(0, ones[:k])
+        done += k
+    v = c.dump(0).cpu().numpy().astype(np.int64)
+    assert (v[:, 0] == 98 * tmax).all() and not v[:, 1].any()
+    c.close()
+
+
+def test_presum_full_size_digest(X):
+    import parity_util as pu
+    x = pu.fc.channel_n2048()
+    print("presum full size n=2048 t=32768", flush=True)
+    c = X.Correlator(2048, 1)
+    c.correlate_presum(0, gpu(x))
+    pu.assert_matches_oracle_digest("channel_n2048_t32768", c.dump(0), x)
+    c.close()
