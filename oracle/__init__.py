@@ -14,7 +14,9 @@ including autocorrelations, V_ij = sum_t x_i(t) conj(x_j(t))):
 * ``correlate_python`` Python ``complex`` arithmetic, for tiny inputs.
 
 ``oracle.flags`` holds the flag-aware correlation (per-baseline sample
-counts) and its RFI-excision step (spectral kurtosis per block).
+counts) and its RFI-excision step (spectral kurtosis per block);
+``oracle.presum`` the unsigned-nibble form with O(N) pre-sums;
+``oracle.beams`` phased-array beamforming.
 """
 from __future__ import annotations
 

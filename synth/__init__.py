@@ -7,5 +7,5 @@ tests and benchmark.
 """
 from .gen import (  # noqa: F401
     encode, uniform_bytes, chime_channel, gaussian_bytes, flag_inputs,
-    batched_channels, subarray_batch, stream_frames, rank1_tone, rfi_channel,
+    batched_channels, subarray_batch, stream_frames, rank1_tone, rfi_channel, beam_weights,
 )

@@ -188,3 +188,18 @@ def rfi_channel(n_inputs: int, n_samples: int, seed=6, block_len: int = 256, ton
             where = rng.choice(t1 - t0, size=min(4, t1 - t0), replace=False)
             x[t0 + where, i] = spike
     return x
+
+
+def beam_weights(n_beams: int, n_inputs: int, seed=8, amplitude: float = 127.0) -> np.ndarray:
+    """Phased-array weights int8 [B][N][2]: beam b steers by a phase ramp
+    across the inputs, w_bi = A e^{-j 2 pi (b + 1) 0.37 i / N + j theta_b},
+    rounded half to even and clipped to [-127, 127]."""
+    rng = np.random.default_rng(seed)
+    i = np.arange(n_inputs)
+    theta = rng.uniform(0, 2 * np.pi, size=n_beams)
+    ph = -2 * np.pi * (np.arange(1, n_beams + 1)[:, None] * 0.37 * i[None, :] / max(n_inputs, 1)) + theta[:, None]
+    w = amplitude * np.exp(1j * ph)
+    out = np.empty((n_beams, n_inputs, 2), dtype=np.int8)
+    out[:, :, 0] = np.clip(np.rint(w.real), -127, 127)
+    out[:, :, 1] = np.clip(np.rint(w.imag), -127, 127)
+    return out
