@@ -316,6 +316,40 @@ def bench_presum(args, xeng, synth, torch, np):
     print(json.dumps(res), flush=True)
 
 
+def bench_beamform(args, xeng, synth, torch, np):
+    """Phased-array beamforming of the CHIME-shaped channel: 10 beams of
+    complex int8 weights, exact int32 beams; HBM-bound (every sample byte
+    read once, about 10 complex MACs per byte), so the roofline is GB/s."""
+    n, t, nb = args.n, args.t, 10
+    x = torch.from_numpy(synth.chime_channel(n, t, seed=2)).cuda()
+    beams = xeng.Beams(synth.beam_weights(nb, n, seed=8))
+    out = torch.empty((t, nb, 2), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    t_settle = time.perf_counter() + args.settle_ms / 1e3
+    while time.perf_counter() < t_settle:
+        beams.form(x, out=out, stream=stream)
+        torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        beams.form(x, out=out, stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k_s = float(np.mean([a.elapsed_time(b) for a, b in evs])) / 1e3
+    nbytes = n * t + t * nb * 8
+    gbs = nbytes / k_s / 1e9
+    res = {"metric": "beamformed samples/s, 10 beams at N=2048", "value": round(t / k_s / 1e6, 3),
+           "unit": "Msamples/s", "n_gpus": 1, "steps": args.steps, "ms_per_step": round(wall / args.steps * 1e3, 4),
+           "higher_is_better": True, "dtype": "int8", "data": "synthetic",
+           "config": {"workload": f"CHIME-shaped channel N={n}, T={t}, {nb} beams, int32 output"},
+           "beamform_us": round(k_s * 1e6, 2), "tcmacs": round(t * n * nb / k_s / 1e12, 3),
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,7 +364,7 @@ def main():
                     help="do not stamp the shader clock of the timed launches")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", default="channel",
-                    choices=["channel", "channels16", "subarrays64", "serve", "flagged", "presum"],
+                    choices=["channel", "channels16", "subarrays64", "serve", "flagged", "presum", "beamform"],
                     help="channel: the one-channel step (default, the JSON contract line); "
                          "channels16 / subarrays64: batched launches against plain launches; "
                          "serve: streaming channels, largest real-time K")
@@ -371,6 +405,8 @@ def main():
         return bench_flagged(args, xeng, synth, torch, np)
     if args.workload == "presum":
         return bench_presum(args, xeng, synth, torch, np)
+    if args.workload == "beamform":
+        return bench_beamform(args, xeng, synth, torch, np)
     if args.workload != "channel":
         return bench_batch(args, xeng, synth, torch, np)
 

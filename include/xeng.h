@@ -213,6 +213,40 @@ int xeng_dump_counts(xeng_ctx *ctx, int32_t slot, int32_t *out, void *hip_stream
 int xeng_correlate_presum(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_t n_samples,
                           int64_t row_stride, void *hip_stream);
 
+/*
+ * Phased-array beamforming (Sec. 2.1: the nodes form 10 phased-array beams
+ * for pulsar timing; "Pulsar Beamforming" in Table tab:computing):
+ *     y_b(t) = sum_i w_bi x_i(t),   b < n_beams, t < n_samples,
+ * with complex int8 weights, parts in [-127, 127].  A beam set holds the
+ * weights on the device in the order the kernel's matrix-core operands read
+ * them.  weights: HOST memory, int8 [n_beams][n_inputs][2] (re, im), read
+ * before the call returns; XENG_EINVAL for a part equal to -128, for
+ * n_beams outside 1..XENG_BEAMS_MAX, or for flags other than
+ * XENG_NIBBLE_RE_LOW.  xeng_beams_create uploads synchronously;
+ * xeng_beams_set_weights replaces the weights asynchronously on hip_stream
+ * (beamform calls queued after it on that stream see the new weights; it
+ * waits for the previous update's copy before reusing its pinned staging).
+ */
+#define XENG_BEAMS_MAX 16
+typedef struct xeng_beams xeng_beams;
+int xeng_beams_create(int32_t n_inputs, int32_t n_beams, int32_t device, uint32_t flags, const int8_t *weights,
+                      xeng_beams **out);
+int xeng_beams_set_weights(xeng_beams *bm, const int8_t *weights, void *hip_stream);
+int xeng_beams_destroy(xeng_beams *bm);
+
+/*
+ * Form the beams of n_samples time samples: d_samples as in xeng_correlate
+ * (N = the beam set's n_inputs).  shift = -1: d_out is int32
+ * [n_samples][n_beams][2], the exact sums; shift = 0..24: d_out is int8
+ * [n_samples][n_beams][2], each part divided by 2^shift, rounded half to
+ * even and clipped to [-127, 127] (the 8 + 8-bit beam export: the paper's
+ * 0.25 Gb/s of pulsar beams per node is 16 bits per beam sample).  Device
+ * memory owned by the caller.  Asynchronous on hip_stream; XENG_ENOTSUP
+ * while capturing.
+ */
+int xeng_beamform(xeng_beams *bm, const uint8_t *d_samples, int64_t n_samples, int64_t row_stride, int32_t shift,
+                  void *d_out, void *hip_stream);
+
 /* One unit of a batched correlation: correlate d_samples into ctx/slot. */
 typedef struct {
     xeng_ctx *ctx;

@@ -40,6 +40,11 @@ hipError_t launch_batch_guard(const GuardJob *d_jobs, int n_jobs, int32_t *d_ski
                               hipStream_t stream);
 hipError_t launch_set_count(int64_t *p, int64_t v, hipStream_t stream);
 hipError_t static_scratch_address(void **ptr);
+hipError_t init_beam_kernel();
+int64_t beam_image_bytes(int n);
+void beam_image(const int8_t *w, int n, int n_beams, uint8_t *img);
+hipError_t launch_beamform(const uint8_t *s, int64_t n_samples, int n, int64_t stride, uint32_t re_low,
+                           const int8_t *d_w, int n_beams, int shift, void *out, int grid, hipStream_t stream);
 hipError_t launch_sk_flags(const uint8_t *s, int64_t n_samples, int n, int64_t stride, uint32_t re_low,
                            int block_len, int64_t lo_num, int64_t hi_num, int64_t den, uint8_t *flags,
                            hipStream_t stream);
@@ -163,7 +168,8 @@ DeviceState *device_state(int device)
     if (hipMalloc(&st->d_zeros, ZERO_BYTES) != hipSuccess) return nullptr;
     void *scr = nullptr;
     if (hipMemset(st->d_zeros, 0x88, ZERO_BYTES) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
-        init_dma_kernel() != hipSuccess || static_scratch_address(&scr) != hipSuccess || !scr) {
+        init_dma_kernel() != hipSuccess || init_beam_kernel() != hipSuccess ||
+        static_scratch_address(&scr) != hipSuccess || !scr) {
         (void)hipFree(st->d_zeros);
         return nullptr;
     }
@@ -318,6 +324,19 @@ struct xeng_batch {
     const uint8_t *zeros = nullptr;
     std::vector<Acct> acct;
     std::vector<Launch> launches;
+};
+
+struct xeng_beams {
+    int32_t device = 0;
+    int32_t n = 0;
+    int32_t n_beams = 0;
+    uint32_t flags = 0;
+    int32_t cu_count = 0;
+    int64_t bytes = 0;           // operand-order image: one LDS load per chunk of inputs
+    uint8_t *d_w = nullptr;
+    uint8_t *h_w = nullptr;      // pinned staging of weight updates
+    hipEvent_t ev = nullptr;
+    bool pending = false;
 };
 
 struct xeng_ctx {
@@ -1514,6 +1533,100 @@ int xeng_set_tuning(int32_t wgs_per_cu, int32_t min_stages, int32_t kernel)
         kv.second->tuned.clear();
     }
     return XENG_OK;
+}
+
+int xeng_beams_create(int32_t n_inputs, int32_t n_beams, int32_t device, uint32_t flags, const int8_t *weights,
+                      xeng_beams **out)
+{
+    if (!out) return XENG_EINVAL;
+    *out = nullptr;
+    if (n_inputs < 1 || n_inputs > 65535 || n_beams < 1 || n_beams > XENG_BEAMS_MAX || device < 0 ||
+        (flags & ~XENG_NIBBLE_RE_LOW) || !weights)
+        return XENG_EINVAL;
+    const int64_t wbytes = (int64_t)n_beams * n_inputs * 2;
+    for (int64_t k = 0; k < wbytes; ++k)
+        if (weights[k] == INT8_MIN) return XENG_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) return XENG_EDEVICE;
+    DeviceGuard guard(device);
+    if (!guard.ok) return XENG_EDEVICE;
+    DeviceState *st = device_state(device);
+    if (!st) return XENG_EDEVICE;
+    auto *bm = new (std::nothrow) xeng_beams;
+    if (!bm) return XENG_ENOMEM;
+    bm->device = device;
+    bm->n = n_inputs;
+    bm->n_beams = n_beams;
+    bm->flags = flags;
+    bm->bytes = beam_image_bytes(n_inputs);
+    bm->cu_count = st->cu_count;
+    hipError_t e = hipMalloc(&bm->d_w, (size_t)bm->bytes);
+    if (e == hipSuccess) e = hipHostMalloc(&bm->h_w, (size_t)bm->bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&bm->ev, hipEventDisableTiming);
+    if (e == hipSuccess) {
+        beam_image(weights, n_inputs, n_beams, bm->h_w);
+        e = hipMemcpy(bm->d_w, bm->h_w, (size_t)bm->bytes, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        (void)xeng_beams_destroy(bm);
+        return map_err(e);
+    }
+    *out = bm;
+    return XENG_OK;
+}
+
+int xeng_beams_set_weights(xeng_beams *bm, const int8_t *weights, void *hip_stream)
+{
+    if (!bm || !weights) return XENG_EINVAL;
+    const int64_t wbytes = (int64_t)bm->n_beams * bm->n * 2;
+    for (int64_t k = 0; k < wbytes; ++k)
+        if (weights[k] == INT8_MIN) return XENG_EINVAL;
+    DeviceGuard guard(bm->device);
+    if (!guard.ok) return XENG_EDEVICE;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    int rc = refuse_capture(stream);
+    if (rc != XENG_OK) return rc;
+    // the staging buffer is reused once the previous update's copy is done
+    if (bm->pending && hipEventSynchronize(bm->ev) != hipSuccess) return XENG_EDEVICE;
+    bm->pending = false;
+    beam_image(weights, bm->n, bm->n_beams, bm->h_w);
+    hipError_t e = hipMemcpyAsync(bm->d_w, bm->h_w, (size_t)bm->bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(bm->ev, stream);
+    if (e != hipSuccess) return map_err(e);
+    bm->pending = true;
+    return XENG_OK;
+}
+
+int xeng_beamform(xeng_beams *bm, const uint8_t *d_samples, int64_t n_samples, int64_t row_stride, int32_t shift,
+                  void *d_out, void *hip_stream)
+{
+    if (!bm || n_samples < 0 || row_stride < bm->n || row_stride > MAX_STRIDE || shift < -1 || shift > 24)
+        return XENG_EINVAL;
+    if (n_samples > 0 && (!d_samples || !d_out || row_stride > INT64_MAX / n_samples)) return XENG_EINVAL;
+    if (n_samples == 0) return XENG_OK;
+    DeviceGuard guard(bm->device);
+    if (!guard.ok) return XENG_EDEVICE;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int rc = refuse_capture(stream);
+    if (rc != XENG_OK) return rc;
+    const int64_t blocks = (n_samples + 127) / 128;      // row blocks of the kernel
+    const int grid = (int)std::min<int64_t>(blocks, bm->cu_count);
+    return map_err(launch_beamform(d_samples, n_samples, bm->n, row_stride, (bm->flags & XENG_NIBBLE_RE_LOW) ? 1u : 0u,
+                                   reinterpret_cast<const int8_t *>(bm->d_w), bm->n_beams, shift, d_out, grid,
+                                   stream));
+}
+
+int xeng_beams_destroy(xeng_beams *bm)
+{
+    if (!bm) return XENG_EINVAL;
+    DeviceGuard guard(bm->device);
+    if (bm->pending) (void)hipEventSynchronize(bm->ev);
+    if (bm->ev) (void)hipEventDestroy(bm->ev);
+    if (bm->h_w) (void)hipHostFree(bm->h_w);
+    int rc = XENG_OK;
+    if (bm->d_w && hipFree(bm->d_w) != hipSuccess) rc = XENG_EDEVICE;
+    delete bm;
+    return rc;
 }
 
 int xeng_set_plan_order(int32_t order)

@@ -24,6 +24,7 @@ XENG_ENOTSUP = -6
 XENG_NIBBLE_RE_LOW = 1
 XENG_COUNTS = 4
 XENG_RFI_MAX_BLOCK = 1024
+XENG_BEAMS_MAX = 16
 XENG_SERVER_STAGGER_EXPORTS = 2
 XENG_KERNEL_AUTO = 0
 XENG_KERNEL_GENERAL = 1
@@ -134,6 +135,10 @@ def lib() -> ctypes.CDLL:
         "xeng_correlate_flagged": (ctypes.c_int, [vp, i32, vp, i64, i64, vp, i32, vp]),
         "xeng_dump_counts": (ctypes.c_int, [vp, i32, vp, vp]),
         "xeng_correlate_presum": (ctypes.c_int, [vp, i32, vp, i64, i64, vp]),
+        "xeng_beams_create": (ctypes.c_int, [i32, i32, i32, u32, vp, ctypes.POINTER(vp)]),
+        "xeng_beams_set_weights": (ctypes.c_int, [vp, vp, vp]),
+        "xeng_beams_destroy": (ctypes.c_int, [vp]),
+        "xeng_beamform": (ctypes.c_int, [vp, vp, i64, i64, i32, vp, vp]),
         "xeng_correlate_static": (ctypes.c_int, [vp, i32, vp, i64, i64, vp]),
         "xeng_plan_inspect_static": (i64, [i32, i64, i32, i32, i32, ctypes.POINTER(_PieceInfo), i64]),
         "xeng_server_export_ring": (ctypes.c_int, [vp, i32, vp, i32]),
@@ -440,6 +445,66 @@ def rfi_flags(samples, n_inputs: int | None = None, block_len: int = 256, lo_num
     _check(lib().xeng_rfi_flags(ptr, t, n, row_stride, XENG_NIBBLE_RE_LOW if re_low else 0, ctypes.byref(cfg),
                                 ctypes.c_void_p(out.data_ptr()), _stream_handle(stream, dev)), "xeng_rfi_flags")
     return out
+
+
+class Beams:
+    """A beam set (``xeng_beams_*``): complex int8 weights [B][N][2] held on
+    the device; ``form`` computes y_b(t) = sum_i w_bi x_i(t)."""
+
+    def __init__(self, weights, device: int = 0, re_low: bool = False):
+        import numpy as np
+        w = np.ascontiguousarray(weights, dtype=np.int8)
+        if w.ndim != 3 or w.shape[2] != 2:
+            raise ValueError("weights must be int8 [B][N][2]")
+        self.n_beams, self.n_inputs, self.device = w.shape[0], w.shape[1], device
+        h = ctypes.c_void_p()
+        _check(lib().xeng_beams_create(self.n_inputs, self.n_beams, device, XENG_NIBBLE_RE_LOW if re_low else 0,
+                                       w.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)), "xeng_beams_create")
+        self._h = h
+
+    def set_weights(self, weights, stream=None):
+        import numpy as np
+        w = np.ascontiguousarray(weights, dtype=np.int8)
+        if w.shape != (self.n_beams, self.n_inputs, 2):
+            raise ValueError("weights must keep the beam set's [B][N][2] shape")
+        _check(lib().xeng_beams_set_weights(self._h, w.ctypes.data_as(ctypes.c_void_p),
+                                            _stream_handle(stream, self.device)), "xeng_beams_set_weights")
+
+    def form(self, samples, shift: int = -1, out=None, stream=None):
+        """int32 [T][B][2] (shift -1) or int8 [T][B][2] (8-bit export)."""
+        import torch
+        ptr, t, row_stride = _samples_args(samples, self.n_inputs, self.device)
+        dtype = torch.int32 if shift < 0 else torch.int8
+        if out is None:
+            out = torch.empty((t, self.n_beams, 2), dtype=dtype, device=f"cuda:{self.device}")
+        if out.dtype != dtype or tuple(out.shape) != (t, self.n_beams, 2) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous [T][B][2] tensor of the export's dtype")
+        _check(lib().xeng_beamform(self._h, ptr, t, row_stride, shift, ctypes.c_void_p(out.data_ptr()),
+                                   _stream_handle(stream, self.device)), "xeng_beamform")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().xeng_beams_destroy(self._h), "xeng_beams_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def beamform(samples, weights, shift: int = -1, re_low: bool = False, stream=None):
+    """One-off beams of ``samples`` with ``weights`` (a beam set made for the call)."""
+    dev = samples.device.index if samples.device.type == "cuda" else 0
+    bm = Beams(weights, device=dev, re_low=re_low)
+    try:
+        return bm.form(samples, shift=shift, stream=stream)
+    finally:
+        import torch
+        torch.cuda.synchronize(dev)
+        bm.close()
 
 
 def correlate_reference(samples, n_inputs: int | None = None, re_low: bool = False, stream=None):
