@@ -33,12 +33,20 @@ _lib = None
 _DUMMY = np.zeros(1, dtype=np.uint8)
 
 
-def compile_source(src: str, out: str) -> str:
-    """Compile an oracle C source into a shared library (plain -O2, OpenMP)."""
+def compile_source(src: str, out: str, native: bool = False) -> str:
+    """Compile an oracle C source into a shared library (OpenMP).  The
+    shipped build is portable (-O2); ``native`` builds for the host it runs
+    on (-O3 -march=native), for timing the oracle there."""
     tmp = out + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, src])
+    opt = ["-O3", "-march=native"] if native else ["-O2"]
+    subprocess.check_call(["gcc", *opt, "-fopenmp", "-shared", "-fPIC", "-o", tmp, src])
     os.replace(tmp, out)
     return out
+
+
+def build_native(out_dir: str) -> str:
+    """The oracle compiled -O3 -march=native into ``out_dir`` (timing only)."""
+    return compile_source(_SRC, os.path.join(out_dir, "liboracle_native.so"), native=True)
 
 
 def build(force: bool = True) -> str:
@@ -56,6 +64,8 @@ def load_library(path: str):
                                  ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_void_p]
     lib.xo_num_threads.restype = ctypes.c_int
+    lib.xo_set_threads.argtypes = [ctypes.c_int]
+    lib.xo_set_threads.restype = None
     return lib
 
 

@@ -81,6 +81,16 @@ int xo_correlate(const uint8_t *samples, int64_t n_samples, int64_t n_inputs,
     return 0;
 }
 
+/* Threads of later parallel regions (n >= 1; ignored without OpenMP). */
+void xo_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Number of threads an OpenMP parallel region would use (0 without OpenMP). */
 int xo_num_threads(void)
 {
