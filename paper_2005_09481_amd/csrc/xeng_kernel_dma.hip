@@ -599,6 +599,9 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
         // rows 64 wa.. of tile ti against columns 32 cb0 .. 32 (cb0 + BW) - 1
         // of tile tj: wholly below the diagonal?
         const bool below = WA_ROWS * (tj - ti) + BLK * (cb0 + L::BW) <= 64 * wa;
+        // or wholly past the last input (rows or columns >= N: never
+        // exported; small N and the edge tiles of N not a multiple of 256)
+        const bool outside = WA_ROWS * ti + 64 * wa >= jd.n || WA_ROWS * tj + BLK * cb0 >= jd.n;
 
         Acc<NW> acc;
 #pragma unroll
@@ -614,7 +617,7 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
         const bool diag = NW == 8 && tj == ti && cb0 == 2 * wa;
         // a wave whose tile lies past the last tile column (odd tile count)
         // has nothing to compute either
-        if (below || tj >= jd.nt)
+        if (below || outside || tj >= jd.nt)
             idle_piece<NW>(ring, tl, wave, lane);
         else if (jd.flags & JOB_RE_LOW) {
             if (diag)
@@ -628,7 +631,7 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
                 run_piece<NW, false, false>(acc, ring, tl, wave, lane, a_lane, b_lane);
         }
 
-        if (valid && !below) {
+        if (valid && !below && !outside) {
             const int64_t tile_idx = (int64_t)ti * jd.nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);
             gw64 *tb = (gw64 *)(jd.acc + tile_idx * TILE_I32) + lane;
             if (atomic) {

@@ -322,7 +322,7 @@ __device__ __forceinline__ void stage_mfma(Acc &acc, const uint8_t *buf, int lan
 // adds exactly nothing.
 template <bool ALIGNED, bool ROLE_A, bool RE_LOW, bool UNSIGNED>
 __device__ __forceinline__ void run_piece(Acc &acc, uint8_t *smem, const PieceCtx &pc, int lane,
-                                          int wa, int wb, int wslot)
+                                          int wa, int wb, int wslot, bool compute)
 {
     const int nst = (pc.t1 - pc.t0 + STAGE - 1) / STAGE;
     uint8_t *buf0 = smem, *buf1 = smem + STAGE_BYTES;
@@ -335,11 +335,11 @@ __device__ __forceinline__ void run_piece(Acc &acc, uint8_t *smem, const PieceCt
 
     for (int s = 0; s < nst; s += NBUF) {
         load_stage<ALIGNED>(r0, pc, s + 2);
-        stage_mfma(acc, buf0, lane, wa, wb);
+        if (compute) stage_mfma(acc, buf0, lane, wa, wb);
         stage_write<ROLE_A, RE_LOW, UNSIGNED>(buf1, r1, wslot);
         __syncthreads();
         load_stage<ALIGNED>(r1, pc, s + 3);
-        stage_mfma(acc, buf1, lane, wa, wb);
+        if (compute) stage_mfma(acc, buf1, lane, wa, wb);
         stage_write<ROLE_A, RE_LOW, UNSIGNED>(buf0, r0, wslot);
         __syncthreads();
     }
@@ -401,15 +401,20 @@ __global__ __launch_bounds__(256, 2) void xcorr_mfma(KernelArgs args)
                 }
 
         const bool re_low = (jd.flags & JOB_RE_LOW) != 0;
+        // a wave whose 64 x 64 region lies wholly past the last input (rows
+        // or columns >= N, never exported) stages its share but multiplies
+        // and flushes nothing
+        const bool compute = TILE * ti + 64 * wa < jd.n && TILE * tj + 64 * wb < jd.n;
         if (role_a) {
-            if (re_low) run_piece<ALIGNED, true, true, UNSIGNED>(acc, smem, pc, lane, wa, wb, wslot);
-            else run_piece<ALIGNED, true, false, UNSIGNED>(acc, smem, pc, lane, wa, wb, wslot);
+            if (re_low) run_piece<ALIGNED, true, true, UNSIGNED>(acc, smem, pc, lane, wa, wb, wslot, compute);
+            else run_piece<ALIGNED, true, false, UNSIGNED>(acc, smem, pc, lane, wa, wb, wslot, compute);
         } else {
-            if (re_low) run_piece<ALIGNED, false, true, UNSIGNED>(acc, smem, pc, lane, wa, wb, wslot);
-            else run_piece<ALIGNED, false, false, UNSIGNED>(acc, smem, pc, lane, wa, wb, wslot);
+            if (re_low) run_piece<ALIGNED, false, true, UNSIGNED>(acc, smem, pc, lane, wa, wb, wslot, compute);
+            else run_piece<ALIGNED, false, false, UNSIGNED>(acc, smem, pc, lane, wa, wb, wslot, compute);
         }
 
         // integrate into the slot's accumulators
+        if (!compute) continue;
         const int64_t tile_idx = (int64_t)ti * jd.nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);
         gw64 *tb = (gw64 *)(jd.acc + tile_idx * TILE_I32) + lane;
         if (atomic) {
