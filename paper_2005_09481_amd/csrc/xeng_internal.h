@@ -63,6 +63,13 @@ constexpr int MAX_PIECE_STAGES_WIDE = ((1 << 16) - 1) / STAGE;  // 1023 stages
 constexpr int MAX_PIECE_STAGES_UNSIGNED = ((1 << 19) - 1) / STAGE;   // 8191 stages
 
 // Largest row stride: lane offsets inside a stage (up to 31 rows) stay 32-bit.
+// Most workgroups one tile is shared among in a launch.  Every share of a
+// tile flushes all of it with atomics, and shares of one tile end together,
+// so their atomics meet on the same addresses: past about 16 shares the
+// flush costs more than the extra workgroups save (measured on N = 64 to
+// 512 with T of 4096 and 8192).
+constexpr int64_t MAX_UNIT_SPLIT = 16;
+
 constexpr int64_t MAX_STRIDE = INT64_C(1) << 26;
 
 // Largest number of samples a slot may integrate: the largest |term| of

@@ -87,7 +87,9 @@ Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, Til
         plan.wg_off.assign(1, 0);
         return plan;
     }
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(max_wgs, (total + min_stages - 1) / min_stages));
+    const int64_t grid = std::max<int64_t>(
+        1, std::min<int64_t>({(int64_t)max_wgs, (total + min_stages - 1) / min_stages,
+                              (int64_t)units.size() * MAX_UNIT_SPLIT}));
 
     // Smallest per-workgroup budget with which the greedy fill fits in
     // `grid` workgroups (the fill is monotone in the budget).
@@ -280,7 +282,8 @@ SinglePlanArgs single_plan(int32_t n, int64_t t, TileShape shape, int max_wgs, i
     if (max_wgs < 1) max_wgs = 1;
     const int64_t units = single_units(a);
     const int64_t total = units * single_stages(a);
-    a.grid = std::max<int64_t>(1, std::min<int64_t>(max_wgs, (total + min_stages - 1) / min_stages));
+    a.grid = std::max<int64_t>(
+        1, std::min<int64_t>({(int64_t)max_wgs, (total + min_stages - 1) / min_stages, units * MAX_UNIT_SPLIT}));
     auto none = [](int64_t, int32_t, int32_t, int64_t, int64_t, int64_t) {};
     // the budget search of make_plan, over the same unit order
     int64_t lo = a.overhead + 1, hi = a.overhead + total + 1;
