@@ -431,6 +431,9 @@ def main():
     ap.add_argument("--many-channels", type=int, default=256,
                     help="HBM-bound N: also time this many channels of the same size "
                          "in one batched launch (0: skip)")
+    ap.add_argument("--kernel", default="auto", choices=["auto", "dma4", "general"],
+                    help="correlation kernel: the eight-wave DMA kernel (auto), its four-wave "
+                         "instance, or the general 128 x 128 kernel")
     ap.add_argument("--plan-order", default="xcd", choices=["xcd", "linear"],
                     help="work order of the single-channel launch (xeng_set_plan_order; never changes results)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -451,6 +454,8 @@ def main():
     from paper_2005_09481_amd import xeng
 
     xeng.set_plan_order({"xcd": xeng.XENG_PLAN_XCD, "linear": xeng.XENG_PLAN_LINEAR}[args.plan_order])
+    xeng.set_tuning(0, 0, {"auto": xeng.XENG_KERNEL_AUTO, "dma4": xeng.XENG_KERNEL_DMA4,
+                           "general": xeng.XENG_KERNEL_GENERAL}[args.kernel])
     if args.workload == "serve":
         return bench_serve(args, xeng, synth, torch, np)
     if args.workload == "flagged":
@@ -542,7 +547,7 @@ def main():
                                 f"single channel N={n}, T={t}, 4+4-bit, uniform nibbles, ")
                                + "correlate + dump/reset per step",
                    "n_inputs": n, "n_samples": t, "parallelism": "single GPU",
-                   "plan_order": args.plan_order},
+                   "plan_order": args.plan_order, "kernel": args.kernel},
         "roofline": roofline,
         "mfma_util_pct": round(100 * achieved / INT8_PEAK_TOPS, 2),
         # the int8 peak assumes 2.4 GHz; under this load the chip runs slower

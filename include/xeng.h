@@ -418,26 +418,69 @@ int xeng_batch_launch(xeng_batch *b, void *hip_stream);
 int xeng_batch_check(xeng_batch *b);
 int xeng_batch_destroy(xeng_batch *b);
 
-/* A launch configuration chosen by xeng_autotune. */
+/* A launch configuration (xeng_autotune, xeng_tuning_lookup). */
 typedef struct {
-    int32_t kernel;        /* XENG_KERNEL_AUTO or XENG_KERNEL_GENERAL */
+    int32_t kernel;        /* XENG_KERNEL_* */
     int32_t wgs_per_cu;    /* general kernel's workgroups per compute unit */
     int32_t min_stages;    /* minimum piece length, 64-sample stages */
-    int32_t reserved;
-    double us_per_launch;  /* measured time of the chosen configuration */
+    int32_t plan_order;    /* XENG_PLAN_* of single-job launches */
+    double us_per_launch;  /* measured time of a tuned configuration, else 0 */
+    int32_t source;        /* XENG_TUNE_SETTINGS, XENG_TUNE_MEASURED or XENG_TUNE_CACHE_FILE */
+    int32_t saved;         /* xeng_autotune: 1 if the tune-cache file was written */
 } xeng_tuning;
 
+#define XENG_TUNE_SETTINGS 0    /* the global settings (xeng_set_tuning, xeng_set_plan_order) */
+#define XENG_TUNE_MEASURED 1    /* chosen by xeng_autotune in this process */
+#define XENG_TUNE_CACHE_FILE 2  /* read from the tune-cache file */
+
 /*
- * Autotuner: times every candidate launch configuration (kernel kind and
- * so tile shape, workgroups per CU, minimum piece length) on these jobs,
- * `iters` launches each on hip_stream, and keeps the fastest for every later
- * call with the same job sizes (N, T in order) on this device.  The jobs'
- * slots serve as scratch: they are zeroed, and their counters reset, when it
- * returns.  Synchronous.  Results never depend on the configuration.
- * xeng_set_tuning discards every autotuned choice.
+ * Autotuner (Sec. 2.3: each GPU processes its share of frequency channels;
+ * what runs fastest depends on their N and T).  Times every candidate launch
+ * configuration on these jobs, `iters` launches each on hip_stream: the
+ * kernel (the eight- or four-wave DMA kernel, or the general kernel with one
+ * or two workgroups per CU), the minimum piece length and, for a single
+ * job, the work order.  The trials read the jobs' samples and accumulate
+ * into accumulators the library allocates for the call and frees after:
+ * the jobs' slots, their contents and their sample counts are left as they
+ * were.  The fastest configuration is kept for every later call on this
+ * device whose jobs fall into the same class: the largest N, the
+ * power-of-two classes of the largest T and of the number of jobs, and
+ * whether any job can take the DMA kernel (so that a streaming server's
+ * launches, whose job counts and lengths vary, find it).  The device's
+ * tuned entries are then written to the tune-cache file of its
+ * architecture (xeng_tune_cache_path), which the library reads when it
+ * first uses a device in a later process; best->saved says whether that
+ * write succeeded (a failed write is not an error).  Synchronous; refused
+ * (XENG_ENOTSUP) while hip_stream is capturing.  Results never depend on
+ * the configuration.  xeng_set_tuning discards every tuned entry of this
+ * process (the file keeps them; a later xeng_autotune updates the file's
+ * entry for its own class only).
  */
 int xeng_autotune(const xeng_job *jobs, int32_t n_jobs, int32_t iters, void *hip_stream,
                   xeng_tuning *best);
+
+/*
+ * The configuration a batched call (or, for one job, xeng_correlate) of
+ * these jobs would launch with now, and where it comes from (out->source).
+ * Jobs as for xeng_correlate_batch; nothing is launched.
+ */
+int xeng_tuning_lookup(const xeng_job *jobs, int32_t n_jobs, xeng_tuning *out);
+
+/*
+ * Path of the tune-cache file for `device`'s architecture:
+ * $XENG_TUNE_DIR/xeng_tune_<arch>.json, else under $XDG_CACHE_HOME/xeng,
+ * else under $HOME/.cache/xeng.  The environment is read at every call; the
+ * file itself is read once per process, when the library first uses the
+ * device.  Writes at most len - 1 characters and a terminating zero into
+ * buf (nothing if len is 0) and returns the path's full length;
+ * XENG_ENOTSUP if none of the three variables is set, XENG_EDEVICE for a
+ * device that does not exist.  The file holds one JSON object: the
+ * architecture, and one entry per job class (N, T class, jobs class, DMA
+ * eligibility) with the chosen kernel, workgroups per CU, minimum piece
+ * length, work order and measured microseconds per launch.  Processes that
+ * tune at the same time each write the whole file; the last write wins.
+ */
+int32_t xeng_tune_cache_path(int32_t device, char *buf, int32_t len);
 
 /*
  * Streaming server (Sec. 2.1: every channel delivers a sample every 2.56 us
@@ -537,8 +580,9 @@ int xeng_server_last_dump(xeng_server *s, int32_t channel, int32_t *out);
 int xeng_server_export_ring(xeng_server *s, int32_t channel, int32_t *ring, int32_t n_entries);
 
 /* Kernel selection for xeng_set_tuning. */
-#define XENG_KERNEL_AUTO 0     /* wide DMA kernel where the job allows it, else general */
+#define XENG_KERNEL_AUTO 0     /* wide DMA kernel (eight waves) where the job allows it, else general */
 #define XENG_KERNEL_GENERAL 1  /* always the general kernel */
+#define XENG_KERNEL_DMA4 2     /* wide DMA kernel with four waves where the job allows it, else general */
 
 /*
  * Launch tuning: workgroups per compute unit of the general kernel (1 or 2),

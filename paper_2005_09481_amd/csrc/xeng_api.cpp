@@ -5,6 +5,9 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cerrno>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <list>
 #include <map>
@@ -14,6 +17,9 @@
 #include <string>
 #include <unordered_map>
 #include <vector>
+
+#include <sys/stat.h>
+#include <unistd.h>
 
 #include "../../include/xeng.h"
 #include "xeng_internal.h"
@@ -26,7 +32,7 @@ hipError_t launch_presum(const uint8_t *s, int64_t n_samples, int n, int64_t str
                          int32_t *si, hipStream_t stream);
 hipError_t launch_presum_correct(int32_t *acc, int n, int nt, int64_t n_samples, const int32_t *sr,
                                  const int32_t *si, hipStream_t stream);
-hipError_t launch_correlate_dma(const KernelArgs &a, int grid, hipStream_t stream);
+hipError_t launch_correlate_dma(const KernelArgs &a, int grid, int waves, hipStream_t stream);
 hipError_t init_dma_kernel();
 hipError_t launch_dump(int32_t *acc, int32_t *diag, int n, int nt, int32_t *out, bool reset,
                        hipStream_t stream);
@@ -74,11 +80,11 @@ std::atomic<int> g_plan_order{XENG_PLAN_XCD};
 // The plan of a launch: single jobs take the XCD-aware decomposition where
 // it applies (and the order asks for it), everything else the linear
 // stream-K plan.
-Plan build_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, TileShape shape, int64_t cap = 0)
+Plan build_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, TileShape shape, int order,
+                int64_t cap = 0)
 {
     if (cap > 0) return make_plan(jobs, n_jobs, max_wgs, min_stages, shape, cap);
     Plan p;
-    const int order = g_plan_order.load();
     if (order == XENG_PLAN_XCD && n_jobs == 1 && make_plan_xcd(jobs[0], max_wgs, shape, &p)) return p;
     return make_plan(jobs, n_jobs, max_wgs, min_stages, shape);
 }
@@ -89,9 +95,19 @@ struct Tuning {
     int kernel;       // XENG_KERNEL_*
     int wgs_per_cu;   // general kernel
     int min_stages;
+    int order;        // XENG_PLAN_* of single-job launches
+    int source;       // XENG_TUNE_*
+    double us;        // measured time of a tuned entry (0: not measured)
 };
 
-Tuning global_tuning() { return Tuning{g_kernel.load(), g_wgs_per_cu.load(), g_min_stages.load()}; }
+Tuning global_tuning()
+{
+    return Tuning{g_kernel.load(), g_wgs_per_cu.load(), g_min_stages.load(), g_plan_order.load(), XENG_TUNE_SETTINGS,
+                  0.0};
+}
+
+// Waves per workgroup of the DMA kernel instance a configuration launches.
+int dma_waves(const Tuning &tu) { return tu.kernel == XENG_KERNEL_DMA4 ? 4 : 8; }
 
 // Restores the caller's current device on scope exit.
 struct DeviceGuard {
@@ -128,6 +144,45 @@ struct JobTable {
 constexpr int PLAN_CACHE_MAX = 64;
 constexpr int JOB_RING = 8;
 
+// Class of a call's jobs in the autotuner's table: the largest N, the
+// power-of-two classes of the largest T and of the number of jobs, and
+// whether any job can take the DMA kernel.  Calls of one class share a
+// tuned configuration, so that a streaming server's launches, whose job
+// counts and lengths vary from launch to launch, find one.
+struct TuneClass {
+    int32_t n = 0, t_class = 0, jobs_class = 0, dma = 0;
+    std::string key() const
+    {
+        char b[64];
+        std::snprintf(b, sizeof b, "%d/%d/%d/%d", n, t_class, jobs_class, dma);
+        return b;
+    }
+};
+
+int log2_floor(int64_t v)
+{
+    int k = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++k;
+    }
+    return k;
+}
+
+TuneClass tune_class(const PlanJob *jobs, int n_jobs, bool any_dma)
+{
+    TuneClass c;
+    int64_t t_max = 1;
+    for (int j = 0; j < n_jobs; ++j) {
+        c.n = std::max(c.n, jobs[j].n);
+        t_max = std::max(t_max, jobs[j].t);
+    }
+    c.t_class = log2_floor(t_max);
+    c.jobs_class = log2_floor(std::max(1, n_jobs));
+    c.dma = any_dma ? 1 : 0;
+    return c;
+}
+
 struct DeviceState {
     int device = 0;
     int cu_count = 0;
@@ -142,7 +197,11 @@ struct DeviceState {
     std::list<std::string> host_lru;
     JobTable ring[JOB_RING];
     int ring_next = 0;
-    std::unordered_map<std::string, Tuning> tuned;   // job sizes -> autotuned configuration
+    struct Tuned {
+        TuneClass cls;
+        Tuning tu;
+    };
+    std::unordered_map<std::string, Tuned> tuned;   // job class -> autotuned configuration
     std::atomic<int64_t *> clock{nullptr};             // xeng_clock_probe buffer
     hipMemPool_t pad_pool = nullptr;   // scratch of padded single-channel calls (keeps up to 1 GiB)
     uint8_t *static_scratch = nullptr;  // this device's copy of the fixed plan array (xeng_correlate_static)
@@ -150,6 +209,129 @@ struct DeviceState {
 
 std::mutex g_states_mu;
 std::map<int, std::unique_ptr<DeviceState>> g_states;
+
+// The device's architecture name ("gfx950"), without target features.
+std::string arch_name(int device)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    if (colon != std::string::npos) a.resize(colon);
+    return a;
+}
+
+// The tune-cache file of an architecture: $XENG_TUNE_DIR, else
+// $XDG_CACHE_HOME/xeng, else $HOME/.cache/xeng, holding
+// xeng_tune_<arch>.json.  Empty if none of them is set.
+std::string tune_cache_path(const std::string &arch)
+{
+    std::string dir;
+    const char *d = std::getenv("XENG_TUNE_DIR");
+    const char *x = std::getenv("XDG_CACHE_HOME");
+    const char *h = std::getenv("HOME");
+    if (d && *d)
+        dir = d;
+    else if (x && *x)
+        dir = std::string(x) + "/xeng";
+    else if (h && *h)
+        dir = std::string(h) + "/.cache/xeng";
+    if (dir.empty() || arch.empty()) return "";
+    return dir + "/xeng_tune_" + arch + ".json";
+}
+
+// One entry per line, so that the reader needs no JSON parser: the library
+// writes every line in exactly this form.
+constexpr const char *TUNE_LINE =
+    "  {\"n\": %d, \"t_class\": %d, \"jobs_class\": %d, \"dma\": %d, \"kernel\": %d, \"wgs_per_cu\": %d, "
+    "\"min_stages\": %d, \"plan_order\": %d, \"us_per_launch\": %lf}";
+
+// The entries of the cache file at `path` written for `arch` (none if there
+// is no such file); lines that do not parse or hold values out of range are
+// skipped.
+void read_tune_file(const std::string &path, const std::string &arch,
+                    std::unordered_map<std::string, DeviceState::Tuned> *out)
+{
+    if (path.empty()) return;
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[512];
+    bool arch_ok = false;
+    const std::string head = "{\"arch\": \"" + arch + "\",";
+    while (std::fgets(line, sizeof line, f)) {
+        if (std::strncmp(line, head.c_str(), head.size()) == 0) {
+            arch_ok = true;
+            continue;
+        }
+        if (!arch_ok) continue;
+        TuneClass c;
+        Tuning tu{};
+        double us = 0.0;
+        if (std::sscanf(line, TUNE_LINE, &c.n, &c.t_class, &c.jobs_class, &c.dma, &tu.kernel, &tu.wgs_per_cu,
+                        &tu.min_stages, &tu.order, &us) != 9)
+            continue;
+        if (c.n < 1 || c.t_class < 0 || c.t_class > 62 || c.jobs_class < 0 || c.jobs_class > 31 ||
+            (c.dma != 0 && c.dma != 1) || tu.kernel < XENG_KERNEL_AUTO || tu.kernel > XENG_KERNEL_DMA4 ||
+            tu.wgs_per_cu < 1 || tu.wgs_per_cu > 2 || tu.min_stages < 1 || tu.min_stages > (1 << 20) ||
+            (tu.order != XENG_PLAN_LINEAR && tu.order != XENG_PLAN_XCD) || !(us >= 0.0))
+            continue;
+        tu.source = XENG_TUNE_CACHE_FILE;
+        tu.us = us;
+        (*out)[c.key()] = DeviceState::Tuned{c, tu};
+    }
+    std::fclose(f);
+}
+
+// Called once per device, at its first use.
+void load_tune_cache(DeviceState *st)
+{
+    const std::string arch = arch_name(st->device);
+    read_tune_file(tune_cache_path(arch), arch, &st->tuned);
+}
+
+// mkdir -p of the directory part of `path`.
+bool make_parent_dirs(const std::string &path)
+{
+    for (size_t k = 1; k < path.size(); ++k) {
+        if (path[k] != '/') continue;
+        const std::string d = path.substr(0, k);
+        if (mkdir(d.c_str(), 0755) != 0 && errno != EEXIST) return false;
+    }
+    return true;
+}
+
+// Writes the file's entries, updated by every tuned entry of `st`, back to
+// its architecture's cache file (through a temporary file renamed over it,
+// so that a reader never sees half a file).  Called with st->mu held.
+// False if it could not.
+bool save_tune_cache(DeviceState *st)
+{
+    const std::string arch = arch_name(st->device);
+    const std::string path = tune_cache_path(arch);
+    if (path.empty() || !make_parent_dirs(path)) return false;
+    std::unordered_map<std::string, DeviceState::Tuned> all;
+    read_tune_file(path, arch, &all);
+    for (const auto &kv : st->tuned) all[kv.first] = kv.second;
+    const std::string tmp = path + ".tmp." + std::to_string((long)getpid());
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    std::fprintf(f, "{\"arch\": \"%s\", \"format\": 1, \"entries\": [\n", arch.c_str());
+    size_t k = 0;
+    for (const auto &kv : all) {
+        const TuneClass &c = kv.second.cls;
+        const Tuning &tu = kv.second.tu;
+        std::fprintf(f, TUNE_LINE, c.n, c.t_class, c.jobs_class, c.dma, tu.kernel, tu.wgs_per_cu, tu.min_stages,
+                     tu.order, tu.us);
+        std::fprintf(f, "%s\n", ++k < all.size() ? "," : "");
+    }
+    std::fprintf(f, "]}\n");
+    const bool ok = std::fflush(f) == 0 && std::ferror(f) == 0;
+    if (std::fclose(f) != 0 || !ok || std::rename(tmp.c_str(), path.c_str()) != 0) {
+        std::remove(tmp.c_str());
+        return false;
+    }
+    return true;
+}
 
 DeviceState *device_state(int device)
 {
@@ -174,19 +356,20 @@ DeviceState *device_state(int device)
         return nullptr;
     }
     st->static_scratch = static_cast<uint8_t *>(scr);
+    load_tune_cache(st.get());
     DeviceState *p = st.get();
     g_states[device] = std::move(st);
     return p;
 }
 
-std::string plan_key(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, TileShape shape,
+std::string plan_key(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, TileShape shape, int order,
                      int64_t cap = 0)
 {
     std::string k;
     k.reserve(40 + 16 * (size_t)n_jobs);
     k.append(reinterpret_cast<const char *>(&cap), sizeof cap);
     k.push_back(shape == TileShape::Wide ? 'w' : 's');
-    k.push_back((char)('0' + g_plan_order.load()));
+    k.push_back((char)('0' + order));
     k.append(reinterpret_cast<const char *>(&max_wgs), sizeof max_wgs);
     k.append(reinterpret_cast<const char *>(&min_stages), sizeof min_stages);
     for (int j = 0; j < n_jobs; ++j) {
@@ -196,24 +379,12 @@ std::string plan_key(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stage
     return k;
 }
 
-// Key of a list of job sizes (the autotuner's table).
-std::string sizes_key(const PlanJob *jobs, int n_jobs)
-{
-    std::string k;
-    k.reserve(16 * (size_t)n_jobs);
-    for (int j = 0; j < n_jobs; ++j) {
-        k.append(reinterpret_cast<const char *>(&jobs[j].n), sizeof jobs[j].n);
-        k.append(reinterpret_cast<const char *>(&jobs[j].t), sizeof jobs[j].t);
-    }
-    return k;
-}
-
-// Configuration for calls with these job sizes.  Called with st->mu held.
-Tuning tuning_for(DeviceState *st, const PlanJob *jobs, int n_jobs)
+// Configuration for calls with these jobs.  Called with st->mu held.
+Tuning tuning_for(DeviceState *st, const PlanJob *jobs, int n_jobs, bool any_dma)
 {
     if (!st->tuned.empty()) {
-        auto it = st->tuned.find(sizes_key(jobs, n_jobs));
-        if (it != st->tuned.end()) return it->second;
+        auto it = st->tuned.find(tune_class(jobs, n_jobs, any_dma).key());
+        if (it != st->tuned.end()) return it->second.tu;
     }
     return global_tuning();
 }
@@ -284,9 +455,9 @@ int get_plan(DeviceState *st, const PlanJob *jobs, int n_jobs, TileShape shape, 
 {
     int max_wgs, min_stages;
     plan_limits(st, shape, tu, &max_wgs, &min_stages);
-    const std::string key = plan_key(jobs, n_jobs, max_wgs, min_stages, shape, cap);
+    const std::string key = plan_key(jobs, n_jobs, max_wgs, min_stages, shape, tu.order, cap);
     if (find_plan(st, key, out)) return XENG_OK;
-    return cache_plan(st, key, build_plan(jobs, n_jobs, max_wgs, min_stages, shape, cap), out);
+    return cache_plan(st, key, build_plan(jobs, n_jobs, max_wgs, min_stages, shape, tu.order, cap), out);
 }
 
 int map_err(hipError_t e)
@@ -314,6 +485,7 @@ struct xeng_batch {
     bool bound = false;          // the jobs' slots count this batch in ctx->bound
     struct Launch {
         bool dma;
+        int waves;
         uint32_t flags_and;
         int32_t grid;
         JobDesc *d_jobs;
@@ -428,9 +600,9 @@ JobDesc make_job(const xeng_ctx *c, int32_t slot, const uint8_t *d_samples, int6
 // Kernel choice for one job.
 bool use_dma(uint32_t flags, const Tuning &tu) { return tu.kernel != XENG_KERNEL_GENERAL && (flags & JOB_DMA); }
 
-hipError_t launch(const KernelArgs &a, int32_t grid, bool dma, uint32_t flags_and, hipStream_t stream)
+hipError_t launch(const KernelArgs &a, int32_t grid, bool dma, int waves, uint32_t flags_and, hipStream_t stream)
 {
-    if (dma) return launch_correlate_dma(a, grid, stream);
+    if (dma) return launch_correlate_dma(a, grid, waves, stream);
     return launch_correlate(a, grid, (flags_and & JOB_ALIGNED8) != 0, stream);
 }
 
@@ -507,7 +679,7 @@ int correlate_padded(xeng_ctx *ctx, int32_t slot, const uint8_t *samples, int64_
         if ((rc = get_plan(ctx->st, &pj, 1, dma ? TileShape::Wide : TileShape::Square, tu, &dp)) != XENG_OK) break;
         a.pieces = dp.d_pieces;
         a.wg_off = dp.d_off;
-        if ((e = launch(a, dp.grid, dma, a.job0.flags, stream)) != hipSuccess) {
+        if ((e = launch(a, dp.grid, dma, dma_waves(tu), a.job0.flags, stream)) != hipSuccess) {
             rc = map_err(e);
             break;
         }
@@ -613,6 +785,13 @@ int pad_batch_jobs(JobList &jl, const Tuning &tu, hipStream_t stream, uint8_t **
     return XENG_OK;
 }
 
+bool any_dma_job(const JobList &jl)
+{
+    for (const JobDesc &jd : jl.descs)
+        if (jd.flags & JOB_DMA) return true;
+    return false;
+}
+
 std::vector<Part> split_by_kernel(const JobList &jl, const Tuning &tu)
 {
     Part wide, square;
@@ -675,6 +854,7 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
         KernelArgs a;
         int32_t grid;
         bool dma;
+        int waves;
         uint32_t flags_and;
     };
     std::vector<Staged> staged;
@@ -683,7 +863,7 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
         const TileShape shape = part.dma ? TileShape::Wide : TileShape::Square;
         int max_wgs, min_stages;
         plan_limits(st, shape, tu, &max_wgs, &min_stages);
-        const std::string key = plan_key(part.pj.data(), (int)part.pj.size(), max_wgs, min_stages, shape);
+        const std::string key = plan_key(part.pj.data(), (int)part.pj.size(), max_wgs, min_stages, shape, tu.order);
         std::shared_ptr<const Plan> plan;
         auto it = st->host_plans.find(key);
         if (it != st->host_plans.end()) {
@@ -692,7 +872,7 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
             st->host_lru.push_front(key);
         } else {
             plan = std::make_shared<const Plan>(
-                build_plan(part.pj.data(), (int)part.pj.size(), max_wgs, min_stages, shape));
+                build_plan(part.pj.data(), (int)part.pj.size(), max_wgs, min_stages, shape, tu.order));
             if ((int)st->host_plans.size() >= PLAN_CACHE_MAX) {
                 st->host_plans.erase(st->host_lru.back());
                 st->host_lru.pop_back();
@@ -725,12 +905,13 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
         sg.a.wg_off = reinterpret_cast<const int32_t *>(tbp->d + o_off);
         sg.grid = plan->grid;
         sg.dma = part.dma;
+        sg.waves = dma_waves(tu);
         sg.flags_and = part.flags_and;
         staged.push_back(sg);
     }
     for (Staged &sg : staged) {
         hipError_t e = hipMemcpyAsync(sg.tb->d, sg.tb->h, sg.bytes, hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess) e = launch(sg.a, sg.grid, sg.dma, sg.flags_and, stream);
+        if (e == hipSuccess) e = launch(sg.a, sg.grid, sg.dma, sg.waves, sg.flags_and, stream);
         if (e == hipSuccess) e = hipEventRecord(sg.tb->ev, stream);
         if (e != hipSuccess) return map_err(e);
         sg.tb->pending = true;
@@ -842,7 +1023,7 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_
     a.clock = ctx->st->clock.load();
     // held through the launch so that no other thread evicts the plan first
     std::lock_guard<std::mutex> lk(ctx->st->mu);
-    const Tuning tu = tuning_for(ctx->st, &pj, 1);
+    const Tuning tu = tuning_for(ctx->st, &pj, 1, (a.job0.flags & JOB_DMA) != 0);
     const bool dma = use_dma(a.job0.flags, tu);
     if (!dma && tu.kernel != XENG_KERNEL_GENERAL && ctx->n >= PAD_MIN_N)
         return correlate_padded(ctx, slot, d_samples, n_samples, row_stride, tu, stream);
@@ -850,7 +1031,7 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_
     if (rc != XENG_OK) return rc;
     a.pieces = dp.d_pieces;
     a.wg_off = dp.d_off;
-    hipError_t e = launch(a, dp.grid, dma, a.job0.flags, stream);
+    hipError_t e = launch(a, dp.grid, dma, dma_waves(tu), a.job0.flags, stream);
     if (e != hipSuccess) return map_err(e);
     ctx->acc_t[(size_t)slot] += n_samples;
     return map_err(publish_count(ctx, slot, stream));
@@ -894,7 +1075,7 @@ int xeng_correlate_flagged(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples
     const int last_len = (int)(n_samples - (nb - 1) * block_len);
     std::lock_guard<std::mutex> lk(ctx->st->mu);
     PlanJob pj{ctx->n, n_samples};
-    const Tuning tu = tuning_for(ctx->st, &pj, 1);
+    const Tuning tu = tuning_for(ctx->st, &pj, 1, true);   // masked rows are padded for the DMA kernel
     // the counts' bit masks first (scratch), so that a failure to get it
     // queues nothing
     hipMemPool_t pool = nullptr;
@@ -941,7 +1122,7 @@ int xeng_correlate_presum(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples,
     if (e != hipSuccess) return map_err(e);
     PlanJob pj{ctx->n, n_samples};
     DevicePlan dp;
-    const Tuning tu = tuning_for(ctx->st, &pj, 1);
+    const Tuning tu = tuning_for(ctx->st, &pj, 1, false);
     rc = get_plan(ctx->st, &pj, 1, TileShape::Square, tu, &dp, MAX_PIECE_STAGES_UNSIGNED);
     if (rc == XENG_OK) {
         KernelArgs a{};
@@ -1019,7 +1200,7 @@ int xeng_correlate_static(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples,
     a.clock = st->clock.load();
     a.pieces = pieces;
     a.wg_off = wg_off;
-    if ((e = launch(a, (int32_t)used, dma, a.job0.flags, stream)) != hipSuccess) return map_err(e);
+    if ((e = launch(a, (int32_t)used, dma, dma_waves(tu), a.job0.flags, stream)) != hipSuccess) return map_err(e);
     ctx->acc_t[(size_t)slot] += n_samples;
     return map_err(publish_count(ctx, slot, stream));
 }
@@ -1043,7 +1224,7 @@ int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
     rc = validate_jobs(jobs, n_jobs, 1, true, &jl);
     if (rc != XENG_OK || jl.descs.empty()) return rc;
     std::lock_guard<std::mutex> lk(jl.st->mu);
-    const Tuning tu = tuning_for(jl.st, jl.pj.data(), (int)jl.pj.size());
+    const Tuning tu = tuning_for(jl.st, jl.pj.data(), (int)jl.pj.size(), any_dma_job(jl));
     uint8_t *scratch = nullptr;
     rc = pad_batch_jobs(jl, tu, stream, &scratch);
     if (rc == XENG_OK) rc = run_parts(jl.st, split_by_kernel(jl, tu), tu, stream);
@@ -1219,7 +1400,7 @@ int64_t xeng_plan_inspect(const int32_t *n_inputs, const int64_t *n_samples, int
     }
     if (min_stages <= 0) min_stages = g_min_stages.load();
     const TileShape shape = wide ? TileShape::Wide : TileShape::Square;
-    Plan plan = build_plan(pj.data(), n_jobs, n_workgroups, min_stages, shape);
+    Plan plan = build_plan(pj.data(), n_jobs, n_workgroups, min_stages, shape, g_plan_order.load());
     const int64_t np = (int64_t)plan.pieces.size();
     for (int64_t k = 0; k < np && k < cap; ++k) {
         const Piece &p = plan.pieces[(size_t)k];
@@ -1337,14 +1518,14 @@ int xeng_batch_create(const xeng_job *jobs, int32_t n_jobs, xeng_batch **out)
     Tuning tu;
     {
         std::lock_guard<std::mutex> lk(jl.st->mu);
-        tu = tuning_for(jl.st, jl.pj.data(), (int)jl.pj.size());
+        tu = tuning_for(jl.st, jl.pj.data(), (int)jl.pj.size(), any_dma_job(jl));
     }
     for (const Part &part : split_by_kernel(jl, tu)) {
         const TileShape shape = part.dma ? TileShape::Wide : TileShape::Square;
         const int per_cu = part.dma ? 1 : std::max(1, tu.wgs_per_cu);
         const Plan plan = build_plan(part.pj.data(), (int)part.pj.size(), jl.st->cu_count * per_cu,
-                                     std::max(1, tu.min_stages), shape);
-        xeng_batch::Launch l{part.dma, part.flags_and, plan.grid, nullptr, nullptr, nullptr};
+                                     std::max(1, tu.min_stages), shape, tu.order);
+        xeng_batch::Launch l{part.dma, dma_waves(tu), part.flags_and, plan.grid, nullptr, nullptr, nullptr};
         b->launches.push_back(l);
         xeng_batch::Launch &lb = b->launches.back();
         const size_t nj = part.descs.size() * sizeof(JobDesc);
@@ -1410,7 +1591,7 @@ int xeng_batch_launch(xeng_batch *b, void *hip_stream)
         a.zeros = b->zeros;
         a.clock = bst ? bst->clock.load() : nullptr;
         a.skip = b->d_skip;
-        if ((e = launch(a, l.grid, l.dma, l.flags_and, stream)) != hipSuccess) return map_err(e);
+        if ((e = launch(a, l.grid, l.dma, l.waves, l.flags_and, stream)) != hipSuccess) return map_err(e);
     }
     return XENG_OK;
 }
@@ -1440,6 +1621,17 @@ int xeng_batch_destroy(xeng_batch *b)
     return XENG_OK;
 }
 
+static void fill_tuning(const Tuning &tu, xeng_tuning *out)
+{
+    out->kernel = tu.kernel;
+    out->wgs_per_cu = tu.wgs_per_cu;
+    out->min_stages = tu.min_stages;
+    out->plan_order = tu.order;
+    out->us_per_launch = tu.us;
+    out->source = tu.source;
+    out->saved = 0;
+}
+
 int xeng_autotune(const xeng_job *jobs, int32_t n_jobs, int32_t iters, void *hip_stream, xeng_tuning *best)
 {
     if (iters < 1 || iters > 1000) return XENG_EINVAL;
@@ -1450,26 +1642,37 @@ int xeng_autotune(const xeng_job *jobs, int32_t n_jobs, int32_t iters, void *hip
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     DeviceGuard guard(jl.device);
     if (!guard.ok) return XENG_EDEVICE;
+    if ((rc = refuse_capture(stream)) != XENG_OK) return rc;
 
-    bool any_dma = false;
-    for (const JobDesc &jd : jl.descs) any_dma = any_dma || (jd.flags & JOB_DMA);
-    std::vector<Tuning> cands;
-    for (int ms : {1, 4, 16, 64}) {
-        if (any_dma) cands.push_back(Tuning{XENG_KERNEL_AUTO, 2, ms});
-        for (int w : {1, 2}) cands.push_back(Tuning{XENG_KERNEL_GENERAL, w, ms});
+    // the trials accumulate into accumulators of the library's own (one per
+    // job, zeroed before every candidate), never into the callers' slots
+    int64_t scratch_i32 = 0;
+    std::vector<int64_t> off;
+    for (int32_t k : jl.idx) {
+        off.push_back(scratch_i32);
+        scratch_i32 += jobs[k].ctx->slot_i32;
     }
-    // the jobs' slots are scratch: zeroed before every candidate, so no
-    // accumulator wraps whatever the number of trial launches
-    auto zero_slots = [&]() -> hipError_t {
-        for (int32_t k : jl.idx) {
-            xeng_ctx *c = jobs[k].ctx;
-            hipError_t e = launch_zero(c->d_acc + (int64_t)jobs[k].slot * c->slot_i32, c->slot_i32, stream);
-            if (e != hipSuccess) return e;
+    int32_t *scratch = nullptr;
+    hipError_t e = hipMalloc(&scratch, (size_t)scratch_i32 * sizeof(int32_t));
+    if (e != hipSuccess) return map_err(e);
+    for (size_t k = 0; k < jl.descs.size(); ++k) {
+        jl.descs[k].acc = scratch + off[k];
+        jl.descs[k].flags &= ~JOB_FRESH;
+    }
+
+    const bool any_dma = any_dma_job(jl);
+    const bool single = jl.descs.size() == 1;
+    std::vector<Tuning> cands;
+    for (int ms : {1, 4, 16, 64})
+        for (int order : {XENG_PLAN_XCD, XENG_PLAN_LINEAR}) {
+            if (!single && order == XENG_PLAN_XCD) continue;   // batches always take the linear order
+            if (any_dma)
+                for (int kern : {XENG_KERNEL_AUTO, XENG_KERNEL_DMA4})
+                    cands.push_back(Tuning{kern, 2, ms, order, XENG_TUNE_MEASURED, 0.0});
+            for (int w : {1, 2}) cands.push_back(Tuning{XENG_KERNEL_GENERAL, w, ms, order, XENG_TUNE_MEASURED, 0.0});
         }
-        return hipSuccess;
-    };
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipEventCreate(&e0);
+    e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     Tuning best_t = cands[0];
     float best_us = -1.0f;
@@ -1477,7 +1680,7 @@ int xeng_autotune(const xeng_job *jobs, int32_t n_jobs, int32_t iters, void *hip
     for (const Tuning &tu : cands) {
         if (e != hipSuccess) break;
         const std::vector<Part> parts = split_by_kernel(jl, tu);
-        if ((e = zero_slots()) != hipSuccess) break;
+        if ((e = launch_zero(scratch, scratch_i32, stream)) != hipSuccess) break;
         if ((rc = run_parts(jl.st, parts, tu, stream)) != XENG_OK) break;   // warm-up, plan upload
         if ((e = hipEventRecord(e0, stream)) != hipSuccess) break;
         for (int it = 0; it < iters && rc == XENG_OK; ++it) rc = run_parts(jl.st, parts, tu, stream);
@@ -1491,22 +1694,54 @@ int xeng_autotune(const xeng_job *jobs, int32_t n_jobs, int32_t iters, void *hip
             best_t = tu;
         }
     }
-    if (e == hipSuccess && rc == XENG_OK) e = zero_slots();
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    // the trial launches read the job table ring and the scratch: wait for
+    // them before freeing it
+    const hipError_t es = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = es;
+    (void)hipFree(scratch);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (rc != XENG_OK) return rc;
     if (e != hipSuccess) return map_err(e);
-    for (int32_t k : jl.idx) jobs[k].ctx->acc_t[(size_t)jobs[k].slot] = 0;
-    jl.st->tuned[sizes_key(jl.pj.data(), (int)jl.pj.size())] = best_t;
+    best_t.us = best_us;
+    const TuneClass cls = tune_class(jl.pj.data(), (int)jl.pj.size(), any_dma);
+    jl.st->tuned[cls.key()] = DeviceState::Tuned{cls, best_t};
+    const bool saved = save_tune_cache(jl.st);
     if (best) {
-        best->kernel = best_t.kernel;
-        best->wgs_per_cu = best_t.wgs_per_cu;
-        best->min_stages = best_t.min_stages;
-        best->reserved = 0;
-        best->us_per_launch = best_us;
+        fill_tuning(best_t, best);
+        best->saved = saved ? 1 : 0;
     }
     return XENG_OK;
+}
+
+int xeng_tuning_lookup(const xeng_job *jobs, int32_t n_jobs, xeng_tuning *out)
+{
+    if (!out) return XENG_EINVAL;
+    JobList jl;
+    int rc = validate_jobs(jobs, n_jobs, 0, false, &jl);
+    if (rc != XENG_OK) return rc;
+    Tuning tu = global_tuning();
+    if (!jl.descs.empty()) {
+        std::lock_guard<std::mutex> lk(jl.st->mu);
+        tu = tuning_for(jl.st, jl.pj.data(), (int)jl.pj.size(), any_dma_job(jl));
+    }
+    fill_tuning(tu, out);
+    return XENG_OK;
+}
+
+int32_t xeng_tune_cache_path(int32_t device, char *buf, int32_t len)
+{
+    if (device < 0 || len < 0 || (len > 0 && !buf)) return XENG_EINVAL;
+    int n_dev = 0;
+    if (hipGetDeviceCount(&n_dev) != hipSuccess || device >= n_dev) return XENG_EDEVICE;
+    const std::string path = tune_cache_path(arch_name(device));
+    if (path.empty()) return XENG_ENOTSUP;
+    if (len > 0) {
+        const size_t n = std::min(path.size(), (size_t)len - 1);
+        std::memcpy(buf, path.data(), n);
+        buf[n] = '\0';
+    }
+    return (int32_t)path.size();
 }
 
 int xeng_clock_probe(int32_t device, int64_t *dev_buf)
@@ -1522,7 +1757,7 @@ int xeng_clock_probe(int32_t device, int64_t *dev_buf)
 
 int xeng_set_tuning(int32_t wgs_per_cu, int32_t min_stages, int32_t kernel)
 {
-    if (wgs_per_cu > 2 || kernel > XENG_KERNEL_GENERAL) return XENG_EINVAL;
+    if (wgs_per_cu > 2 || kernel > XENG_KERNEL_DMA4) return XENG_EINVAL;
     if (wgs_per_cu > 0) g_wgs_per_cu.store(wgs_per_cu);
     if (min_stages > 0) g_min_stages.store(min_stages);
     if (kernel >= 0) g_kernel.store(kernel);

@@ -661,25 +661,29 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
 
 constexpr int DMA_LDS_BYTES = dma::NSLOT * dma::SLOT;
 
-// Waves per workgroup of the launched instance (4 or 8).
-#ifndef XENG_DMA_WAVES
-#define XENG_DMA_WAVES 8
-#endif
-static_assert(XENG_DMA_WAVES == 4 || XENG_DMA_WAVES == 8, "4 or 8 waves");
-
+// Both instances are built: eight waves (two per SIMD, so one wave's
+// unpack overlaps the other's matrix work) and four (one per SIMD, four
+// column blocks each, fewer transposed reads per multiply).  The launch
+// configuration picks one per call.
+//
 // Once per device, before any launch (and outside any stream capture): the
 // kernel's LDS ring exceeds the default dynamic-LDS limit.
 hipError_t init_dma_kernel()
 {
-    return hipFuncSetAttribute((const void *)dma::xcorr_dma<XENG_DMA_WAVES>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, DMA_LDS_BYTES);
+    hipError_t e = hipFuncSetAttribute((const void *)dma::xcorr_dma<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       DMA_LDS_BYTES);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)dma::xcorr_dma<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               DMA_LDS_BYTES);
 }
 
-hipError_t launch_correlate_dma(const KernelArgs &a, int grid, hipStream_t stream)
+hipError_t launch_correlate_dma(const KernelArgs &a, int grid, int waves, hipStream_t stream)
 {
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(dma::xcorr_dma<XENG_DMA_WAVES>, dim3(grid), dim3(64 * XENG_DMA_WAVES), DMA_LDS_BYTES,
-                       stream, a);
+    if (waves == 4)
+        hipLaunchKernelGGL(dma::xcorr_dma<4>, dim3(grid), dim3(64 * 4), DMA_LDS_BYTES, stream, a);
+    else
+        hipLaunchKernelGGL(dma::xcorr_dma<8>, dim3(grid), dim3(64 * 8), DMA_LDS_BYTES, stream, a);
     return hipGetLastError();
 }
 

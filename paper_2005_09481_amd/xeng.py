@@ -28,6 +28,10 @@ XENG_BEAMS_MAX = 16
 XENG_SERVER_STAGGER_EXPORTS = 2
 XENG_KERNEL_AUTO = 0
 XENG_KERNEL_GENERAL = 1
+XENG_KERNEL_DMA4 = 2
+XENG_TUNE_SETTINGS = 0
+XENG_TUNE_MEASURED = 1
+XENG_TUNE_CACHE_FILE = 2
 XENG_PLAN_LINEAR = 0
 XENG_PLAN_XCD = 1
 
@@ -62,8 +66,9 @@ class _DumpJob(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
-                ("min_stages", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("us_per_launch", ctypes.c_double)]
+                ("min_stages", ctypes.c_int32), ("plan_order", ctypes.c_int32),
+                ("us_per_launch", ctypes.c_double), ("source", ctypes.c_int32),
+                ("saved", ctypes.c_int32)]
 
 
 class _ServerConfig(ctypes.Structure):
@@ -144,6 +149,8 @@ def lib() -> ctypes.CDLL:
         "xeng_server_export_ring": (ctypes.c_int, [vp, i32, vp, i32]),
         "xeng_batch_destroy": (ctypes.c_int, [vp]),
         "xeng_autotune": (ctypes.c_int, [ctypes.POINTER(_Job), i32, i32, vp, ctypes.POINTER(_Tuning)]),
+        "xeng_tuning_lookup": (ctypes.c_int, [ctypes.POINTER(_Job), i32, ctypes.POINTER(_Tuning)]),
+        "xeng_tune_cache_path": (i32, [i32, ctypes.c_char_p, i32]),
         "xeng_server_create": (ctypes.c_int, [ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]),
         "xeng_server_destroy": (ctypes.c_int, [vp]),
         "xeng_server_max_channels": (i32, [vp]),
@@ -185,7 +192,8 @@ def slot_bytes(n_inputs: int) -> int:
 def set_tuning(wgs_per_cu: int = 0, min_stages: int = 0, kernel: int = -1):
     """Launch tuning (results never depend on it): general-kernel workgroups
     per CU, minimum piece length in 64-sample stages, kernel selection
-    (XENG_KERNEL_AUTO / XENG_KERNEL_GENERAL; -1 keeps the current one)."""
+    (XENG_KERNEL_AUTO / XENG_KERNEL_GENERAL / XENG_KERNEL_DMA4; -1 keeps the
+    current one)."""
     _check(lib().xeng_set_tuning(wgs_per_cu, min_stages, kernel), "xeng_set_tuning")
 
 
@@ -416,17 +424,42 @@ class Tuning:
     kernel: int
     wgs_per_cu: int
     min_stages: int
+    plan_order: int
     us_per_launch: float
+    source: int
+    saved: bool
+
+
+def _tuning(t) -> Tuning:
+    return Tuning(t.kernel, t.wgs_per_cu, t.min_stages, t.plan_order, t.us_per_launch, t.source, bool(t.saved))
 
 
 def autotune(jobs, iters: int = 5, stream=None) -> Tuning:
-    """Time the candidate launch configurations on ``jobs`` and keep the best
-    for later calls of the same job sizes.  The jobs' slots are zeroed."""
+    """Time the candidate launch configurations on ``jobs`` (on scratch
+    accumulators: the jobs' slots are untouched), keep the best for later
+    calls of the same job class and write it to the tune-cache file."""
     t = _Tuning()
     _check(lib().xeng_autotune(_job_array(jobs), len(jobs), iters,
                                _stream_handle(stream, jobs[0][0].device), ctypes.byref(t)),
            "xeng_autotune")
-    return Tuning(t.kernel, t.wgs_per_cu, t.min_stages, t.us_per_launch)
+    return _tuning(t)
+
+
+def tuning_lookup(jobs) -> Tuning:
+    """The configuration a batched call of ``jobs`` would launch with now."""
+    t = _Tuning()
+    _check(lib().xeng_tuning_lookup(_job_array(jobs), len(jobs), ctypes.byref(t)), "xeng_tuning_lookup")
+    return _tuning(t)
+
+
+def tune_cache_path(device: int = 0) -> str:
+    """Path of the tune-cache file of ``device``'s architecture."""
+    n = int(lib().xeng_tune_cache_path(device, None, 0))
+    if n < 0:
+        _check(n, "xeng_tune_cache_path")
+    buf = ctypes.create_string_buffer(n + 1)
+    _check(min(0, int(lib().xeng_tune_cache_path(device, buf, n + 1))), "xeng_tune_cache_path")
+    return buf.value.decode()
 
 
 def rfi_flags(samples, n_inputs: int | None = None, block_len: int = 256, lo_num: int = 625,

@@ -183,13 +183,20 @@ def test_dump_to_pinned_host(X):
     np.testing.assert_array_equal(host.numpy(), oracle.correlate(x))
 
 
+def kernel_id(X, name):
+    """auto: the eight-wave DMA kernel where the job allows it; dma4: its
+    four-wave instance; general: the 128 x 128 kernel."""
+    return {"auto": X.XENG_KERNEL_AUTO, "general": X.XENG_KERNEL_GENERAL, "dma4": X.XENG_KERNEL_DMA4}[name]
+
+
 def test_tuning_does_not_change_results(X):
     x = synth.uniform_bytes(512, 2000, seed=22)
     outs = []
     try:
         for wpc, ms, kern in ((2, 4, X.XENG_KERNEL_AUTO), (1, 1, X.XENG_KERNEL_GENERAL),
                               (2, 1, X.XENG_KERNEL_GENERAL), (1, 64, X.XENG_KERNEL_AUTO),
-                              (2, 1, X.XENG_KERNEL_AUTO)):
+                              (2, 1, X.XENG_KERNEL_AUTO), (2, 4, X.XENG_KERNEL_DMA4),
+                              (2, 1, X.XENG_KERNEL_DMA4)):
             X.set_tuning(wpc, ms, kern)
             outs.append(run(X, x))
     finally:
@@ -207,32 +214,32 @@ def test_tuning_does_not_change_results(X):
 @pytest.mark.parametrize("n,t", [(256, 1), (256, 63), (256, 64), (256, 65), (512, 1000),
                                  (768, 4097), (1024, 333), (16, 1), (48, 65), (144, 300),
                                  (272, 129), (400, 1000), (1008, 333), (1904, 64), (2000, 200)])
-@pytest.mark.parametrize("kernel", ["auto", "general"])
+@pytest.mark.parametrize("kernel", ["auto", "general", "dma4"])
 def test_both_kernels_match_oracle(X, n, t, kernel):
     print(f"kernel={kernel} n={n} t={t}", flush=True)
     x = synth.uniform_bytes(n, t, seed=3000 + n + t)
     try:
-        X.set_tuning(0, 0, X.XENG_KERNEL_GENERAL if kernel == "general" else X.XENG_KERNEL_AUTO)
+        X.set_tuning(0, 0, kernel_id(X, kernel))
         got = run(X, x)
     finally:
         X.set_tuning(0, 0, X.XENG_KERNEL_AUTO)
     np.testing.assert_array_equal(got, oracle.correlate(x))
 
 
-@pytest.mark.parametrize("kernel", ["auto", "general"])
+@pytest.mark.parametrize("kernel", ["auto", "general", "dma4"])
 def test_both_kernels_re_low(X, kernel):
     n, t = 512, 1000
     print(f"re_low kernel={kernel} n={n} t={t}", flush=True)
     x = synth.uniform_bytes(n, t, seed=77)
     try:
-        X.set_tuning(0, 0, X.XENG_KERNEL_GENERAL if kernel == "general" else X.XENG_KERNEL_AUTO)
+        X.set_tuning(0, 0, kernel_id(X, kernel))
         got = run(X, x, re_low=True)
     finally:
         X.set_tuning(0, 0, X.XENG_KERNEL_AUTO)
     np.testing.assert_array_equal(got, oracle.correlate(x, re_low=True))
 
 
-@pytest.mark.parametrize("kernel", ["auto", "general"])
+@pytest.mark.parametrize("kernel", ["auto", "general", "dma4"])
 def test_pieces_split_past_register_bound(X, kernel):
     # T beyond 2^16 samples: the DMA kernel's plan cuts every tile into
     # several pieces (atomic flushes); extreme samples maximise the sums
@@ -241,7 +248,7 @@ def test_pieces_split_past_register_bound(X, kernel):
     rng = np.random.default_rng(5)
     x = rng.choice(np.array([0x00, 0x0F, 0xF0, 0xFF, 0x80, 0x08], dtype=np.uint8), size=(t, n))
     try:
-        X.set_tuning(1, 1 << 20, X.XENG_KERNEL_GENERAL if kernel == "general" else X.XENG_KERNEL_AUTO)
+        X.set_tuning(1, 1 << 20, kernel_id(X, kernel))
         got = run(X, x)
     finally:
         X.set_tuning(2, 4, X.XENG_KERNEL_AUTO)     # the library's defaults
