@@ -486,7 +486,8 @@ int32_t xeng_tune_cache_path(int32_t device, char *buf, int32_t len);
  * Streaming server (Sec. 2.1: every channel delivers a sample every 2.56 us
  * and its integrated visibilities are exported at a chosen cadence).
  * Channels of N inputs ingest frames of frame_len samples every
- * frame_period_us; the server keeps their accumulators on the device,
+ * frame_period_us; the server keeps their accumulators on the device
+ * (admitting channels as slots and device memory allow),
  * correlates every channel's newly arrived frames in one batched launch
  * about every launch_period_us (continuous batching: frames that arrive
  * while launches run join the next one), and exports each channel every
@@ -511,10 +512,10 @@ typedef struct {
     int32_t dump_frames;      /* frames per export; frame_len * dump_frames <= xeng_max_integration() */
     int32_t ring_frames;      /* device ring of a host-sourced channel, in frames */
     int32_t max_inflight;     /* batched launches queued on the device at once, >= 1 */
-    int32_t max_channels;     /* slots; 0 = as many as mem_budget_bytes admits */
+    int32_t max_channels;     /* slots; 0 = as many as mem_budget_bytes holds */
     double frame_period_us;   /* frame cadence per channel (256 samples at 390625/s: 655.36) */
     double launch_period_us;  /* batching period */
-    int64_t mem_budget_bytes; /* device bytes for channels (0 = none): admission by memory */
+    int64_t mem_budget_bytes; /* most device bytes for slots and rings (0 = no budget) */
     int32_t reserved;         /* must be 0 */
 } xeng_server_config;
 
@@ -525,6 +526,8 @@ typedef struct {
     int64_t launches;
     int64_t dumps;
     int64_t backlog_frames;   /* released, not dropped, not yet integrated at the end */
+    int64_t channels_waiting; /* admitted channels still waiting for a slot or memory at the end */
+    int64_t device_bytes;     /* device memory the server holds for slots and rings */
     double seconds;           /* wall time of the run */
     double tcmacs;            /* integrated CMAC / wall time, 1e12/s */
     double p50_ms, p99_ms, max_ms;   /* frame latency: release -> its launch completed */
@@ -536,12 +539,21 @@ typedef struct {
     int64_t frames_done;
     int64_t dumps;
     int64_t last_dump_first_frame;   /* first frame of the last export, -1 if none */
+    double admitted_s;        /* when it took its slot, seconds into the run; -1 if it has not */
 } xeng_server_channel;
 
-/* Create a server; XENG_ENOMEM if not even one channel fits the budget. */
+/*
+ * Create a server; XENG_ENOMEM if not even one slot fits the budget.  No
+ * device memory for channels is allocated here: a slot's accumulators and
+ * export buffer (xeng_slot_bytes(N) + N(N+1)/2 * 8 bytes) are allocated
+ * when a channel first takes it, a host source's ring (ring_frames *
+ * frame_len * N bytes) when no finished host source left one; both stay
+ * with the server for later channels and are freed by xeng_server_destroy.
+ */
 int xeng_server_create(const xeng_server_config *cfg, xeng_server **out);
 int xeng_server_destroy(xeng_server *s);
-/* Slots of the server (channels streaming at once). */
+/* Slots of the server: the most channels streaming at once (max_channels,
+ * capped by how many slots mem_budget_bytes holds). */
 int32_t xeng_server_max_channels(const xeng_server *s);
 /*
  * Admit a channel.  Its frames come from `frames`, [n_frames][frame_len][N]
@@ -549,8 +561,14 @@ int32_t xeng_server_max_channels(const xeng_server *s);
  * (host_frames = 1) pinned host memory copied into the channel's device
  * ring on release.  Caller-owned; must outlive the server.  Frame 0 is
  * released start_s seconds into the next run; total_frames frames (0 =
- * unlimited) are streamed.  With every slot in use the channel waits and
- * takes the first slot freed by a finished channel (its stream then starts).
+ * unlimited) are streamed.  The channel waits for admission, which the
+ * run loop grants in order of arrival (no channel overtakes one that
+ * waits): it needs a free slot and the device memory it lacks (the slot's
+ * own at its first use, a ring for a host source unless a finished one left
+ * one) within mem_budget_bytes and within the device's free memory at that
+ * moment, less a 512 MiB reserve.  A slot freed by a finished channel keeps
+ * its memory, so the next channel takes it at once.  Its stream starts
+ * when it is admitted (frame 0 no earlier than start_s).
  */
 int xeng_server_admit(xeng_server *s, const uint8_t *frames, int64_t n_frames, int32_t host_frames,
                       double start_s, int64_t total_frames, int32_t *channel);

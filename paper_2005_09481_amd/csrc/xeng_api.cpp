@@ -921,9 +921,13 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
 
 }  // namespace
 
-extern "C" {
+namespace xeng {
 
-int xeng_create(const xeng_config *cfg, xeng_ctx **out)
+// A context (see xeng_create).  With `stream` null its memory is zeroed and
+// the device synchronized before it returns; otherwise the zeroing is queued
+// on `stream` and nothing waits, so every use of the context must be
+// ordered after it on that stream (the streaming server's slots).
+int create_ctx(const xeng_config *cfg, hipStream_t stream, xeng_ctx **out)
 {
     if (!cfg || !out) return XENG_EINVAL;
     *out = nullptr;
@@ -964,16 +968,22 @@ int xeng_create(const xeng_config *cfg, xeng_ctx **out)
         delete c;
         return map_err(e);
     }
-    if ((e = hipMalloc(&c->d_count, (size_t)cfg->n_slots * sizeof(int64_t))) != hipSuccess) {
+    // counters padded to a multiple of 16 bytes (the zero kernel's unit)
+    const int64_t n_count = ((int64_t)cfg->n_slots + 1) / 2 * 2;
+    if ((e = hipMalloc(&c->d_count, (size_t)n_count * sizeof(int64_t))) != hipSuccess) {
         (void)hipFree(c->d_acc);
         delete c;
         return map_err(e);
     }
     c->d_diag = c->d_acc + (int64_t)cfg->n_slots * c->slot_i32;
     if (count_i32) c->d_counts = c->d_diag + (int64_t)cfg->n_slots * diag_i32(cfg->n_inputs);
-    e = launch_zero(c->d_acc, bytes / 4, nullptr);
-    if (e == hipSuccess) e = hipMemset(c->d_count, 0, (size_t)cfg->n_slots * sizeof(int64_t));
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    e = launch_zero(c->d_acc, bytes / 4, stream);
+    if (stream) {
+        if (e == hipSuccess) e = launch_zero(reinterpret_cast<int32_t *>(c->d_count), 2 * n_count, stream);
+    } else {
+        if (e == hipSuccess) e = hipMemset(c->d_count, 0, (size_t)cfg->n_slots * sizeof(int64_t));
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+    }
     if (e != hipSuccess) {
         (void)hipFree(c->d_acc);
         (void)hipFree(c->d_count);
@@ -983,6 +993,12 @@ int xeng_create(const xeng_config *cfg, xeng_ctx **out)
     *out = c;
     return XENG_OK;
 }
+
+}  // namespace xeng
+
+extern "C" {
+
+int xeng_create(const xeng_config *cfg, xeng_ctx **out) { return create_ctx(cfg, nullptr, out); }
 
 int xeng_destroy(xeng_ctx *ctx)
 {

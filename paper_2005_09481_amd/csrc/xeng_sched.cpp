@@ -29,22 +29,13 @@ Scheduler::Scheduler(const Config &cfg) : cfg_(cfg)
 {
     for (int32_t k = cfg_.slots - 1; k >= 0; --k) free_slots_.push_back(k);
     slot_owner_.assign((size_t)cfg_.slots, -1);
+    slot_mem_.assign((size_t)cfg_.slots, 0);
 }
 
 int64_t Scheduler::export_phase(int32_t slot) const
 {
     if (!cfg_.stagger_exports) return 0;
     return (int64_t)slot * cfg_.dump_frames / (int64_t)cfg_.slots;
-}
-
-void Scheduler::take_slot(int32_t chan)
-{
-    Chan &c = chans_[(size_t)chan];
-    c.slot = free_slots_.back();
-    free_slots_.pop_back();
-    c.state = 1;
-    c.phase = export_phase(c.slot);
-    slot_owner_[(size_t)c.slot] = chan;
 }
 
 int32_t Scheduler::admit(int64_t src_frames, bool host, double start_s, int64_t total_frames)
@@ -55,9 +46,64 @@ int32_t Scheduler::admit(int64_t src_frames, bool host, double start_s, int64_t 
     c.start_s = start_s;
     c.total_frames = total_frames;
     chans_.push_back(c);
-    const int32_t k = (int32_t)chans_.size() - 1;
-    if (!free_slots_.empty()) take_slot(k);
-    return k;
+    return (int32_t)chans_.size() - 1;
+}
+
+// Admits at most one waiting channel (in the loop, an admission may
+// allocate, and the channels already streaming are served between
+// admissions).  Before the run's clock starts, the admission time is set
+// once it has started.
+int Scheduler::admit_waiting(Executor &ex, double t, bool before_start, bool *admitted_out)
+{
+    bool admitted = false;
+    *admitted_out = false;
+    for (; next_waiting_ < chans_.size() && !admitted; ++next_waiting_) {
+        Chan &c = chans_[next_waiting_];
+        if (c.state != 0) continue;
+        if (free_slots_.empty()) return XENG_OK;
+        // a free slot whose memory exists, else the most recently freed one
+        size_t pick = free_slots_.size() - 1;
+        for (size_t k = free_slots_.size(); k-- > 0;)
+            if (slot_mem_[(size_t)free_slots_[k]]) {
+                pick = k;
+                break;
+            }
+        const int32_t slot = free_slots_[pick];
+        const bool new_slot = !slot_mem_[(size_t)slot];
+        const bool new_ring = c.host && rings_free_ == 0;
+        const int64_t need = (new_slot ? cfg_.slot_bytes : 0) + (new_ring ? cfg_.ring_bytes : 0);
+        if (need > 0) {
+            if (cfg_.mem_budget > 0 && bytes_held() + need > cfg_.mem_budget) return XENG_OK;
+            if (need > ex.free_bytes() - cfg_.mem_reserve) return XENG_OK;
+        }
+        const int rc = ex.attach(c, (int32_t)next_waiting_, slot, new_slot, new_ring);
+        if (rc == XENG_ENOMEM) return XENG_OK;   // the device had less than it said: wait
+        if (rc != XENG_OK) return rc;
+        if (new_slot) {
+            slot_mem_[(size_t)slot] = 1;
+            ++slots_with_mem_;
+        }
+        if (new_ring) {
+            ++rings_held_;
+            ++rings_free_;
+        }
+        if (c.host) --rings_free_;
+        free_slots_.erase(free_slots_.begin() + (std::ptrdiff_t)pick);
+        c.slot = slot;
+        c.state = 1;
+        c.phase = export_phase(slot);
+        // its stream starts once admitted (and its memory is ready: taken
+        // after attach, which may have allocated)
+        if (!before_start) {
+            const double ta = std::max(t, ex.now());
+            c.admitted_s = ta;
+            if (c.start_s < ta) c.start_s = ta;
+        }
+        slot_owner_[(size_t)slot] = (int32_t)next_waiting_;
+        admitted = true;
+        *admitted_out = true;
+    }
+    return XENG_OK;
 }
 
 int Scheduler::run(Executor &ex, double seconds, Stats *stats)
@@ -86,11 +132,13 @@ int Scheduler::run(Executor &ex, double seconds, Stats *stats)
                 c.done = r.f1;
                 if (c.state == 1 && c.total_frames > 0 && c.done >= c.total_frames) {
                     // finished: zero what it integrated past its last export
-                    // (queued behind that export) and free the slot
+                    // (queued behind that export), free the slot and keep
+                    // the ring
                     c.state = 2;
-                    const int e = ex.reset(c.slot);
+                    const int e = ex.detach(c, r.chan, c.slot);
                     if (e != XENG_OK) return e;
                     free_slots_.push_back(c.slot);
+                    if (c.host) ++rings_free_;
                 }
             }
             ex.release(f.token);
@@ -99,17 +147,22 @@ int Scheduler::run(Executor &ex, double seconds, Stats *stats)
         return XENG_OK;
     };
 
+    // every channel that fits now is admitted before the clock starts
+    for (bool more = true; more && rc == XENG_OK;) rc = admit_waiting(ex, 0.0, true, &more);
+    ex.start();
+    const double t_start = ex.now();
+    for (Chan &c : chans_)
+        if (c.state == 1 && c.admitted_s < 0) {
+            c.admitted_s = t_start;
+            if (c.start_s < t_start) c.start_s = t_start;
+        }
+
     while (rc == XENG_OK) {
         const double t = ex.now();
         if (t >= seconds) break;
-        // admissions into freed slots
-        for (size_t k = 0; k < chans_.size(); ++k) {
-            Chan &c = chans_[k];
-            if (c.state == 0 && !free_slots_.empty()) {
-                take_slot((int32_t)k);
-                if (c.start_s < t) c.start_s = t;   // its stream starts once admitted
-            }
-        }
+        // admissions into free slots, by memory
+        bool admitted = false;
+        if ((rc = admit_waiting(ex, t, false, &admitted)) != XENG_OK) break;
         // releases (and ingest copies for host sources)
         for (size_t k = 0; k < chans_.size() && rc == XENG_OK; ++k) {
             Chan &c = chans_[k];
@@ -213,6 +266,8 @@ int Scheduler::run(Executor &ex, double seconds, Stats *stats)
         stats->max_ms = lat.back();
     }
     stats->backlog_frames = released - frames_done - dropped;
+    for (const Chan &c : chans_) stats->waiting += c.state == 0 ? 1 : 0;
+    stats->device_bytes = bytes_held();
     return rc;
 }
 

@@ -12,8 +12,13 @@
 //     exported (with reset) right after that launch; boundaries every
 //     dump_frames frames, offset by slot * dump_frames / slots when exports
 //     are staggered;
-//   * admission: a channel waits for a slot and takes the first one freed by
-//     a finished channel;
+//   * admission by memory: waiting channels, in order of arrival, take a
+//     free slot once the device memory they need is there -- the slot's
+//     accumulators and export buffer at its first use, a ring for a host
+//     source unless a finished channel left one -- within the server's
+//     budget and within the device's free memory at that moment (less a
+//     reserve); a slot's memory and a finished channel's ring stay with the
+//     server for the next channel;
 //   * latency of a frame: from its release time to the completion of the
 //     launch that integrated it.
 // It makes no device call.  An Executor carries out copies, launches,
@@ -40,11 +45,16 @@ struct Config {
     double launch_period_us = 0;
     bool stagger_exports = false;
     double pairs = 0;           // N(N+1)/2, for the CMAC rate
+    int64_t slot_bytes = 0;     // device bytes a slot takes at its first use
+    int64_t ring_bytes = 0;     // device bytes of a host source's ring
+    int64_t mem_budget = 0;     // most device bytes the server may hold (0: no budget)
+    int64_t mem_reserve = 0;    // device bytes admission leaves free
 };
 
 struct Chan {
     int state = 0;                 // 0 waiting for a slot, 1 active, 2 finished
     int32_t slot = -1;
+    double admitted_s = -1;        // when it took its slot (seconds into the run)
     bool host = false;             // frames copied from host memory into a device ring
     int64_t src_frames = 0;        // distinct source frames, cycled
     double start_s = 0;            // release time of frame 0 (seconds into the run)
@@ -71,6 +81,8 @@ struct Job {
 struct Stats {
     int64_t frames_released = 0, frames_done = 0, frames_dropped = 0;
     int64_t launches = 0, dumps = 0, backlog_frames = 0;
+    int64_t waiting = 0;           // channels still waiting for a slot or memory at the end
+    int64_t device_bytes = 0;      // device memory the server holds for slots and rings
     double seconds = 0, tcmacs = 0, p50_ms = 0, p99_ms = 0, max_ms = 0;
 };
 
@@ -78,16 +90,26 @@ struct Stats {
 class Executor {
 public:
     virtual ~Executor() = default;
-    // seconds since the run began
+    // seconds since the run began (since start())
     virtual double now() = 0;
+    // the run's clock starts: called once per run, after the channels that
+    // could be admitted before it were (their allocations stall no stream)
+    virtual void start() = 0;
     // host source: start copying frame `frame` of channel `chan` into its
     // ring slot frame % ring_frames; `token` names the copy's completion
     virtual int copy(const Chan &c, int32_t chan, int64_t frame, int64_t *token) = 0;
     // one batched launch over `jobs` (possibly none), then the exports, in
     // order after everything queued before; `token` names its completion
     virtual int launch(const std::vector<Job> &jobs, const std::vector<Job> &exports, int64_t *token) = 0;
-    // zero a slot, in order after everything queued before
-    virtual int reset(int32_t slot) = 0;
+    // device bytes free right now
+    virtual int64_t free_bytes() = 0;
+    // channel `chan` enters `slot`: allocate the slot's memory if `new_slot`
+    // and one more ring if `new_ring`, and give a host source a ring.
+    // XENG_ENOMEM, with nothing allocated, leaves the channel waiting.
+    virtual int attach(const Chan &c, int32_t chan, int32_t slot, bool new_slot, bool new_ring) = 0;
+    // channel `chan` finished: zero its slot, in order after everything
+    // queued before, and keep its ring (if any) for the next host source
+    virtual int detach(const Chan &c, int32_t chan, int32_t slot) = 0;
     // 1 complete, 0 not yet; `wait` blocks until complete
     virtual int poll(int64_t token, bool wait) = 0;
     // the token will not be polled again
@@ -99,7 +121,8 @@ public:
 class Scheduler {
 public:
     explicit Scheduler(const Config &cfg);
-    // a new channel; it takes a free slot at once if there is one
+    // a new channel; it waits for admission (at the start of the next run,
+    // or later if no slot or memory is free)
     int32_t admit(int64_t src_frames, bool host, double start_s, int64_t total_frames);
     // the real-time loop for `seconds`, then wait for what is queued
     int run(Executor &ex, double seconds, Stats *stats);
@@ -111,12 +134,18 @@ public:
 private:
     double release_time(const Chan &c, int64_t f) const { return c.start_s + (double)f * cfg_.frame_period_us * 1e-6; }
     int64_t export_phase(int32_t slot) const;
-    void take_slot(int32_t chan);
+    int admit_waiting(Executor &ex, double t, bool before_start, bool *admitted);
+    int64_t bytes_held() const { return slots_with_mem_ * cfg_.slot_bytes + rings_held_ * cfg_.ring_bytes; }
 
     Config cfg_;
     std::vector<Chan> chans_;
     std::vector<int32_t> free_slots_;
     std::vector<int32_t> slot_owner_;   // channel using each slot, -1 if none
+    std::vector<char> slot_mem_;        // slots whose memory exists
+    int64_t slots_with_mem_ = 0;
+    int64_t rings_held_ = 0;            // rings allocated
+    int64_t rings_free_ = 0;            // rings left by finished channels
+    size_t next_waiting_ = 0;           // no channel before it waits
 };
 
 }  // namespace sched

@@ -6,8 +6,11 @@
 // xeng_server_run drives the real-time loop of the scheduling core
 // (xeng_sched.h: releases, ingest, continuous batching, export boundaries,
 // admission, latency) on the calling thread.  This file is its executor on
-// one device: per-channel device rings for host sources and copy streams
-// for their frames (channel k on stream k % COPY_STREAMS, so one channel's
+// one device: the device memory of slots (accumulators and export buffer,
+// allocated when a channel first takes the slot and kept for later
+// channels) and of host sources' rings (kept for the next host source), the
+// free device memory that admission weighs them against, copy streams for
+// host frames (channel k on stream k % COPY_STREAMS, so one channel's
 // copies complete in order while several DMA engines share the ingest), one
 // compute stream for the batched correlation launches
 // (xeng_correlate_batch), the exports due after each (xeng_dump_batch, into
@@ -17,12 +20,17 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstring>
 #include <new>
 #include <thread>
 #include <vector>
 
 #include "../../include/xeng.h"
 #include "xeng_sched.h"
+
+namespace xeng {
+int create_ctx(const xeng_config *cfg, hipStream_t stream, xeng_ctx **out);
+}
 
 namespace {
 
@@ -31,6 +39,10 @@ using Clock = std::chrono::steady_clock;
 // Measured with 256-sample frames of N=2048 (512 KiB copies): one stream
 // sustained 24 host-sourced channels, four 40, eight fewer than four.
 constexpr int COPY_STREAMS = 4;
+
+// Device memory admission leaves free (for the library's plans and staging
+// and for other users of the device).
+constexpr int64_t MEM_RESERVE = INT64_C(512) << 20;
 
 // A roctx range over a scope: the server's phases show up in a
 // rocprofv3 --marker-trace beside the kernels they queue.
@@ -44,7 +56,7 @@ struct Range {
 // Device-side state of a channel (its scheduling state lives in the core).
 struct ChanMem {
     const uint8_t *src = nullptr;  // [src_frames][frame_len][N], device or pinned host
-    uint8_t *ring = nullptr;       // device ring of a host source
+    uint8_t *ring = nullptr;       // device ring of a host source (while it streams)
     int32_t *exports = nullptr;    // caller's export ring ([n_exports][N(N+1)/2][2]) or null
     int32_t n_exports = 0;
     int64_t issued = 0;            // exports queued into the caller's ring
@@ -55,9 +67,11 @@ struct ChanMem {
 struct xeng_server {
     xeng_server_config cfg;
     xeng::sched::Scheduler *sch = nullptr;
-    xeng_ctx *ctx = nullptr;
-    int32_t *d_out = nullptr;            // max_channels dump buffers
-    int64_t out_i32 = 0;                 // per buffer
+    std::vector<xeng_ctx *> slot_ctx;    // per slot: its accumulators (a one-slot context), once used
+    std::vector<int32_t *> slot_out;     // per slot: its export buffer, once used
+    std::vector<uint8_t *> rings;        // every ring allocated
+    std::vector<uint8_t *> free_rings;   // rings no channel holds
+    int64_t out_i32 = 0;                 // per export buffer
     int64_t frame_bytes = 0;
     std::vector<ChanMem> mem;
     hipStream_t compute = nullptr;
@@ -75,6 +89,8 @@ public:
     explicit HipExec(xeng_server *s) : s_(s), t0_(Clock::now()) {}
 
     double now() override { return std::chrono::duration<double>(Clock::now() - t0_).count(); }
+
+    void start() override { t0_ = Clock::now(); }
 
     int copy(const xeng::sched::Chan &c, int32_t chan, int64_t frame, int64_t *token) override
     {
@@ -103,8 +119,8 @@ public:
                 const uint8_t *base = c.host ? m.ring + (j.f0 % cf.ring_frames) * s_->frame_bytes
                                              : m.src + (j.f0 % c.src_frames) * s_->frame_bytes;
                 xeng_job x;
-                x.ctx = s_->ctx;
-                x.slot = j.slot;
+                x.ctx = s_->slot_ctx[(size_t)j.slot];
+                x.slot = 0;
                 x.reserved = 0;
                 x.d_samples = base;
                 x.n_samples = (j.f1 - j.f0) * cf.frame_len;
@@ -118,19 +134,72 @@ public:
             dj.reserve(exports.size());
             for (const xeng::sched::Job &e : exports) {
                 ChanMem &m = s_->mem[(size_t)e.chan];
-                int32_t *dst = s_->d_out + (int64_t)e.slot * s_->out_i32;
+                int32_t *dst = s_->slot_out[(size_t)e.slot];
                 if (m.exports) dst = m.exports + (m.issued++ % m.n_exports) * s_->out_i32;
-                dj.push_back({s_->ctx, e.slot, 1, dst, 0, 0});
+                dj.push_back({s_->slot_ctx[(size_t)e.slot], 0, 1, dst, 0, 0});
             }
             if ((rc = xeng_dump_batch(dj.data(), (int32_t)dj.size(), s_->compute)) != XENG_OK) return rc;
         }
         return record(s_->compute, token);
     }
 
-    int reset(int32_t slot) override
+    int64_t free_bytes() override
+    {
+        size_t free = 0, total = 0;
+        if (hipMemGetInfo(&free, &total) != hipSuccess) return 0;
+        return (int64_t)free;
+    }
+
+    int attach(const xeng::sched::Chan &c, int32_t chan, int32_t slot, bool new_slot, bool new_ring) override
+    {
+        Range r("xeng server: admit");
+        if (new_slot) {
+            xeng_config cc{s_->cfg.n_inputs, 1, s_->cfg.device, s_->cfg.flags & XENG_NIBBLE_RE_LOW, 0};
+            xeng_ctx *ctx = nullptr;
+            int32_t *out = nullptr;
+            // zeroed on the compute stream, where every later use of the
+            // slot is queued: no wait for the launches in flight
+            const int rc = xeng::create_ctx(&cc, s_->compute, &ctx);
+            if (rc != XENG_OK) return rc;
+            if (hipMalloc(&out, (size_t)(s_->out_i32 * 4)) != hipSuccess) {
+                (void)xeng_destroy(ctx);
+                return XENG_ENOMEM;
+            }
+            s_->slot_ctx[(size_t)slot] = ctx;
+            s_->slot_out[(size_t)slot] = out;
+        }
+        if (new_ring) {
+            uint8_t *ring = nullptr;
+            if (hipMalloc(&ring, (size_t)(s_->cfg.ring_frames * s_->frame_bytes)) != hipSuccess) {
+                // leave nothing allocated: the core counts memory only for
+                // channels it admits
+                if (new_slot) {
+                    (void)xeng_destroy(s_->slot_ctx[(size_t)slot]);
+                    (void)hipFree(s_->slot_out[(size_t)slot]);
+                    s_->slot_ctx[(size_t)slot] = nullptr;
+                    s_->slot_out[(size_t)slot] = nullptr;
+                }
+                return XENG_ENOMEM;
+            }
+            s_->rings.push_back(ring);
+            s_->free_rings.push_back(ring);
+        }
+        if (c.host) {
+            s_->mem[(size_t)chan].ring = s_->free_rings.back();
+            s_->free_rings.pop_back();
+        }
+        return XENG_OK;
+    }
+
+    int detach(const xeng::sched::Chan &c, int32_t chan, int32_t slot) override
     {
         Range r("xeng server: slot reset");
-        return xeng_reset(s_->ctx, slot, s_->compute);
+        if (c.host) {
+            // every launch that read the ring has completed
+            s_->free_rings.push_back(s_->mem[(size_t)chan].ring);
+            s_->mem[(size_t)chan].ring = nullptr;
+        }
+        return xeng_reset(s_->slot_ctx[(size_t)slot], 0, s_->compute);
     }
 
     int poll(int64_t token, bool wait) override
@@ -186,16 +255,17 @@ void destroy_server(xeng_server *s)
     if (s->compute) (void)hipStreamSynchronize(s->compute);
     for (hipStream_t c : s->copy)
         if (c) (void)hipStreamSynchronize(c);
-    for (ChanMem &m : s->mem)
-        if (m.ring) (void)hipFree(m.ring);
+    for (uint8_t *r : s->rings) (void)hipFree(r);
     for (hipEvent_t e : s->tokens)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
     if (s->compute) (void)hipStreamDestroy(s->compute);
     for (hipStream_t c : s->copy)
         if (c) (void)hipStreamDestroy(c);
-    if (s->d_out) (void)hipFree(s->d_out);
-    if (s->ctx) (void)xeng_destroy(s->ctx);
+    for (int32_t *o : s->slot_out)
+        if (o) (void)hipFree(o);
+    for (xeng_ctx *c : s->slot_ctx)
+        if (c) (void)xeng_destroy(c);
     delete s->sch;
     delete s;
 }
@@ -217,13 +287,20 @@ int xeng_server_create(const xeng_server_config *cfg, xeng_server **out)
     const int64_t n = cfg->n_inputs;
     const int64_t frame_bytes = (int64_t)cfg->frame_len * n;
     const int64_t out_bytes = n * (n + 1) / 2 * 8;
-    // device bytes per channel: accumulators, export buffer and (for host
-    // sources) the ingest ring
-    const int64_t per_chan = xeng_slot_bytes(cfg->n_inputs) + out_bytes + (int64_t)cfg->ring_frames * frame_bytes;
+    // device bytes of a slot (accumulators and export buffer) and of a host
+    // source's ingest ring, allocated as channels are admitted
+    const int64_t slot_bytes = xeng_slot_bytes(cfg->n_inputs) + out_bytes;
+    const int64_t ring_bytes = (int64_t)cfg->ring_frames * frame_bytes;
     int64_t chans = cfg->max_channels;
-    if (cfg->mem_budget_bytes > 0) chans = std::min<int64_t>(chans > 0 ? chans : INT32_MAX, cfg->mem_budget_bytes / per_chan);
+    if (cfg->mem_budget_bytes > 0)
+        chans = std::min<int64_t>(chans > 0 ? chans : INT32_MAX, cfg->mem_budget_bytes / slot_bytes);
     if (chans < 1) return XENG_ENOMEM;
     if (chans > 65536) return XENG_EINVAL;
+    int n_dev = 0;
+    if (hipGetDeviceCount(&n_dev) != hipSuccess || cfg->device >= n_dev) return XENG_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, cfg->device) != hipSuccess) return XENG_EDEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return XENG_ENOTSUP;
 
     auto *s = new (std::nothrow) xeng_server;
     if (!s) return XENG_ENOMEM;
@@ -241,20 +318,18 @@ int xeng_server_create(const xeng_server_config *cfg, xeng_server **out)
     sc.launch_period_us = cfg->launch_period_us;
     sc.stagger_exports = (cfg->flags & XENG_SERVER_STAGGER_EXPORTS) != 0;
     sc.pairs = (double)(n * (n + 1) / 2);
+    sc.slot_bytes = slot_bytes;
+    sc.ring_bytes = ring_bytes;
+    sc.mem_budget = cfg->mem_budget_bytes;
+    sc.mem_reserve = MEM_RESERVE;
     s->sch = new (std::nothrow) xeng::sched::Scheduler(sc);
     if (!s->sch) {
         delete s;
         return XENG_ENOMEM;
     }
-    xeng_config c{cfg->n_inputs, (int32_t)chans, cfg->device, cfg->flags & XENG_NIBBLE_RE_LOW, 0};
-    int rc = xeng_create(&c, &s->ctx);
-    if (rc != XENG_OK) {
-        delete s->sch;
-        delete s;
-        return rc;
-    }
+    s->slot_ctx.assign((size_t)chans, nullptr);
+    s->slot_out.assign((size_t)chans, nullptr);
     bool ok = hipSetDevice(cfg->device) == hipSuccess &&
-              hipMalloc(&s->d_out, (size_t)(out_bytes * chans)) == hipSuccess &&
               hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking) == hipSuccess;
     for (int k = 0; ok && k < COPY_STREAMS; ++k) {
         hipStream_t c = nullptr;
@@ -263,7 +338,7 @@ int xeng_server_create(const xeng_server_config *cfg, xeng_server **out)
     }
     if (!ok) {
         destroy_server(s);
-        return XENG_ENOMEM;
+        return XENG_EDEVICE;
     }
     *out = s;
     return XENG_OK;
@@ -287,10 +362,6 @@ int xeng_server_admit(xeng_server *s, const uint8_t *frames, int64_t n_frames, i
         return XENG_EINVAL;
     ChanMem m;
     m.src = frames;
-    if (host_frames) {
-        if (hipSetDevice(s->cfg.device) != hipSuccess) return XENG_EDEVICE;
-        if (hipMalloc(&m.ring, (size_t)(s->cfg.ring_frames * s->frame_bytes)) != hipSuccess) return XENG_ENOMEM;
-    }
     s->mem.push_back(m);
     *channel = s->sch->admit(n_frames, host_frames != 0, start_s, total_frames);
     return XENG_OK;
@@ -313,6 +384,8 @@ int xeng_server_run(xeng_server *s, double seconds, xeng_server_stats *stats)
     stats->launches = st.launches;
     stats->dumps = st.dumps;
     stats->backlog_frames = st.backlog_frames;
+    stats->channels_waiting = st.waiting;
+    stats->device_bytes = st.device_bytes;
     stats->seconds = st.seconds;
     stats->tcmacs = st.tcmacs;
     stats->p50_ms = st.p50_ms;
@@ -330,6 +403,7 @@ int xeng_server_channel_info(const xeng_server *s, int32_t channel, xeng_server_
     info->frames_done = c.done;
     info->dumps = c.dumps;
     info->last_dump_first_frame = c.last_dump_first;
+    info->admitted_s = c.admitted_s;
     return XENG_OK;
 }
 
@@ -344,7 +418,7 @@ int xeng_server_last_dump(xeng_server *s, int32_t channel, int32_t *out)
         src = m.exports + ((m.issued - 1) % m.n_exports) * s->out_i32;
     } else {
         if (s->sch->slot_owner(c.slot) != channel) return XENG_EBUSY;   // slot reused since
-        src = s->d_out + (int64_t)c.slot * s->out_i32;
+        src = s->slot_out[(size_t)c.slot];
     }
     if (hipSetDevice(s->cfg.device) != hipSuccess) return XENG_EDEVICE;
     if (hipStreamSynchronize(s->compute) != hipSuccess) return XENG_EDEVICE;

@@ -84,13 +84,15 @@ class _ServerStats(ctypes.Structure):
     _fields_ = [("frames_released", ctypes.c_int64), ("frames_done", ctypes.c_int64),
                 ("frames_dropped", ctypes.c_int64), ("launches", ctypes.c_int64),
                 ("dumps", ctypes.c_int64), ("backlog_frames", ctypes.c_int64),
+                ("channels_waiting", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("seconds", ctypes.c_double), ("tcmacs", ctypes.c_double),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
 
 
 class _ServerChannel(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int32), ("slot", ctypes.c_int32), ("frames_done", ctypes.c_int64),
-                ("dumps", ctypes.c_int64), ("last_dump_first_frame", ctypes.c_int64)]
+                ("dumps", ctypes.c_int64), ("last_dump_first_frame", ctypes.c_int64),
+                ("admitted_s", ctypes.c_double)]
 
 
 class _PieceInfo(ctypes.Structure):

@@ -9,7 +9,11 @@
 //     ring slot overwritten while it holds a frame not yet integrated or
 //     still being read;
 //   * an export holding frames of another channel;
-//   * more launches in flight than max_inflight.
+//   * more launches in flight than max_inflight;
+//   * a channel attached to a slot another active channel holds, or
+//     detached from a slot it does not hold.
+// Its free device memory is a step in time (before, switch time, after),
+// for admission by memory.
 // Built by the tests with g++ together with csrc/xeng_sched.cpp.
 #include <algorithm>
 #include <cstdint>
@@ -38,6 +42,8 @@ public:
         : tm_(tm), ring_(ring_frames), max_inflight_(max_inflight) {}
 
     double now() override { return t; }
+
+    void start() override {}   // the simulated clock runs on across runs
 
     int copy(const Chan &, int32_t chan, int64_t frame, int64_t *token) override
     {
@@ -103,11 +109,35 @@ public:
         return XENG_OK;
     }
 
-    int reset(int32_t slot) override
+    int64_t free_bytes() override { return t < free_switch_ ? free_before_ : free_after_; }
+
+    int attach(const Chan &, int32_t chan, int32_t slot, bool new_slot, bool new_ring) override
     {
+        grow(chan);
+        if (holder_[(size_t)slot] >= 0) ++violations;
+        holder_[(size_t)slot] = chan;
+        attach_log.push_back(chan);
+        attach_log.push_back(slot);
+        attach_log.push_back(new_slot ? 1 : 0);
+        attach_log.push_back(new_ring ? 1 : 0);
+        attach_log.push_back((int64_t)(t * 1e9));
+        return XENG_OK;
+    }
+
+    int detach(const Chan &, int32_t chan, int32_t slot) override
+    {
+        if (holder_[(size_t)slot] != chan) ++violations;
+        holder_[(size_t)slot] = -1;
         acc_[(size_t)slot].clear();
         ++resets;
         return XENG_OK;
+    }
+
+    void set_free(int64_t before, double t_switch, int64_t after)
+    {
+        free_before_ = before;
+        free_switch_ = t_switch;
+        free_after_ = after;
     }
 
     int poll(int64_t token, bool wait) override
@@ -121,7 +151,11 @@ public:
 
     void idle() override { t += tm_.idle_us * 1e-6; }
 
-    void set_slots(int32_t slots) { acc_.resize((size_t)slots); }
+    void set_slots(int32_t slots)
+    {
+        acc_.resize((size_t)slots);
+        holder_.assign((size_t)slots, -1);
+    }
     void set_host(int32_t chan, bool host)
     {
         grow(chan);
@@ -130,7 +164,7 @@ public:
 
     double t = 0;
     int64_t violations = 0, launches = 0, resets = 0;
-    std::vector<int64_t> copy_log, int_log, exp_log, exp_frames;
+    std::vector<int64_t> copy_log, int_log, exp_log, exp_frames, attach_log;
 
 private:
     struct RingSlot {
@@ -167,6 +201,9 @@ private:
     std::vector<std::set<int64_t>> integrated_;
     std::vector<bool> host_;
     std::vector<std::vector<std::pair<int32_t, int64_t>>> acc_;   // per slot: (channel, frame) since export
+    std::vector<int32_t> holder_;   // per slot: the attached channel, -1 if none
+    int64_t free_before_ = INT64_C(1) << 50, free_after_ = INT64_C(1) << 50;
+    double free_switch_ = 0;
 };
 
 struct Sim {
@@ -185,6 +222,7 @@ const std::vector<int64_t> *log_of(const Sim *s, int which)
     case 1: return &s->ex.int_log;
     case 2: return &s->ex.exp_log;
     case 3: return &s->ex.exp_frames;
+    case 4: return &s->ex.attach_log;
     default: return nullptr;
     }
 }
@@ -193,9 +231,9 @@ const std::vector<int64_t> *log_of(const Sim *s, int which)
 
 extern "C" {
 
-// cfg: frame_len, dump_frames, ring_frames, max_inflight, slots, stagger;
-// per: frame_period_us, launch_period_us; tm: idle, copy, launch, frame,
-// export (us).
+// cfg: frame_len, dump_frames, ring_frames, max_inflight, slots, stagger,
+// slot_bytes, ring_bytes, mem_budget, mem_reserve; per: frame_period_us,
+// launch_period_us; tm: idle, copy, launch, frame, export (us).
 void *sim_create(const int64_t *cfg, const double *per, const double *tm)
 {
     xeng::sched::Config c;
@@ -205,6 +243,10 @@ void *sim_create(const int64_t *cfg, const double *per, const double *tm)
     c.max_inflight = (int32_t)cfg[3];
     c.slots = (int32_t)cfg[4];
     c.stagger_exports = cfg[5] != 0;
+    c.slot_bytes = cfg[6];
+    c.ring_bytes = cfg[7];
+    c.mem_budget = cfg[8];
+    c.mem_reserve = cfg[9];
     c.frame_period_us = per[0];
     c.launch_period_us = per[1];
     c.pairs = 1.0;
@@ -212,6 +254,11 @@ void *sim_create(const int64_t *cfg, const double *per, const double *tm)
 }
 
 void sim_destroy(void *h) { delete static_cast<Sim *>(h); }
+
+void sim_set_free(void *h, int64_t before, double t_switch, int64_t after)
+{
+    static_cast<Sim *>(h)->ex.set_free(before, t_switch, after);
+}
 
 int32_t sim_admit(void *h, int64_t src_frames, int32_t host, double start_s, int64_t total_frames)
 {
@@ -222,7 +269,8 @@ int32_t sim_admit(void *h, int64_t src_frames, int32_t host, double start_s, int
 }
 
 // stats: released, done, dropped, launches, dumps, backlog, violations,
-// resets (int64); seconds, p50_ms, p99_ms, max_ms (double)
+// resets, waiting, device_bytes (int64); seconds, p50_ms, p99_ms, max_ms
+// (double)
 int sim_run(void *h, double seconds, int64_t *istats, double *dstats)
 {
     Sim *s = static_cast<Sim *>(h);
@@ -236,6 +284,8 @@ int sim_run(void *h, double seconds, int64_t *istats, double *dstats)
     istats[5] = st.backlog_frames;
     istats[6] = s->ex.violations;
     istats[7] = s->ex.resets;
+    istats[8] = st.waiting;
+    istats[9] = st.device_bytes;
     dstats[0] = st.seconds;
     dstats[1] = st.p50_ms;
     dstats[2] = st.p99_ms;
@@ -255,7 +305,8 @@ void sim_log_copy(void *h, int which, int64_t *dst)
     if (v) std::copy(v->begin(), v->end(), dst);
 }
 
-// state, slot, released, done, dumps, last_dump_first, start_s * 1e9
+// state, slot, released, done, dumps, last_dump_first, start_s * 1e9,
+// admitted_s * 1e9 (-1: never)
 void sim_chan(void *h, int32_t k, int64_t *out)
 {
     const Chan &c = static_cast<Sim *>(h)->sch.chans()[(size_t)k];
@@ -266,6 +317,7 @@ void sim_chan(void *h, int32_t k, int64_t *out)
     out[4] = c.dumps;
     out[5] = c.last_dump_first;
     out[6] = (int64_t)(c.start_s * 1e9);
+    out[7] = c.admitted_s < 0 ? -1 : (int64_t)(c.admitted_s * 1e9);
 }
 
 }  // extern "C"

@@ -14,12 +14,12 @@ int sim_run(void *h, double seconds, int64_t *istats, double *dstats);
 static int scenario(int64_t dump, int64_t ring, int64_t inflight, int64_t slots, int64_t stagger, double frame_us,
                     double launch_us, double t_frame, int n_chans, int host, int64_t total, double seconds)
 {
-    const int64_t cfg[6] = {256, dump, ring, inflight, slots, stagger};
+    const int64_t cfg[10] = {256, dump, ring, inflight, slots, stagger, 1000, 100, 1000 * slots + 100 * n_chans, 0};
     const double per[2] = {frame_us, launch_us};
     const double tm[5] = {20.0, 20.0, 50.0, t_frame, 10.0};
     void *h = sim_create(cfg, per, tm);
     for (int c = 0; c < n_chans; ++c) sim_admit(h, 5 + c, host, 0.0001 * c, total);
-    int64_t ist[8];
+    int64_t ist[10];
     double dst[4];
     int rc = sim_run(h, seconds, ist, dst);
     if (rc == 0 && ist[6] != 0) rc = 1;   // violations

@@ -1,5 +1,6 @@
 """GPU tests of the streaming server: real-time frame releases, continuous
-batching over channels, admission as slots free up, exports every
+batching over channels, admission as slots and device memory free up,
+exports every
 dump_frames frames.  Each export is compared bit for bit with the oracle on
 the frames it covers, and with the same channel served alone."""
 import numpy as np
@@ -157,9 +158,9 @@ def test_server_argument_checks(X):
     with pytest.raises(X.XengError) as e:
         X.Server(N, max_channels=0, mem_budget_bytes=1000)          # not one channel fits
     assert e.value.status == X.XENG_ENOMEM
-    srv = X.Server(2048, max_channels=0, mem_budget_bytes=3 * (X.slot_bytes(2048) + 2048 * 2049 * 4
-                                                              + 64 * 256 * 2048))
-    assert srv.max_channels == 3                                   # admission by memory
+    srv = X.Server(2048, max_channels=0, mem_budget_bytes=3 * (X.slot_bytes(2048) + 2048 * 2049 * 4)
+                   + 64 * 256 * 2048)
+    assert srv.max_channels == 3                                   # slots the budget holds
     with pytest.raises(ValueError):
         srv.admit(torch.zeros((4, 256, 100), dtype=torch.uint8, device="cuda"))
     srv.close()
@@ -202,3 +203,55 @@ def test_full_size_n2048_every_export(X):
                                             fc.serve_window(srcs[c], m))
     solo = serve([0])
     assert torch.equal(solo[0], mix[0])
+
+
+def slot_mem(X, n):
+    """Device bytes of a server slot: accumulators and export buffer."""
+    return X.slot_bytes(n) + n * (n + 1) // 2 * 8
+
+
+def test_channel_waits_until_freed_memory_admits_it(X):
+    # two slots, but a budget of two slots and ONE host ring: the second
+    # host source waits for memory (not for a slot), is admitted when the
+    # first finishes and leaves its ring, and then runs in the freed slot
+    # and ring with nothing newly allocated; every export equals the oracle
+    ring_frames = 8
+    ring = ring_frames * 256 * N
+    srcs = [frames_of(seed=[11, c], n_frames=40) for c in range(2)]
+    hosts = [torch.from_numpy(f).pin_memory() for f in srcs]
+    srv = X.Server(N, dump_frames=DUMP, max_channels=2, ring_frames=ring_frames, launch_period_us=2000.0,
+                   mem_budget_bytes=2 * slot_mem(X, N) + ring)
+    assert srv.max_channels == 2
+    a = srv.admit(hosts[0], total_frames=2 * DUMP)
+    b = srv.admit(hosts[1], total_frames=2 * DUMP)
+    rings = [torch.zeros((2, X.tri(N), 2), dtype=torch.int32, device="cuda") for _ in range(2)]
+    srv.export_ring(a, rings[0])
+    srv.export_ring(b, rings[1])
+    st = srv.run(0.4)
+    print("admission by memory", st, flush=True)
+    ia, ib = srv.channel_info(a), srv.channel_info(b)
+    print("channels", ia, ib, flush=True)
+    assert st["channels_waiting"] == 0 and st["frames_dropped"] == 0 and st["frames_done"] == 4 * DUMP
+    assert st["device_bytes"] == slot_mem(X, N) + ring               # one slot, one ring, both reused
+    assert ia["state"] == 2 and ib["state"] == 2 and ib["slot"] == ia["slot"]
+    # b waited for a's last frame (released at 2 DUMP - 1 frame periods)
+    assert ib["admitted_s"] >= (2 * DUMP - 1) * 655.36e-6 > ia["admitted_s"]
+    for r, f in zip(rings, srcs):
+        for k in range(2):
+            np.testing.assert_array_equal(r[k].cpu().numpy(), expected(f, k * DUMP))
+    srv.close()
+
+
+def test_budget_smaller_than_a_ring_never_admits_a_host_source(X):
+    # a budget with room for a slot but not for slot + ring: the device
+    # channel runs, the host source waits through the whole run
+    dev_src, host_src = frames_of(seed=[12, 0]), frames_of(seed=[12, 1])
+    srv = X.Server(N, dump_frames=DUMP, max_channels=2, ring_frames=64, launch_period_us=2000.0,
+                   mem_budget_bytes=2 * slot_mem(X, N))
+    d = srv.admit(torch.from_numpy(dev_src).cuda(), total_frames=DUMP)
+    h = srv.admit(torch.from_numpy(host_src).pin_memory(), total_frames=DUMP)
+    st = srv.run(0.1)
+    assert st["channels_waiting"] == 1 and st["frames_done"] == DUMP
+    assert srv.channel_info(h)["state"] == 0 and srv.channel_info(h)["admitted_s"] < 0
+    np.testing.assert_array_equal(srv.last_dump(d).cpu().numpy(), expected(dev_src, 0))
+    srv.close()

@@ -1,7 +1,9 @@
 """The streaming server's scheduling core (csrc/xeng_sched.cpp) on a simulated
 device and clock (tests/sched_sim.cpp), on the CPU: exact frame accounting
 for every export, ring safety for host sources, drops, staggered export
-phases, admission into freed slots, the in-flight limit and the statistics.
+phases, admission into freed slots and by memory (the server's budget and
+the device's free memory at admission time), the in-flight limit and the
+statistics.
 
 The core is the same code the HIP server runs; here its Executor is a model
 with serial copy and compute queues, so every run is deterministic."""
@@ -28,6 +30,7 @@ def sim_lib(tmp_path_factory):
     L.sim_create.restype = vp
     L.sim_create.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     L.sim_destroy.argtypes = [vp]
+    L.sim_set_free.argtypes = [vp, i64, dbl, i64]
     L.sim_admit.restype = i32
     L.sim_admit.argtypes = [vp, i64, i32, dbl, i64]
     L.sim_run.restype = ctypes.c_int
@@ -41,10 +44,12 @@ def sim_lib(tmp_path_factory):
 
 class Sim:
     def __init__(self, L, dump=16, ring=8, inflight=2, slots=4, stagger=False, frame_us=655.36,
-                 launch_us=2000.0, t_idle=20.0, t_copy=50.0, t_launch=100.0, t_frame=5.0, t_export=10.0):
+                 launch_us=2000.0, t_idle=20.0, t_copy=50.0, t_launch=100.0, t_frame=5.0, t_export=10.0,
+                 slot_bytes=0, ring_bytes=0, budget=0, reserve=0):
         self.L = L
         self.dump, self.ring, self.slots, self.stagger = dump, ring, slots, stagger
-        cfg = (ctypes.c_int64 * 6)(256, dump, ring, inflight, slots, int(stagger))
+        cfg = (ctypes.c_int64 * 10)(256, dump, ring, inflight, slots, int(stagger), slot_bytes, ring_bytes,
+                                    budget, reserve)
         per = (ctypes.c_double * 2)(frame_us, launch_us)
         tm = (ctypes.c_double * 5)(t_idle, t_copy, t_launch, t_frame, t_export)
         self.h = L.sim_create(cfg, per, tm)
@@ -54,12 +59,16 @@ class Sim:
         self.host.append(host)
         return self.L.sim_admit(self.h, src_frames, int(host), start_s, total)
 
+    def set_free(self, before, t_switch, after):
+        self.L.sim_set_free(self.h, before, t_switch, after)
+
     def run(self, seconds):
-        ist = (ctypes.c_int64 * 8)()
+        ist = (ctypes.c_int64 * 10)()
         dst = (ctypes.c_double * 4)()
         rc = self.L.sim_run(self.h, seconds, ist, dst)
         assert rc == 0
-        keys = ["released", "done", "dropped", "launches", "dumps", "backlog", "violations", "resets"]
+        keys = ["released", "done", "dropped", "launches", "dumps", "backlog", "violations", "resets",
+                "waiting", "device_bytes"]
         st = dict(zip(keys, list(ist)))
         st.update(zip(["seconds", "p50_ms", "p99_ms", "max_ms"], list(dst)))
         return st
@@ -71,9 +80,15 @@ class Sim:
         return np.array(buf[:n], dtype=np.int64)
 
     def chan(self, k):
-        out = (ctypes.c_int64 * 7)()
+        out = (ctypes.c_int64 * 8)()
         self.L.sim_chan(self.h, k, out)
-        return dict(zip(["state", "slot", "released", "done", "dumps", "last_first", "start_ns"], list(out)))
+        return dict(zip(["state", "slot", "released", "done", "dumps", "last_first", "start_ns", "admitted_ns"],
+                        list(out)))
+
+    def attaches(self):
+        a = self.log(4).reshape(-1, 5)
+        return [dict(chan=int(r[0]), slot=int(r[1]), new_slot=bool(r[2]), new_ring=bool(r[3]), t_ns=int(r[4]))
+                for r in a]
 
     def copies(self):
         c = self.log(0).reshape(-1, 2)
@@ -262,3 +277,81 @@ def test_core_under_sanitizers(tmp_path):
     assert r.returncode == 0, r.stdout + r.stderr
     assert "ERROR" not in r.stderr and "runtime error" not in r.stderr, r.stderr
     assert r.stdout.count("rc=0") == 4
+
+
+def test_admission_by_budget_reuses_freed_slot_memory(sim_lib):
+    # the budget holds two slots' memory: the third channel waits (a free
+    # slot id is there, its memory is not), then takes the slot the first
+    # finished channel left, with no new allocation
+    sim = Sim(sim_lib, dump=8, slots=4, slot_bytes=1000, budget=2500)
+    c0 = sim.admit(total=16)
+    c1 = sim.admit(total=40)
+    c2 = sim.admit(total=24)
+    st = sim.run(0.3)
+    check_accounting(sim, st)
+    att = {a["chan"]: a for a in sim.attaches()}
+    assert att[c0]["new_slot"] and att[c1]["new_slot"] and not att[c2]["new_slot"]
+    assert att[c2]["slot"] == att[c0]["slot"]
+    assert sim.chan(c2)["admitted_ns"] > 15 * 655360          # after c0's last frame
+    assert st["device_bytes"] == 2000 and st["waiting"] == 0
+    assert [sim.chan(k)["dumps"] for k in (c0, c1, c2)] == [2, 5, 3]
+    sim.close()
+
+
+def test_admission_waits_for_free_device_memory(sim_lib):
+    # the device has too little free memory (less the reserve) until 50 ms
+    # into the run: both channels wait, then both are admitted and stream
+    sim = Sim(sim_lib, dump=8, slots=4, slot_bytes=1000, reserve=500)
+    sim.set_free(1200, 0.05, 10_000)
+    a = sim.admit(total=16)
+    b = sim.admit(total=16)
+    st = sim.run(0.2)
+    check_accounting(sim, st)
+    for k in (a, b):
+        ch = sim.chan(k)
+        assert ch["admitted_ns"] >= 50_000_000 and ch["start_ns"] >= 50_000_000
+        assert ch["state"] == 2 and ch["done"] == 16 and ch["dumps"] == 2
+    sim.close()
+
+
+def test_admission_stays_waiting_without_memory(sim_lib):
+    sim = Sim(sim_lib, dump=8, slots=4, slot_bytes=1000, reserve=500)
+    sim.set_free(1200, 10.0, 1200)
+    a = sim.admit(total=16)
+    st = sim.run(0.05)
+    assert st["waiting"] == 1 and st["done"] == 0 and st["device_bytes"] == 0
+    assert sim.chan(a)["state"] == 0 and sim.chan(a)["slot"] == -1 and sim.attaches() == []
+    sim.close()
+
+
+def test_host_rings_are_kept_for_the_next_host_channel(sim_lib):
+    # budget: two slots and one ring; the second host channel waits for the
+    # first's ring (not for a slot), then reuses ring and slot memory
+    sim = Sim(sim_lib, dump=8, ring=8, slots=2, slot_bytes=1000, ring_bytes=300, budget=2300)
+    a = sim.admit(src_frames=5, host=True, total=16)
+    b = sim.admit(src_frames=7, host=True, total=16, start_s=0.0002)
+    st = sim.run(0.3)
+    check_accounting(sim, st)
+    att = {x["chan"]: x for x in sim.attaches()}
+    assert att[a]["new_slot"] and att[a]["new_ring"]
+    assert not att[b]["new_ring"] and not att[b]["new_slot"]
+    assert sim.chan(b)["admitted_ns"] > 15 * 655360
+    assert st["device_bytes"] == 1300 and st["dropped"] == 0 and st["done"] == 32
+    sim.close()
+
+
+def test_waiting_channels_are_admitted_in_order(sim_lib):
+    # a host channel that needs a ring the budget lacks holds back the
+    # device channel behind it (no overtaking), until memory frees up
+    sim = Sim(sim_lib, dump=8, ring=8, slots=3, slot_bytes=1000, ring_bytes=300, budget=2300)
+    d0 = sim.admit(total=16)
+    h1 = sim.admit(src_frames=5, host=True, total=16)      # slot + ring: 2300 with d0's slot
+    h2 = sim.admit(src_frames=5, host=True, total=16)      # needs a second ring: waits
+    d3 = sim.admit(total=16)                               # would fit (a free slot with memory later)
+    st = sim.run(0.4)
+    check_accounting(sim, st)
+    order = [x["chan"] for x in sim.attaches()]
+    assert order == [d0, h1, h2, d3]
+    assert sim.chan(h2)["admitted_ns"] <= sim.chan(d3)["admitted_ns"]
+    assert all(sim.chan(k)["state"] == 2 for k in (d0, h1, h2, d3))
+    sim.close()
