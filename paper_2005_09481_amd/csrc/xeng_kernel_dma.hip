@@ -562,11 +562,11 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
     const int lane = tid & 63;
     // wave-uniform, so that everything derived from it stays scalar
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wa = wave / L::WB_WAVES, wb = wave % L::WB_WAVES;
-    // per-lane parts of the transposed-read addresses (see read_k)
+    // per-lane parts of the transposed-read addresses (see read_k); the
+    // wave's region adds to them per piece
     const int grp = lane >> 4, jl = lane & 15;
-    const uint32_t a_lane = GRP_A * (grp >> 1) + 128 * (grp & 1) + 8 * jl + 512 * wa;
-    const uint32_t b_lane = A_STAGE + GRP_B * (grp >> 1) + 128 * (grp & 1) + 8 * jl + 256 * L::BW * wb;
+    const uint32_t a_lane0 = GRP_A * (grp >> 1) + 128 * (grp & 1) + 8 * jl;
+    const uint32_t b_lane0 = A_STAGE + GRP_B * (grp >> 1) + 128 * (grp & 1) + 8 * jl;
 
     // clock probe (measurement only): workgroup 0's start and end
     const bool stamp = args.clock != nullptr && blockIdx.x == 0 && tid == 0;
@@ -590,6 +590,22 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
         tl.col0 = __builtin_amdgcn_readfirstlane(tj2 * WB_COLS);
         tl.t0 = __builtin_amdgcn_readfirstlane(pce.t0);
         tl.t1 = __builtin_amdgcn_readfirstlane(pce.t1_atomic & 0x7FFFFFFF);
+        // this wave's region: rows 64 wa.. of the A block against column
+        // blocks of the B block.  The waves of a workgroup run on SIMD
+        // wave % 4.  Where one tile of the window is not in the triangle
+        // (below the diagonal: the window of an odd tile row that starts one
+        // tile left of it; or past the last tile column), four of the eight
+        // regions have no work; the region map then puts the other four on
+        // four different SIMDs instead of two waves each on two of them,
+        // halving the matrix time of such a window's stages.
+        int wa = wave / L::WB_WAVES, wb = wave % L::WB_WAVES;
+        if constexpr (NW == 8) {
+            const int tjl = 2 * tj2, tjr = tjl + 1;
+            const bool vl = tjl >= ti && tjl < jd.nt, vr = tjr >= ti && tjr < jd.nt;
+            if (vr && !vl && wa == 0) wb ^= 2;
+            if (vl && !vr && wa == 1) wb ^= 2;
+        }
+        const uint32_t a_lane = a_lane0 + 512 * wa, b_lane = b_lane0 + 256 * L::BW * wb;
         // this wave's accumulator tile; a region wholly below the diagonal
         // is neither computed nor stored (the wave stays in step for the
         // workgroup's DMA and barriers)

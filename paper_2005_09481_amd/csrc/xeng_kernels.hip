@@ -588,18 +588,22 @@ __global__ __launch_bounds__(256) void fill_zero(int4 *__restrict__ p, int64_t n
 // launches: if every job's slot can take its samples without passing T_MAX,
 // the counters advance and *skip = 0; otherwise nothing changes, *skip = 1
 // (the correlation launches then return at once) and *skipped counts the
-// refusal.  One thread: a batch holds few jobs, and the check must see all
-// of them before any counter moves.
-__global__ void batch_guard(const GuardJob *__restrict__ jobs, int n_jobs, int32_t *skip, int64_t *skipped)
+// refusal.  One workgroup: every thread checks its share of the jobs, the
+// verdict is agreed at a barrier before any counter moves, and the jobs'
+// counters are distinct (a batch names each slot once), so each thread
+// advances its own.
+__global__ __launch_bounds__(1024) void batch_guard(const GuardJob *__restrict__ jobs, int n_jobs, int32_t *skip,
+                                                    int64_t *skipped)
 {
-    if (threadIdx.x != 0) return;
     bool ok = true;
-    for (int k = 0; k < n_jobs; ++k) ok = ok && jobs[k].n <= T_MAX - *jobs[k].count;
+    for (int k = threadIdx.x; k < n_jobs; k += blockDim.x) ok = ok && jobs[k].n <= T_MAX - *jobs[k].count;
+    ok = __syncthreads_and(ok ? 1 : 0) != 0;
     if (ok)
-        for (int k = 0; k < n_jobs; ++k) *jobs[k].count += jobs[k].n;
-    else
-        *skipped += 1;
-    *skip = ok ? 0 : 1;
+        for (int k = threadIdx.x; k < n_jobs; k += blockDim.x) *jobs[k].count += jobs[k].n;
+    if (threadIdx.x == 0) {
+        if (!ok) *skipped += 1;
+        *skip = ok ? 0 : 1;
+    }
 }
 
 // Stores one value into a device sample counter, in stream order.
@@ -708,7 +712,8 @@ hipError_t launch_zero(int32_t *p, int64_t n_i32, hipStream_t stream)
 hipError_t launch_batch_guard(const GuardJob *d_jobs, int n_jobs, int32_t *d_skip, int64_t *d_skipped,
                               hipStream_t stream)
 {
-    hipLaunchKernelGGL(batch_guard, dim3(1), dim3(64), 0, stream, d_jobs, n_jobs, d_skip, d_skipped);
+    const int threads = std::min(1024, std::max(64, (n_jobs + 63) / 64 * 64));
+    hipLaunchKernelGGL(batch_guard, dim3(1), dim3(threads), 0, stream, d_jobs, n_jobs, d_skip, d_skipped);
     return hipGetLastError();
 }
 

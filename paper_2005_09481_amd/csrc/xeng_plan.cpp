@@ -1,5 +1,6 @@
 // Stream-K style decomposition of the upper-triangle tiles into pieces.
 #include "xeng_plan.h"
+#include "xeng_plan_single.h"
 
 #include <algorithm>
 #include <cstdint>
@@ -34,11 +35,12 @@ struct UnitRef {
     int job, ti, tj;
     int64_t ns;   // stages
     int64_t t;    // samples
+    int64_t wc;   // cost of one stage (unit_stage_cost)
 };
 
 // Greedy fill: workgroups in order, each taking pieces of the linear (job,
-// unit, stage) order until its cost (stages + overhead per piece) would
-// exceed `budget`.  Returns the number of workgroups used (or grid + 1 if
+// unit, stage) order until its cost (stage costs + overhead per piece)
+// would exceed `budget`.  Returns the number of workgroups used (or grid + 1 if
 // the work does not fit), emitting pieces when `out` is given.
 template <typename Emit>
 int64_t fill(const std::vector<UnitRef> &units, int64_t budget, int64_t overhead, int64_t cap, int64_t grid,
@@ -47,15 +49,16 @@ int64_t fill(const std::vector<UnitRef> &units, int64_t budget, int64_t overhead
     int64_t w = 0, left = budget;
     for (size_t u = 0; u < units.size(); ++u) {
         int64_t done = 0;
+        const int64_t wc = units[u].wc;
         while (done < units[u].ns) {
-            if (left <= overhead) {
+            if (left - overhead < wc) {
                 if (++w >= grid) return grid + 1;
                 left = budget;
             }
-            const int64_t take = std::min({units[u].ns - done, left - overhead, cap});
+            const int64_t take = std::min({units[u].ns - done, (left - overhead) / wc, cap});
             emit(w, u, done, done + take);
             done += take;
-            left -= take + overhead;
+            left -= take * wc + overhead;
         }
     }
     return w + 1;
@@ -70,16 +73,19 @@ Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, Til
     if (max_wgs < 1) max_wgs = 1;
     const int64_t cap = cap_override > 0 ? cap_override
                                          : (shape == TileShape::Wide ? MAX_PIECE_STAGES_WIDE : MAX_PIECE_STAGES);
-    const int64_t ovh = piece_overhead(shape);
+    const int64_t ovh = piece_overhead(shape) * STAGE_COST;
 
     std::vector<UnitRef> units;
-    int64_t total = 0;
+    int64_t total = 0, total_cost = 0;
     for (int j = 0; j < n_jobs; ++j) {
         if (jobs[j].t <= 0 || jobs[j].n <= 0) continue;
         const int64_t ns = (jobs[j].t + STAGE - 1) / STAGE;
+        const int64_t nt = n_tiles_side(jobs[j].n);
         for (const auto &unit : plan_units(jobs[j].n, shape)) {
-            units.push_back(UnitRef{j, unit.first, unit.second, ns, jobs[j].t});
+            const int64_t wc = unit_stage_cost(shape == TileShape::Wide, unit.first, unit.second, nt);
+            units.push_back(UnitRef{j, unit.first, unit.second, ns, jobs[j].t, wc});
             total += ns;
+            total_cost += ns * wc;
         }
     }
     if (total == 0) {
@@ -94,8 +100,8 @@ Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, Til
     // Smallest per-workgroup budget with which the greedy fill fits in
     // `grid` workgroups (the fill is monotone in the budget).
     auto none = [](int64_t, size_t, int64_t, int64_t) {};
-    int64_t lo = ovh + 1, hi = ovh + total + 1;   // hi always fits: one piece per unit at most... per workgroup
-    hi = std::max(hi, (total + grid - 1) / grid + ovh * ((int64_t)units.size() + 1) + 1);
+    int64_t lo = ovh + STAGE_COST, hi = ovh + total_cost + 1;
+    hi = std::max(hi, (total_cost + grid - 1) / grid + ovh * ((int64_t)units.size() + 1) + 1);
     while (fill(units, hi, ovh, cap, grid, none) > grid) hi *= 2;
     while (lo < hi) {
         const int64_t mid = lo + (hi - lo) / 2;
@@ -152,39 +158,59 @@ uint64_t morton(uint32_t a, uint32_t b)
 
 namespace {
 
-// One candidate of make_plan_xcd for segment length L: the pieces of each
-// logical workgroup, and the largest workgroup cost (stages + overhead per
-// piece).  Returns -1 if the work does not fit in G workgroups.
+// One candidate of make_plan_xcd for segment length L (in stages of a full
+// unit): the pieces of each logical workgroup, and the largest workgroup
+// cost (stage costs + overhead per piece, in sixteenths of a stage).  A
+// unit whose stages cost less (`wc`) takes longer segments of the same
+// cost.  Returns -1 if the work does not fit in G workgroups.
 struct XSeg {
     int64_t u, s0, s1;
 };
 
-int64_t xcd_candidate(int64_t U, int64_t ns, int64_t G, int64_t L, int64_t ovh, int64_t cap,
+int64_t xcd_candidate(const std::vector<int64_t> &wc, int64_t ns, int64_t G, int64_t L, int64_t ovh, int64_t cap,
                       std::vector<std::vector<XSeg>> *out)
 {
-    const int64_t F = ns / L;          // full segments per unit
-    const int64_t r = ns - F * L;      // each unit's tail
-    const int64_t main = U * F;
-    if (main > G || (r > 0 && main == G)) return -1;
-    if (out) out->assign((size_t)G, {});
-    if (out)
-        for (int64_t p = 0; p < F; ++p)
-            for (int64_t u = 0; u < U; ++u) (*out)[(size_t)(p * U + u)].push_back(XSeg{u, p * L, (p + 1) * L});
-    const int64_t worst = F > 0 ? L + ovh : 0;
-    if (r == 0) return worst;
+    const int64_t U = (int64_t)wc.size();
+    std::vector<int64_t> Lu((size_t)U), Fu((size_t)U), ru((size_t)U);
+    int64_t main = 0, max_f = 0, worst = 0;
+    bool tails = false;
+    for (int64_t u = 0; u < U; ++u) {
+        Lu[(size_t)u] = std::min({ns, cap, std::max<int64_t>(1, L * STAGE_COST / wc[(size_t)u])});
+        Fu[(size_t)u] = ns / Lu[(size_t)u];                  // full segments of the unit
+        ru[(size_t)u] = ns - Fu[(size_t)u] * Lu[(size_t)u];  // its tail
+        main += Fu[(size_t)u];
+        max_f = std::max(max_f, Fu[(size_t)u]);
+        tails = tails || ru[(size_t)u] > 0;
+        if (Fu[(size_t)u] > 0) worst = std::max(worst, Lu[(size_t)u] * wc[(size_t)u] + ovh);
+    }
+    if (main > G || (tails && main == G)) return -1;
+    if (out) {
+        out->assign((size_t)G, {});
+        int64_t k = 0;
+        for (int64_t p = 0; p < max_f; ++p)
+            for (int64_t u = 0; u < U; ++u)
+                if (p < Fu[(size_t)u])
+                    (*out)[(size_t)k++].push_back(XSeg{u, p * Lu[(size_t)u], (p + 1) * Lu[(size_t)u]});
+    }
+    if (!tails) return worst;
     // the tails: stream-K over the remaining workgroups, smallest budget that fits
-    const int64_t rest = G - main;
     auto fill = [&](int64_t budget, bool emit) -> bool {
         int64_t k = main, left = budget, u = 0, done = 0;
         while (u < U) {
-            if (left <= ovh) {
-                if (++k >= main + rest) return false;
+            const int64_t r = ru[(size_t)u], w = wc[(size_t)u];
+            if (r == 0) {
+                ++u;
+                continue;
+            }
+            if (left - ovh < w) {
+                if (++k >= G) return false;
                 left = budget;
             }
-            const int64_t take = std::min({r - done, left - ovh, cap});
-            if (emit) (*out)[(size_t)k].push_back(XSeg{u, F * L + done, F * L + done + take});
+            const int64_t take = std::min({r - done, (left - ovh) / w, cap});
+            const int64_t base = Fu[(size_t)u] * Lu[(size_t)u];
+            if (emit) (*out)[(size_t)k].push_back(XSeg{u, base + done, base + done + take});
             done += take;
-            left -= take + ovh;
+            left -= take * w + ovh;
             if (done == r) {
                 ++u;
                 done = 0;
@@ -192,7 +218,7 @@ int64_t xcd_candidate(int64_t U, int64_t ns, int64_t G, int64_t L, int64_t ovh, 
         }
         return true;
     };
-    int64_t lo = ovh + 1, hi = ovh + 1;
+    int64_t lo = ovh + STAGE_COST, hi = ovh + STAGE_COST;
     while (!fill(hi, false)) hi *= 2;
     while (lo < hi) {
         const int64_t mid = lo + (hi - lo) / 2;
@@ -214,29 +240,37 @@ bool make_plan_xcd(const PlanJob &job, int max_wgs, TileShape shape, Plan *out)
     std::vector<std::pair<int, int>> units = plan_units(job.n, shape);
     const int64_t U = (int64_t)units.size();
     const int64_t ns = (job.t + STAGE - 1) / STAGE;
-    const int64_t ovh = piece_overhead(shape);
+    const int64_t ovh_st = piece_overhead(shape);
     const int64_t cap = shape == TileShape::Wide ? MAX_PIECE_STAGES_WIDE : MAX_PIECE_STAGES;
+    const int col_scale = shape == TileShape::Wide ? 2 : 1;
+    std::stable_sort(units.begin(), units.end(), [col_scale](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+        return morton((uint32_t)a.first, (uint32_t)(col_scale * a.second)) <
+               morton((uint32_t)b.first, (uint32_t)(col_scale * b.second));
+    });
+    const int64_t nt = n_tiles_side(job.n);
+    std::vector<int64_t> wc((size_t)U);
+    int64_t total_cost = 0;
+    for (int64_t u = 0; u < U; ++u) {
+        wc[(size_t)u] = unit_stage_cost(shape == TileShape::Wide, units[(size_t)u].first, units[(size_t)u].second, nt);
+        total_cost += ns * wc[(size_t)u];
+    }
     // segment lengths around the balanced share (longer ones leave less
     // for the tail workgroups): the candidate with the smallest largest
     // workgroup cost wins
-    const int64_t L0 = (U * ns + G - 1) / G;
+    const int64_t L0 = (total_cost + STAGE_COST * G - 1) / (STAGE_COST * G);
     if (L0 < XCD_MIN_SEGMENT || L0 >= ns) return false;
     int64_t best_L = -1, best_cost = -1;
-    for (int64_t L = std::min({L0 + 4 * ovh, cap, ns - 1}); L >= std::max<int64_t>(XCD_MIN_SEGMENT, L0 - ovh); --L) {
-        const int64_t c = xcd_candidate(U, ns, G, L, ovh, cap, nullptr);
+    for (int64_t L = std::min({L0 + 4 * ovh_st, cap, ns - 1}); L >= std::max<int64_t>(XCD_MIN_SEGMENT, L0 - ovh_st);
+         --L) {
+        const int64_t c = xcd_candidate(wc, ns, G, L, ovh_st * STAGE_COST, cap, nullptr);
         if (c >= 0 && (best_cost < 0 || c < best_cost)) {
             best_cost = c;
             best_L = L;
         }
     }
     if (best_L < 0) return false;
-    const int col_scale = shape == TileShape::Wide ? 2 : 1;
-    std::stable_sort(units.begin(), units.end(), [col_scale](const std::pair<int, int> &a, const std::pair<int, int> &b) {
-        return morton((uint32_t)a.first, (uint32_t)(col_scale * a.second)) <
-               morton((uint32_t)b.first, (uint32_t)(col_scale * b.second));
-    });
     std::vector<std::vector<XSeg>> logical;
-    xcd_candidate(U, ns, G, best_L, ovh, cap, &logical);
+    xcd_candidate(wc, ns, G, best_L, ovh_st * STAGE_COST, cap, &logical);
     // a unit cut into several pieces is shared: flushed with atomics
     std::vector<int> pieces_of(units.size(), 0);
     for (const auto &v : logical)
@@ -276,7 +310,7 @@ SinglePlanArgs single_plan(int32_t n, int64_t t, TileShape shape, int max_wgs, i
     a.n = n;
     a.t = t;
     a.wide = shape == TileShape::Wide ? 1 : 0;
-    a.overhead = piece_overhead(shape);
+    a.overhead = piece_overhead(shape) * STAGE_COST;
     a.cap = shape == TileShape::Wide ? MAX_PIECE_STAGES_WIDE : MAX_PIECE_STAGES;
     if (min_stages < 1) min_stages = 1;
     if (max_wgs < 1) max_wgs = 1;
@@ -285,9 +319,10 @@ SinglePlanArgs single_plan(int32_t n, int64_t t, TileShape shape, int max_wgs, i
     a.grid = std::max<int64_t>(
         1, std::min<int64_t>({(int64_t)max_wgs, (total + min_stages - 1) / min_stages, units * MAX_UNIT_SPLIT}));
     auto none = [](int64_t, int32_t, int32_t, int64_t, int64_t, int64_t) {};
-    // the budget search of make_plan, over the same unit order
-    int64_t lo = a.overhead + 1, hi = a.overhead + total + 1;
-    hi = std::max(hi, (total + a.grid - 1) / a.grid + a.overhead * (units + 1) + 1);
+    // the budget search of make_plan, over the same unit order (total
+    // stages at full cost bound the total cost from above)
+    int64_t lo = a.overhead + STAGE_COST, hi = a.overhead + total * STAGE_COST + 1;
+    hi = std::max(hi, (total * STAGE_COST + a.grid - 1) / a.grid + a.overhead * (units + 1) + 1);
     a.budget = hi;
     while (single_fill(a, none) > a.grid) a.budget = (hi *= 2);
     while (lo < hi) {

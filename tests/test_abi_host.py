@@ -110,6 +110,34 @@ def _check_cover(pieces, jobs, grid):
     return per_wg, n_pieces
 
 
+def stage_cost(p, n, wide):
+    """The planners' cost of one stage of a piece's unit, in sixteenths: a
+    wide window with one of its two tiles outside the triangle (below the
+    diagonal, or past the last tile column) costs 13, any other unit 16."""
+    if not wide:
+        return 16
+    nt = -(-n // 128)
+    vl = p.ti <= p.tj < nt
+    vr = p.ti <= p.tj + 1 < nt
+    return 13 if vl != vr else 16
+
+
+def test_half_windows_are_costed_lower(X):
+    # N = 2048: the eight windows of the odd tile rows that start one tile
+    # left of the diagonal are the only half windows; the linear plan gives
+    # their workgroups more stages than the others
+    X.set_plan_order(X.XENG_PLAN_LINEAR)
+    try:
+        pieces = X.plan_inspect([2048], [32768], 256, 4, True)
+    finally:
+        X.set_plan_order(X.XENG_PLAN_XCD)
+    half = {(p.ti, p.tj) for p in pieces if stage_cost(p, 2048, True) == 13}
+    assert half == {(ti, ti - 1) for ti in range(1, 16, 2)}
+    st_half = [p.t1 - p.t0 for p in pieces if (p.ti, p.tj) in half]
+    st_full = [p.t1 - p.t0 for p in pieces if (p.ti, p.tj) not in half]
+    assert max(st_half) > max(st_full)
+
+
 @pytest.mark.parametrize("wide", [False, True])
 @pytest.mark.parametrize("jobs,grid,min_st", [
     ([(2048, 32768)], 512, 8),
@@ -126,15 +154,19 @@ def test_plan_covers_exactly_once(X, jobs, grid, min_st, wide):
     finally:
         X.set_plan_order(X.XENG_PLAN_XCD)
     stages, n_pieces = _check_cover(pieces, jobs, grid)
-    # balance: the cost of a workgroup, its stages plus a fixed overhead per
-    # piece (prologue and flush), is within one overhead of every other's;
-    # only the last workgroup may have less
-    ovh = 16 if wide else 8
+    # balance: the cost of a workgroup -- its stages, each weighted by its
+    # unit's stage cost, plus a fixed overhead per piece (prologue and
+    # flush) -- is within one overhead and one stage of every other's; only
+    # the last workgroup may have less
+    ovh = (16 if wide else 8) * 16
     ws = sorted(stages)
     assert ws == list(range(len(ws)))
-    cost = np.array([stages[w] + ovh * n_pieces[w] for w in ws])
+    cost = {w: ovh * n_pieces[w] for w in ws}
+    for p in pieces:
+        cost[p.workgroup] += (p.t1 - p.t0 + 63) // 64 * stage_cost(p, jobs[p.job][0], wide)
+    cost = np.array([cost[w] for w in ws])
     if len(cost) > 2:
-        assert cost[:-1].max() - cost[:-1].min() <= ovh
+        assert cost[:-1].max() - cost[:-1].min() <= ovh + 16
         assert cost[-1] <= cost[:-1].max()
 
 
@@ -202,8 +234,9 @@ def test_static_planner_rejects_bad_arguments(X):
                                       (2048, 4096, 256), (256, 5000, 64), (2048, 16_777_215, 256)])
 def test_xcd_plan_covers_exactly_once_and_balances(X, n, t, grid, wide):
     # the XCD-aware order (the default for single jobs): every (pair, sample)
-    # exactly once, no workgroup costlier than under the linear order by
-    # more than one piece overhead, and where it applies the main segments
+    # exactly once, no workgroup costlier (in unweighted stages) than under
+    # the linear order by more than one piece overhead, and where it applies
+    # the main segments
     # of the 32 workgroups of one XCD (physical id % 8) share a time window
     pieces = X.plan_inspect([n], [t], grid, 4, wide)
     stages, n_pieces = _check_cover(pieces, [(n, t)], grid)
@@ -221,5 +254,6 @@ def test_xcd_plan_covers_exactly_once_and_balances(X, n, t, grid, wide):
         last = {}
         for p in pieces:
             last[p.workgroup] = p            # a workgroup's last piece is its main segment
-        for x in (0, 1, 3, 5, 7):            # XCDs wholly inside one window
-            assert len({last[w].t0 for w in range(x, grid, 8)}) == 1
+        for x in (0, 1, 3, 5, 7):            # XCDs wholly inside one window (full units;
+            # a half window's segments are longer, for the same cost)
+            assert len({last[w].t0 for w in range(x, grid, 8) if stage_cost(last[w], n, wide) == 16}) == 1
