@@ -437,7 +437,7 @@ def main():
     ap.add_argument("--data", default="auto", choices=["auto", "uniform", "chime"],
                     help="channel workload data: uniform nibbles (default below N=256) "
                          "or the CHIME-shaped sky + tones + noise")
-    ap.add_argument("--many-channels", type=int, default=256,
+    ap.add_argument("--many-channels", type=int, default=1024,
                     help="HBM-bound N: also time this many channels of the same size "
                          "in one batched launch (0: skip)")
     ap.add_argument("--kernel", default="auto", choices=["auto", "dma4", "general"],

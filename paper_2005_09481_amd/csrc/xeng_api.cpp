@@ -26,6 +26,10 @@
 #include "xeng_plan.h"
 
 namespace xeng {
+// The correlation kernels: general (128 x 128 tiles, any layout), wide
+// (DMA, 128 x 256) and narrow (N <= 64, time split over the waves).
+enum class Kind { General, Wide, Narrow };
+
 hipError_t launch_correlate(const KernelArgs &a, int grid, bool aligned, hipStream_t stream);
 hipError_t launch_correlate_unsigned(const KernelArgs &a, int grid, bool aligned, hipStream_t stream);
 hipError_t launch_presum(const uint8_t *s, int64_t n_samples, int n, int64_t stride, uint32_t re_low, int32_t *sr,
@@ -33,6 +37,7 @@ hipError_t launch_presum(const uint8_t *s, int64_t n_samples, int n, int64_t str
 hipError_t launch_presum_correct(int32_t *acc, int n, int nt, int64_t n_samples, const int32_t *sr,
                                  const int32_t *si, hipStream_t stream);
 hipError_t launch_correlate_dma(const KernelArgs &a, int grid, int waves, hipStream_t stream);
+hipError_t launch_correlate_narrow(const KernelArgs &a, int grid, hipStream_t stream);
 hipError_t init_dma_kernel();
 hipError_t launch_dump(int32_t *acc, int32_t *diag, int n, int nt, int32_t *out, bool reset,
                        hipStream_t stream);
@@ -394,7 +399,9 @@ Tuning tuning_for(DeviceState *st, const PlanJob *jobs, int n_jobs, bool any_dma
 // CU); the general kernel fits two.
 void plan_limits(const DeviceState *st, TileShape shape, const Tuning &tu, int *max_wgs, int *min_stages)
 {
-    const int per_cu = shape == TileShape::Wide ? 1 : std::max(1, tu.wgs_per_cu);
+    const int per_cu = shape == TileShape::Square   ? std::max(1, tu.wgs_per_cu)
+                       : shape == TileShape::Narrow ? NARROW_WGS_PER_CU
+                                                    : 1;
     *max_wgs = st->cu_count * per_cu;
     *min_stages = std::max(1, tu.min_stages);
 }
@@ -484,7 +491,7 @@ struct xeng_batch {
     int64_t skipped_seen = 0;
     bool bound = false;          // the jobs' slots count this batch in ctx->bound
     struct Launch {
-        bool dma;
+        Kind kind;
         int waves;
         uint32_t flags_and;
         int32_t grid;
@@ -597,12 +604,27 @@ JobDesc make_job(const xeng_ctx *c, int32_t slot, const uint8_t *d_samples, int6
     return jd;
 }
 
-// Kernel choice for one job.
+// Kernel choice for one job: the general kernel where the tuning asks for
+// it or the job cannot be read by DMA, else the narrow kernel for N up to
+// 64 and the wide DMA kernel above.
+
 bool use_dma(uint32_t flags, const Tuning &tu) { return tu.kernel != XENG_KERNEL_GENERAL && (flags & JOB_DMA); }
 
-hipError_t launch(const KernelArgs &a, int32_t grid, bool dma, int waves, uint32_t flags_and, hipStream_t stream)
+Kind kind_of(const JobDesc &jd, const Tuning &tu)
 {
-    if (dma) return launch_correlate_dma(a, grid, waves, stream);
+    if (!use_dma(jd.flags, tu)) return Kind::General;
+    return jd.n <= NARROW_MAX_N ? Kind::Narrow : Kind::Wide;
+}
+
+TileShape shape_of(Kind k)
+{
+    return k == Kind::Wide ? TileShape::Wide : k == Kind::Narrow ? TileShape::Narrow : TileShape::Square;
+}
+
+hipError_t launch(const KernelArgs &a, int32_t grid, Kind kind, int waves, uint32_t flags_and, hipStream_t stream)
+{
+    if (kind == Kind::Wide) return launch_correlate_dma(a, grid, waves, stream);
+    if (kind == Kind::Narrow) return launch_correlate_narrow(a, grid, stream);
     return launch_correlate(a, grid, (flags_and & JOB_ALIGNED8) != 0, stream);
 }
 
@@ -679,7 +701,8 @@ int correlate_padded(xeng_ctx *ctx, int32_t slot, const uint8_t *samples, int64_
         if ((rc = get_plan(ctx->st, &pj, 1, dma ? TileShape::Wide : TileShape::Square, tu, &dp)) != XENG_OK) break;
         a.pieces = dp.d_pieces;
         a.wg_off = dp.d_off;
-        if ((e = launch(a, dp.grid, dma, dma_waves(tu), a.job0.flags, stream)) != hipSuccess) {
+        if ((e = launch(a, dp.grid, dma ? Kind::Wide : Kind::General, dma_waves(tu), a.job0.flags, stream)) !=
+            hipSuccess) {
             rc = map_err(e);
             break;
         }
@@ -735,7 +758,7 @@ int validate_jobs(const xeng_job *jobs, int32_t n_jobs, int64_t launches, bool m
 
 // One persistent launch: the jobs of a batch that take the same kernel.
 struct Part {
-    bool dma = false;
+    Kind kind = Kind::General;
     uint32_t flags_and = ~0u;
     std::vector<PlanJob> pj;
     std::vector<JobDesc> descs;
@@ -794,17 +817,18 @@ bool any_dma_job(const JobList &jl)
 
 std::vector<Part> split_by_kernel(const JobList &jl, const Tuning &tu)
 {
-    Part wide, square;
-    wide.dma = true;
+    Part by_kind[3];
+    by_kind[(int)Kind::Wide].kind = Kind::Wide;
+    by_kind[(int)Kind::Narrow].kind = Kind::Narrow;
     for (size_t k = 0; k < jl.descs.size(); ++k) {
-        Part &p = use_dma(jl.descs[k].flags, tu) ? wide : square;
+        Part &p = by_kind[(int)kind_of(jl.descs[k], tu)];
         p.pj.push_back(jl.pj[k]);
         p.descs.push_back(jl.descs[k]);
         p.flags_and &= jl.descs[k].flags;
     }
     std::vector<Part> parts;
-    if (!wide.descs.empty()) parts.push_back(std::move(wide));
-    if (!square.descs.empty()) parts.push_back(std::move(square));
+    for (Kind k : {Kind::Wide, Kind::Narrow, Kind::General})
+        if (!by_kind[(int)k].descs.empty()) parts.push_back(std::move(by_kind[(int)k]));
     return parts;
 }
 
@@ -853,14 +877,14 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
         size_t bytes;
         KernelArgs a;
         int32_t grid;
-        bool dma;
+        Kind kind;
         int waves;
         uint32_t flags_and;
     };
     std::vector<Staged> staged;
     staged.reserve(parts.size());
     for (const Part &part : parts) {
-        const TileShape shape = part.dma ? TileShape::Wide : TileShape::Square;
+        const TileShape shape = shape_of(part.kind);
         int max_wgs, min_stages;
         plan_limits(st, shape, tu, &max_wgs, &min_stages);
         const std::string key = plan_key(part.pj.data(), (int)part.pj.size(), max_wgs, min_stages, shape, tu.order);
@@ -904,14 +928,14 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
         sg.a.pieces = reinterpret_cast<const Piece *>(tbp->d + o_pieces);
         sg.a.wg_off = reinterpret_cast<const int32_t *>(tbp->d + o_off);
         sg.grid = plan->grid;
-        sg.dma = part.dma;
+        sg.kind = part.kind;
         sg.waves = dma_waves(tu);
         sg.flags_and = part.flags_and;
         staged.push_back(sg);
     }
     for (Staged &sg : staged) {
         hipError_t e = hipMemcpyAsync(sg.tb->d, sg.tb->h, sg.bytes, hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess) e = launch(sg.a, sg.grid, sg.dma, sg.waves, sg.flags_and, stream);
+        if (e == hipSuccess) e = launch(sg.a, sg.grid, sg.kind, sg.waves, sg.flags_and, stream);
         if (e == hipSuccess) e = hipEventRecord(sg.tb->ev, stream);
         if (e != hipSuccess) return map_err(e);
         sg.tb->pending = true;
@@ -1040,14 +1064,14 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_
     // held through the launch so that no other thread evicts the plan first
     std::lock_guard<std::mutex> lk(ctx->st->mu);
     const Tuning tu = tuning_for(ctx->st, &pj, 1, (a.job0.flags & JOB_DMA) != 0);
-    const bool dma = use_dma(a.job0.flags, tu);
-    if (!dma && tu.kernel != XENG_KERNEL_GENERAL && ctx->n >= PAD_MIN_N)
+    const Kind kind = kind_of(a.job0, tu);
+    if (kind == Kind::General && tu.kernel != XENG_KERNEL_GENERAL && ctx->n >= PAD_MIN_N)
         return correlate_padded(ctx, slot, d_samples, n_samples, row_stride, tu, stream);
-    rc = get_plan(ctx->st, &pj, 1, dma ? TileShape::Wide : TileShape::Square, tu, &dp);
+    rc = get_plan(ctx->st, &pj, 1, shape_of(kind), tu, &dp);
     if (rc != XENG_OK) return rc;
     a.pieces = dp.d_pieces;
     a.wg_off = dp.d_off;
-    hipError_t e = launch(a, dp.grid, dma, dma_waves(tu), a.job0.flags, stream);
+    hipError_t e = launch(a, dp.grid, kind, dma_waves(tu), a.job0.flags, stream);
     if (e != hipSuccess) return map_err(e);
     ctx->acc_t[(size_t)slot] += n_samples;
     return map_err(publish_count(ctx, slot, stream));
@@ -1216,7 +1240,9 @@ int xeng_correlate_static(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples,
     a.clock = st->clock.load();
     a.pieces = pieces;
     a.wg_off = wg_off;
-    if ((e = launch(a, (int32_t)used, dma, dma_waves(tu), a.job0.flags, stream)) != hipSuccess) return map_err(e);
+    if ((e = launch(a, (int32_t)used, dma ? Kind::Wide : Kind::General, dma_waves(tu), a.job0.flags, stream)) !=
+        hipSuccess)
+        return map_err(e);
     ctx->acc_t[(size_t)slot] += n_samples;
     return map_err(publish_count(ctx, slot, stream));
 }
@@ -1537,11 +1563,13 @@ int xeng_batch_create(const xeng_job *jobs, int32_t n_jobs, xeng_batch **out)
         tu = tuning_for(jl.st, jl.pj.data(), (int)jl.pj.size(), any_dma_job(jl));
     }
     for (const Part &part : split_by_kernel(jl, tu)) {
-        const TileShape shape = part.dma ? TileShape::Wide : TileShape::Square;
-        const int per_cu = part.dma ? 1 : std::max(1, tu.wgs_per_cu);
+        const TileShape shape = shape_of(part.kind);
+        const int per_cu = part.kind == Kind::General  ? std::max(1, tu.wgs_per_cu)
+                           : part.kind == Kind::Narrow ? NARROW_WGS_PER_CU
+                                                       : 1;
         const Plan plan = build_plan(part.pj.data(), (int)part.pj.size(), jl.st->cu_count * per_cu,
                                      std::max(1, tu.min_stages), shape, tu.order);
-        xeng_batch::Launch l{part.dma, dma_waves(tu), part.flags_and, plan.grid, nullptr, nullptr, nullptr};
+        xeng_batch::Launch l{part.kind, dma_waves(tu), part.flags_and, plan.grid, nullptr, nullptr, nullptr};
         b->launches.push_back(l);
         xeng_batch::Launch &lb = b->launches.back();
         const size_t nj = part.descs.size() * sizeof(JobDesc);
@@ -1607,7 +1635,7 @@ int xeng_batch_launch(xeng_batch *b, void *hip_stream)
         a.zeros = b->zeros;
         a.clock = bst ? bst->clock.load() : nullptr;
         a.skip = b->d_skip;
-        if ((e = launch(a, l.grid, l.dma, l.waves, l.flags_and, stream)) != hipSuccess) return map_err(e);
+        if ((e = launch(a, l.grid, l.kind, l.waves, l.flags_and, stream)) != hipSuccess) return map_err(e);
     }
     return XENG_OK;
 }

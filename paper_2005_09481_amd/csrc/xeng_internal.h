@@ -91,9 +91,12 @@ constexpr uint32_t JOB_ALIGNED8 = 2u;   // samples, stride and N are multiples o
 constexpr uint32_t JOB_DMA = 4u;        // samples and stride multiples of 16 bytes, N of 16: DMA kernel
 constexpr uint32_t JOB_FRESH = 8u;      // the slot holds zeros: whole-tile flushes store instead of add
 
-// Work decomposition shapes: 128 x 128 tiles (general kernel) or
-// 128 x 256 workgroup tiles covering two accumulator tiles (DMA kernel).
-enum class TileShape { Square = 0, Wide = 1 };
+// Work decomposition shapes: 128 x 128 tiles (general kernel), 128 x 256
+// workgroup tiles covering two accumulator tiles (DMA kernel), or a narrow
+// job's single 64 x 64 region (narrow kernel, N <= NARROW_MAX_N).
+enum class TileShape { Square = 0, Wide = 1, Narrow = 2 };
+constexpr int NARROW_MAX_N = 64;
+constexpr int NARROW_WGS_PER_CU = 2;   // the narrow kernel's workgroups resident per CU
 
 // One piece of work: tile (ti, tj) of job `job` over samples [t0, t1).
 struct Piece {

@@ -12,7 +12,9 @@ std::vector<std::pair<int, int>> plan_units(int n, TileShape shape)
 {
     std::vector<std::pair<int, int>> u;
     const int nt = n_tiles_side(n);
-    if (shape == TileShape::Square) {
+    if (shape == TileShape::Narrow) {
+        u.emplace_back(0, 0);
+    } else if (shape == TileShape::Square) {
         for (int ti = 0; ti < nt; ++ti)
             for (int tj = ti; tj < nt; ++tj) u.emplace_back(ti, tj);
     } else {
@@ -28,6 +30,8 @@ std::vector<std::pair<int, int>> plan_units(int n, TileShape shape)
 // accumulators to memory.  Measured on the DMA kernel's 128 x 256 tiles at
 // about 16 stage times; a 128 x 128 tile flushes half as much.
 int64_t piece_overhead(TileShape shape) { return shape == TileShape::Wide ? 16 : 8; }
+
+int64_t piece_cap(TileShape shape) { return shape == TileShape::Square ? MAX_PIECE_STAGES : MAX_PIECE_STAGES_WIDE; }
 
 namespace {
 
@@ -71,8 +75,7 @@ Plan make_plan(const PlanJob *jobs, int n_jobs, int max_wgs, int min_stages, Til
     Plan plan;
     if (min_stages < 1) min_stages = 1;
     if (max_wgs < 1) max_wgs = 1;
-    const int64_t cap = cap_override > 0 ? cap_override
-                                         : (shape == TileShape::Wide ? MAX_PIECE_STAGES_WIDE : MAX_PIECE_STAGES);
+    const int64_t cap = cap_override > 0 ? cap_override : piece_cap(shape);
     const int64_t ovh = piece_overhead(shape) * STAGE_COST;
 
     std::vector<UnitRef> units;
@@ -236,7 +239,7 @@ int64_t xcd_candidate(const std::vector<int64_t> &wc, int64_t ns, int64_t G, int
 bool make_plan_xcd(const PlanJob &job, int max_wgs, TileShape shape, Plan *out)
 {
     const int64_t G = max_wgs;
-    if (G < XCDS || G % XCDS != 0 || job.n <= 0 || job.t <= 0) return false;
+    if (G < XCDS || G % XCDS != 0 || job.n <= 0 || job.t <= 0 || shape == TileShape::Narrow) return false;
     std::vector<std::pair<int, int>> units = plan_units(job.n, shape);
     const int64_t U = (int64_t)units.size();
     const int64_t ns = (job.t + STAGE - 1) / STAGE;

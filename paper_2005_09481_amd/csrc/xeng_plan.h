@@ -60,6 +60,10 @@ bool make_plan_xcd(const PlanJob &job, int max_wgs, TileShape shape, Plan *out);
 
 // Stage-equivalents charged per piece (prologue and flush) by the planners.
 int64_t piece_overhead(TileShape shape);
+// Longest piece of a shape's kernel, in stages: its int32 register sums
+// stay exact (the general kernel's B operands carry 16x the samples, the
+// DMA and narrow kernels' A and B operands both do).
+int64_t piece_cap(TileShape shape);
 
 // Plan parameters of one job as make_plan would choose them (grid and
 // budget), for the container-free planner of xeng_plan_single.h; also the
