@@ -354,7 +354,9 @@ int xeng_correlate_reference(const uint8_t *d_samples, int64_t n_samples, int32_
  * persistent launch.  Tiles cut into several pieces are flushed with integer
  * atomic adds, the others with a plain add.  Jobs whose samples pointer and
  * row stride are multiples of 16 bytes and whose N is a multiple of 16 use
- * workgroup tiles of 128 x 256 inputs ("wide"), others 128 x 128.
+ * workgroup tiles of 128 x 256 inputs ("wide") -- or, for N <= 64, the
+ * single 64 x 64 region of tile (0, 0) ("narrow": the workgroup's waves
+ * split the piece's time) -- others 128 x 128.
  */
 typedef struct {
     int32_t job;       /* index into the batch */
@@ -369,7 +371,8 @@ typedef struct {
  * Fill `out` (capacity `cap`) with the pieces the library would launch for
  * jobs of sizes (n_inputs[k], n_samples[k]) on `n_workgroups` workgroups
  * with at least `min_stages` 64-sample stages per piece (0 = library
- * default), for square (wide = 0) or wide (wide = 1) tiles.  Returns the
+ * default), for square (wide = 0), wide (wide = 1) or narrow (wide = 2,
+ * jobs of N <= 64 only) units.  Returns the
  * number of pieces (which may exceed cap: then only cap are written), or a
  * negative status.  A wide piece's tile below the diagonal or past N is
  * computed but not stored.

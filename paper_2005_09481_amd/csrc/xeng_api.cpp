@@ -1433,15 +1433,16 @@ int64_t xeng_plan_inspect(const int32_t *n_inputs, const int64_t *n_samples, int
                           xeng_piece_info *out, int64_t cap)
 {
     if (n_jobs < 0 || (n_jobs > 0 && (!n_inputs || !n_samples)) || n_workgroups < 1 || cap < 0 ||
-        (cap > 0 && !out) || (wide != 0 && wide != 1))
+        (cap > 0 && !out) || wide < 0 || wide > 2)
         return XENG_EINVAL;
     std::vector<PlanJob> pj((size_t)n_jobs);
     for (int32_t k = 0; k < n_jobs; ++k) {
         if (n_inputs[k] < 1 || n_samples[k] < 0 || n_samples[k] > T_MAX) return XENG_EINVAL;
+        if (wide == 2 && n_inputs[k] > NARROW_MAX_N) return XENG_EINVAL;
         pj[(size_t)k] = PlanJob{n_inputs[k], n_samples[k]};
     }
     if (min_stages <= 0) min_stages = g_min_stages.load();
-    const TileShape shape = wide ? TileShape::Wide : TileShape::Square;
+    const TileShape shape = wide == 1 ? TileShape::Wide : wide == 2 ? TileShape::Narrow : TileShape::Square;
     Plan plan = build_plan(pj.data(), n_jobs, n_workgroups, min_stages, shape, g_plan_order.load());
     const int64_t np = (int64_t)plan.pieces.size();
     for (int64_t k = 0; k < np && k < cap; ++k) {
@@ -1450,12 +1451,12 @@ int64_t xeng_plan_inspect(const int32_t *n_inputs, const int64_t *n_samples, int
         const int a = p.tile & 0xFFFF, b = (p.tile >> 16) & 0xFFFF;
         o.job = p.job;
         o.ti = a;
-        o.tj = wide ? 2 * b : b;
+        o.tj = wide == 1 ? 2 * b : b;
         o.atomic = p.t1_atomic < 0 ? 1 : 0;
         o.t0 = p.t0;
         o.t1 = p.t1_atomic & 0x7FFFFFFF;
         o.workgroup = plan.piece_wg[(size_t)k];
-        o.n_tiles = wide ? 2 : 1;
+        o.n_tiles = wide == 1 ? 2 : 1;
     }
     return np;
 }

@@ -568,8 +568,9 @@ class PieceInfo:
     n_tiles: int
 
 
-def plan_inspect(n_inputs, n_samples, n_workgroups: int, min_stages: int = 0, wide: bool = False):
-    """Pieces the library would launch for jobs of these sizes (host only)."""
+def plan_inspect(n_inputs, n_samples, n_workgroups: int, min_stages: int = 0, wide=False):
+    """Pieces the library would launch for jobs of these sizes (host only);
+    ``wide``: False / 0 square tiles, True / 1 wide, 2 narrow (N <= 64)."""
     n = len(n_inputs)
     ni = (ctypes.c_int32 * n)(*n_inputs)
     ns = (ctypes.c_int64 * n)(*n_samples)

@@ -170,6 +170,24 @@ def test_plan_covers_exactly_once(X, jobs, grid, min_st, wide):
         assert cost[-1] <= cost[:-1].max()
 
 
+@pytest.mark.parametrize("jobs,grid,min_st", [
+    ([(64, 4096)], 512, 1), ([(64, 4096)], 512, 4), ([(16, 1), (48, 65), (64, 100_000)], 512, 4),
+    ([(64, 4096)] * 300, 512, 4), ([(32, 63)], 7, 1),
+])
+def test_narrow_plan_covers_exactly_once(X, jobs, grid, min_st):
+    # narrow units (N <= 64): one 64 x 64 region per job, pieces of at most
+    # 1023 stages, a grid of at most 16 workgroups per unit
+    pieces = X.plan_inspect([j[0] for j in jobs], [j[1] for j in jobs], grid, min_st, 2)
+    _check_cover(pieces, jobs, grid)
+    assert all(p.ti == 0 and p.tj == 0 and p.n_tiles == 1 for p in pieces)
+    assert max(p.t1 - p.t0 for p in pieces) <= 1023 * 64
+    assert len({p.workgroup for p in pieces}) <= 16 * len(jobs)
+    L = X.lib()
+    ni = (ctypes.c_int32 * 1)(65)
+    ns = (ctypes.c_int64 * 1)(100)
+    assert L.xeng_plan_inspect(ni, ns, 1, 8, 1, 2, None, 0) == X.XENG_EINVAL   # N > 64 is not narrow
+
+
 def test_plan_random_batches(X):
     rng = np.random.default_rng(0)
     for _ in range(20):
