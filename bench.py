@@ -440,9 +440,9 @@ def main():
     ap.add_argument("--many-channels", type=int, default=1024,
                     help="HBM-bound N: also time this many channels of the same size "
                          "in one batched launch (0: skip)")
-    ap.add_argument("--kernel", default="auto", choices=["auto", "dma4", "general"],
+    ap.add_argument("--kernel", default="auto", choices=["auto", "dma4", "general", "fp8"],
                     help="correlation kernel: the eight-wave DMA kernel (auto), its four-wave "
-                         "instance, or the general 128 x 128 kernel")
+                         "instance, the general 128 x 128 kernel, or its exact FP8 instance")
     ap.add_argument("--plan-order", default="xcd", choices=["xcd", "linear"],
                     help="work order of the single-channel launch (xeng_set_plan_order; never changes results)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -464,7 +464,7 @@ def main():
 
     xeng.set_plan_order({"xcd": xeng.XENG_PLAN_XCD, "linear": xeng.XENG_PLAN_LINEAR}[args.plan_order])
     xeng.set_tuning(0, 0, {"auto": xeng.XENG_KERNEL_AUTO, "dma4": xeng.XENG_KERNEL_DMA4,
-                           "general": xeng.XENG_KERNEL_GENERAL}[args.kernel])
+                           "general": xeng.XENG_KERNEL_GENERAL, "fp8": xeng.XENG_KERNEL_FP8}[args.kernel])
     if args.workload == "serve":
         return bench_serve(args, xeng, synth, torch, np)
     if args.workload == "flagged":
@@ -537,7 +537,8 @@ def main():
     else:
         roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4),
-                    "traffic": measured_traffic() if (n, t) == (2048, 32768) else None}
+                    "traffic": measured_traffic() if (n, t) == (2048, 32768) and args.kernel == "auto"
+                    and args.plan_order == "xcd" else None}
     res = {
         "metric": "Tera-CMAC/s at N=2048 (int8 MFMA util %)",
         "value": round(value, 3),
@@ -549,7 +550,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8",
+        "dtype": "fp8-e4m3" if args.kernel == "fp8" else "int8",
         "data": "synthetic",
         "config": {"workload": (f"CHIME-shaped single channel N={n}, T={t}, 4+4-bit, "
                                 if data == "chime" else

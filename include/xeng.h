@@ -604,6 +604,15 @@ int xeng_server_export_ring(xeng_server *s, int32_t channel, int32_t *ring, int3
 #define XENG_KERNEL_AUTO 0     /* wide DMA kernel (eight waves) where the job allows it, else general */
 #define XENG_KERNEL_GENERAL 1  /* always the general kernel */
 #define XENG_KERNEL_DMA4 2     /* wide DMA kernel with four waves where the job allows it, else general */
+/*
+ * The general kernel's exact FP8 instance for every job: each 4-bit value
+ * as its OCP E4M3 code (exact for every integer of magnitude <= 16), products
+ * on v_mfma_f32_32x32x16_fp8_fp8 with fp32 sums, pieces below 2^17 samples so
+ * that every sum is an exact integer (below 2^24), converted to int32 at the
+ * flush.  The same results as every other kernel (Sec. 4.1: low-bit matrix
+ * units as the way forward).
+ */
+#define XENG_KERNEL_FP8 3
 
 /*
  * Launch tuning: workgroups per compute unit of the general kernel (1 or 2),

@@ -27,11 +27,13 @@
 
 namespace xeng {
 // The correlation kernels: general (128 x 128 tiles, any layout), wide
-// (DMA, 128 x 256) and narrow (N <= 64, time split over the waves).
-enum class Kind { General, Wide, Narrow };
+// (DMA, 128 x 256), narrow (N <= 64, time split over the waves) and the
+// general kernel's exact FP8 instance.
+enum class Kind { General, Wide, Narrow, Fp8 };
 
 hipError_t launch_correlate(const KernelArgs &a, int grid, bool aligned, hipStream_t stream);
 hipError_t launch_correlate_unsigned(const KernelArgs &a, int grid, bool aligned, hipStream_t stream);
+hipError_t launch_correlate_fp8(const KernelArgs &a, int grid, bool aligned, hipStream_t stream);
 hipError_t launch_presum(const uint8_t *s, int64_t n_samples, int n, int64_t stride, uint32_t re_low, int32_t *sr,
                          int32_t *si, hipStream_t stream);
 hipError_t launch_presum_correct(int32_t *acc, int n, int nt, int64_t n_samples, const int32_t *sr,
@@ -608,10 +610,14 @@ JobDesc make_job(const xeng_ctx *c, int32_t slot, const uint8_t *d_samples, int6
 // it or the job cannot be read by DMA, else the narrow kernel for N up to
 // 64 and the wide DMA kernel above.
 
-bool use_dma(uint32_t flags, const Tuning &tu) { return tu.kernel != XENG_KERNEL_GENERAL && (flags & JOB_DMA); }
+bool use_dma(uint32_t flags, const Tuning &tu)
+{
+    return tu.kernel != XENG_KERNEL_GENERAL && tu.kernel != XENG_KERNEL_FP8 && (flags & JOB_DMA);
+}
 
 Kind kind_of(const JobDesc &jd, const Tuning &tu)
 {
+    if (tu.kernel == XENG_KERNEL_FP8) return Kind::Fp8;
     if (!use_dma(jd.flags, tu)) return Kind::General;
     return jd.n <= NARROW_MAX_N ? Kind::Narrow : Kind::Wide;
 }
@@ -621,10 +627,17 @@ TileShape shape_of(Kind k)
     return k == Kind::Wide ? TileShape::Wide : k == Kind::Narrow ? TileShape::Narrow : TileShape::Square;
 }
 
+// Longest piece of a kernel, in stages (0: its shape's default).  The FP8
+// instance's fp32 sums stay exact integers below 2^24: at most 128 per
+// sample, so pieces below 2^17 samples.
+constexpr int64_t MAX_PIECE_STAGES_FP8 = ((1 << 17) - 1) / STAGE;   // 2047 stages
+int64_t cap_of(Kind k) { return k == Kind::Fp8 ? MAX_PIECE_STAGES_FP8 : 0; }
+
 hipError_t launch(const KernelArgs &a, int32_t grid, Kind kind, int waves, uint32_t flags_and, hipStream_t stream)
 {
     if (kind == Kind::Wide) return launch_correlate_dma(a, grid, waves, stream);
     if (kind == Kind::Narrow) return launch_correlate_narrow(a, grid, stream);
+    if (kind == Kind::Fp8) return launch_correlate_fp8(a, grid, (flags_and & JOB_ALIGNED8) != 0, stream);
     return launch_correlate(a, grid, (flags_and & JOB_ALIGNED8) != 0, stream);
 }
 
@@ -817,9 +830,10 @@ bool any_dma_job(const JobList &jl)
 
 std::vector<Part> split_by_kernel(const JobList &jl, const Tuning &tu)
 {
-    Part by_kind[3];
+    Part by_kind[4];
     by_kind[(int)Kind::Wide].kind = Kind::Wide;
     by_kind[(int)Kind::Narrow].kind = Kind::Narrow;
+    by_kind[(int)Kind::Fp8].kind = Kind::Fp8;
     for (size_t k = 0; k < jl.descs.size(); ++k) {
         Part &p = by_kind[(int)kind_of(jl.descs[k], tu)];
         p.pj.push_back(jl.pj[k]);
@@ -827,7 +841,7 @@ std::vector<Part> split_by_kernel(const JobList &jl, const Tuning &tu)
         p.flags_and &= jl.descs[k].flags;
     }
     std::vector<Part> parts;
-    for (Kind k : {Kind::Wide, Kind::Narrow, Kind::General})
+    for (Kind k : {Kind::Wide, Kind::Narrow, Kind::General, Kind::Fp8})
         if (!by_kind[(int)k].descs.empty()) parts.push_back(std::move(by_kind[(int)k]));
     return parts;
 }
@@ -887,7 +901,8 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
         const TileShape shape = shape_of(part.kind);
         int max_wgs, min_stages;
         plan_limits(st, shape, tu, &max_wgs, &min_stages);
-        const std::string key = plan_key(part.pj.data(), (int)part.pj.size(), max_wgs, min_stages, shape, tu.order);
+        const std::string key =
+            plan_key(part.pj.data(), (int)part.pj.size(), max_wgs, min_stages, shape, tu.order, cap_of(part.kind));
         std::shared_ptr<const Plan> plan;
         auto it = st->host_plans.find(key);
         if (it != st->host_plans.end()) {
@@ -896,7 +911,8 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
             st->host_lru.push_front(key);
         } else {
             plan = std::make_shared<const Plan>(
-                build_plan(part.pj.data(), (int)part.pj.size(), max_wgs, min_stages, shape, tu.order));
+                build_plan(part.pj.data(), (int)part.pj.size(), max_wgs, min_stages, shape, tu.order,
+                           cap_of(part.kind)));
             if ((int)st->host_plans.size() >= PLAN_CACHE_MAX) {
                 st->host_plans.erase(st->host_lru.back());
                 st->host_lru.pop_back();
@@ -1067,7 +1083,7 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_
     const Kind kind = kind_of(a.job0, tu);
     if (kind == Kind::General && tu.kernel != XENG_KERNEL_GENERAL && ctx->n >= PAD_MIN_N)
         return correlate_padded(ctx, slot, d_samples, n_samples, row_stride, tu, stream);
-    rc = get_plan(ctx->st, &pj, 1, shape_of(kind), tu, &dp);
+    rc = get_plan(ctx->st, &pj, 1, shape_of(kind), tu, &dp, cap_of(kind));
     if (rc != XENG_OK) return rc;
     a.pieces = dp.d_pieces;
     a.wg_off = dp.d_off;
@@ -1565,11 +1581,11 @@ int xeng_batch_create(const xeng_job *jobs, int32_t n_jobs, xeng_batch **out)
     }
     for (const Part &part : split_by_kernel(jl, tu)) {
         const TileShape shape = shape_of(part.kind);
-        const int per_cu = part.kind == Kind::General  ? std::max(1, tu.wgs_per_cu)
+        const int per_cu = shape == TileShape::Square   ? std::max(1, tu.wgs_per_cu)
                            : part.kind == Kind::Narrow ? NARROW_WGS_PER_CU
                                                        : 1;
         const Plan plan = build_plan(part.pj.data(), (int)part.pj.size(), jl.st->cu_count * per_cu,
-                                     std::max(1, tu.min_stages), shape, tu.order);
+                                     std::max(1, tu.min_stages), shape, tu.order, cap_of(part.kind));
         xeng_batch::Launch l{part.kind, dma_waves(tu), part.flags_and, plan.grid, nullptr, nullptr, nullptr};
         b->launches.push_back(l);
         xeng_batch::Launch &lb = b->launches.back();
@@ -1802,7 +1818,7 @@ int xeng_clock_probe(int32_t device, int64_t *dev_buf)
 
 int xeng_set_tuning(int32_t wgs_per_cu, int32_t min_stages, int32_t kernel)
 {
-    if (wgs_per_cu > 2 || kernel > XENG_KERNEL_DMA4) return XENG_EINVAL;
+    if (wgs_per_cu > 2 || kernel > XENG_KERNEL_FP8) return XENG_EINVAL;
     if (wgs_per_cu > 0) g_wgs_per_cu.store(wgs_per_cu);
     if (min_stages > 0) g_min_stages.store(min_stages);
     if (kernel >= 0) g_kernel.store(kernel);

@@ -26,6 +26,16 @@
 // multiply-adds on GCN3 (Sec. 2.3, "GPUs"); on CDNA4 the int8 matrix cores
 // do this work instead (Sec. 4.1 anticipates low-bit matrix units).
 //
+// FP8 instances (an exact matrix-core path on 8-bit floats, Sec. 4.1's
+// low-bit matrix units) stage every 4-bit value v in [-8, 7] as its OCP
+// E4M3 code (1 sign, 4 exponent bits with bias 7, 3 mantissa bits: every
+// integer of magnitude <= 16 is exact, -v included, so the imaginary
+// operand is [Im | -Re] and carries no bias) and multiply on
+// v_mfma_f32_32x32x16_fp8_fp8 into fp32 accumulators.  Products are
+// exact, and fp32 sums of integers are exact while below 2^24: with at most
+// 128 per sample, pieces below 2^17 samples flush exact integers, converted
+// to int32.
+//
 // UNSIGNED instances multiply the stored nibbles u = x + 8 themselves (the
 // paper's unsigned form, whose O(N) bookkeeping is the pre-sum correction
 // of xeng_presum.hip): A = [uR | uI] and [uI | -uR], B = [8 uR | 8 uI], so
@@ -40,6 +50,7 @@ namespace xeng {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // LDS stage layout.  A stage is 64 samples = 4 MFMA k-steps.  For each
@@ -84,6 +95,24 @@ __device__ __forceinline__ void transpose4(uint32_t i0, uint32_t i1, uint32_t i2
 //   n - 8 = (n + 0x78) ^ 0x80,   7 - n = (0x87 - n) ^ 0x80.
 __device__ __forceinline__ uint32_t nib_to_i8(uint32_t n) { return (n + 0x78787878u) ^ 0x80808080u; }
 __device__ __forceinline__ uint32_t nib_to_not_i8(uint32_t n) { return (0x87878787u - n) ^ 0x80808080u; }
+
+// Offset-binary nibbles (0..15, one per byte) -> the E4M3 codes of v = n - 8,
+// four at a time.  For n >= 8 the code of v = n - 8 in 0..7 is
+// POS[n - 8]; for n < 8, v = -(8 - n) and the code is 0x80 | NEG[n] with
+// NEG[n] the code of 8 - n.  Codes: 1 = 0x38 (2^0), 2 = 0x40, 3 = 0x44
+// (1.5 x 2), 4 = 0x48, 5 = 0x4A (1.25 x 4), 6 = 0x4C, 7 = 0x4E, 8 = 0x50.
+// Each table is eight bytes, read by a byte permute with selector n & 7;
+// bit 3 of n picks the table.
+constexpr uint32_t E4M3_POS_LO = 0x44403800u, E4M3_POS_HI = 0x4E4C4A48u;   // v = 0, 1, .. 7
+constexpr uint32_t E4M3_NEG_LO = 0x4A4C4E50u, E4M3_NEG_HI = 0x38404448u;   // |v| = 8, 7, .. 1
+__device__ __forceinline__ uint32_t nib_to_e4m3(uint32_t n)
+{
+    const uint32_t sel = n & 0x07070707u;
+    const uint32_t pos = vperm(E4M3_POS_HI, E4M3_POS_LO, sel);
+    const uint32_t neg = vperm(E4M3_NEG_HI, E4M3_NEG_LO, sel) | 0x80808080u;
+    const uint32_t hi = ((n >> 3) & 0x01010101u) * 0xFFu;   // 0xFF in the bytes with n >= 8
+    return (pos & hi) | (neg & ~hi);
+}
 
 // Global-memory views: loads through these pointers are global (not flat)
 // instructions, so they only count against the vector-memory counter and
@@ -177,7 +206,7 @@ __device__ __forceinline__ void load_stage(StageRegs &r, const PieceCtx &pc, int
 // Unpack one lane's share of a stage into the stage buffer.  `slot` is the
 // byte offset of this lane's (first input, half) in a component region;
 // input c of the lane sits 16 * c bytes further.
-template <bool ROLE_A, bool RE_LOW, bool UNSIGNED>
+template <bool ROLE_A, bool RE_LOW, bool UNSIGNED, bool FP8>
 __device__ __forceinline__ void stage_write(uint8_t *region, const StageRegs &r, int slot)
 {
     uint32_t lo[8], hi[8];
@@ -226,6 +255,18 @@ __device__ __forceinline__ void stage_write(uint8_t *region, const StageRegs &r,
             }
             continue;
         }
+        if (FP8) {
+            // A rows: Re, Im, -Re; B rows: Re, Im (E4M3 codes; -v flips
+            // the sign bit, exactly)
+            const uint32_t h0 = (p[c][0] >> 4) & 0x0F0F0F0Fu, l0 = p[c][0] & 0x0F0F0F0Fu;
+            const uint32_t h1 = (p[c][1] >> 4) & 0x0F0F0F0Fu, l1 = p[c][1] & 0x0F0F0F0Fu;
+            const uint32_t re0 = nib_to_e4m3(RE_LOW ? l0 : h0), im0 = nib_to_e4m3(RE_LOW ? h0 : l0);
+            const uint32_t re1 = nib_to_e4m3(RE_LOW ? l1 : h1), im1 = nib_to_e4m3(RE_LOW ? h1 : l1);
+            *(uint2 *)(dst) = make_uint2(re0, re1);
+            *(uint2 *)(dst + CH) = make_uint2(im0, im1);
+            if (ROLE_A) *(uint2 *)(dst + 2 * CH) = make_uint2(re0 ^ 0x80808080u, re1 ^ 0x80808080u);
+            continue;
+        }
         if (ROLE_A) {
             const uint32_t h0 = (p[c][0] >> 4) & 0x0F0F0F0Fu, l0 = p[c][0] & 0x0F0F0F0Fu;
             const uint32_t h1 = (p[c][1] >> 4) & 0x0F0F0F0Fu, l1 = p[c][1] & 0x0F0F0F0Fu;
@@ -248,29 +289,40 @@ __device__ __forceinline__ void stage_write(uint8_t *region, const StageRegs &r,
 
 __device__ __forceinline__ v4i lds128(const uint8_t *p) { return *(const v4i *)p; }
 
+// An accumulator register as the integer it holds (fp32 sums of the FP8
+// instances are exact integers below 2^24).
+__device__ __forceinline__ int32_t acc_int(int32_t v) { return v; }
+__device__ __forceinline__ int32_t acc_int(float v) { return (int32_t)v; }
+
 // Accumulators hold 16x the stored values (B operands are scaled by 16), so
 // the flush adds acc >> 4; every value is a multiple of 16, so this is
 // exact.  Pairs go to the slot as packed 64-bit words (see the layout note):
 // a shared tile takes one 64-bit atomic add per pair.
-template <int SHIFT>
-__device__ __forceinline__ void flush_block(gw64 *blk, const v16i &re, const v16i &im)
+template <int SHIFT, typename V>
+__device__ __forceinline__ void flush_block(gw64 *blk, const V &re, const V &im)
 {
 #pragma unroll
     for (int r = 0; r < 16; ++r)
-        __hip_atomic_fetch_add(blk + r * 64, pack_pair(re[r] >> SHIFT, im[r] >> SHIFT), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(blk + r * 64, pack_pair(acc_int(re[r]) >> SHIFT, acc_int(im[r]) >> SHIFT),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-struct Acc {
+template <bool FP8> struct AccT {
     v16i re[2][2];
     v16i im[2][2];
 };
+template <> struct AccT<true> {
+    v16f re[2][2];
+    v16f im[2][2];
+};
+typedef AccT<false> Acc;
+
 
 // Whole-tile flush of one wave's 2 x 2 blocks: stores if the slot holds
 // zeros, else read-modify-write with the loads of a row of blocks issued
 // before their stores (one memory latency per row, not one per value).
-template <int SHIFT>
-__device__ __forceinline__ void flush_owned(gw64 *tb, const Acc &acc, int wa, int wb, bool fresh)
+template <int SHIFT, bool FP8>
+__device__ __forceinline__ void flush_owned(gw64 *tb, const AccT<FP8> &acc, int wa, int wb, bool fresh)
 {
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
@@ -286,13 +338,35 @@ __device__ __forceinline__ void flush_owned(gw64 *tb, const Acc &acc, int wa, in
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                blk[b][r * 64] = old[b][r] + pack_pair(acc.re[a][b][r] >> SHIFT, acc.im[a][b][r] >> SHIFT);
+                blk[b][r * 64] =
+                    old[b][r] + pack_pair(acc_int(acc.re[a][b][r]) >> SHIFT, acc_int(acc.im[a][b][r]) >> SHIFT);
         __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-// The 32 MFMAs of one stage (4 k-steps x 2 x 2 blocks x Re/Im) on `buf`.
-__device__ __forceinline__ void stage_mfma(Acc &acc, const uint8_t *buf, int lane, int wa, int wb)
+// The FP8 form of a k-step's products: each 16-byte operand is two 8-byte
+// E4M3 operands of v_mfma_f32_32x32x16_fp8_fp8 (samples 0..7 of the
+// k-step's Re and Im halves, then samples 8..15).
+__device__ __forceinline__ v16f mfma_fp8(const v4i &a, const v4i &b, v16f c)
+{
+    const long a0 = (long)(((uint64_t)(uint32_t)a.y << 32) | (uint32_t)a.x);
+    const long a1 = (long)(((uint64_t)(uint32_t)a.w << 32) | (uint32_t)a.z);
+    const long b0 = (long)(((uint64_t)(uint32_t)b.y << 32) | (uint32_t)b.x);
+    const long b1 = (long)(((uint64_t)(uint32_t)b.w << 32) | (uint32_t)b.z);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a0, b0, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a1, b1, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ v16i mfma_k(const v4i &a, const v4i &b, v16i c)
+{
+    return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v16f mfma_k(const v4i &a, const v4i &b, v16f c) { return mfma_fp8(a, b, c); }
+
+// The 32 MFMAs of one stage (4 k-steps x 2 x 2 blocks x Re/Im) on `buf`
+// (64 for the FP8 instances, two per block and k-step).
+template <bool FP8>
+__device__ __forceinline__ void stage_mfma(AccT<FP8> &acc, const uint8_t *buf, int lane, int wa, int wb)
 {
 #pragma unroll
     for (int q = 0; q < QSTEPS; ++q) {
@@ -304,14 +378,14 @@ __device__ __forceinline__ void stage_mfma(Acc &acc, const uint8_t *buf, int lan
         const uint8_t *bp = buf + A_BYTES + q * B_Q + (lane >> 5) * CH + 16 * (lane & 31);
         const v4i b0 = lds128(bp + 512 * (2 * wb));
         const v4i b1 = lds128(bp + 512 * (2 * wb + 1));
-        acc.re[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(re_a0, b0, acc.re[0][0], 0, 0, 0);
-        acc.im[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im_a0, b0, acc.im[0][0], 0, 0, 0);
-        acc.re[0][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(re_a0, b1, acc.re[0][1], 0, 0, 0);
-        acc.im[0][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im_a0, b1, acc.im[0][1], 0, 0, 0);
-        acc.re[1][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(re_a1, b0, acc.re[1][0], 0, 0, 0);
-        acc.im[1][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im_a1, b0, acc.im[1][0], 0, 0, 0);
-        acc.re[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(re_a1, b1, acc.re[1][1], 0, 0, 0);
-        acc.im[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im_a1, b1, acc.im[1][1], 0, 0, 0);
+        acc.re[0][0] = mfma_k(re_a0, b0, acc.re[0][0]);
+        acc.im[0][0] = mfma_k(im_a0, b0, acc.im[0][0]);
+        acc.re[0][1] = mfma_k(re_a0, b1, acc.re[0][1]);
+        acc.im[0][1] = mfma_k(im_a0, b1, acc.im[0][1]);
+        acc.re[1][0] = mfma_k(re_a1, b0, acc.re[1][0]);
+        acc.im[1][0] = mfma_k(im_a1, b0, acc.im[1][0]);
+        acc.re[1][1] = mfma_k(re_a1, b1, acc.re[1][1]);
+        acc.im[1][1] = mfma_k(im_a1, b1, acc.im[1][1]);
     }
 }
 
@@ -320,8 +394,8 @@ __device__ __forceinline__ void stage_mfma(Acc &acc, const uint8_t *buf, int lan
 // other LDS buffer and stage s+2 loads from memory.  Steps run in pairs with
 // no early exit: a stage past the end of the piece holds zero samples and
 // adds exactly nothing.
-template <bool ALIGNED, bool ROLE_A, bool RE_LOW, bool UNSIGNED>
-__device__ __forceinline__ void run_piece(Acc &acc, uint8_t *smem, const PieceCtx &pc, int lane,
+template <bool ALIGNED, bool ROLE_A, bool RE_LOW, bool UNSIGNED, bool FP8>
+__device__ __forceinline__ void run_piece(AccT<FP8> &acc, uint8_t *smem, const PieceCtx &pc, int lane,
                                           int wa, int wb, int wslot, bool compute)
 {
     const int nst = (pc.t1 - pc.t0 + STAGE - 1) / STAGE;
@@ -330,17 +404,17 @@ __device__ __forceinline__ void run_piece(Acc &acc, uint8_t *smem, const PieceCt
 
     load_stage<ALIGNED>(r0, pc, 0);
     load_stage<ALIGNED>(r1, pc, 1);
-    stage_write<ROLE_A, RE_LOW, UNSIGNED>(buf0, r0, wslot);
+    stage_write<ROLE_A, RE_LOW, UNSIGNED, FP8>(buf0, r0, wslot);
     __syncthreads();
 
     for (int s = 0; s < nst; s += NBUF) {
         load_stage<ALIGNED>(r0, pc, s + 2);
-        if (compute) stage_mfma(acc, buf0, lane, wa, wb);
-        stage_write<ROLE_A, RE_LOW, UNSIGNED>(buf1, r1, wslot);
+        if (compute) stage_mfma<FP8>(acc, buf0, lane, wa, wb);
+        stage_write<ROLE_A, RE_LOW, UNSIGNED, FP8>(buf1, r1, wslot);
         __syncthreads();
         load_stage<ALIGNED>(r1, pc, s + 3);
-        if (compute) stage_mfma(acc, buf1, lane, wa, wb);
-        stage_write<ROLE_A, RE_LOW, UNSIGNED>(buf0, r0, wslot);
+        if (compute) stage_mfma<FP8>(acc, buf1, lane, wa, wb);
+        stage_write<ROLE_A, RE_LOW, UNSIGNED, FP8>(buf0, r0, wslot);
         __syncthreads();
     }
 }
@@ -351,7 +425,7 @@ __device__ __forceinline__ void run_piece(Acc &acc, uint8_t *smem, const PieceCt
 // waves 0-1 unpack the A (row) block, waves 2-3 the B (column) block; a lane
 // takes 8 inputs x 8 samples (lane bits 0-2 and 4 pick the 8-input group,
 // bit 3 the half of a k-step, bit 5 and the wave the k-step).
-template <bool ALIGNED, bool UNSIGNED>
+template <bool ALIGNED, bool UNSIGNED, bool FP8>
 __global__ __launch_bounds__(256, 2) void xcorr_mfma(KernelArgs args)
 {
     __shared__ __attribute__((aligned(16))) uint8_t smem[NBUF * STAGE_BYTES];
@@ -389,7 +463,7 @@ __global__ __launch_bounds__(256, 2) void xcorr_mfma(KernelArgs args)
         pc.off = (uint32_t)(pc.t_lane * jd.stride) + (uint32_t)pc.i0;
         pc.full_rows = blk0 + TILE <= jd.n;
 
-        Acc acc;
+        AccT<FP8> acc;
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -406,15 +480,17 @@ __global__ __launch_bounds__(256, 2) void xcorr_mfma(KernelArgs args)
         // and flushes nothing
         const bool compute = TILE * ti + 64 * wa < jd.n && TILE * tj + 64 * wb < jd.n;
         if (role_a) {
-            if (re_low) run_piece<ALIGNED, true, true, UNSIGNED>(acc, smem, pc, lane, wa, wb, wslot, compute);
-            else run_piece<ALIGNED, true, false, UNSIGNED>(acc, smem, pc, lane, wa, wb, wslot, compute);
+            if (re_low) run_piece<ALIGNED, true, true, UNSIGNED, FP8>(acc, smem, pc, lane, wa, wb, wslot, compute);
+            else run_piece<ALIGNED, true, false, UNSIGNED, FP8>(acc, smem, pc, lane, wa, wb, wslot, compute);
         } else {
-            if (re_low) run_piece<ALIGNED, false, true, UNSIGNED>(acc, smem, pc, lane, wa, wb, wslot, compute);
-            else run_piece<ALIGNED, false, false, UNSIGNED>(acc, smem, pc, lane, wa, wb, wslot, compute);
+            if (re_low) run_piece<ALIGNED, false, true, UNSIGNED, FP8>(acc, smem, pc, lane, wa, wb, wslot, compute);
+            else run_piece<ALIGNED, false, false, UNSIGNED, FP8>(acc, smem, pc, lane, wa, wb, wslot, compute);
         }
 
-        // integrate into the slot's accumulators
+        // integrate into the slot's accumulators: the signed int8 sums carry
+        // 16x the value, the unsigned 8x, the FP8 ones the value itself
         if (!compute) continue;
+        constexpr int SHIFT = FP8 ? 0 : UNSIGNED ? 3 : 4;
         const int64_t tile_idx = (int64_t)ti * jd.nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);
         gw64 *tb = (gw64 *)(jd.acc + tile_idx * TILE_I32) + lane;
         if (atomic) {
@@ -422,12 +498,12 @@ __global__ __launch_bounds__(256, 2) void xcorr_mfma(KernelArgs args)
             for (int a = 0; a < 2; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b)
-                    flush_block<UNSIGNED ? 3 : 4>(tb + ((2 * wa + a) * BLKS + (2 * wb + b)) * BLOCK_W, acc.re[a][b],
+                    flush_block<SHIFT>(tb + ((2 * wa + a) * BLKS + (2 * wb + b)) * BLOCK_W, acc.re[a][b],
                                 acc.im[a][b]);
         } else if (jd.flags & JOB_FRESH) {
-            flush_owned<UNSIGNED ? 3 : 4>(tb, acc, wa, wb, true);
+            flush_owned<SHIFT, FP8>(tb, acc, wa, wb, true);
         } else {
-            flush_owned<UNSIGNED ? 3 : 4>(tb, acc, wa, wb, false);
+            flush_owned<SHIFT, FP8>(tb, acc, wa, wb, false);
         }
     }
 }
@@ -651,9 +727,21 @@ hipError_t launch_correlate(const KernelArgs &a, int grid, bool aligned, hipStre
 {
     if (grid <= 0) return hipSuccess;
     if (aligned)
-        hipLaunchKernelGGL((xcorr_mfma<true, false>), dim3(grid), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL((xcorr_mfma<true, false, false>), dim3(grid), dim3(256), 0, stream, a);
     else
-        hipLaunchKernelGGL((xcorr_mfma<false, false>), dim3(grid), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL((xcorr_mfma<false, false, false>), dim3(grid), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+// The exact FP8 path: the same kernel with E4M3 operands and fp32 sums
+// (pieces below 2^17 samples).
+hipError_t launch_correlate_fp8(const KernelArgs &a, int grid, bool aligned, hipStream_t stream)
+{
+    if (grid <= 0) return hipSuccess;
+    if (aligned)
+        hipLaunchKernelGGL((xcorr_mfma<true, false, true>), dim3(grid), dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL((xcorr_mfma<false, false, true>), dim3(grid), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -663,9 +751,9 @@ hipError_t launch_correlate_unsigned(const KernelArgs &a, int grid, bool aligned
 {
     if (grid <= 0) return hipSuccess;
     if (aligned)
-        hipLaunchKernelGGL((xcorr_mfma<true, true>), dim3(grid), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL((xcorr_mfma<true, true, false>), dim3(grid), dim3(256), 0, stream, a);
     else
-        hipLaunchKernelGGL((xcorr_mfma<false, true>), dim3(grid), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL((xcorr_mfma<false, true, false>), dim3(grid), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 

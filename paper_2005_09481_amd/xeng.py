@@ -29,6 +29,7 @@ XENG_SERVER_STAGGER_EXPORTS = 2
 XENG_KERNEL_AUTO = 0
 XENG_KERNEL_GENERAL = 1
 XENG_KERNEL_DMA4 = 2
+XENG_KERNEL_FP8 = 3
 XENG_TUNE_SETTINGS = 0
 XENG_TUNE_MEASURED = 1
 XENG_TUNE_CACHE_FILE = 2
@@ -194,8 +195,8 @@ def slot_bytes(n_inputs: int) -> int:
 def set_tuning(wgs_per_cu: int = 0, min_stages: int = 0, kernel: int = -1):
     """Launch tuning (results never depend on it): general-kernel workgroups
     per CU, minimum piece length in 64-sample stages, kernel selection
-    (XENG_KERNEL_AUTO / XENG_KERNEL_GENERAL / XENG_KERNEL_DMA4; -1 keeps the
-    current one)."""
+    (XENG_KERNEL_AUTO / XENG_KERNEL_GENERAL / XENG_KERNEL_DMA4 /
+    XENG_KERNEL_FP8; -1 keeps the current one)."""
     _check(lib().xeng_set_tuning(wgs_per_cu, min_stages, kernel), "xeng_set_tuning")
 
 

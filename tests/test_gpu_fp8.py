@@ -1,0 +1,124 @@
+"""GPU parity of the exact FP8 path (XENG_KERNEL_FP8): every 4-bit value as
+its E4M3 code, products on the FP8 matrix cores with fp32 sums, pieces
+below 2^17 samples so that every sum is an exact integer.  Bit for bit
+against the CPU oracle: ragged shapes, both nibble orders, aligned and
+byte-addressed rows, pieces at the exactness bound with extreme samples,
+batches, and a slot integrated by the int8 and the FP8 kernels in turn."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def X():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_09481_amd import xeng
+    xeng.lib()
+    return xeng
+
+
+@pytest.fixture
+def fp8(X):
+    X.set_tuning(0, 0, X.XENG_KERNEL_FP8)
+    yield
+    X.set_tuning(2, 4, X.XENG_KERNEL_AUTO)
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def run(X, x, re_low=False):
+    c = X.Correlator(x.shape[1], 1, re_low=re_low)
+    try:
+        c.correlate(0, gpu(x))
+        return c.dump(0).cpu().numpy().astype(np.int64)
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("n,t", [(1, 1), (5, 64), (16, 65), (64, 4096), (100, 1000), (128, 128), (129, 300),
+                                 (256, 333), (300, 1000), (512, 2000)])
+def test_fp8_matches_oracle(X, fp8, n, t):
+    print(f"fp8 n={n} t={t}", flush=True)
+    x = synth.uniform_bytes(n, t, seed=5000 + n + t)
+    np.testing.assert_array_equal(run(X, x), oracle.correlate(x))
+
+
+def test_fp8_re_low(X, fp8):
+    x = synth.uniform_bytes(200, 700, seed=5101)
+    np.testing.assert_array_equal(run(X, x, re_low=True), oracle.correlate(x, re_low=True))
+
+
+def test_fp8_byte_addressed_rows(X, fp8):
+    # an odd row stride and base: the byte-load path of the kernel
+    full = synth.uniform_bytes(101, 500, seed=5102)
+    x = gpu(full)[:, 1:100]
+    c = X.Correlator(99, 1)
+    try:
+        c.correlate(0, x)
+        np.testing.assert_array_equal(c.dump(0).cpu().numpy().astype(np.int64), oracle.correlate(full[:, 1:100]))
+    finally:
+        c.close()
+
+
+def test_fp8_pieces_at_the_exactness_bound(X):
+    # every sample (-8, -8): each pair adds 128 per sample.  One workgroup
+    # takes the whole job in pieces of 2047 stages (131008 samples), whose
+    # fp32 sums reach 128 * 131008 = 16,769,024, just under 2^24; every
+    # piece but the last is exactly that long
+    n, t = 128, 2 * 131008 + 4000
+    x = np.zeros((t, n), dtype=np.uint8)
+    X.set_tuning(1, 1 << 20, X.XENG_KERNEL_FP8)
+    try:
+        got = run(X, x)
+    finally:
+        X.set_tuning(2, 4, X.XENG_KERNEL_AUTO)
+    assert (got[:, 0] == 128 * t).all()
+    np.testing.assert_array_equal(got, oracle.correlate(x))
+
+
+def test_fp8_extreme_samples_split(X, fp8):
+    rng = np.random.default_rng(18)
+    n, t = 256, 140_000
+    x = rng.choice(np.array([0x00, 0x0F, 0xF0, 0xFF, 0x80, 0x08, 0x77], dtype=np.uint8), size=(t, n))
+    np.testing.assert_array_equal(run(X, x), oracle.correlate(x))
+
+
+def test_fp8_batch(X, fp8):
+    shapes = [(64, 1000), (256, 700), (100, 333), (512, 129)]
+    xs = [synth.uniform_bytes(n, t, seed=5200 + i) for i, (n, t) in enumerate(shapes)]
+    cs = [X.Correlator(n, 1) for n, _ in shapes]
+    try:
+        X.correlate_batch([(c, 0, gpu(x)) for c, x in zip(cs, xs)])
+        for c, x in zip(cs, xs):
+            np.testing.assert_array_equal(c.dump(0).cpu().numpy().astype(np.int64), oracle.correlate(x))
+    finally:
+        for c in cs:
+            c.close()
+
+
+def test_fp8_and_int8_on_one_slot(X):
+    # the int8 kernels store Im V_ij - S_j (the dump removes S_j through the
+    # diagonal), the FP8 kernel Im V_ij itself; a slot integrated by both in
+    # turn still exports exact visibilities
+    n, t = 256, 3000
+    x = synth.uniform_bytes(n, t, seed=5300)
+    c = X.Correlator(n, 1)
+    try:
+        X.set_tuning(0, 0, X.XENG_KERNEL_AUTO)
+        c.correlate(0, gpu(x[:1000]))
+        X.set_tuning(0, 0, X.XENG_KERNEL_FP8)
+        c.correlate(0, gpu(x[1000:2200]))
+        X.set_tuning(0, 0, X.XENG_KERNEL_GENERAL)
+        c.correlate(0, gpu(x[2200:]))
+        np.testing.assert_array_equal(c.dump(0).cpu().numpy().astype(np.int64), oracle.correlate(x))
+    finally:
+        X.set_tuning(2, 4, X.XENG_KERNEL_AUTO)
+        c.close()
