@@ -172,6 +172,8 @@ def bench_serve(args, xeng, synth, torch, np):
               st["backlog_frames"] <= k * (st["p99_ms"] + 2 * launch_ms) / frame_ms)
         r = {"k": k, "source": "host" if host else "device", "real_time": bool(ok),
              "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+             "max_pass_ms": round(st["max_pass_ms"], 3), "max_launch_call_ms": round(st["max_launch_call_ms"], 3),
+             "max_copy_call_ms": round(st["max_copy_call_ms"], 3),
              "max_ms": round(st["max_ms"], 3), "tcmacs": round(st["tcmacs"], 2),
              "frames_done": st["frames_done"], "dropped": st["frames_dropped"],
              "backlog": st["backlog_frames"], "launches": st["launches"], "dumps": st["dumps"],

@@ -534,6 +534,9 @@ typedef struct {
     double seconds;           /* wall time of the run */
     double tcmacs;            /* integrated CMAC / wall time, 1e12/s */
     double p50_ms, p99_ms, max_ms;   /* frame latency: release -> its launch completed */
+    double max_pass_ms;          /* the real-time loop's longest pass */
+    double max_launch_call_ms;   /* the longest time to queue one launch and its exports */
+    double max_copy_call_ms;     /* the longest time to queue one ingest copy */
 } xeng_server_stats;
 
 typedef struct {

@@ -157,8 +157,11 @@ int Scheduler::run(Executor &ex, double seconds, Stats *stats)
             if (c.start_s < t_start) c.start_s = t_start;
         }
 
+    double prev_pass = -1, max_pass = 0, max_launch_call = 0, max_copy_call = 0;
     while (rc == XENG_OK) {
         const double t = ex.now();
+        if (prev_pass >= 0) max_pass = std::max(max_pass, t - prev_pass);
+        prev_pass = t;
         if (t >= seconds) break;
         // admissions into free slots, by memory
         bool admitted = false;
@@ -182,7 +185,9 @@ int Scheduler::run(Executor &ex, double seconds, Stats *stats)
                     continue;
                 }
                 int64_t tok = -1;
+                const double tc = ex.now();
                 if ((rc = ex.copy(c, (int32_t)k, f, &tok)) != XENG_OK) break;
+                max_copy_call = std::max(max_copy_call, ex.now() - tc);
                 c.copies.push_back({f + 1, tok});
             }
             while (rc == XENG_OK && !c.copies.empty()) {
@@ -230,7 +235,9 @@ int Scheduler::run(Executor &ex, double seconds, Stats *stats)
                 if (f1 == boundary) exports.push_back({(int32_t)k, c.slot, std::max<int64_t>(0, f1 - cf.dump_frames), f1});
             }
             if (!f.ranges.empty()) {
+                const double tl = ex.now();
                 if ((rc = ex.launch(jobs, exports, &f.token)) != XENG_OK) break;
+                max_launch_call = std::max(max_launch_call, ex.now() - tl);
                 for (const Job &e : exports) {
                     Chan &c = chans_[(size_t)e.chan];
                     c.last_dump_first = e.f0;
@@ -268,6 +275,9 @@ int Scheduler::run(Executor &ex, double seconds, Stats *stats)
     stats->backlog_frames = released - frames_done - dropped;
     for (const Chan &c : chans_) stats->waiting += c.state == 0 ? 1 : 0;
     stats->device_bytes = bytes_held();
+    stats->max_pass_ms = 1e3 * max_pass;
+    stats->max_launch_call_ms = 1e3 * max_launch_call;
+    stats->max_copy_call_ms = 1e3 * max_copy_call;
     return rc;
 }
 

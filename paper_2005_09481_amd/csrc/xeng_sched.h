@@ -84,6 +84,9 @@ struct Stats {
     int64_t waiting = 0;           // channels still waiting for a slot or memory at the end
     int64_t device_bytes = 0;      // device memory the server holds for slots and rings
     double seconds = 0, tcmacs = 0, p50_ms = 0, p99_ms = 0, max_ms = 0;
+    // where the real-time loop's time went: its longest pass, and the
+    // longest single launch (with its exports) and ingest copy it queued
+    double max_pass_ms = 0, max_launch_call_ms = 0, max_copy_call_ms = 0;
 };
 
 // Status values are the library's (0 = ok, < 0 = error).

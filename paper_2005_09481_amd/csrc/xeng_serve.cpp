@@ -391,6 +391,9 @@ int xeng_server_run(xeng_server *s, double seconds, xeng_server_stats *stats)
     stats->p50_ms = st.p50_ms;
     stats->p99_ms = st.p99_ms;
     stats->max_ms = st.max_ms;
+    stats->max_pass_ms = st.max_pass_ms;
+    stats->max_launch_call_ms = st.max_launch_call_ms;
+    stats->max_copy_call_ms = st.max_copy_call_ms;
     return rc;
 }
 

@@ -87,7 +87,9 @@ class _ServerStats(ctypes.Structure):
                 ("dumps", ctypes.c_int64), ("backlog_frames", ctypes.c_int64),
                 ("channels_waiting", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("seconds", ctypes.c_double), ("tcmacs", ctypes.c_double),
-                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("max_pass_ms", ctypes.c_double), ("max_launch_call_ms", ctypes.c_double),
+                ("max_copy_call_ms", ctypes.c_double)]
 
 
 class _ServerChannel(ctypes.Structure):
