@@ -119,6 +119,9 @@ __device__ __forceinline__ uint32_t nib_to_e4m3(uint32_t n)
 // stay in flight while the LDS reads and MFMAs of the current stage run.
 typedef __attribute__((address_space(1))) const u32x2 gcu64;
 typedef __attribute__((address_space(1))) const uint8_t gcu8;
+// the same eight bytes at any byte address
+typedef u32x2 u32x2_u __attribute__((aligned(1)));
+typedef __attribute__((address_space(1))) const u32x2_u gcu64u;
 typedef __attribute__((address_space(1))) uint64_t gw64;
 
 // One lane's share of a stage: 8 inputs x 8 consecutive samples of one
@@ -169,24 +172,47 @@ __device__ __forceinline__ void load_clamped(StageRegs &r, const PieceCtx &pc, i
     r.valid = valid;
 }
 
-// Unaligned data, or N not a multiple of 8: byte loads, clamped the same way.
-__device__ __forceinline__ void load_bytes(StageRegs &r, const PieceCtx &pc, int t_first)
+// Unaligned rows (a base or stride not a multiple of 8, or N not a multiple
+// of 8): one 8-byte load per row at any byte address -- global loads run in
+// unaligned-access mode, which the compiler also assumes for align-1 loads.
+// A lane whose eight inputs cross input N - 1 reads the eight bytes that end
+// there and shifts its own down to the bottom, so no load reaches past the
+// row's N bytes; the inputs past N become the zero sample.  For N < 8 the
+// one lane with inputs reads them byte by byte.
+__device__ __forceinline__ void load_unaligned(StageRegs &r, const PieceCtx &pc, int t_first)
 {
+    constexpr uint64_t ZERO8 = 0x8888888888888888ull;
+    const int nb = pc.n - pc.i0;                                  // this lane's inputs that exist
+    const int off = min(pc.i0, pc.n - 8);                         // first byte read (n >= 8)
+    const uint32_t sh = 8u * (uint32_t)(pc.i0 - off);             // bits below this lane's first input
+    const uint64_t keep = nb >= 8 ? ~0ull : nb > 0 ? (1ull << (8 * nb)) - 1 : 0ull;
     uint32_t valid = 0;
+    if (pc.n >= 8) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int t = t_first + k;
-        const bool vt = t < pc.t1;
-        const uint8_t *row = pc.samples + (int64_t)(vt ? t : pc.t0) * pc.stride;
-        uint32_t w[2] = {0, 0};
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool ok = pc.i0 + b < pc.n;
-            const uint32_t x = ((gcu8 *)row)[ok ? pc.i0 + b : 0];
-            w[b >> 2] |= (ok ? x : 0x88u) << (8 * (b & 3));
+        for (int k = 0; k < 8; ++k) {
+            const int t = t_first + k;
+            const bool vt = t < pc.t1;
+            const uint8_t *row = pc.samples + (int64_t)(vt ? t : pc.t0) * pc.stride;
+            uint64_t v = ZERO8;
+            if (nb > 0) {
+                const u32x2 w = *(gcu64u *)(row + off);
+                v = ((((uint64_t)w.y << 32) | w.x) >> sh & keep) | (ZERO8 & ~keep);
+            }
+            r.d[k] = u32x2{(uint32_t)v, (uint32_t)(v >> 32)};
+            valid |= (vt ? 1u : 0u) << k;
         }
-        r.d[k] = u32x2{w[0], w[1]};
-        valid |= (vt ? 1u : 0u) << k;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int t = t_first + k;
+            const bool vt = t < pc.t1;
+            const uint8_t *row = pc.samples + (int64_t)(vt ? t : pc.t0) * pc.stride;
+            uint64_t v = ZERO8;
+            for (int b = 0; b < nb; ++b)
+                v = (v & ~(0xFFull << (8 * b))) | ((uint64_t)((gcu8 *)row)[pc.i0 + b] << (8 * b));
+            r.d[k] = u32x2{(uint32_t)v, (uint32_t)(v >> 32)};
+            valid |= (vt ? 1u : 0u) << k;
+        }
     }
     r.valid = valid;
 }
@@ -196,7 +222,7 @@ __device__ __forceinline__ void load_stage(StageRegs &r, const PieceCtx &pc, int
 {
     const int ts = pc.t0 + s * STAGE;
     if (!ALIGNED)
-        load_bytes(r, pc, ts + pc.t_lane);
+        load_unaligned(r, pc, ts + pc.t_lane);
     else if (pc.full_rows && ts + STAGE <= pc.t1)
         load_fast(r, pc.samples + (int64_t)ts * pc.stride, pc.stride, pc.off);
     else

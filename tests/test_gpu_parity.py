@@ -91,6 +91,26 @@ def test_strides_and_misaligned_base(X, n, stride, offset):
     np.testing.assert_array_equal(got, oracle.correlate(big[:, offset:offset + n]))
 
 
+@pytest.mark.parametrize("n", [3, 7, 8, 9, 15, 23, 100, 131, 250])
+def test_unaligned_rows_every_base_offset(X, n):
+    # rows at every byte offset modulo 8 with a stride that is not a
+    # multiple of 8: one 8-byte load per row at any address; the lane whose
+    # eight inputs cross input N - 1 reads the eight bytes ending there and
+    # shifts (N >= 8), single bytes for N < 8.  T = 70 crosses a stage.
+    t, stride = 70, n + 5
+    big = synth.uniform_bytes(stride + 8, t, seed=4700 + n)
+    for offset in range(8):
+        print(f"unaligned rows n={n} offset={offset}", flush=True)
+        dev = gpu(big)[:, offset:offset + n]
+        c = X.Correlator(n, 1)
+        try:
+            c.correlate(0, dev)
+            got = c.dump(0).cpu().numpy().astype(np.int64)
+        finally:
+            c.close()
+        np.testing.assert_array_equal(got, oracle.correlate(big[:, offset:offset + n]))
+
+
 def test_accumulates_across_calls(X):
     n = 150
     chunks = [37, 1000, 5, 2048, 1]
