@@ -417,6 +417,9 @@ def main():
     ap.add_argument("--settle-ms", type=float, default=300.0,
                     help="untimed steps for this long before the warm-up steps (clock ramp)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ceiling-ms", type=int, default=400,
+                    help="after the timed steps, run the matrix-core ceiling loop (xeng_mfma_ceiling) this "
+                         "long and report it beside the kernel (0: skip)")
     ap.add_argument("--no-clock-probe", action="store_true",
                     help="do not stamp the shader clock of the timed launches")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -570,6 +573,14 @@ def main():
     }
     if hbm_bound and many is not None:
         res["many_channels_one_launch"] = many
+    if not hbm_bound and args.ceiling_ms > 0:
+        # the same chip in the same state, running nothing but int8 MFMAs: the
+        # rate its power limit allows any int8 kernel
+        mac_s, ceil_ghz = xeng.mfma_ceiling(args.ceiling_ms, 0)
+        ceil_frac = 2.0 * mac_s / 1e12 / INT8_PEAK_TOPS
+        res["mfma_ceiling"] = {"tops": round(2.0 * mac_s / 1e12, 1), "frac_of_peak": round(ceil_frac, 4),
+                               "sclk_ghz": round(ceil_ghz, 3), "ms": args.ceiling_ms}
+        res["frac_of_ceiling"] = round(achieved / INT8_PEAK_TOPS / ceil_frac, 4) if ceil_frac > 0 else None
     if args.copy_mib > 0:
         src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device=dev).fill_(1)
         dst = torch.empty_like(src)

@@ -667,6 +667,24 @@ int xeng_set_pad_chunk_bytes(int64_t bytes);
  */
 int xeng_clock_probe(int32_t device, int64_t *dev_buf);
 
+/*
+ * Matrix-core ceiling, for measurement (Table tab:computing puts three
+ * quarters of the node's time in the correlation; this bounds how fast any
+ * int8 kernel can run it here).  Runs, synchronously on `device`'s null
+ * stream for about `ms` milliseconds, a loop of nothing but
+ * v_mfma_i32_32x32x32_i8 on every compute unit in the wide correlation
+ * kernel's shape (eight waves per CU, eight 32 x 32 accumulators per wave)
+ * on operands of the correlator's form that change every instruction, and
+ * stores the int8 MAC/s of the second half (the first lets the clock
+ * settle under the load) and the shader clock of that half, in GHz.  The
+ * chip's power limit holds its clock below the 2.4 GHz its peak is quoted
+ * at under such a load, and the rate follows.  Allocates (device memory,
+ * events) and waits for the device.  XENG_EINVAL for a negative device, ms
+ * outside 10..10000 or null outputs; XENG_EDEVICE, XENG_ENOMEM on HIP
+ * failures.
+ */
+int xeng_mfma_ceiling(int32_t device, int32_t ms, double *mac_per_s, double *sclk_ghz);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxeng.so")
 SOURCES = ["xeng_kernels.hip", "xeng_kernel_dma.hip", "xeng_static.hip", "xeng_flags.hip", "xeng_presum.hip",
-           "xeng_beam.hip", "xeng_narrow.hip",
+           "xeng_beam.hip", "xeng_narrow.hip", "xeng_ceiling.hip",
            "xeng_plan.cpp",
            "xeng_api.cpp", "xeng_sched.cpp", "xeng_serve.cpp"]
 ARCH = "gfx950"

@@ -54,6 +54,10 @@ hipError_t launch_batch_guard(const GuardJob *d_jobs, int n_jobs, int32_t *d_ski
 hipError_t launch_set_count(int64_t *p, int64_t v, hipStream_t stream);
 hipError_t static_scratch_address(void **ptr);
 hipError_t init_beam_kernel();
+double ceiling_macs(int grid, int iters);
+int ceiling_threads();
+hipError_t launch_mfma_ceiling(int grid, int iters, int32_t *out, int64_t *clk, bool stamp_start, bool stamp_end,
+                               hipStream_t stream);
 int64_t beam_image_bytes(int n);
 void beam_image(const int8_t *w, int n, int n_beams, uint8_t *img);
 hipError_t launch_beamform(const uint8_t *s, int64_t n_samples, int n, int64_t stride, uint32_t re_low,
@@ -1814,6 +1818,56 @@ int xeng_clock_probe(int32_t device, int64_t *dev_buf)
     if (!st) return XENG_EDEVICE;
     st->clock.store(dev_buf);
     return XENG_OK;
+}
+
+int xeng_mfma_ceiling(int32_t device, int32_t ms, double *mac_per_s, double *sclk_ghz)
+{
+    if (device < 0 || ms < 10 || ms > 10000 || !mac_per_s || !sclk_ghz) return XENG_EINVAL;
+    DeviceGuard guard(device);
+    if (!guard.ok) return XENG_EDEVICE;
+    DeviceState *st = device_state(device);
+    if (!st) return XENG_EDEVICE;
+    const int grid = st->cu_count;
+    int32_t *d_out = nullptr;
+    int64_t *d_clk = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&d_out, (size_t)grid * ceiling_threads() * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&d_clk, 4 * sizeof(int64_t));
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int iters = 256;
+    float t_ms = 0.f;
+    // one short launch sizes the rest at about 5 ms each
+    if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+    if (e == hipSuccess) e = launch_mfma_ceiling(grid, iters, d_out, d_clk, false, false, nullptr);
+    if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t_ms, e0, e1);
+    if (e == hipSuccess) {
+        const double want = iters * 5.0 / std::max(1e-3, (double)t_ms);
+        iters = (int)std::min(1 << 22, std::max(256, (int)want / 4 * 4));
+        // the first half lets the clock settle under the load; the second is timed
+        const int n = std::max(2, ms / 5), half = n / 2;
+        for (int k = 0; k < half && e == hipSuccess; ++k)
+            e = launch_mfma_ceiling(grid, iters, d_out, d_clk, false, false, nullptr);
+        if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+        for (int k = half; k < n && e == hipSuccess; ++k)
+            e = launch_mfma_ceiling(grid, iters, d_out, d_clk, k == half, k == n - 1, nullptr);
+        if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t_ms, e0, e1);
+        int64_t clk[4] = {0, 0, 0, 0};
+        if (e == hipSuccess) e = hipMemcpy(clk, d_clk, sizeof(clk), hipMemcpyDeviceToHost);
+        if (e == hipSuccess) {
+            *mac_per_s = ceiling_macs(grid, iters) * (n - half) / (t_ms / 1e3);
+            *sclk_ghz = clk[3] > clk[1] ? (double)(clk[2] - clk[0]) / ((double)(clk[3] - clk[1]) / 1e8) / 1e9 : 0.0;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (d_out) (void)hipFree(d_out);
+    if (d_clk) (void)hipFree(d_clk);
+    return map_err(e);
 }
 
 int xeng_set_tuning(int32_t wgs_per_cu, int32_t min_stages, int32_t kernel)

@@ -136,6 +136,8 @@ def lib() -> ctypes.CDLL:
                                     ctypes.POINTER(_PieceInfo), i64]),
         "xeng_set_tuning": (ctypes.c_int, [i32, i32, i32]),
         "xeng_clock_probe": (ctypes.c_int, [i32, vp]),
+        "xeng_mfma_ceiling": (ctypes.c_int, [i32, i32, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double)]),
         "xeng_batch_create": (ctypes.c_int, [ctypes.POINTER(_Job), i32, ctypes.POINTER(vp)]),
         "xeng_batch_launch": (ctypes.c_int, [vp, vp]),
         "xeng_batch_check": (ctypes.c_int, [vp]),
@@ -226,6 +228,15 @@ def clock_probe(buf=None, device: int = 0):
     else:
         ptr = ctypes.c_void_p(0)
     _check(lib().xeng_clock_probe(device, ptr), "xeng_clock_probe")
+
+
+def mfma_ceiling(ms: int = 400, device: int = 0):
+    """Matrix-core ceiling (``xeng_mfma_ceiling``, measurement only): runs a
+    loop of nothing but int8 MFMAs on every CU for about ``ms`` ms and
+    returns (int8 MAC/s of its second half, shader clock in GHz then)."""
+    mac, ghz = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib().xeng_mfma_ceiling(device, ms, ctypes.byref(mac), ctypes.byref(ghz)), "xeng_mfma_ceiling")
+    return mac.value, ghz.value
 
 
 def sclk_ghz(buf) -> float:
