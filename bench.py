@@ -173,7 +173,7 @@ def bench_serve(args, xeng, synth, torch, np):
         r = {"k": k, "source": "host" if host else "device", "real_time": bool(ok),
              "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
              "max_pass_ms": round(st["max_pass_ms"], 3), "max_launch_call_ms": round(st["max_launch_call_ms"], 3),
-             "max_copy_call_ms": round(st["max_copy_call_ms"], 3),
+             "max_copy_call_ms": round(st["max_copy_call_ms"], 3), "frames_gathered": st["frames_gathered"],
              "max_ms": round(st["max_ms"], 3), "tcmacs": round(st["tcmacs"], 2),
              "frames_done": st["frames_done"], "dropped": st["frames_dropped"],
              "backlog": st["backlog_frames"], "launches": st["launches"], "dumps": st["dumps"],
@@ -437,7 +437,7 @@ def main():
                          "(XENG_SERVER_STAGGER_EXPORTS); 0: every channel exports in the same launch")
     ap.add_argument("--serve-k", default="256,288,320,336,352,368,384",
                     help="channel counts to try (device-sourced frames)")
-    ap.add_argument("--serve-host-k", default="16,24,32,40,48",
+    ap.add_argument("--serve-host-k", default="40,48,56,64",
                     help="channel counts to try with pinned-host frames (0 to skip)")
     ap.add_argument("--data", default="auto", choices=["auto", "uniform", "chime"],
                     help="channel workload data: uniform nibbles (default below N=256) "

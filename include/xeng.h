@@ -536,7 +536,9 @@ typedef struct {
     double p50_ms, p99_ms, max_ms;   /* frame latency: release -> its launch completed */
     double max_pass_ms;          /* the real-time loop's longest pass */
     double max_launch_call_ms;   /* the longest time to queue one launch and its exports */
-    double max_copy_call_ms;     /* the longest time to queue one ingest copy */
+    double max_copy_call_ms;     /* the longest time to queue one ingest copy or gather */
+    int64_t frames_gathered;     /* host frames ingested by the gather kernel (the others by
+                                    DMA-engine copies: sources not verified pinned and 16-byte aligned) */
 } xeng_server_stats;
 
 typedef struct {

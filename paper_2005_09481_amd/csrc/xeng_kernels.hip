@@ -644,6 +644,36 @@ __global__ __launch_bounds__(256) void vis_dump_batch(const DumpDesc *__restrict
     dump_block_row(jd.acc, jd.n, jd.nt, jd.diag, jd.out, jd.reset, blockIdx.x, blockIdx.y, stage);
 }
 
+// Ingest of host-sourced frames (the streaming server): up to GATHER_MAX
+// frames of `words` 16-byte words each, every frame from pinned host memory
+// (read over PCIe by the workgroups themselves, no DMA-engine copy) into
+// device memory.  Workgroups (x, f) share frame f; each thread keeps eight
+// 16-byte loads in flight.
+constexpr int GATHER_MAX = 120;
+constexpr int GATHER_WGS_PER_FRAME = 4;
+struct GatherArgs {
+    int32_t n;                       // frames
+    int32_t words;                   // 16-byte words per frame
+    const uint4 *src[GATHER_MAX];    // device-visible addresses of pinned host frames
+    uint4 *dst[GATHER_MAX];
+};
+
+__global__ __launch_bounds__(256) void gather_frames(GatherArgs a)
+{
+    const uint4 *__restrict__ src = a.src[blockIdx.y];
+    uint4 *__restrict__ dst = a.dst[blockIdx.y];
+    const int step = (int)(blockDim.x * gridDim.x);
+    int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    for (; i + 7 * step < a.words; i += 8 * step) {
+        uint4 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = src[i + k * step];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) dst[i + k * step] = v[k];
+    }
+    for (; i < a.words; i += step) dst[i] = src[i];
+}
+
 // Rows of n samples (any stride and alignment) copied into rows of n16 = n
 // rounded up to 16 bytes, padded with zero samples (0x88): a layout the DMA
 // kernel reads.  Workgroup t copies row t, one output dword per thread and
@@ -810,6 +840,26 @@ hipError_t launch_pad_rows(const uint8_t *src, int64_t stride, int n, int64_t ro
     if (rows <= 0) return hipSuccess;
     hipLaunchKernelGGL(pad_rows, dim3((unsigned)rows), dim3(256), 0, stream, src, stride, n, n16, dst);
     return hipGetLastError();
+}
+
+// `n` frames of `bytes` each (a multiple of 16, below 2^31), every address
+// 16-byte aligned; any number of frames (GATHER_MAX per launch).
+hipError_t launch_gather_frames(const uint8_t *const *src, uint8_t *const *dst, int n, int64_t bytes,
+                                hipStream_t stream)
+{
+    for (int f0 = 0; f0 < n; f0 += GATHER_MAX) {
+        GatherArgs a;
+        a.n = std::min(GATHER_MAX, n - f0);
+        a.words = (int32_t)(bytes / 16);
+        for (int k = 0; k < a.n; ++k) {
+            a.src[k] = reinterpret_cast<const uint4 *>(src[f0 + k]);
+            a.dst[k] = reinterpret_cast<uint4 *>(dst[f0 + k]);
+        }
+        hipLaunchKernelGGL(gather_frames, dim3(GATHER_WGS_PER_FRAME, (unsigned)a.n), dim3(256), 0, stream, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_zero(int32_t *p, int64_t n_i32, hipStream_t stream)

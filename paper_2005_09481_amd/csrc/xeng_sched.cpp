@@ -200,6 +200,12 @@ int Scheduler::run(Executor &ex, double seconds, Stats *stats)
             }
         }
         if (rc != XENG_OK) break;
+        // the pass's ingest copies, together
+        {
+            const double tc = ex.now();
+            if ((rc = ex.flush()) != XENG_OK) break;
+            max_copy_call = std::max(max_copy_call, ex.now() - tc);
+        }
         if ((rc = retire(false)) != XENG_OK) break;
         // one batched launch over every channel's available frames
         if (t >= next_launch && (int)inflight.size() < cf.max_inflight) {

@@ -100,7 +100,11 @@ public:
     virtual void start() = 0;
     // host source: start copying frame `frame` of channel `chan` into its
     // ring slot frame % ring_frames; `token` names the copy's completion
+    // (an executor may hold copies back until flush)
     virtual int copy(const Chan &c, int32_t chan, int64_t frame, int64_t *token) = 0;
+    // start every copy held back so far: called once per pass of the loop,
+    // after its releases
+    virtual int flush() { return 0; }
     // one batched launch over `jobs` (possibly none), then the exports, in
     // order after everything queued before; `token` names its completion
     virtual int launch(const std::vector<Job> &jobs, const std::vector<Job> &exports, int64_t *token) = 0;

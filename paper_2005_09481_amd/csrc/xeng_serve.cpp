@@ -10,9 +10,11 @@
 // allocated when a channel first takes the slot and kept for later
 // channels) and of host sources' rings (kept for the next host source), the
 // free device memory that admission weighs them against, copy streams for
-// host frames (channel k on stream k % COPY_STREAMS, so one channel's
-// copies complete in order while several DMA engines share the ingest), one
-// compute stream for the batched correlation launches
+// host frames (the due frames of every host source in one gather kernel per
+// pass of the loop, the workgroups reading pinned host memory over PCIe,
+// gathers taking the streams in turn; a source that is not verified pinned
+// and 16-byte aligned is copied frame by frame instead, channel k on stream
+// k % COPY_STREAMS), one compute stream for the batched correlation launches
 // (xeng_correlate_batch), the exports due after each (xeng_dump_batch, into
 // one device buffer per slot) and slot resets, and events for completion.
 #include <hip/hip_runtime.h>
@@ -23,6 +25,8 @@
 #include <cstring>
 #include <new>
 #include <thread>
+#include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/xeng.h"
@@ -30,14 +34,18 @@
 
 namespace xeng {
 int create_ctx(const xeng_config *cfg, hipStream_t stream, xeng_ctx **out);
+hipError_t launch_gather_frames(const uint8_t *const *src, uint8_t *const *dst, int n, int64_t bytes,
+                                hipStream_t stream);
 }
 
 namespace {
 
 using Clock = std::chrono::steady_clock;
 
-// Measured with 256-sample frames of N=2048 (512 KiB copies): one stream
-// sustained 24 host-sourced channels, four 40, eight fewer than four.
+// Streams for host frames (gathers, and copies of the frames that cannot be
+// gathered).  Copies alone, measured with 256-sample frames of N=2048 (512
+// KiB copies): one stream sustained 24 host-sourced channels, four 40, eight
+// fewer than four.
 constexpr int COPY_STREAMS = 4;
 
 // Device memory admission leaves free (for the library's plans and staging
@@ -56,6 +64,7 @@ struct Range {
 // Device-side state of a channel (its scheduling state lives in the core).
 struct ChanMem {
     const uint8_t *src = nullptr;  // [src_frames][frame_len][N], device or pinned host
+    const uint8_t *src_dev = nullptr;  // host source the gather kernel reads: its device-visible address
     uint8_t *ring = nullptr;       // device ring of a host source (while it streams)
     int32_t *exports = nullptr;    // caller's export ring ([n_exports][N(N+1)/2][2]) or null
     int32_t n_exports = 0;
@@ -77,8 +86,16 @@ struct xeng_server {
     hipStream_t compute = nullptr;
     std::vector<hipStream_t> copy;       // COPY_STREAMS ingest streams
     std::vector<hipEvent_t> event_pool;  // recorded events no longer named by a token
-    std::vector<hipEvent_t> tokens;      // token -> event
+    std::vector<hipEvent_t> tokens;      // token -> event (the copies of one gather share one)
     std::vector<int64_t> free_tokens;
+    std::unordered_map<hipEvent_t, int> ev_refs;   // tokens naming each event
+    // copies held for the next gather: sources, ring destinations, and the
+    // event their tokens name (recorded after the gather)
+    std::vector<const uint8_t *> g_src;
+    std::vector<uint8_t *> g_dst;
+    hipEvent_t g_ev = nullptr;
+    int64_t g_next = 0;                  // gathers so far: the copy streams take them in turn
+    int64_t gathered = 0;                // frames gathered in the current run
 };
 
 namespace {
@@ -97,11 +114,49 @@ public:
         Range r("xeng server: ingest copy");
         const ChanMem &m = s_->mem[(size_t)chan];
         uint8_t *dst = m.ring + (frame % s_->cfg.ring_frames) * s_->frame_bytes;
+        if (m.src_dev) {
+            // held for this pass's gather
+            if (!s_->g_ev) {
+                if ((s_->g_ev = take_event()) == nullptr) return XENG_EDEVICE;
+                s_->ev_refs[s_->g_ev] = 0;
+            }
+            s_->g_src.push_back(m.src_dev + (frame % c.src_frames) * s_->frame_bytes);
+            s_->g_dst.push_back(dst);
+            ++s_->ev_refs[s_->g_ev];
+            *token = name(s_->g_ev);
+            return XENG_OK;
+        }
         const uint8_t *src = m.src + (frame % c.src_frames) * s_->frame_bytes;
         hipStream_t st = s_->copy[(size_t)chan % s_->copy.size()];
         if (hipMemcpyAsync(dst, src, (size_t)s_->frame_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
             return XENG_EDEVICE;
         return record(st, token);
+    }
+
+    // The copies held this pass: one gather kernel, then their shared
+    // event.  Gathers take the copy streams in turn: a gather cannot start
+    // while a correlation launch holds every CU, and those queued meanwhile
+    // then run side by side (one stream held the ingest to 48 channels of
+    // N=2048, four reach 56; holding copies back for larger gathers, which
+    // keep more CUs from the next correlation launch, did worse).  A
+    // channel's frames become available in order whatever order gathers
+    // complete in: its copies are polled front first.
+    int flush() override { return gather(); }
+
+    int gather()
+    {
+        if (s_->g_src.empty()) return XENG_OK;
+        Range r("xeng server: ingest gather");
+        hipStream_t st = s_->copy[(size_t)(s_->g_next++ % (int64_t)s_->copy.size())];
+        const hipError_t e = xeng::launch_gather_frames(s_->g_src.data(), s_->g_dst.data(), (int)s_->g_src.size(),
+                                                        s_->frame_bytes, st);
+        s_->gathered += (int64_t)s_->g_src.size();
+        s_->g_src.clear();
+        s_->g_dst.clear();
+        hipEvent_t ev = s_->g_ev;
+        s_->g_ev = nullptr;
+        if (e != hipSuccess || hipEventRecord(ev, st) != hipSuccess) return XENG_EDEVICE;
+        return XENG_OK;
     }
 
     int launch(const std::vector<xeng::sched::Job> &jobs, const std::vector<xeng::sched::Job> &exports,
@@ -205,6 +260,12 @@ public:
     int poll(int64_t token, bool wait) override
     {
         hipEvent_t e = s_->tokens[(size_t)token];
+        if (e == s_->g_ev) {
+            // a copy still held for the gather (its event not yet recorded)
+            if (!wait) return 0;
+            const int rc = gather();
+            if (rc != XENG_OK) return rc;
+        }
         const hipError_t q = wait ? hipEventSynchronize(e) : hipEventQuery(e);
         if (q == hipErrorNotReady) return 0;
         return q == hipSuccess ? 1 : XENG_EDEVICE;
@@ -212,7 +273,12 @@ public:
 
     void release(int64_t token) override
     {
-        s_->event_pool.push_back(s_->tokens[(size_t)token]);
+        hipEvent_t e = s_->tokens[(size_t)token];
+        auto it = s_->ev_refs.find(e);
+        if (it != s_->ev_refs.end() && --it->second == 0) {
+            s_->ev_refs.erase(it);
+            s_->event_pool.push_back(e);
+        }
         s_->tokens[(size_t)token] = nullptr;
         s_->free_tokens.push_back(token);
     }
@@ -220,19 +286,20 @@ public:
     void idle() override { std::this_thread::sleep_for(std::chrono::microseconds(20)); }
 
 private:
-    int record(hipStream_t stream, int64_t *token)
+    hipEvent_t take_event()
     {
         hipEvent_t e = nullptr;
         if (!s_->event_pool.empty()) {
             e = s_->event_pool.back();
             s_->event_pool.pop_back();
         } else if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-            return XENG_EDEVICE;
+            return nullptr;
         }
-        if (hipEventRecord(e, stream) != hipSuccess) {
-            s_->event_pool.push_back(e);
-            return XENG_EDEVICE;
-        }
+        return e;
+    }
+
+    int64_t name(hipEvent_t e)
+    {
         int64_t k;
         if (!s_->free_tokens.empty()) {
             k = s_->free_tokens.back();
@@ -242,7 +309,19 @@ private:
             k = (int64_t)s_->tokens.size();
             s_->tokens.push_back(e);
         }
-        *token = k;
+        return k;
+    }
+
+    int record(hipStream_t stream, int64_t *token)
+    {
+        hipEvent_t e = take_event();
+        if (!e) return XENG_EDEVICE;
+        if (hipEventRecord(e, stream) != hipSuccess) {
+            s_->event_pool.push_back(e);
+            return XENG_EDEVICE;
+        }
+        s_->ev_refs[e] = 1;
+        *token = name(e);
         return XENG_OK;
     }
 
@@ -250,15 +329,47 @@ private:
     Clock::time_point t0_;
 };
 
+// A host source the gather kernel may read in place: pinned host memory
+// holding all its frames in one allocation, 16-byte aligned, with frames of
+// a multiple of 16 bytes.  Returns its device-visible address, or null (the
+// source is then copied frame by frame).
+const uint8_t *gather_source(const xeng_server *s, const uint8_t *frames, int64_t n_frames)
+{
+    if (s->frame_bytes % 16 != 0 || s->frame_bytes >= (INT64_C(1) << 31) ||
+        reinterpret_cast<uintptr_t>(frames) % 16 != 0 || n_frames > INT64_MAX / s->frame_bytes)
+        return nullptr;
+    if (hipSetDevice(s->cfg.device) != hipSuccess) return nullptr;
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, frames) != hipSuccess || at.type != hipMemoryTypeHost || !at.devicePointer)
+        return nullptr;
+    void *start = nullptr;
+    size_t size = 0;
+    hipDeviceptr_t p = const_cast<uint8_t *>(frames);
+    if (hipPointerGetAttribute(&start, HIP_POINTER_ATTRIBUTE_RANGE_START_ADDR, p) != hipSuccess ||
+        hipPointerGetAttribute(&size, HIP_POINTER_ATTRIBUTE_RANGE_SIZE, p) != hipSuccess)
+        return nullptr;
+    const uintptr_t lo = reinterpret_cast<uintptr_t>(start), hi = lo + size;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(frames);
+    if (a < lo || (uint64_t)n_frames * (uint64_t)s->frame_bytes > hi - a) return nullptr;
+    // the device view of `frames` itself (both fields name the same byte,
+    // whether they are given for the allocation's start or for the pointer)
+    const uint8_t *dev = static_cast<const uint8_t *>(at.devicePointer);
+    if (at.hostPointer) dev += a - reinterpret_cast<uintptr_t>(at.hostPointer);
+    return reinterpret_cast<uintptr_t>(dev) % 16 == 0 ? dev : nullptr;
+}
+
 void destroy_server(xeng_server *s)
 {
     if (s->compute) (void)hipStreamSynchronize(s->compute);
     for (hipStream_t c : s->copy)
         if (c) (void)hipStreamSynchronize(c);
     for (uint8_t *r : s->rings) (void)hipFree(r);
+    // every event once: the copies of one gather share theirs
+    std::unordered_set<hipEvent_t> evs(s->event_pool.begin(), s->event_pool.end());
     for (hipEvent_t e : s->tokens)
-        if (e) (void)hipEventDestroy(e);
-    for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
+        if (e) evs.insert(e);
+    if (s->g_ev) evs.insert(s->g_ev);
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
     if (s->compute) (void)hipStreamDestroy(s->compute);
     for (hipStream_t c : s->copy)
         if (c) (void)hipStreamDestroy(c);
@@ -362,6 +473,7 @@ int xeng_server_admit(xeng_server *s, const uint8_t *frames, int64_t n_frames, i
         return XENG_EINVAL;
     ChanMem m;
     m.src = frames;
+    if (host_frames) m.src_dev = gather_source(s, frames, n_frames);
     s->mem.push_back(m);
     *channel = s->sch->admit(n_frames, host_frames != 0, start_s, total_frames);
     return XENG_OK;
@@ -374,9 +486,13 @@ int xeng_server_run(xeng_server *s, double seconds, xeng_server_stats *stats)
     HipExec ex(s);
     xeng::sched::Stats st;
     int rc;
+    s->gathered = 0;
     {
         Range r("xeng server: run");
         rc = s->sch->run(ex, seconds, &st);
+        // nothing stays held for a gather between runs
+        const int rf = ex.gather();
+        if (rc == XENG_OK) rc = rf;
     }
     stats->frames_released = st.frames_released;
     stats->frames_done = st.frames_done;
@@ -394,6 +510,7 @@ int xeng_server_run(xeng_server *s, double seconds, xeng_server_stats *stats)
     stats->max_pass_ms = st.max_pass_ms;
     stats->max_launch_call_ms = st.max_launch_call_ms;
     stats->max_copy_call_ms = st.max_copy_call_ms;
+    stats->frames_gathered = s->gathered;
     return rc;
 }
 

@@ -89,7 +89,8 @@ class _ServerStats(ctypes.Structure):
                 ("seconds", ctypes.c_double), ("tcmacs", ctypes.c_double),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
                 ("max_pass_ms", ctypes.c_double), ("max_launch_call_ms", ctypes.c_double),
-                ("max_copy_call_ms", ctypes.c_double)]
+                ("max_copy_call_ms", ctypes.c_double),
+                ("frames_gathered", ctypes.c_int64)]
 
 
 class _ServerChannel(ctypes.Structure):

@@ -110,8 +110,8 @@ def test_admission_waits_for_a_free_slot(X):
 
 
 def test_host_sourced_frames(X):
-    # pinned host frames, copied into each channel's device ring on release;
-    # five channels over the server's four copy streams, so two share one
+    # pinned host frames, gathered into each channel's device ring on
+    # release (one gather kernel per pass over every due frame)
     srcs = [frames_of(seed=[7, c], n_frames=40) for c in range(5)]
     srv = X.Server(N, dump_frames=DUMP, max_channels=5, ring_frames=16, launch_period_us=2000.0)
     hosts = [torch.from_numpy(f).pin_memory() for f in srcs]
@@ -119,6 +119,32 @@ def test_host_sourced_frames(X):
     st = srv.run(0.3)
     print("host frames", st, flush=True)
     assert st["frames_dropped"] == 0 and st["frames_done"] == 5 * 2 * DUMP
+    assert st["frames_gathered"] == 5 * 2 * DUMP
+    for c, f in zip(chans, srcs):
+        np.testing.assert_array_equal(srv.last_dump(c).cpu().numpy(), expected(f, DUMP))
+    srv.close()
+
+
+def test_host_frames_copied_when_not_gatherable(X):
+    # pinned sources at an odd address cannot be gathered with 16-byte
+    # loads: they are copied frame by frame on the copy streams (five
+    # channels over four streams, so two share one), beside a gathered one
+    srcs = [frames_of(seed=[8, c], n_frames=40) for c in range(6)]
+    srv = X.Server(N, dump_frames=DUMP, max_channels=6, ring_frames=16, launch_period_us=2000.0)
+    hosts = []
+    for c, f in enumerate(srcs):
+        if c == 5:
+            hosts.append(torch.from_numpy(f).pin_memory())
+            continue
+        raw = torch.empty(f.size + 1, dtype=torch.uint8).pin_memory()
+        view = raw[1:].view(f.shape)
+        view.copy_(torch.from_numpy(f))
+        hosts.append(view)
+    chans = [srv.admit(h, start_s=0.0005 * c, total_frames=2 * DUMP) for c, h in enumerate(hosts)]
+    st = srv.run(0.3)
+    print("copied host frames", st, flush=True)
+    assert st["frames_dropped"] == 0 and st["frames_done"] == 6 * 2 * DUMP
+    assert st["frames_gathered"] == 2 * DUMP
     for c, f in zip(chans, srcs):
         np.testing.assert_array_equal(srv.last_dump(c).cpu().numpy(), expected(f, DUMP))
     srv.close()
