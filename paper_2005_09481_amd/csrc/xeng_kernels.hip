@@ -651,21 +651,22 @@ __global__ __launch_bounds__(256) void vis_dump_batch(const DumpDesc *__restrict
 // 16-byte loads in flight.
 constexpr int GATHER_MAX = 120;
 constexpr int GATHER_WGS_PER_FRAME = 4;
+typedef unsigned int gv4u __attribute__((ext_vector_type(4)));
 struct GatherArgs {
     int32_t n;                       // frames
     int32_t words;                   // 16-byte words per frame
-    const uint4 *src[GATHER_MAX];    // device-visible addresses of pinned host frames
-    uint4 *dst[GATHER_MAX];
+    const gv4u *src[GATHER_MAX];     // device-visible addresses of pinned host frames
+    gv4u *dst[GATHER_MAX];
 };
 
 __global__ __launch_bounds__(256) void gather_frames(GatherArgs a)
 {
-    const uint4 *__restrict__ src = a.src[blockIdx.y];
-    uint4 *__restrict__ dst = a.dst[blockIdx.y];
+    const gv4u *__restrict__ src = a.src[blockIdx.y];
+    gv4u *__restrict__ dst = a.dst[blockIdx.y];
     const int step = (int)(blockDim.x * gridDim.x);
     int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     for (; i + 7 * step < a.words; i += 8 * step) {
-        uint4 v[8];
+        gv4u v[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) v[k] = src[i + k * step];
 #pragma unroll
@@ -852,8 +853,8 @@ hipError_t launch_gather_frames(const uint8_t *const *src, uint8_t *const *dst, 
         a.n = std::min(GATHER_MAX, n - f0);
         a.words = (int32_t)(bytes / 16);
         for (int k = 0; k < a.n; ++k) {
-            a.src[k] = reinterpret_cast<const uint4 *>(src[f0 + k]);
-            a.dst[k] = reinterpret_cast<uint4 *>(dst[f0 + k]);
+            a.src[k] = reinterpret_cast<const gv4u *>(src[f0 + k]);
+            a.dst[k] = reinterpret_cast<gv4u *>(dst[f0 + k]);
         }
         hipLaunchKernelGGL(gather_frames, dim3(GATHER_WGS_PER_FRAME, (unsigned)a.n), dim3(256), 0, stream, a);
         const hipError_t e = hipGetLastError();
