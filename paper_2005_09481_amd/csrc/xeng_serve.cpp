@@ -338,19 +338,22 @@ const uint8_t *gather_source(const xeng_server *s, const uint8_t *frames, int64_
     if (s->frame_bytes % 16 != 0 || s->frame_bytes >= (INT64_C(1) << 31) ||
         reinterpret_cast<uintptr_t>(frames) % 16 != 0 || n_frames > INT64_MAX / s->frame_bytes)
         return nullptr;
-    if (hipSetDevice(s->cfg.device) != hipSuccess) return nullptr;
+    // the caller's current device is restored on return
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(s->cfg.device) != hipSuccess) return nullptr;
     hipPointerAttribute_t at;
-    if (hipPointerGetAttributes(&at, frames) != hipSuccess || at.type != hipMemoryTypeHost || !at.devicePointer)
-        return nullptr;
     void *start = nullptr;
     size_t size = 0;
     hipDeviceptr_t p = const_cast<uint8_t *>(frames);
-    if (hipPointerGetAttribute(&start, HIP_POINTER_ATTRIBUTE_RANGE_START_ADDR, p) != hipSuccess ||
-        hipPointerGetAttribute(&size, HIP_POINTER_ATTRIBUTE_RANGE_SIZE, p) != hipSuccess)
-        return nullptr;
+    const bool ok = hipPointerGetAttributes(&at, frames) == hipSuccess && at.type == hipMemoryTypeHost &&
+                    at.devicePointer &&
+                    hipPointerGetAttribute(&start, HIP_POINTER_ATTRIBUTE_RANGE_START_ADDR, p) == hipSuccess &&
+                    hipPointerGetAttribute(&size, HIP_POINTER_ATTRIBUTE_RANGE_SIZE, p) == hipSuccess;
+    (void)hipSetDevice(prev);
+    if (!ok) return nullptr;
     const uintptr_t lo = reinterpret_cast<uintptr_t>(start), hi = lo + size;
     const uintptr_t a = reinterpret_cast<uintptr_t>(frames);
-    if (a < lo || (uint64_t)n_frames * (uint64_t)s->frame_bytes > hi - a) return nullptr;
+    if (a < lo || a >= hi || (uint64_t)n_frames * (uint64_t)s->frame_bytes > hi - a) return nullptr;
     // the device view of `frames` itself (both fields name the same byte,
     // whether they are given for the allocation's start or for the pointer)
     const uint8_t *dev = static_cast<const uint8_t *>(at.devicePointer);
