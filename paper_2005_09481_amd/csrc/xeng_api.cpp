@@ -39,6 +39,7 @@ hipError_t launch_presum(const uint8_t *s, int64_t n_samples, int n, int64_t str
 hipError_t launch_presum_correct(int32_t *acc, int n, int nt, int64_t n_samples, const int32_t *sr,
                                  const int32_t *si, hipStream_t stream);
 hipError_t launch_correlate_dma(const KernelArgs &a, int grid, int waves, hipStream_t stream);
+hipError_t launch_correlate_dma_unsigned(const KernelArgs &a, int grid, hipStream_t stream);
 hipError_t launch_correlate_narrow(const KernelArgs &a, int grid, hipStream_t stream);
 hipError_t init_dma_kernel();
 hipError_t launch_dump(int32_t *acc, int32_t *diag, int n, int nt, int32_t *out, bool reset,
@@ -197,7 +198,8 @@ TuneClass tune_class(const PlanJob *jobs, int n_jobs, bool any_dma)
 struct DeviceState {
     int device = 0;
     int cu_count = 0;
-    uint8_t *d_zeros = nullptr;   // ZERO_BYTES zero samples (0x88) for the DMA kernel
+    uint8_t *d_zeros = nullptr;   // ZERO_BYTES zero samples (0x88) for the DMA kernel, then ZERO_BYTES of
+                                  // the unsigned form's zero (0x00: nibbles u = 0, products of nothing)
     std::mutex mu;
     std::unordered_map<std::string, DevicePlan> plans;
     std::list<std::string> lru;
@@ -358,9 +360,10 @@ DeviceState *device_state(int device)
     st->cu_count = cus;
     // zero samples that the DMA kernel reads in place of rows past a
     // piece's end; written once, before any launch that could read them
-    if (hipMalloc(&st->d_zeros, ZERO_BYTES) != hipSuccess) return nullptr;
+    if (hipMalloc(&st->d_zeros, 2 * ZERO_BYTES) != hipSuccess) return nullptr;
     void *scr = nullptr;
-    if (hipMemset(st->d_zeros, 0x88, ZERO_BYTES) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+    if (hipMemset(st->d_zeros, 0x88, ZERO_BYTES) != hipSuccess ||
+        hipMemset(st->d_zeros + ZERO_BYTES, 0x00, ZERO_BYTES) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
         init_dma_kernel() != hipSuccess || init_beam_kernel() != hipSuccess ||
         static_scratch_address(&scr) != hipSuccess || !scr) {
         (void)hipFree(st->d_zeros);
@@ -1182,19 +1185,26 @@ int xeng_correlate_presum(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples,
     if (e != hipSuccess) return map_err(e);
     PlanJob pj{ctx->n, n_samples};
     DevicePlan dp;
-    const Tuning tu = tuning_for(ctx->st, &pj, 1, false);
-    rc = get_plan(ctx->st, &pj, 1, TileShape::Square, tu, &dp, MAX_PIECE_STAGES_UNSIGNED);
+    KernelArgs a{};
+    a.job0 = make_job(ctx, slot, d_samples, row_stride, true);
+    // the wide kernel's unsigned instance where the array allows the DMA
+    // kernel (and the tuning does not ask for the general one), else the
+    // general kernel's
+    const Tuning tu = tuning_for(ctx->st, &pj, 1, (a.job0.flags & JOB_DMA) != 0);
+    const bool wide = (a.job0.flags & JOB_DMA) != 0 && tu.kernel != XENG_KERNEL_GENERAL;
+    rc = wide ? get_plan(ctx->st, &pj, 1, TileShape::Wide, tu, &dp, MAX_PIECE_STAGES_WIDE)
+              : get_plan(ctx->st, &pj, 1, TileShape::Square, tu, &dp, MAX_PIECE_STAGES_UNSIGNED);
     if (rc == XENG_OK) {
-        KernelArgs a{};
-        a.job0 = make_job(ctx, slot, d_samples, row_stride, true);
-        a.zeros = ctx->st->d_zeros;
+        // the unsigned form's zero sample is the nibble pair (0, 0)
+        a.zeros = ctx->st->d_zeros + ZERO_BYTES;
         a.pieces = dp.d_pieces;
         a.wg_off = dp.d_off;
         const uint32_t re_low = (ctx->flags & XENG_NIBBLE_RE_LOW) ? 1u : 0u;
         e = launch_zero(sums, 2 * n4, stream);
         if (e == hipSuccess) e = launch_presum(d_samples, n_samples, ctx->n, row_stride, re_low, sums, sums + n4, stream);
         if (e == hipSuccess)
-            e = launch_correlate_unsigned(a, dp.grid, (a.job0.flags & JOB_ALIGNED8) != 0, stream);
+            e = wide ? launch_correlate_dma_unsigned(a, dp.grid, stream)
+                     : launch_correlate_unsigned(a, dp.grid, (a.job0.flags & JOB_ALIGNED8) != 0, stream);
         if (e == hipSuccess)
             e = launch_presum_correct(ctx->d_acc + (int64_t)slot * ctx->slot_i32, ctx->n, ctx->nt, n_samples, sums,
                                       sums + n4, stream);

@@ -321,9 +321,34 @@ __device__ __forceinline__ void read_k(Raw<NW> &r, const lds_u8 *pa, const lds_u
 // 16 x (4-bit value) in the high half of each byte: from the high nibbles,
 // (p ^ 0x88) & 0xF0 per byte; from the low nibbles, the same on p << 4.
 // XOR with 0x77 instead of 0x88 gives 16 x the bitwise complement.
-template <int NW, bool RE_LOW>
+//
+// Unsigned form (U): the stored nibbles u in 0..15 themselves, no offset
+// removed -- A real [uR | uI], A imaginary [uI | -uR] (per byte
+// (0x80 - u) ^ 0x80: no borrows), B [8 uR | 8 uI] (at most 120) -- so the
+// sums are 8 x the exact products of the stored values, with no bias.
+template <int NW, bool RE_LOW, bool U>
 __device__ __forceinline__ void unpack_k(Ops<NW> &o, const Raw<NW> &r)
 {
+    if constexpr (U) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const uint32_t x0 = (uint32_t)r.a[a].x, x1 = (uint32_t)r.a[a].y;
+            const uint32_t h0 = (x0 >> 4) & 0x0F0F0F0Fu, h1 = (x1 >> 4) & 0x0F0F0F0Fu;
+            const uint32_t l0 = x0 & 0x0F0F0F0Fu, l1 = x1 & 0x0F0F0F0Fu;
+            const uint32_t re0 = RE_LOW ? l0 : h0, re1 = RE_LOW ? l1 : h1;
+            const uint32_t im0 = RE_LOW ? h0 : l0, im1 = RE_LOW ? h1 : l1;
+            const uint32_t n0 = (0x80808080u - re0) ^ 0x80808080u, n1 = (0x80808080u - re1) ^ 0x80808080u;
+            o.a[a] = v8i{(int)re0, (int)re1, (int)im0, (int)im1, (int)n0, (int)n1, 0, 0};
+        }
+#pragma unroll
+        for (int b = 0; b < Layout<NW>::BW; ++b) {
+            const uint32_t x0 = (uint32_t)r.b[b].x, x1 = (uint32_t)r.b[b].y;
+            const uint32_t h0 = (x0 >> 1) & 0x78787878u, h1 = (x1 >> 1) & 0x78787878u;   // 8 x high nibble
+            const uint32_t l0 = (x0 << 3) & 0x78787878u, l1 = (x1 << 3) & 0x78787878u;   // 8 x low nibble
+            o.b[b] = RE_LOW ? v4i{(int)l0, (int)l1, (int)h0, (int)h1} : v4i{(int)h0, (int)h1, (int)l0, (int)l1};
+        }
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
         const uint32_t x0 = (uint32_t)r.a[a].x, x1 = (uint32_t)r.a[a].y;
@@ -417,7 +442,7 @@ __device__ __forceinline__ void wait_stage_and_sync()
 // the barrier of iteration s - 1; that barrier sits before the first read of
 // stage s.  The last iteration's reads of "stage ns" touch a slot whose
 // contents are never used.
-template <int NW, bool RE_LOW, bool DIAG>
+template <int NW, bool RE_LOW, bool DIAG, bool U>
 __device__ __forceinline__ void run_piece(Acc<NW> &acc, uint32_t ring, const Tile &tl, int wave, int lane,
                                           uint32_t a_lane, uint32_t b_lane)
 {
@@ -437,7 +462,7 @@ __device__ __forceinline__ void run_piece(Acc<NW> &acc, uint32_t ring, const Til
         const lds_u8 *pb = (const lds_u8 *)(uintptr_t)(ring + b_lane);
         read_k<NW>(r0, pa, pb, 0);
         read_k<NW>(r1, pa, pb, 1);
-        unpack_k<NW, RE_LOW>(u0, r0);
+        unpack_k<NW, RE_LOW, U>(u0, r0);
     }
     int cur = 0;    // slot of stage s
     for (int s = 0; s < ns; ++s) {
@@ -451,26 +476,26 @@ __device__ __forceinline__ void run_piece(Acc<NW> &acc, uint32_t ring, const Til
         __builtin_amdgcn_sched_barrier(0);
         // k-step 0
         read_k<NW>(r0, pa, pb, 2);
-        unpack_k<NW, RE_LOW>(u1, r1);
+        unpack_k<NW, RE_LOW, U>(u1, r1);
         mfma_k<NW, DIAG>(acc, u0);
         kstep_schedule<NW, DIAG>();
         __builtin_amdgcn_sched_barrier(0);
         // k-step 1
         read_k<NW>(r1, pa, pb, 3);
-        unpack_k<NW, RE_LOW>(u0, r0);
+        unpack_k<NW, RE_LOW, U>(u0, r0);
         mfma_k<NW, DIAG>(acc, u1);
         kstep_schedule<NW, DIAG>();
         __builtin_amdgcn_sched_barrier(0);
         // k-step 2: stage s + 1 must be in LDS before its first read
         wait_stage_and_sync<NW>();
         read_k<NW>(r0, qa, qb, 0);
-        unpack_k<NW, RE_LOW>(u1, r1);
+        unpack_k<NW, RE_LOW, U>(u1, r1);
         mfma_k<NW, DIAG>(acc, u0);
         kstep_schedule<NW, DIAG>();
         __builtin_amdgcn_sched_barrier(0);
         // k-step 3
         read_k<NW>(r1, qa, qb, 1);
-        unpack_k<NW, RE_LOW>(u0, r0);
+        unpack_k<NW, RE_LOW, U>(u0, r0);
         mfma_k<NW, DIAG>(acc, u1);
         kstep_schedule<NW, DIAG>();
         __builtin_amdgcn_sched_barrier(0);
@@ -510,18 +535,19 @@ __device__ __forceinline__ void idle_piece(uint32_t ring, const Tile &tl, int wa
 // 256, so this is exact.  Pairs go to the slot as packed 64-bit words (see
 // the layout note): a tile shared with other pieces takes one 64-bit atomic
 // add per pair.
+template <int SHIFT>
 __device__ __forceinline__ void flush_atomic(gw64 *blk, const v16i &re, const v16i &im)
 {
 #pragma unroll
     for (int r = 0; r < 16; ++r)
-        __hip_atomic_fetch_add(blk + r * 64, pack_pair(re[r] >> 8, im[r] >> 8), __ATOMIC_RELAXED,
+        __hip_atomic_fetch_add(blk + r * 64, pack_pair(re[r] >> SHIFT, im[r] >> SHIFT), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Whole-tile flush of one wave's 2 x BW blocks (column blocks cb0..): stores
 // if the slot holds zeros, else read-modify-write with the loads of a row of
 // blocks issued together (one memory latency per row, not one per value).
-template <int NW>
+template <int NW, int SHIFT>
 __device__ __forceinline__ void flush_owned(gw64 *tb, const Acc<NW> &acc, int wa, int cb0, bool fresh)
 {
     constexpr int BW = Layout<NW>::BW;
@@ -539,7 +565,7 @@ __device__ __forceinline__ void flush_owned(gw64 *tb, const Acc<NW> &acc, int wa
         for (int b = 0; b < BW; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                blk[b][r * 64] = old[b][r] + pack_pair(acc.re[a][b][r] >> 8, acc.im[a][b][r] >> 8);
+                blk[b][r * 64] = old[b][r] + pack_pair(acc.re[a][b][r] >> SHIFT, acc.im[a][b][r] >> SHIFT);
         __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -548,7 +574,7 @@ __device__ __forceinline__ void flush_owned(gw64 *tb, const Acc<NW> &acc, int wa
 // piece's tile field holds (I, J2): A rows 128 I.., B columns 256 J2.., i.e.
 // accumulator tiles (I, 2 J2) and (I, 2 J2 + 1) where they are in the upper
 // triangle.
-template <int NW>
+template <int NW, bool U = false>
 __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
 {
     using L = Layout<NW>;
@@ -637,17 +663,20 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
             idle_piece<NW>(ring, tl, wave, lane);
         else if (jd.flags & JOB_RE_LOW) {
             if (diag)
-                run_piece<NW, true, true>(acc, ring, tl, wave, lane, a_lane, b_lane);
+                run_piece<NW, true, true, U>(acc, ring, tl, wave, lane, a_lane, b_lane);
             else
-                run_piece<NW, true, false>(acc, ring, tl, wave, lane, a_lane, b_lane);
+                run_piece<NW, true, false, U>(acc, ring, tl, wave, lane, a_lane, b_lane);
         } else {
             if (diag)
-                run_piece<NW, false, true>(acc, ring, tl, wave, lane, a_lane, b_lane);
+                run_piece<NW, false, true, U>(acc, ring, tl, wave, lane, a_lane, b_lane);
             else
-                run_piece<NW, false, false>(acc, ring, tl, wave, lane, a_lane, b_lane);
+                run_piece<NW, false, false, U>(acc, ring, tl, wave, lane, a_lane, b_lane);
         }
 
         if (valid && !below && !outside) {
+            // the sums carry 256x the values (both operands 16x), or 8x in
+            // the unsigned form
+            constexpr int SHIFT = U ? 3 : 8;
             const int64_t tile_idx = (int64_t)ti * jd.nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);
             gw64 *tb = (gw64 *)(jd.acc + tile_idx * TILE_I32) + lane;
             if (atomic) {
@@ -656,14 +685,15 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
 #pragma unroll
                     for (int b = 0; b < L::BW; ++b) {
                         if (diag && a == 1 && b == 0) continue;   // below the diagonal, never computed
-                        flush_atomic(tb + ((2 * wa + a) * BLKS + cb0 + b) * BLOCK_W, acc.re[a][b], acc.im[a][b]);
+                        flush_atomic<SHIFT>(tb + ((2 * wa + a) * BLKS + cb0 + b) * BLOCK_W, acc.re[a][b],
+                                            acc.im[a][b]);
                         // one block at a time: keeps the register file for the main loop
                         __builtin_amdgcn_sched_barrier(0);
                     }
             } else if (jd.flags & JOB_FRESH) {
-                flush_owned<NW>(tb, acc, wa, cb0, true);
+                flush_owned<NW, SHIFT>(tb, acc, wa, cb0, true);
             } else {
-                flush_owned<NW>(tb, acc, wa, cb0, false);
+                flush_owned<NW, SHIFT>(tb, acc, wa, cb0, false);
             }
         }
     }
@@ -688,9 +718,22 @@ hipError_t init_dma_kernel()
 {
     hipError_t e = hipFuncSetAttribute((const void *)dma::xcorr_dma<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        DMA_LDS_BYTES);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)dma::xcorr_dma<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               DMA_LDS_BYTES);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)dma::xcorr_dma<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                DMA_LDS_BYTES);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)dma::xcorr_dma<8, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                DMA_LDS_BYTES);
+    return e;
+}
+
+// The unsigned form (pre-sum path): eight waves; `a.zeros` must then point
+// at zero bytes (nibbles u = 0), the zero sample of that form.
+hipError_t launch_correlate_dma_unsigned(const KernelArgs &a, int grid, hipStream_t stream)
+{
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((dma::xcorr_dma<8, true>), dim3(grid), dim3(64 * 8), DMA_LDS_BYTES, stream, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_correlate_dma(const KernelArgs &a, int grid, int waves, hipStream_t stream)

@@ -1,6 +1,7 @@
 """GPU parity of the unsigned-nibble form with pre-sums
 (xeng_correlate_presum): every visibility against the oracle -- small and
-ragged shapes, both nibble orders, unaligned arrays, pieces split at the
+ragged shapes on the wide kernel's unsigned instance (N a multiple of 16)
+and on the general kernel's, both nibble orders, unaligned arrays, pieces split at the
 unsigned form's register bound, accumulation with the other kernels in one
 slot, the full integration bound where the unsigned sums pass int32, and the
 full-size N=2048 channel against the oracle's recorded digest."""
@@ -104,3 +105,28 @@ def test_presum_full_size_digest(X):
     c.correlate_presum(0, gpu(x))
     pu.assert_matches_oracle_digest("channel_n2048_t32768", c.dump(0), x)
     c.close()
+
+
+def test_presum_wide_and_general_kernels_agree(X):
+    # N a multiple of 16, contiguous: the wide kernel's unsigned instance;
+    # forcing the general kernel gives the same words, both equal to the
+    # oracle (rows past a piece's end read the unsigned zero sample)
+    n, t = 256, 5000
+    x = synth.uniform_bytes(n, t, seed=47)
+    outs = []
+    for kern in (X.XENG_KERNEL_AUTO, X.XENG_KERNEL_GENERAL):
+        c = X.Correlator(n, 1)
+        try:
+            X.set_tuning(0, 0, kern)
+            c.correlate_presum(0, gpu(x))
+            outs.append(c.dump(0).cpu().numpy().astype(np.int64))
+        finally:
+            X.set_tuning(0, 0, X.XENG_KERNEL_AUTO)
+            c.close()
+    np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[0], oracle.correlate(x))
+
+
+def test_presum_wide_re_low(X):
+    x = synth.uniform_bytes(128, 1000, seed=48)
+    np.testing.assert_array_equal(run(X, x, re_low=True), oracle.correlate(x, re_low=True))
