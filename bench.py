@@ -333,8 +333,8 @@ def bench_flagged(args, xeng, synth, torch, np):
 
 def bench_presum(args, xeng, synth, torch, np):
     """The unsigned-nibble form with pre-sums (xeng_correlate_presum) on the
-    CHIME-shaped channel: pre-sum pass, the 128 x 128 kernel on the stored
-    nibbles, the correction pass; timed with HIP events on its stream, next
+    CHIME-shaped channel: pre-sum pass, the wide kernel's unsigned instance
+    on the stored nibbles, the correction pass; timed with HIP events on its stream, next
     to xeng_correlate on the same data."""
     n, t = args.n, args.t
     tri = n * (n + 1) // 2

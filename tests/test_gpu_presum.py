@@ -1,7 +1,9 @@
 """GPU parity of the unsigned-nibble form with pre-sums
 (xeng_correlate_presum): every visibility against the oracle -- small and
 ragged shapes on the wide kernel's unsigned instance (N a multiple of 16)
-and on the general kernel's, both nibble orders, unaligned arrays, pieces split at the
+and on the general kernel's, the pre-sums of aligned rows (16-byte loads,
+ragged column blocks and row slices) and of other arrays, both nibble
+orders, unaligned arrays, pieces split at the
 unsigned form's register bound, accumulation with the other kernels in one
 slot, the full integration bound where the unsigned sums pass int32, and the
 full-size N=2048 channel against the oracle's recorded digest."""
@@ -37,8 +39,9 @@ def run(X, x, re_low=False):
     return v
 
 
-@pytest.mark.parametrize("n,t", [(1, 1), (2, 33), (5, 64), (64, 4096), (100, 1000), (128, 129), (129, 300),
-                                 (256, 65), (513, 129), (1000, 777)])
+@pytest.mark.parametrize("n,t", [(1, 1), (2, 33), (5, 64), (16, 5), (48, 1000), (64, 4096), (100, 1000),
+                                 (128, 129), (129, 300), (256, 65), (272, 300), (513, 129), (1000, 777),
+                                 (32, 70001)])
 def test_presum_matches_oracle(X, n, t):
     print(f"presum n={n} t={t}", flush=True)
     x = synth.uniform_bytes(n, t, seed=[41, n, t])
