@@ -200,15 +200,17 @@ int xeng_dump_counts(xeng_ctx *ctx, int32_t slot, int32_t *out, void *hip_stream
  * The same integration as xeng_correlate (same result, checks and bound),
  * computed in the paper's unsigned form (Sec. 2.3, "GPUs": low-bit
  * products at the cost of O(N) bookkeeping; Table tab:computing, "Re-Order
- * and Pre-Sum"): the int8 matrix cores multiply the stored nibbles
- * u = x + 8 (0..15) themselves, a pre-sum pass forms SR_i = sum_t uR_i and
+ * and Pre-Sum"): the matrix cores multiply the stored nibbles u = x + 8
+ * (0..15) themselves, a pre-sum pass forms SR_i = sum_t uR_i and
  * SI_i = sum_t uI_i, and a correction pass adds, per pair,
  *   Re: -8 (SR_i + SI_i + SR_j + SI_j) + 128 T,
  *   Im:  8 (SR_i - SI_i) - 8 (SR_j - SI_j).
- * A second, independent route to the same integers on the GPU (it takes
- * the 128 x 128 kernel for any alignment).  Pre-sum scratch (8 N bytes)
- * comes from the library's pool; XENG_ENOMEM, nothing queued, if it
- * cannot be had.
+ * A second, independent route to the same integers on the GPU: the wide
+ * kernel's unsigned instance where the array allows it in place (int8, or
+ * FP8 under XENG_KERNEL_FP8), else the 128 x 128 kernel's (int8), which
+ * XENG_KERNEL_GENERAL also selects.  Pre-sum scratch (8 N bytes) comes
+ * from the library's pool; XENG_ENOMEM, nothing queued, if it cannot be
+ * had.
  */
 int xeng_correlate_presum(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_t n_samples,
                           int64_t row_stride, void *hip_stream);
@@ -610,12 +612,17 @@ int xeng_server_export_ring(xeng_server *s, int32_t channel, int32_t *ring, int3
 #define XENG_KERNEL_GENERAL 1  /* always the general kernel */
 #define XENG_KERNEL_DMA4 2     /* wide DMA kernel with four waves where the job allows it, else general */
 /*
- * The general kernel's exact FP8 instance for every job: each 4-bit value
- * as its OCP E4M3 code (exact for every integer of magnitude <= 16), products
- * on v_mfma_f32_32x32x16_fp8_fp8 with fp32 sums, pieces below 2^17 samples so
- * that every sum is an exact integer (below 2^24), converted to int32 at the
- * flush.  The same results as every other kernel (Sec. 4.1: low-bit matrix
- * units as the way forward).
+ * Exact FP8 products on v_mfma_f32_32x32x16_fp8_fp8 with fp32 sums kept
+ * below 2^24, converted to int32 at the flush (Sec. 4.1: low-bit matrix
+ * units as the way forward).  A single-channel xeng_correlate (and
+ * xeng_correlate_presum) on an array the wide kernel reads in place runs
+ * the unsigned form on the wide kernel's FP8 instance: a stored nibble u is
+ * the E4M3 code of u * 2^-9 as it stands (subnormals and the first binade),
+ * its negation the same code with the sign bit set; pieces of at most 582
+ * stages; the O(N) pre-sum correction of xeng_correlate_presum.  Batches
+ * and other arrays take the general kernel's FP8 instance: each signed
+ * 4-bit value as its E4M3 code, pieces below 2^17 samples.  The same
+ * results as every other kernel.
  */
 #define XENG_KERNEL_FP8 3
 

@@ -39,7 +39,7 @@ hipError_t launch_presum(const uint8_t *s, int64_t n_samples, int n, int64_t str
 hipError_t launch_presum_correct(int32_t *acc, int n, int nt, int64_t n_samples, const int32_t *sr,
                                  const int32_t *si, hipStream_t stream);
 hipError_t launch_correlate_dma(const KernelArgs &a, int grid, int waves, hipStream_t stream);
-hipError_t launch_correlate_dma_unsigned(const KernelArgs &a, int grid, hipStream_t stream);
+hipError_t launch_correlate_dma_unsigned(const KernelArgs &a, int grid, bool fp8, hipStream_t stream);
 hipError_t launch_correlate_narrow(const KernelArgs &a, int grid, hipStream_t stream);
 hipError_t init_dma_kernel();
 hipError_t launch_dump(int32_t *acc, int32_t *diag, int n, int nt, int32_t *out, bool reset,
@@ -966,6 +966,53 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
     return XENG_OK;
 }
 
+// The unsigned form with pre-sums, called with st->mu held and the device
+// current, the arguments checked and the guard passed: the wide kernel's
+// unsigned instance where the array allows the DMA kernel (and the tuning
+// does not ask for the general one), int8 or, with `fp8`, FP8 products; else
+// the general kernel's int8 instance.
+int correlate_unsigned(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_t n_samples, int64_t row_stride,
+                       const Tuning &tu, bool fp8, hipStream_t stream)
+{
+    hipMemPool_t pool = nullptr;
+    int rc = pad_pool(ctx->st, &pool);
+    if (rc != XENG_OK) return rc;
+    const int64_t n4 = ((int64_t)ctx->n + 3) / 4 * 4;
+    int32_t *sums = nullptr;   // [SR | SI], n4 each
+    hipError_t e = hipMallocFromPoolAsync(reinterpret_cast<void **>(&sums), (size_t)(2 * n4 * 4), pool, stream);
+    if (e != hipSuccess) return map_err(e);
+    PlanJob pj{ctx->n, n_samples};
+    DevicePlan dp;
+    KernelArgs a{};
+    a.job0 = make_job(ctx, slot, d_samples, row_stride, true);
+    const bool wide = (a.job0.flags & JOB_DMA) != 0 && tu.kernel != XENG_KERNEL_GENERAL;
+    fp8 = fp8 && wide;
+    rc = wide ? get_plan(ctx->st, &pj, 1, TileShape::Wide, tu, &dp,
+                         fp8 ? MAX_PIECE_STAGES_FP8_UNSIGNED : MAX_PIECE_STAGES_WIDE)
+              : get_plan(ctx->st, &pj, 1, TileShape::Square, tu, &dp, MAX_PIECE_STAGES_UNSIGNED);
+    if (rc == XENG_OK) {
+        // the unsigned form's zero sample is the nibble pair (0, 0)
+        a.zeros = ctx->st->d_zeros + ZERO_BYTES;
+        a.pieces = dp.d_pieces;
+        a.wg_off = dp.d_off;
+        const uint32_t re_low = (ctx->flags & XENG_NIBBLE_RE_LOW) ? 1u : 0u;
+        e = launch_zero(sums, 2 * n4, stream);
+        if (e == hipSuccess) e = launch_presum(d_samples, n_samples, ctx->n, row_stride, re_low, sums, sums + n4, stream);
+        if (e == hipSuccess)
+            e = wide ? launch_correlate_dma_unsigned(a, dp.grid, fp8, stream)
+                     : launch_correlate_unsigned(a, dp.grid, (a.job0.flags & JOB_ALIGNED8) != 0, stream);
+        if (e == hipSuccess)
+            e = launch_presum_correct(ctx->d_acc + (int64_t)slot * ctx->slot_i32, ctx->n, ctx->nt, n_samples, sums,
+                                      sums + n4, stream);
+        if (e == hipSuccess) ctx->acc_t[(size_t)slot] += n_samples;
+        rc = map_err(e);
+    }
+    e = hipFreeAsync(sums, stream);
+    if (rc == XENG_OK && e != hipSuccess) rc = map_err(e);
+    if (rc == XENG_OK) rc = map_err(publish_count(ctx, slot, stream));
+    return rc;
+}
+
 }  // namespace
 
 namespace xeng {
@@ -1087,6 +1134,10 @@ int xeng_correlate(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_
     // held through the launch so that no other thread evicts the plan first
     std::lock_guard<std::mutex> lk(ctx->st->mu);
     const Tuning tu = tuning_for(ctx->st, &pj, 1, (a.job0.flags & JOB_DMA) != 0);
+    // FP8 on an array the DMA kernel reads: the unsigned form's FP8 products
+    // on the wide kernel, whose stored nibbles are E4M3 codes as they stand
+    if (tu.kernel == XENG_KERNEL_FP8 && (a.job0.flags & JOB_DMA))
+        return correlate_unsigned(ctx, slot, d_samples, n_samples, row_stride, tu, true, stream);
     const Kind kind = kind_of(a.job0, tu);
     if (kind == Kind::General && tu.kernel != XENG_KERNEL_GENERAL && ctx->n >= PAD_MIN_N)
         return correlate_padded(ctx, slot, d_samples, n_samples, row_stride, tu, stream);
@@ -1177,44 +1228,10 @@ int xeng_correlate_presum(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples,
     if (n_samples > T_MAX - ctx->acc_t[(size_t)slot]) return XENG_EOVERFLOW;
     if (n_samples == 0) return XENG_OK;
     std::lock_guard<std::mutex> lk(ctx->st->mu);
-    hipMemPool_t pool = nullptr;
-    if ((rc = pad_pool(ctx->st, &pool)) != XENG_OK) return rc;
-    const int64_t n4 = ((int64_t)ctx->n + 3) / 4 * 4;
-    int32_t *sums = nullptr;   // [SR | SI], n4 each
-    hipError_t e = hipMallocFromPoolAsync(reinterpret_cast<void **>(&sums), (size_t)(2 * n4 * 4), pool, stream);
-    if (e != hipSuccess) return map_err(e);
     PlanJob pj{ctx->n, n_samples};
-    DevicePlan dp;
-    KernelArgs a{};
-    a.job0 = make_job(ctx, slot, d_samples, row_stride, true);
-    // the wide kernel's unsigned instance where the array allows the DMA
-    // kernel (and the tuning does not ask for the general one), else the
-    // general kernel's
-    const Tuning tu = tuning_for(ctx->st, &pj, 1, (a.job0.flags & JOB_DMA) != 0);
-    const bool wide = (a.job0.flags & JOB_DMA) != 0 && tu.kernel != XENG_KERNEL_GENERAL;
-    rc = wide ? get_plan(ctx->st, &pj, 1, TileShape::Wide, tu, &dp, MAX_PIECE_STAGES_WIDE)
-              : get_plan(ctx->st, &pj, 1, TileShape::Square, tu, &dp, MAX_PIECE_STAGES_UNSIGNED);
-    if (rc == XENG_OK) {
-        // the unsigned form's zero sample is the nibble pair (0, 0)
-        a.zeros = ctx->st->d_zeros + ZERO_BYTES;
-        a.pieces = dp.d_pieces;
-        a.wg_off = dp.d_off;
-        const uint32_t re_low = (ctx->flags & XENG_NIBBLE_RE_LOW) ? 1u : 0u;
-        e = launch_zero(sums, 2 * n4, stream);
-        if (e == hipSuccess) e = launch_presum(d_samples, n_samples, ctx->n, row_stride, re_low, sums, sums + n4, stream);
-        if (e == hipSuccess)
-            e = wide ? launch_correlate_dma_unsigned(a, dp.grid, stream)
-                     : launch_correlate_unsigned(a, dp.grid, (a.job0.flags & JOB_ALIGNED8) != 0, stream);
-        if (e == hipSuccess)
-            e = launch_presum_correct(ctx->d_acc + (int64_t)slot * ctx->slot_i32, ctx->n, ctx->nt, n_samples, sums,
-                                      sums + n4, stream);
-        if (e == hipSuccess) ctx->acc_t[(size_t)slot] += n_samples;
-        rc = map_err(e);
-    }
-    e = hipFreeAsync(sums, stream);
-    if (rc == XENG_OK && e != hipSuccess) rc = map_err(e);
-    if (rc == XENG_OK) rc = map_err(publish_count(ctx, slot, stream));
-    return rc;
+    const JobDesc jd = make_job(ctx, slot, d_samples, row_stride, true);
+    const Tuning tu = tuning_for(ctx->st, &pj, 1, (jd.flags & JOB_DMA) != 0);
+    return correlate_unsigned(ctx, slot, d_samples, n_samples, row_stride, tu, tu.kernel == XENG_KERNEL_FP8, stream);
 }
 
 int xeng_dump_counts(xeng_ctx *ctx, int32_t slot, int32_t *out, void *hip_stream)

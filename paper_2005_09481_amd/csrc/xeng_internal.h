@@ -61,6 +61,9 @@ constexpr int MAX_PIECE_STAGES_WIDE = ((1 << 16) - 1) / STAGE;  // 1023 stages
 // The general kernel on unsigned nibbles: at most 8 x 450 per sample, so
 // pieces below 2^19 samples keep the sums in int32.
 constexpr int MAX_PIECE_STAGES_UNSIGNED = ((1 << 19) - 1) / STAGE;   // 8191 stages
+// The wide kernel's FP8 products of unsigned nibbles: fp32 sums of at most
+// 450 per sample stay exact integers below 2^24 over 582 stages.
+constexpr int MAX_PIECE_STAGES_FP8_UNSIGNED = ((1 << 24) - 1) / (450 * STAGE);   // 582 stages
 
 // Largest row stride: lane offsets inside a stage (up to 31 rows) stay 32-bit.
 // Most workgroups one tile is shared among in a launch.  Every share of a

@@ -52,6 +52,7 @@ typedef int v2i __attribute__((ext_vector_type(2)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __attribute__((address_space(3))) v2i lds_v2i;
 typedef __attribute__((address_space(3))) uint8_t lds_u8;
 typedef __attribute__((address_space(1))) uint64_t gw64;
@@ -299,9 +300,13 @@ template <int NW> struct Ops {
     v8i a[2];   // {16R, 16R, 16I, 16I, 16~R, 16~R, -, -}: real A = s0123, imaginary A = s2345
     v4i b[Layout<NW>::BW];   // {16R, 16R, 16I, 16I}
 };
-template <int NW> struct Acc {
+template <int NW, bool F> struct Acc {
     v16i re[2][Layout<NW>::BW];
     v16i im[2][Layout<NW>::BW];
+};
+template <int NW> struct Acc<NW, true> {
+    v16f re[2][Layout<NW>::BW];
+    v16f im[2][Layout<NW>::BW];
 };
 
 // Transposed reads of k-step q: `pa`, `pb` are this lane's bases in the
@@ -326,9 +331,36 @@ __device__ __forceinline__ void read_k(Raw<NW> &r, const lds_u8 *pa, const lds_u
 // removed -- A real [uR | uI], A imaginary [uI | -uR] (per byte
 // (0x80 - u) ^ 0x80: no borrows), B [8 uR | 8 uI] (at most 120) -- so the
 // sums are 8 x the exact products of the stored values, with no bias.
-template <int NW, bool RE_LOW, bool U>
+//
+// FP8 form (F, unsigned): a byte holding u in 0..15 is the OCP E4M3 code of
+// u x 2^-9 (codes 0..7 are the subnormals m x 2^-9, codes 8..15 the first
+// binade (8 + m) x 2^-9), and setting its top bit negates it exactly.  So A
+// real [uR | uI], A imaginary [uI | -uR] and B [uR | uI] are the masked
+// nibbles themselves (and the sign bit), and the fp32 sums hold the exact
+// integer sums x 2^-18.
+template <int NW, bool RE_LOW, bool U, bool F>
 __device__ __forceinline__ void unpack_k(Ops<NW> &o, const Raw<NW> &r)
 {
+    if constexpr (F) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const uint32_t x0 = (uint32_t)r.a[a].x, x1 = (uint32_t)r.a[a].y;
+            const uint32_t h0 = (x0 >> 4) & 0x0F0F0F0Fu, h1 = (x1 >> 4) & 0x0F0F0F0Fu;
+            const uint32_t l0 = x0 & 0x0F0F0F0Fu, l1 = x1 & 0x0F0F0F0Fu;
+            const uint32_t re0 = RE_LOW ? l0 : h0, re1 = RE_LOW ? l1 : h1;
+            const uint32_t im0 = RE_LOW ? h0 : l0, im1 = RE_LOW ? h1 : l1;
+            o.a[a] = v8i{(int)re0, (int)re1, (int)im0, (int)im1, (int)(re0 | 0x80808080u), (int)(re1 | 0x80808080u),
+                         0, 0};
+        }
+#pragma unroll
+        for (int b = 0; b < Layout<NW>::BW; ++b) {
+            const uint32_t x0 = (uint32_t)r.b[b].x, x1 = (uint32_t)r.b[b].y;
+            const uint32_t h0 = (x0 >> 4) & 0x0F0F0F0Fu, h1 = (x1 >> 4) & 0x0F0F0F0Fu;
+            const uint32_t l0 = x0 & 0x0F0F0F0Fu, l1 = x1 & 0x0F0F0F0Fu;
+            o.b[b] = RE_LOW ? v4i{(int)l0, (int)l1, (int)h0, (int)h1} : v4i{(int)h0, (int)h1, (int)l0, (int)l1};
+        }
+        return;
+    }
     if constexpr (U) {
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
@@ -384,8 +416,35 @@ template <int NW, bool DIAG> __device__ __forceinline__ constexpr bool skip_bloc
 // The real products of a k-step first, then the imaginary ones: measured a
 // little faster than alternating them (the chip runs at its power limit, and
 // this order drew less).
+//
+// FP8 form: the products of two k-steps at once on
+// v_mfma_f32_32x32x64_f8f6f4 (E4M3 on both sides, no block scale), whose
+// 32-byte operands are the two k-steps' unpacked words side by side: real
+// [R | I | R' | I'] . [R | I | R' | I'], imaginary [I | -R | I' | -R'] .
+// [R | I | R' | I'].  All real products of the pair first, then the
+// imaginary ones, so that no product waits for the one before it.
 template <int NW, bool DIAG>
-__device__ __forceinline__ void mfma_k(Acc<NW> &acc, const Ops<NW> &o)
+__device__ __forceinline__ void mfma_pair(Acc<NW, true> &acc, const Ops<NW> &o0, const Ops<NW> &o1)
+{
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int b = 0; b < Layout<NW>::BW; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                if (skip_block<NW, DIAG>(a, b)) continue;
+                const int w = 2 * p;   // real: words 0..3, imaginary: words 2..5
+                const v8i av = {o0.a[a][w], o0.a[a][w + 1], o0.a[a][w + 2], o0.a[a][w + 3],
+                                o1.a[a][w], o1.a[a][w + 1], o1.a[a][w + 2], o1.a[a][w + 3]};
+                const v8i bv = {o0.b[b][0], o0.b[b][1], o0.b[b][2], o0.b[b][3],
+                                o1.b[b][0], o1.b[b][1], o1.b[b][2], o1.b[b][3]};
+                v16f &c = p == 0 ? acc.re[a][b] : acc.im[a][b];
+                c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, c, 0, 0, 0, 0, 0, 0);
+            }
+}
+
+template <int NW, bool DIAG>
+__device__ __forceinline__ void mfma_k(Acc<NW, false> &acc, const Ops<NW> &o)
 {
 #pragma unroll
     for (int b = 0; b < Layout<NW>::BW; ++b)
@@ -442,8 +501,8 @@ __device__ __forceinline__ void wait_stage_and_sync()
 // the barrier of iteration s - 1; that barrier sits before the first read of
 // stage s.  The last iteration's reads of "stage ns" touch a slot whose
 // contents are never used.
-template <int NW, bool RE_LOW, bool DIAG, bool U>
-__device__ __forceinline__ void run_piece(Acc<NW> &acc, uint32_t ring, const Tile &tl, int wave, int lane,
+template <int NW, bool RE_LOW, bool DIAG, bool U, bool F>
+__device__ __forceinline__ void run_piece(Acc<NW, F> &acc, uint32_t ring, const Tile &tl, int wave, int lane,
                                           uint32_t a_lane, uint32_t b_lane)
 {
     const int ns = (tl.t1 - tl.t0 + STAGE - 1) / STAGE;
@@ -457,52 +516,93 @@ __device__ __forceinline__ void run_piece(Acc<NW> &acc, uint32_t ring, const Til
 
     Raw<NW> r0, r1;
     Ops<NW> u0, u1;
-    {
-        const lds_u8 *pa = (const lds_u8 *)(uintptr_t)(ring + a_lane);
-        const lds_u8 *pb = (const lds_u8 *)(uintptr_t)(ring + b_lane);
-        read_k<NW>(r0, pa, pb, 0);
-        read_k<NW>(r1, pa, pb, 1);
-        unpack_k<NW, RE_LOW, U>(u0, r0);
+    if constexpr (F) {
+        // FP8: a k-step pair at a time.  Entering each half stage, the raw
+        // data of its two k-steps is in r0, r1; both are unpacked, the next
+        // pair's reads are issued, then the pair's products.
+        {
+            const lds_u8 *pa = (const lds_u8 *)(uintptr_t)(ring + a_lane);
+            const lds_u8 *pb = (const lds_u8 *)(uintptr_t)(ring + b_lane);
+            read_k<NW>(r0, pa, pb, 0);
+            read_k<NW>(r1, pa, pb, 1);
+        }
+        int cur = 0;
+        for (int s = 0; s < ns; ++s) {
+            const int nxt = cur == NSLOT - 1 ? 0 : cur + 1;
+            const int iss = cur == 0 ? NSLOT - 1 : cur - 1;
+            issue_stage<NW>(ring + iss * SLOT, tl, dl, s + AHEAD, wave, lane);
+            const lds_u8 *pa = (const lds_u8 *)(uintptr_t)(ring + cur * SLOT + a_lane);
+            const lds_u8 *pb = (const lds_u8 *)(uintptr_t)(ring + cur * SLOT + b_lane);
+            const lds_u8 *qa = (const lds_u8 *)(uintptr_t)(ring + nxt * SLOT + a_lane);
+            const lds_u8 *qb = (const lds_u8 *)(uintptr_t)(ring + nxt * SLOT + b_lane);
+            __builtin_amdgcn_sched_barrier(0);
+            // k-steps 0, 1
+            unpack_k<NW, RE_LOW, U, F>(u0, r0);
+            unpack_k<NW, RE_LOW, U, F>(u1, r1);
+            read_k<NW>(r0, pa, pb, 2);
+            read_k<NW>(r1, pa, pb, 3);
+            mfma_pair<NW, DIAG>(acc, u0, u1);
+            __builtin_amdgcn_sched_barrier(0);
+            // k-steps 2, 3; stage s + 1 must be in LDS before its first read
+            unpack_k<NW, RE_LOW, U, F>(u0, r0);
+            unpack_k<NW, RE_LOW, U, F>(u1, r1);
+            wait_stage_and_sync<NW>();
+            read_k<NW>(r0, qa, qb, 0);
+            read_k<NW>(r1, qa, qb, 1);
+            mfma_pair<NW, DIAG>(acc, u0, u1);
+            __builtin_amdgcn_sched_barrier(0);
+            cur = nxt;
+        }
+        __builtin_amdgcn_s_waitcnt(XENG_VMCNT(0));
+        __syncthreads();       // the next piece's DMA reuses the slots
+    } else {
+        {
+            const lds_u8 *pa = (const lds_u8 *)(uintptr_t)(ring + a_lane);
+            const lds_u8 *pb = (const lds_u8 *)(uintptr_t)(ring + b_lane);
+            read_k<NW>(r0, pa, pb, 0);
+            read_k<NW>(r1, pa, pb, 1);
+            unpack_k<NW, RE_LOW, U, F>(u0, r0);
+        }
+        int cur = 0;    // slot of stage s
+        for (int s = 0; s < ns; ++s) {
+            const int nxt = cur == NSLOT - 1 ? 0 : cur + 1;
+            const int iss = cur == 0 ? NSLOT - 1 : cur - 1;   // slot of stage s - 1 = s + AHEAD
+            issue_stage<NW>(ring + iss * SLOT, tl, dl, s + AHEAD, wave, lane);
+            const lds_u8 *pa = (const lds_u8 *)(uintptr_t)(ring + cur * SLOT + a_lane);
+            const lds_u8 *pb = (const lds_u8 *)(uintptr_t)(ring + cur * SLOT + b_lane);
+            const lds_u8 *qa = (const lds_u8 *)(uintptr_t)(ring + nxt * SLOT + a_lane);
+            const lds_u8 *qb = (const lds_u8 *)(uintptr_t)(ring + nxt * SLOT + b_lane);
+            __builtin_amdgcn_sched_barrier(0);
+            // k-step 0
+            read_k<NW>(r0, pa, pb, 2);
+            unpack_k<NW, RE_LOW, U, F>(u1, r1);
+            mfma_k<NW, DIAG>(acc, u0);
+            kstep_schedule<NW, DIAG>();
+            __builtin_amdgcn_sched_barrier(0);
+            // k-step 1
+            read_k<NW>(r1, pa, pb, 3);
+            unpack_k<NW, RE_LOW, U, F>(u0, r0);
+            mfma_k<NW, DIAG>(acc, u1);
+            kstep_schedule<NW, DIAG>();
+            __builtin_amdgcn_sched_barrier(0);
+            // k-step 2: stage s + 1 must be in LDS before its first read
+            wait_stage_and_sync<NW>();
+            read_k<NW>(r0, qa, qb, 0);
+            unpack_k<NW, RE_LOW, U, F>(u1, r1);
+            mfma_k<NW, DIAG>(acc, u0);
+            kstep_schedule<NW, DIAG>();
+            __builtin_amdgcn_sched_barrier(0);
+            // k-step 3
+            read_k<NW>(r1, qa, qb, 1);
+            unpack_k<NW, RE_LOW, U, F>(u0, r0);
+            mfma_k<NW, DIAG>(acc, u1);
+            kstep_schedule<NW, DIAG>();
+            __builtin_amdgcn_sched_barrier(0);
+            cur = nxt;
+        }
+        __builtin_amdgcn_s_waitcnt(XENG_VMCNT(0));
+        __syncthreads();       // the next piece's DMA reuses the slots
     }
-    int cur = 0;    // slot of stage s
-    for (int s = 0; s < ns; ++s) {
-        const int nxt = cur == NSLOT - 1 ? 0 : cur + 1;
-        const int iss = cur == 0 ? NSLOT - 1 : cur - 1;   // slot of stage s - 1 = s + AHEAD
-        issue_stage<NW>(ring + iss * SLOT, tl, dl, s + AHEAD, wave, lane);
-        const lds_u8 *pa = (const lds_u8 *)(uintptr_t)(ring + cur * SLOT + a_lane);
-        const lds_u8 *pb = (const lds_u8 *)(uintptr_t)(ring + cur * SLOT + b_lane);
-        const lds_u8 *qa = (const lds_u8 *)(uintptr_t)(ring + nxt * SLOT + a_lane);
-        const lds_u8 *qb = (const lds_u8 *)(uintptr_t)(ring + nxt * SLOT + b_lane);
-        __builtin_amdgcn_sched_barrier(0);
-        // k-step 0
-        read_k<NW>(r0, pa, pb, 2);
-        unpack_k<NW, RE_LOW, U>(u1, r1);
-        mfma_k<NW, DIAG>(acc, u0);
-        kstep_schedule<NW, DIAG>();
-        __builtin_amdgcn_sched_barrier(0);
-        // k-step 1
-        read_k<NW>(r1, pa, pb, 3);
-        unpack_k<NW, RE_LOW, U>(u0, r0);
-        mfma_k<NW, DIAG>(acc, u1);
-        kstep_schedule<NW, DIAG>();
-        __builtin_amdgcn_sched_barrier(0);
-        // k-step 2: stage s + 1 must be in LDS before its first read
-        wait_stage_and_sync<NW>();
-        read_k<NW>(r0, qa, qb, 0);
-        unpack_k<NW, RE_LOW, U>(u1, r1);
-        mfma_k<NW, DIAG>(acc, u0);
-        kstep_schedule<NW, DIAG>();
-        __builtin_amdgcn_sched_barrier(0);
-        // k-step 3
-        read_k<NW>(r1, qa, qb, 1);
-        unpack_k<NW, RE_LOW, U>(u0, r0);
-        mfma_k<NW, DIAG>(acc, u1);
-        kstep_schedule<NW, DIAG>();
-        __builtin_amdgcn_sched_barrier(0);
-        cur = nxt;
-    }
-    __builtin_amdgcn_s_waitcnt(XENG_VMCNT(0));
-    __syncthreads();       // the next piece's DMA reuses the slots
 }
 
 // A wave whose accumulator region lies wholly below the diagonal: its
@@ -535,20 +635,26 @@ __device__ __forceinline__ void idle_piece(uint32_t ring, const Tile &tl, int wa
 // 256, so this is exact.  Pairs go to the slot as packed 64-bit words (see
 // the layout note): a tile shared with other pieces takes one 64-bit atomic
 // add per pair.
-template <int SHIFT>
-__device__ __forceinline__ void flush_atomic(gw64 *blk, const v16i &re, const v16i &im)
+//
+// FP8 accumulators hold the integer sums x 2^-18 (each operand carries
+// 2^-9), below 2^24 in magnitude: scaling by 2^18 recovers them exactly.
+template <int SHIFT> __device__ __forceinline__ int32_t acc_val(int32_t v) { return v >> SHIFT; }
+template <int SHIFT> __device__ __forceinline__ int32_t acc_val(float v) { return (int32_t)(v * 262144.0f); }
+
+template <int SHIFT, typename V>
+__device__ __forceinline__ void flush_atomic(gw64 *blk, const V &re, const V &im)
 {
 #pragma unroll
     for (int r = 0; r < 16; ++r)
-        __hip_atomic_fetch_add(blk + r * 64, pack_pair(re[r] >> SHIFT, im[r] >> SHIFT), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(blk + r * 64, pack_pair(acc_val<SHIFT>(re[r]), acc_val<SHIFT>(im[r])),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Whole-tile flush of one wave's 2 x BW blocks (column blocks cb0..): stores
 // if the slot holds zeros, else read-modify-write with the loads of a row of
 // blocks issued together (one memory latency per row, not one per value).
-template <int NW, int SHIFT>
-__device__ __forceinline__ void flush_owned(gw64 *tb, const Acc<NW> &acc, int wa, int cb0, bool fresh)
+template <int NW, int SHIFT, bool F>
+__device__ __forceinline__ void flush_owned(gw64 *tb, const Acc<NW, F> &acc, int wa, int cb0, bool fresh)
 {
     constexpr int BW = Layout<NW>::BW;
 #pragma unroll
@@ -565,7 +671,8 @@ __device__ __forceinline__ void flush_owned(gw64 *tb, const Acc<NW> &acc, int wa
         for (int b = 0; b < BW; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                blk[b][r * 64] = old[b][r] + pack_pair(acc.re[a][b][r] >> SHIFT, acc.im[a][b][r] >> SHIFT);
+                blk[b][r * 64] =
+                    old[b][r] + pack_pair(acc_val<SHIFT>(acc.re[a][b][r]), acc_val<SHIFT>(acc.im[a][b][r]));
         __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -573,10 +680,11 @@ __device__ __forceinline__ void flush_owned(gw64 *tb, const Acc<NW> &acc, int wa
 // Persistent kernel: workgroup w runs pieces [wg_off[w], wg_off[w+1]).  A
 // piece's tile field holds (I, J2): A rows 128 I.., B columns 256 J2.., i.e.
 // accumulator tiles (I, 2 J2) and (I, 2 J2 + 1) where they are in the upper
-// triangle.
-template <int NW, bool U = false>
+// triangle.  U: the unsigned form; F (with U): its FP8 products.
+template <int NW, bool U = false, bool F = false>
 __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
 {
+    static_assert(U || !F, "the FP8 form multiplies the unsigned nibbles");
     using L = Layout<NW>;
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     // a prepared batch's device guard refused this launch
@@ -645,7 +753,7 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
         // exported; small N and the edge tiles of N not a multiple of 256)
         const bool outside = WA_ROWS * ti + 64 * wa >= jd.n || WA_ROWS * tj + BLK * cb0 >= jd.n;
 
-        Acc<NW> acc;
+        Acc<NW, F> acc;
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -663,19 +771,19 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
             idle_piece<NW>(ring, tl, wave, lane);
         else if (jd.flags & JOB_RE_LOW) {
             if (diag)
-                run_piece<NW, true, true, U>(acc, ring, tl, wave, lane, a_lane, b_lane);
+                run_piece<NW, true, true, U, F>(acc, ring, tl, wave, lane, a_lane, b_lane);
             else
-                run_piece<NW, true, false, U>(acc, ring, tl, wave, lane, a_lane, b_lane);
+                run_piece<NW, true, false, U, F>(acc, ring, tl, wave, lane, a_lane, b_lane);
         } else {
             if (diag)
-                run_piece<NW, false, true, U>(acc, ring, tl, wave, lane, a_lane, b_lane);
+                run_piece<NW, false, true, U, F>(acc, ring, tl, wave, lane, a_lane, b_lane);
             else
-                run_piece<NW, false, false, U>(acc, ring, tl, wave, lane, a_lane, b_lane);
+                run_piece<NW, false, false, U, F>(acc, ring, tl, wave, lane, a_lane, b_lane);
         }
 
         if (valid && !below && !outside) {
             // the sums carry 256x the values (both operands 16x), or 8x in
-            // the unsigned form
+            // the unsigned form (the FP8 form's scale is undone in acc_val)
             constexpr int SHIFT = U ? 3 : 8;
             const int64_t tile_idx = (int64_t)ti * jd.nt - (int64_t)ti * (ti - 1) / 2 + (tj - ti);
             gw64 *tb = (gw64 *)(jd.acc + tile_idx * TILE_I32) + lane;
@@ -691,9 +799,9 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
                         __builtin_amdgcn_sched_barrier(0);
                     }
             } else if (jd.flags & JOB_FRESH) {
-                flush_owned<NW, SHIFT>(tb, acc, wa, cb0, true);
+                flush_owned<NW, SHIFT, F>(tb, acc, wa, cb0, true);
             } else {
-                flush_owned<NW, SHIFT>(tb, acc, wa, cb0, false);
+                flush_owned<NW, SHIFT, F>(tb, acc, wa, cb0, false);
             }
         }
     }
@@ -724,15 +832,23 @@ hipError_t init_dma_kernel()
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void *)dma::xcorr_dma<8, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 DMA_LDS_BYTES);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)dma::xcorr_dma<8, true, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, DMA_LDS_BYTES);
     return e;
 }
 
-// The unsigned form (pre-sum path): eight waves; `a.zeros` must then point
-// at zero bytes (nibbles u = 0), the zero sample of that form.
-hipError_t launch_correlate_dma_unsigned(const KernelArgs &a, int grid, hipStream_t stream)
+// The unsigned form (pre-sum path): eight waves, int8 or (fp8) FP8
+// products; `a.zeros` must then point at zero bytes (nibbles u = 0), the
+// zero sample of that form.  FP8 pieces must stay within
+// MAX_PIECE_STAGES_FP8_UNSIGNED stages.
+hipError_t launch_correlate_dma_unsigned(const KernelArgs &a, int grid, bool fp8, hipStream_t stream)
 {
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL((dma::xcorr_dma<8, true>), dim3(grid), dim3(64 * 8), DMA_LDS_BYTES, stream, a);
+    if (fp8)
+        hipLaunchKernelGGL((dma::xcorr_dma<8, true, true>), dim3(grid), dim3(64 * 8), DMA_LDS_BYTES, stream, a);
+    else
+        hipLaunchKernelGGL((dma::xcorr_dma<8, true>), dim3(grid), dim3(64 * 8), DMA_LDS_BYTES, stream, a);
     return hipGetLastError();
 }
 

@@ -1,8 +1,12 @@
-"""GPU parity of the exact FP8 path (XENG_KERNEL_FP8): every 4-bit value as
-its E4M3 code, products on the FP8 matrix cores with fp32 sums, pieces
-below 2^17 samples so that every sum is an exact integer.  Bit for bit
-against the CPU oracle: ragged shapes, both nibble orders, aligned and
-byte-addressed rows, pieces at the exactness bound with extreme samples,
+"""GPU parity of the exact FP8 paths (XENG_KERNEL_FP8).  Arrays the DMA
+kernel reads in place take the wide kernel's FP8 instance of the unsigned
+form: the stored nibbles are E4M3 codes as they are, fp32 sums stay exact
+below 2^24 over pieces of at most 582 stages, and the pre-sum correction
+brings them to the signed visibilities.  Batches and other arrays take the
+general kernel's FP8 instance: every signed 4-bit value as its E4M3 code,
+pieces below 2^17 samples.  Bit for bit against the CPU oracle: ragged
+shapes, both nibble orders on both kernels, aligned and byte-addressed
+rows, pieces at each kernel's exactness bound with extreme samples,
 batches, and a slot integrated by the int8 and the FP8 kernels in turn."""
 import numpy as np
 import pytest
@@ -51,8 +55,10 @@ def test_fp8_matches_oracle(X, fp8, n, t):
     np.testing.assert_array_equal(run(X, x), oracle.correlate(x))
 
 
-def test_fp8_re_low(X, fp8):
-    x = synth.uniform_bytes(200, 700, seed=5101)
+@pytest.mark.parametrize("n", [200, 256])
+def test_fp8_re_low(X, fp8, n):
+    # N = 200: the general kernel's instance; N = 256: the wide kernel's
+    x = synth.uniform_bytes(n, 700, seed=5101)
     np.testing.assert_array_equal(run(X, x, re_low=True), oracle.correlate(x, re_low=True))
 
 
@@ -69,18 +75,39 @@ def test_fp8_byte_addressed_rows(X, fp8):
 
 
 def test_fp8_pieces_at_the_exactness_bound(X):
-    # every sample (-8, -8): each pair adds 128 per sample.  One workgroup
+    # the general kernel's instance (rows at an odd byte offset): every
+    # sample (-8, -8), so each pair adds 128 per sample.  One workgroup
     # takes the whole job in pieces of 2047 stages (131008 samples), whose
     # fp32 sums reach 128 * 131008 = 16,769,024, just under 2^24; every
     # piece but the last is exactly that long
     n, t = 128, 2 * 131008 + 4000
-    x = np.zeros((t, n), dtype=np.uint8)
+    full = np.zeros((t, n + 1), dtype=np.uint8)
+    X.set_tuning(1, 1 << 20, X.XENG_KERNEL_FP8)
+    c = X.Correlator(n, 1)
+    try:
+        c.correlate(0, gpu(full)[:, 1:])
+        got = c.dump(0).cpu().numpy().astype(np.int64)
+    finally:
+        X.set_tuning(2, 4, X.XENG_KERNEL_AUTO)
+        c.close()
+    assert (got[:, 0] == 128 * t).all()
+    np.testing.assert_array_equal(got, oracle.correlate(full[:, 1:]))
+
+
+@pytest.mark.parametrize("byte", [0xFF, 0xF0])
+def test_fp8_wide_pieces_at_the_exactness_bound(X, byte):
+    # the wide kernel's instance: every stored nibble pair (15, 15) makes
+    # the unsigned real sums 450 per sample (or (15, 0): 225, with the
+    # imaginary parts of mixed pairs at their extreme); pieces of 582
+    # stages (37248 samples) reach 450 * 37248 = 16,761,600, just under 2^24
+    n, t = 256, 2 * 37248 + 4000
+    x = np.full((t, n), byte, dtype=np.uint8)
+    x[:, 1::3] = 0x0F
     X.set_tuning(1, 1 << 20, X.XENG_KERNEL_FP8)
     try:
         got = run(X, x)
     finally:
         X.set_tuning(2, 4, X.XENG_KERNEL_AUTO)
-    assert (got[:, 0] == 128 * t).all()
     np.testing.assert_array_equal(got, oracle.correlate(x))
 
 
@@ -105,9 +132,10 @@ def test_fp8_batch(X, fp8):
 
 
 def test_fp8_and_int8_on_one_slot(X):
-    # the int8 kernels store Im V_ij - S_j (the dump removes S_j through the
-    # diagonal), the FP8 kernel Im V_ij itself; a slot integrated by both in
-    # turn still exports exact visibilities
+    # the int8 kernels and the wide FP8 path store Im V_ij - S_j (the dump
+    # removes S_j through the diagonal), the general FP8 instance Im V_ij
+    # itself; a slot integrated by all of them in turn still exports exact
+    # visibilities
     n, t = 256, 3000
     x = synth.uniform_bytes(n, t, seed=5300)
     c = X.Correlator(n, 1)
@@ -115,9 +143,12 @@ def test_fp8_and_int8_on_one_slot(X):
         X.set_tuning(0, 0, X.XENG_KERNEL_AUTO)
         c.correlate(0, gpu(x[:1000]))
         X.set_tuning(0, 0, X.XENG_KERNEL_FP8)
-        c.correlate(0, gpu(x[1000:2200]))
+        c.correlate(0, gpu(x[1000:2200]))                                  # wide FP8
+        full = np.zeros((400, n + 3), dtype=np.uint8)
+        full[:, 3:] = x[2200:2600]
+        c.correlate(0, gpu(full)[:, 3:])                                   # general FP8
         X.set_tuning(0, 0, X.XENG_KERNEL_GENERAL)
-        c.correlate(0, gpu(x[2200:]))
+        c.correlate(0, gpu(x[2600:]))
         np.testing.assert_array_equal(c.dump(0).cpu().numpy().astype(np.int64), oracle.correlate(x))
     finally:
         X.set_tuning(2, 4, X.XENG_KERNEL_AUTO)

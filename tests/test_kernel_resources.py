@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(ROOT, "paper_2005_09481_amd", "csrc")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # mangled name -> most scratch bytes per lane allowed
-ALLOWED = {"_ZN4xeng3dma9xcorr_dmaILi4ELb0EEEvNS_10KernelArgsE": 128}
+ALLOWED = {"_ZN4xeng3dma9xcorr_dmaILi4ELb0ELb0EEEvNS_10KernelArgsE": 128}
 
 
 def remarks(src, out_dir):
