@@ -969,8 +969,9 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
 // The unsigned form with pre-sums, called with st->mu held and the device
 // current, the arguments checked and the guard passed: the wide kernel's
 // unsigned instance where the array allows the DMA kernel (and the tuning
-// does not ask for the general one), int8 or, with `fp8`, FP8 products; else
-// the general kernel's int8 instance.
+// does not ask for the general one), int8 or, with `fp8`, FP8 products,
+// which also forms the pre-sums; else the general kernel's int8 instance
+// after a pre-sum pass.
 int correlate_unsigned(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_t n_samples, int64_t row_stride,
                        const Tuning &tu, bool fp8, hipStream_t stream)
 {
@@ -997,7 +998,11 @@ int correlate_unsigned(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, in
         a.wg_off = dp.d_off;
         const uint32_t re_low = (ctx->flags & XENG_NIBBLE_RE_LOW) ? 1u : 0u;
         e = launch_zero(sums, 2 * n4, stream);
-        if (e == hipSuccess) e = launch_presum(d_samples, n_samples, ctx->n, row_stride, re_low, sums, sums + n4, stream);
+        // the wide kernel's diagonal waves form the pre-sums as they go;
+        // the general kernel's instance needs the pass over the samples
+        if (wide) a.presum = sums;
+        else if (e == hipSuccess)
+            e = launch_presum(d_samples, n_samples, ctx->n, row_stride, re_low, sums, sums + n4, stream);
         if (e == hipSuccess)
             e = wide ? launch_correlate_dma_unsigned(a, dp.grid, fp8, stream)
                      : launch_correlate_unsigned(a, dp.grid, (a.job0.flags & JOB_ALIGNED8) != 0, stream);

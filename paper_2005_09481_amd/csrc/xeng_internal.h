@@ -117,6 +117,8 @@ struct KernelArgs {
     const uint8_t *zeros;     // ZERO_BYTES bytes of zero samples (0x88), 16-byte aligned
     int64_t *clock;           // optional (DMA kernel): workgroup 0 stores {shader cycles, 100 MHz time} at start and end
     const int32_t *skip;      // optional: nonzero at launch time -> the launch integrates nothing
+    int32_t *presum;          // optional (the wide kernel's unsigned instances): SR, SI (n4 = N rounded
+                              // up to 4 apart) of the job's inputs, added to atomically
 };
 
 // Device-side integration guard of a prepared batch: one entry per job,

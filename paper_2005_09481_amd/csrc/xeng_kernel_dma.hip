@@ -405,6 +405,24 @@ __device__ __forceinline__ void unpack_k(Ops<NW> &o, const Raw<NW> &r)
     }
 }
 
+// Pre-sums of the unsigned form from the operands a wave multiplies: per A
+// block, this lane's row (lane % 32) over the k-step's samples it holds,
+// real nibbles (words 0, 1) and imaginary ones (words 2, 3), each a byte
+// sum by v_dot4_u32_u8 against ones.
+struct PreSum {
+    uint32_t r[2], i[2];
+};
+template <int NW> __device__ __forceinline__ void presum_k(PreSum &ps, const Ops<NW> &o)
+{
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        ps.r[a] = __builtin_amdgcn_udot4((uint32_t)o.a[a][0], 0x01010101u, ps.r[a], false);
+        ps.r[a] = __builtin_amdgcn_udot4((uint32_t)o.a[a][1], 0x01010101u, ps.r[a], false);
+        ps.i[a] = __builtin_amdgcn_udot4((uint32_t)o.a[a][2], 0x01010101u, ps.i[a], false);
+        ps.i[a] = __builtin_amdgcn_udot4((uint32_t)o.a[a][3], 0x01010101u, ps.i[a], false);
+    }
+}
+
 // DIAG: the wave's 2 x 2 blocks sit on the diagonal (eight waves, rows
 // 64 wa.. against columns 64 wa.. of a diagonal tile); block (1, 0) lies
 // strictly below it and is skipped.
@@ -501,10 +519,15 @@ __device__ __forceinline__ void wait_stage_and_sync()
 // the barrier of iteration s - 1; that barrier sits before the first read of
 // stage s.  The last iteration's reads of "stage ns" touch a slot whose
 // contents are never used.
+//
+// In the unsigned form the waves on the diagonal (DIAG) also add up the
+// nibbles of their A rows into `ps`, at the k-steps they multiply (the
+// reads of "stage ns" never count).
 template <int NW, bool RE_LOW, bool DIAG, bool U, bool F>
-__device__ __forceinline__ void run_piece(Acc<NW, F> &acc, uint32_t ring, const Tile &tl, int wave, int lane,
-                                          uint32_t a_lane, uint32_t b_lane)
+__device__ __forceinline__ void run_piece(Acc<NW, F> &acc, PreSum &ps, uint32_t ring, const Tile &tl, int wave,
+                                          int lane, uint32_t a_lane, uint32_t b_lane)
 {
+    constexpr bool SUMS = U && DIAG;
     const int ns = (tl.t1 - tl.t0 + STAGE - 1) / STAGE;
     DmaLane<NW> dl;
     dma_lane_setup<NW>(dl, tl, wave, lane);
@@ -542,6 +565,10 @@ __device__ __forceinline__ void run_piece(Acc<NW, F> &acc, uint32_t ring, const 
             read_k<NW>(r0, pa, pb, 2);
             read_k<NW>(r1, pa, pb, 3);
             mfma_pair<NW, DIAG>(acc, u0, u1);
+            if constexpr (SUMS) {
+                presum_k<NW>(ps, u0);
+                presum_k<NW>(ps, u1);
+            }
             __builtin_amdgcn_sched_barrier(0);
             // k-steps 2, 3; stage s + 1 must be in LDS before its first read
             unpack_k<NW, RE_LOW, U, F>(u0, r0);
@@ -550,6 +577,10 @@ __device__ __forceinline__ void run_piece(Acc<NW, F> &acc, uint32_t ring, const 
             read_k<NW>(r0, qa, qb, 0);
             read_k<NW>(r1, qa, qb, 1);
             mfma_pair<NW, DIAG>(acc, u0, u1);
+            if constexpr (SUMS) {
+                presum_k<NW>(ps, u0);
+                presum_k<NW>(ps, u1);
+            }
             __builtin_amdgcn_sched_barrier(0);
             cur = nxt;
         }
@@ -577,12 +608,14 @@ __device__ __forceinline__ void run_piece(Acc<NW, F> &acc, uint32_t ring, const 
             read_k<NW>(r0, pa, pb, 2);
             unpack_k<NW, RE_LOW, U, F>(u1, r1);
             mfma_k<NW, DIAG>(acc, u0);
+            if constexpr (SUMS) presum_k<NW>(ps, u0);
             kstep_schedule<NW, DIAG>();
             __builtin_amdgcn_sched_barrier(0);
             // k-step 1
             read_k<NW>(r1, pa, pb, 3);
             unpack_k<NW, RE_LOW, U, F>(u0, r0);
             mfma_k<NW, DIAG>(acc, u1);
+            if constexpr (SUMS) presum_k<NW>(ps, u1);
             kstep_schedule<NW, DIAG>();
             __builtin_amdgcn_sched_barrier(0);
             // k-step 2: stage s + 1 must be in LDS before its first read
@@ -590,12 +623,14 @@ __device__ __forceinline__ void run_piece(Acc<NW, F> &acc, uint32_t ring, const 
             read_k<NW>(r0, qa, qb, 0);
             unpack_k<NW, RE_LOW, U, F>(u1, r1);
             mfma_k<NW, DIAG>(acc, u0);
+            if constexpr (SUMS) presum_k<NW>(ps, u0);
             kstep_schedule<NW, DIAG>();
             __builtin_amdgcn_sched_barrier(0);
             // k-step 3
             read_k<NW>(r1, qa, qb, 1);
             unpack_k<NW, RE_LOW, U, F>(u0, r0);
             mfma_k<NW, DIAG>(acc, u1);
+            if constexpr (SUMS) presum_k<NW>(ps, u1);
             kstep_schedule<NW, DIAG>();
             __builtin_amdgcn_sched_barrier(0);
             cur = nxt;
@@ -754,6 +789,7 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
         const bool outside = WA_ROWS * ti + 64 * wa >= jd.n || WA_ROWS * tj + BLK * cb0 >= jd.n;
 
         Acc<NW, F> acc;
+        PreSum ps = {{0u, 0u}, {0u, 0u}};
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -771,14 +807,37 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
             idle_piece<NW>(ring, tl, wave, lane);
         else if (jd.flags & JOB_RE_LOW) {
             if (diag)
-                run_piece<NW, true, true, U, F>(acc, ring, tl, wave, lane, a_lane, b_lane);
+                run_piece<NW, true, true, U, F>(acc, ps, ring, tl, wave, lane, a_lane, b_lane);
             else
-                run_piece<NW, true, false, U, F>(acc, ring, tl, wave, lane, a_lane, b_lane);
+                run_piece<NW, true, false, U, F>(acc, ps, ring, tl, wave, lane, a_lane, b_lane);
         } else {
             if (diag)
-                run_piece<NW, false, true, U, F>(acc, ring, tl, wave, lane, a_lane, b_lane);
+                run_piece<NW, false, true, U, F>(acc, ps, ring, tl, wave, lane, a_lane, b_lane);
             else
-                run_piece<NW, false, false, U, F>(acc, ring, tl, wave, lane, a_lane, b_lane);
+                run_piece<NW, false, false, U, F>(acc, ps, ring, tl, wave, lane, a_lane, b_lane);
+        }
+
+        // unsigned form: the diagonal waves of a job's tiles see every A
+        // row of the job over every sample exactly once (each window's
+        // pieces split its samples; a diagonal wave is never idle while its
+        // rows hold inputs), so their nibble sums are the job's pre-sums;
+        // lanes l and l + 32 hold the same row
+        if constexpr (U) {
+            if (diag && args.presum != nullptr && !outside) {
+                const int n4 = (jd.n + 3) & ~3;
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const uint32_t r = ps.r[a] + (uint32_t)__shfl_xor((int)ps.r[a], 32);
+                    const uint32_t i = ps.i[a] + (uint32_t)__shfl_xor((int)ps.i[a], 32);
+                    const int row = WA_ROWS * ti + 64 * wa + 32 * a + lane;
+                    if (lane < 32 && row < jd.n) {
+                        __hip_atomic_fetch_add(args.presum + row, (int32_t)r, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_fetch_add(args.presum + n4 + row, (int32_t)i, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+            }
         }
 
         if (valid && !below && !outside) {
