@@ -7,7 +7,9 @@ general kernel's FP8 instance: every signed 4-bit value as its E4M3 code,
 pieces below 2^17 samples.  Bit for bit against the CPU oracle: ragged
 shapes, both nibble orders on both kernels, aligned and byte-addressed
 rows, pieces at each kernel's exactness bound with extreme samples,
-batches, and a slot integrated by the int8 and the FP8 kernels in turn."""
+batches, a slot integrated by the int8 and the FP8 kernels in turn, and
+the full-size N=2048 channel on both instances against the oracle's
+recorded digest."""
 import numpy as np
 import pytest
 
@@ -99,10 +101,14 @@ def test_fp8_wide_pieces_at_the_exactness_bound(X, byte):
     # the wide kernel's instance: every stored nibble pair (15, 15) makes
     # the unsigned real sums 450 per sample (or (15, 0): 225, with the
     # imaginary parts of mixed pairs at their extreme); pieces of 582
-    # stages (37248 samples) reach 450 * 37248 = 16,761,600, just under 2^24
+    # stages (37248 samples) reach 450 * 37248 = 16,761,600, just under
+    # 2^24.  Columns of (15, 14) give odd sums per sample (435 against
+    # (15, 15), 421 on their own diagonal), so pieces any longer would
+    # round in fp32 and fail
     n, t = 256, 2 * 37248 + 4000
     x = np.full((t, n), byte, dtype=np.uint8)
     x[:, 1::3] = 0x0F
+    x[:, 2::3] = 0xFE
     X.set_tuning(1, 1 << 20, X.XENG_KERNEL_FP8)
     try:
         got = run(X, x)
@@ -152,4 +158,25 @@ def test_fp8_and_int8_on_one_slot(X):
         np.testing.assert_array_equal(c.dump(0).cpu().numpy().astype(np.int64), oracle.correlate(x))
     finally:
         X.set_tuning(2, 4, X.XENG_KERNEL_AUTO)
+        c.close()
+
+
+@pytest.mark.parametrize("path", ["wide", "general"])
+def test_fp8_full_size_digest(X, fp8, path):
+    # the N=2048, T=32768 channel on each FP8 instance (the general one
+    # through a view at a one-byte offset), every pair against the oracle's
+    # recorded digest
+    import parity_util as pu
+    x = pu.fc.channel_n2048()
+    print(f"fp8 full size n=2048 t=32768 {path}", flush=True)
+    c = X.Correlator(2048, 1)
+    try:
+        if path == "wide":
+            c.correlate(0, gpu(x))
+        else:
+            full = np.zeros((x.shape[0], x.shape[1] + 1), dtype=np.uint8)
+            full[:, 1:] = x
+            c.correlate(0, gpu(full)[:, 1:])
+        pu.assert_matches_oracle_digest("channel_n2048_t32768", c.dump(0), x)
+    finally:
         c.close()
