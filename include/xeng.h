@@ -201,16 +201,20 @@ int xeng_dump_counts(xeng_ctx *ctx, int32_t slot, int32_t *out, void *hip_stream
  * computed in the paper's unsigned form (Sec. 2.3, "GPUs": low-bit
  * products at the cost of O(N) bookkeeping; Table tab:computing, "Re-Order
  * and Pre-Sum"): the matrix cores multiply the stored nibbles u = x + 8
- * (0..15) themselves, a pre-sum pass forms SR_i = sum_t uR_i and
- * SI_i = sum_t uI_i, and a correction pass adds, per pair,
+ * (0..15) themselves, the pre-sums SR_i = sum_t uR_i and SI_i = sum_t uI_i
+ * are added up per slot (by the wide kernel itself, else by a pass over
+ * the samples), and a correction adds, per pair,
  *   Re: -8 (SR_i + SI_i + SR_j + SI_j) + 128 T,
  *   Im:  8 (SR_i - SI_i) - 8 (SR_j - SI_j).
- * A second, independent route to the same integers on the GPU: the wide
- * kernel's unsigned instance where the array allows it in place (int8, or
- * FP8 under XENG_KERNEL_FP8), else the 128 x 128 kernel's (int8), which
- * XENG_KERNEL_GENERAL also selects.  Pre-sum scratch (8 N bytes) comes
- * from the library's pool; XENG_ENOMEM, nothing queued, if it cannot be
- * had.
+ * The correction is linear in (SR, SI, T), so it is applied once for all
+ * such calls on a slot, in stream order before the slot's next xeng_dump or
+ * xeng_dump_batch (on that call's stream, which must be ordered after
+ * them, as for any dump) or discarded by xeng_reset: a slot's exports are
+ * exactly those of xeng_correlate.  A second, independent route to the same
+ * integers on the GPU: the wide kernel's unsigned instance where the array
+ * allows it in place (int8, or FP8 under XENG_KERNEL_FP8), else the
+ * 128 x 128 kernel's (int8), which XENG_KERNEL_GENERAL also selects.  The
+ * per-slot pre-sums (8 N bytes) are allocated with the context.
  */
 int xeng_correlate_presum(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_t n_samples,
                           int64_t row_stride, void *hip_stream);

@@ -541,6 +541,13 @@ struct xeng_ctx {
     int64_t count_i32 = 0;       // N(N+1)/2 rounded up to a multiple of 4
     std::vector<int64_t> acc_t;
     std::vector<int64_t> flagged_t;   // samples integrated by flagged calls (their counts are in d_counts)
+    // the unsigned form (xeng_correlate_presum, FP8 calls on the wide
+    // kernel): per slot [SR | SI] (n4 = N rounded up to 4, each) of the
+    // samples integrated that way since the slot's correction was last
+    // applied, and their count; the correction is linear in (SR, SI, T), so
+    // it is applied once, before the slot is next read or cleared
+    int32_t *d_psum = nullptr;
+    std::vector<int64_t> psum_t;
     // live prepared batches naming each slot; while > 0 the slot's device
     // counter (advanced by the batches' device guard) is the true count and
     // acc_t is refreshed from it before any host-side check
@@ -972,50 +979,58 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
 // does not ask for the general one), int8 or, with `fp8`, FP8 products,
 // which also forms the pre-sums; else the general kernel's int8 instance
 // after a pre-sum pass.
+int64_t psum_n4(const xeng_ctx *c) { return ((int64_t)c->n + 3) / 4 * 4; }
+
+// The slot's pending unsigned-form correction (see xeng_ctx::d_psum) into
+// its accumulators, and its sums cleared; stream-ordered, before anything
+// reads the slot.  With `discard` (the slot is being cleared) only the
+// sums are cleared.
+hipError_t settle_presum(xeng_ctx *c, int32_t slot, hipStream_t stream, bool discard = false)
+{
+    if (c->psum_t[(size_t)slot] == 0) return hipSuccess;
+    const int64_t n4 = psum_n4(c);
+    int32_t *sums = c->d_psum + (int64_t)slot * 2 * n4;
+    hipError_t e = hipSuccess;
+    if (!discard)
+        e = launch_presum_correct(c->d_acc + (int64_t)slot * c->slot_i32, c->n, c->nt, c->psum_t[(size_t)slot], sums,
+                                  sums + n4, stream);
+    if (e == hipSuccess) e = launch_zero(sums, 2 * n4, stream);
+    if (e == hipSuccess) c->psum_t[(size_t)slot] = 0;
+    return e;
+}
+
 int correlate_unsigned(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, int64_t n_samples, int64_t row_stride,
                        const Tuning &tu, bool fp8, hipStream_t stream)
 {
-    hipMemPool_t pool = nullptr;
-    int rc = pad_pool(ctx->st, &pool);
-    if (rc != XENG_OK) return rc;
-    const int64_t n4 = ((int64_t)ctx->n + 3) / 4 * 4;
-    int32_t *sums = nullptr;   // [SR | SI], n4 each
-    hipError_t e = hipMallocFromPoolAsync(reinterpret_cast<void **>(&sums), (size_t)(2 * n4 * 4), pool, stream);
-    if (e != hipSuccess) return map_err(e);
+    const int64_t n4 = psum_n4(ctx);
+    int32_t *sums = ctx->d_psum + (int64_t)slot * 2 * n4;   // [SR | SI], accumulated across calls
     PlanJob pj{ctx->n, n_samples};
     DevicePlan dp;
     KernelArgs a{};
     a.job0 = make_job(ctx, slot, d_samples, row_stride, true);
     const bool wide = (a.job0.flags & JOB_DMA) != 0 && tu.kernel != XENG_KERNEL_GENERAL;
     fp8 = fp8 && wide;
-    rc = wide ? get_plan(ctx->st, &pj, 1, TileShape::Wide, tu, &dp,
-                         fp8 ? MAX_PIECE_STAGES_FP8_UNSIGNED : MAX_PIECE_STAGES_WIDE)
-              : get_plan(ctx->st, &pj, 1, TileShape::Square, tu, &dp, MAX_PIECE_STAGES_UNSIGNED);
-    if (rc == XENG_OK) {
-        // the unsigned form's zero sample is the nibble pair (0, 0)
-        a.zeros = ctx->st->d_zeros + ZERO_BYTES;
-        a.pieces = dp.d_pieces;
-        a.wg_off = dp.d_off;
-        const uint32_t re_low = (ctx->flags & XENG_NIBBLE_RE_LOW) ? 1u : 0u;
-        e = launch_zero(sums, 2 * n4, stream);
-        // the wide kernel's diagonal waves form the pre-sums as they go;
-        // the general kernel's instance needs the pass over the samples
-        if (wide) a.presum = sums;
-        else if (e == hipSuccess)
-            e = launch_presum(d_samples, n_samples, ctx->n, row_stride, re_low, sums, sums + n4, stream);
-        if (e == hipSuccess)
-            e = wide ? launch_correlate_dma_unsigned(a, dp.grid, fp8, stream)
-                     : launch_correlate_unsigned(a, dp.grid, (a.job0.flags & JOB_ALIGNED8) != 0, stream);
-        if (e == hipSuccess)
-            e = launch_presum_correct(ctx->d_acc + (int64_t)slot * ctx->slot_i32, ctx->n, ctx->nt, n_samples, sums,
-                                      sums + n4, stream);
-        if (e == hipSuccess) ctx->acc_t[(size_t)slot] += n_samples;
-        rc = map_err(e);
-    }
-    e = hipFreeAsync(sums, stream);
-    if (rc == XENG_OK && e != hipSuccess) rc = map_err(e);
-    if (rc == XENG_OK) rc = map_err(publish_count(ctx, slot, stream));
-    return rc;
+    int rc = wide ? get_plan(ctx->st, &pj, 1, TileShape::Wide, tu, &dp,
+                             fp8 ? MAX_PIECE_STAGES_FP8_UNSIGNED : MAX_PIECE_STAGES_WIDE)
+                  : get_plan(ctx->st, &pj, 1, TileShape::Square, tu, &dp, MAX_PIECE_STAGES_UNSIGNED);
+    if (rc != XENG_OK) return rc;
+    // the unsigned form's zero sample is the nibble pair (0, 0)
+    a.zeros = ctx->st->d_zeros + ZERO_BYTES;
+    a.pieces = dp.d_pieces;
+    a.wg_off = dp.d_off;
+    const uint32_t re_low = (ctx->flags & XENG_NIBBLE_RE_LOW) ? 1u : 0u;
+    // the wide kernel's diagonal waves add the pre-sums as they go; the
+    // general kernel's instance needs the pass over the samples
+    hipError_t e = hipSuccess;
+    if (wide) a.presum = sums;
+    else e = launch_presum(d_samples, n_samples, ctx->n, row_stride, re_low, sums, sums + n4, stream);
+    if (e == hipSuccess)
+        e = wide ? launch_correlate_dma_unsigned(a, dp.grid, fp8, stream)
+                 : launch_correlate_unsigned(a, dp.grid, (a.job0.flags & JOB_ALIGNED8) != 0, stream);
+    if (e != hipSuccess) return map_err(e);
+    ctx->acc_t[(size_t)slot] += n_samples;
+    ctx->psum_t[(size_t)slot] += n_samples;
+    return map_err(publish_count(ctx, slot, stream));
 }
 
 }  // namespace
@@ -1059,6 +1074,7 @@ int create_ctx(const xeng_config *cfg, hipStream_t stream, xeng_ctx **out)
     c->slot_i32 = slot_i32(cfg->n_inputs);
     c->acc_t.assign((size_t)cfg->n_slots, 0);
     c->flagged_t.assign((size_t)cfg->n_slots, 0);
+    c->psum_t.assign((size_t)cfg->n_slots, 0);
     c->bound.assign((size_t)cfg->n_slots, 0);
     c->count_i32 = count_i32;
     c->st = st;
@@ -1074,9 +1090,17 @@ int create_ctx(const xeng_config *cfg, hipStream_t stream, xeng_ctx **out)
         delete c;
         return map_err(e);
     }
+    const int64_t psum_i32 = (int64_t)cfg->n_slots * 2 * (((int64_t)cfg->n_inputs + 3) / 4 * 4);
+    if ((e = hipMalloc(&c->d_psum, (size_t)psum_i32 * 4)) != hipSuccess) {
+        (void)hipFree(c->d_acc);
+        (void)hipFree(c->d_count);
+        delete c;
+        return map_err(e);
+    }
     c->d_diag = c->d_acc + (int64_t)cfg->n_slots * c->slot_i32;
     if (count_i32) c->d_counts = c->d_diag + (int64_t)cfg->n_slots * diag_i32(cfg->n_inputs);
     e = launch_zero(c->d_acc, bytes / 4, stream);
+    if (e == hipSuccess) e = launch_zero(c->d_psum, psum_i32, stream);
     if (stream) {
         if (e == hipSuccess) e = launch_zero(reinterpret_cast<int32_t *>(c->d_count), 2 * n_count, stream);
     } else {
@@ -1086,6 +1110,7 @@ int create_ctx(const xeng_config *cfg, hipStream_t stream, xeng_ctx **out)
     if (e != hipSuccess) {
         (void)hipFree(c->d_acc);
         (void)hipFree(c->d_count);
+        (void)hipFree(c->d_psum);
         delete c;
         return map_err(e);
     }
@@ -1107,6 +1132,7 @@ int xeng_destroy(xeng_ctx *ctx)
         DeviceGuard guard(ctx->device);
         if (ctx->d_acc && hipFree(ctx->d_acc) != hipSuccess) rc = XENG_EDEVICE;
         if (ctx->d_count && hipFree(ctx->d_count) != hipSuccess) rc = XENG_EDEVICE;
+        if (ctx->d_psum && hipFree(ctx->d_psum) != hipSuccess) rc = XENG_EDEVICE;
     }
     delete ctx;
     return rc;
@@ -1345,7 +1371,8 @@ int xeng_dump(xeng_ctx *ctx, int32_t slot, int32_t *out, int32_t reset, void *hi
     if (rc != XENG_OK) return rc;
     int32_t *acc = ctx->d_acc + (int64_t)slot * ctx->slot_i32;
     int32_t *diag = ctx->d_diag + (int64_t)slot * diag_i32(ctx->n);
-    hipError_t e = launch_dump(acc, diag, ctx->n, ctx->nt, out, reset != 0, stream);
+    hipError_t e = settle_presum(ctx, slot, stream);
+    if (e == hipSuccess) e = launch_dump(acc, diag, ctx->n, ctx->nt, out, reset != 0, stream);
     if (e != hipSuccess) return map_err(e);
     if (reset) {
         ctx->acc_t[(size_t)slot] = 0;
@@ -1384,6 +1411,10 @@ int xeng_dump_batch(const xeng_dump_job *jobs, int32_t n_jobs, void *hip_stream)
     const int crc = refuse_capture(stream);
     if (crc != XENG_OK) return crc;
     std::lock_guard<std::mutex> lk(st->mu);
+    for (int32_t k = 0; k < n_jobs; ++k) {
+        const hipError_t e = settle_presum(jobs[k].ctx, jobs[k].slot, stream);
+        if (e != hipSuccess) return map_err(e);
+    }
     constexpr int32_t CHUNK = 65535;   // grid z limit
     for (int32_t k0 = 0; k0 < n_jobs; k0 += CHUNK) {
         const int32_t m = std::min(CHUNK, n_jobs - k0);
@@ -1423,6 +1454,7 @@ int xeng_reset(xeng_ctx *ctx, int32_t slot, void *hip_stream)
     const int rc = refuse_capture(stream);
     if (rc != XENG_OK) return rc;
     hipError_t e = launch_zero(ctx->d_acc + (int64_t)slot * ctx->slot_i32, ctx->slot_i32, stream);
+    if (e == hipSuccess) e = settle_presum(ctx, slot, stream, true);
     if (e == hipSuccess) e = reset_counts(ctx, slot, stream);
     if (e != hipSuccess) return map_err(e);
     ctx->acc_t[(size_t)slot] = 0;

@@ -5,8 +5,10 @@ and on the general kernel's, the pre-sums of aligned rows (16-byte loads,
 ragged column blocks and row slices) and of other arrays, both nibble
 orders, unaligned arrays, pieces split at the
 unsigned form's register bound, accumulation with the other kernels in one
-slot, the full integration bound where the unsigned sums pass int32, and the
-full-size N=2048 channel against the oracle's recorded digest."""
+slot, the correction applied once per dump (plain and batched exports, a
+dump without reset, a reset that discards it), the full integration bound
+where the unsigned sums pass int32, and the full-size N=2048 channel
+against the oracle's recorded digest."""
 import numpy as np
 import pytest
 
@@ -133,3 +135,64 @@ def test_presum_wide_and_general_kernels_agree(X):
 def test_presum_wide_re_low(X):
     x = synth.uniform_bytes(128, 1000, seed=48)
     np.testing.assert_array_equal(run(X, x, re_low=True), oracle.correlate(x, re_low=True))
+
+
+def test_presum_correction_applied_once_per_dump(X):
+    # the correction of several unsigned-form calls (the wide kernel's, the
+    # general kernel's through an unaligned view, and a signed call between
+    # them) is applied once, before the dump; a dump without reset applies
+    # it for good and later calls start a new one
+    n = 256
+    xs = [synth.uniform_bytes(n, t, seed=[49, t]) for t in (700, 300, 900, 500)]
+    c = X.Correlator(n, 1)
+    try:
+        c.correlate_presum(0, gpu(xs[0]))                          # wide
+        full = np.zeros((xs[1].shape[0], n + 3), dtype=np.uint8)
+        full[:, 3:] = xs[1]
+        c.correlate_presum(0, gpu(full)[:, 3:])                    # general, pre-sum pass
+        c.correlate(0, gpu(xs[2]))                                  # signed
+        got = c.dump(0, reset=False).cpu().numpy().astype(np.int64)
+        np.testing.assert_array_equal(got, oracle.correlate(np.concatenate(xs[:3])))
+        c.correlate_presum(0, gpu(xs[3]))
+        got = c.dump(0).cpu().numpy().astype(np.int64)
+        np.testing.assert_array_equal(got, oracle.correlate(np.concatenate(xs)))
+        c.correlate(0, gpu(xs[0]))                                  # after the reset: no correction left
+        np.testing.assert_array_equal(c.dump(0).cpu().numpy().astype(np.int64), oracle.correlate(xs[0]))
+    finally:
+        c.close()
+
+
+def test_presum_reset_discards_pending_correction(X):
+    n = 128
+    x1 = synth.uniform_bytes(n, 400, seed=50)
+    x2 = synth.uniform_bytes(n, 300, seed=51)
+    c = X.Correlator(n, 1)
+    try:
+        c.correlate_presum(0, gpu(x1))
+        c.reset(0)
+        c.correlate(0, gpu(x2))
+        np.testing.assert_array_equal(c.dump(0).cpu().numpy().astype(np.int64), oracle.correlate(x2))
+    finally:
+        c.close()
+
+
+def test_presum_pending_corrections_in_a_batched_dump(X):
+    # two contexts, three slots, pending corrections on two of them: one
+    # batched export applies each before its slot is read
+    a, b = X.Correlator(256, 2), X.Correlator(96, 1)
+    xa0 = synth.uniform_bytes(256, 600, seed=52)
+    xa1 = synth.uniform_bytes(256, 350, seed=53)
+    xb = synth.uniform_bytes(96, 800, seed=54)
+    try:
+        a.correlate_presum(0, gpu(xa0))
+        a.correlate(1, gpu(xa1))
+        b.correlate_presum(0, gpu(xb))
+        b.correlate_presum(0, gpu(xb))
+        outs = X.dump_batch([(a, 0), (a, 1), (b, 0)])
+        np.testing.assert_array_equal(outs[0].cpu().numpy().astype(np.int64), oracle.correlate(xa0))
+        np.testing.assert_array_equal(outs[1].cpu().numpy().astype(np.int64), oracle.correlate(xa1))
+        np.testing.assert_array_equal(outs[2].cpu().numpy().astype(np.int64),
+                                      oracle.correlate(np.concatenate([xb, xb])))
+    finally:
+        a.close()
+        b.close()
