@@ -289,7 +289,11 @@ int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
  *   sample counter after the export.  Asynchronous on hip_stream.  Exports
  *   of one slot must not run concurrently on different streams (they share
  *   the slot's diagonal staging, and a reset export writes the accumulators
- *   the other reads).
+ *   the other reads).  A slot integrated by xeng_correlate_presum (or an FP8
+ *   call on the wide kernel) since its last export first takes the pending
+ *   O(N) correction into its accumulators, on hip_stream (see
+ *   xeng_correlate_presum); xeng_dump_batch does the same per slot, and
+ *   xeng_reset discards it.
  */
 int xeng_dump(xeng_ctx *ctx, int32_t slot, int32_t *out, int32_t reset, void *hip_stream);
 
