@@ -45,6 +45,8 @@ hipError_t init_dma_kernel();
 hipError_t launch_dump(int32_t *acc, int32_t *diag, int n, int nt, int32_t *out, bool reset,
                        hipStream_t stream);
 hipError_t launch_dump_batch(const DumpDesc *d_jobs, int n_jobs, int n_max, int nt_max, hipStream_t stream);
+hipError_t launch_dump_corr(int32_t *acc, int32_t *diag, int n, int nt, int32_t *out, bool reset,
+                            const int32_t *sums, int n4, int64_t t, int32_t *other, hipStream_t stream);
 hipError_t launch_zero(int32_t *p, int64_t n_i32, hipStream_t stream);
 hipError_t launch_pad_rows(const uint8_t *src, int64_t stride, int n, int64_t rows, int n16, uint8_t *dst,
                            hipStream_t stream);
@@ -542,12 +544,16 @@ struct xeng_ctx {
     std::vector<int64_t> acc_t;
     std::vector<int64_t> flagged_t;   // samples integrated by flagged calls (their counts are in d_counts)
     // the unsigned form (xeng_correlate_presum, FP8 calls on the wide
-    // kernel): per slot [SR | SI] (n4 = N rounded up to 4, each) of the
-    // samples integrated that way since the slot's correction was last
-    // applied, and their count; the correction is linear in (SR, SI, T), so
-    // it is applied once, before the slot is next read or cleared
+    // kernel): per slot two buffers of [SR | SI] (n4 = N rounded up to 4,
+    // each); the current one sums the samples integrated that way since the
+    // slot's correction was last applied, psum_t counts them.  The
+    // correction is linear in (SR, SI, T), so it is applied once, before
+    // the slot is next read or cleared.  A resetting export applies it in
+    // its own kernels, clears the other buffer and makes it current (the one
+    // it read is cleared by the next such export).
     int32_t *d_psum = nullptr;
     std::vector<int64_t> psum_t;
+    std::vector<uint8_t> psum_cur;
     // live prepared batches naming each slot; while > 0 the slot's device
     // counter (advanced by the batches' device guard) is the true count and
     // acc_t is refreshed from it before any host-side check
@@ -980,6 +986,11 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
 // which also forms the pre-sums; else the general kernel's int8 instance
 // after a pre-sum pass.
 int64_t psum_n4(const xeng_ctx *c) { return ((int64_t)c->n + 3) / 4 * 4; }
+// Buffer `which` (0, 1) of the slot's pre-sums: [SR | SI].
+int32_t *psum_buf(const xeng_ctx *c, int32_t slot, int which)
+{
+    return c->d_psum + ((int64_t)slot * 2 + which) * 2 * psum_n4(c);
+}
 
 // The slot's pending unsigned-form correction (see xeng_ctx::d_psum) into
 // its accumulators, and its sums cleared; stream-ordered, before anything
@@ -989,7 +1000,7 @@ hipError_t settle_presum(xeng_ctx *c, int32_t slot, hipStream_t stream, bool dis
 {
     if (c->psum_t[(size_t)slot] == 0) return hipSuccess;
     const int64_t n4 = psum_n4(c);
-    int32_t *sums = c->d_psum + (int64_t)slot * 2 * n4;
+    int32_t *sums = psum_buf(c, slot, c->psum_cur[(size_t)slot]);
     hipError_t e = hipSuccess;
     if (!discard)
         e = launch_presum_correct(c->d_acc + (int64_t)slot * c->slot_i32, c->n, c->nt, c->psum_t[(size_t)slot], sums,
@@ -1003,7 +1014,7 @@ int correlate_unsigned(xeng_ctx *ctx, int32_t slot, const uint8_t *d_samples, in
                        const Tuning &tu, bool fp8, hipStream_t stream)
 {
     const int64_t n4 = psum_n4(ctx);
-    int32_t *sums = ctx->d_psum + (int64_t)slot * 2 * n4;   // [SR | SI], accumulated across calls
+    int32_t *sums = psum_buf(ctx, slot, ctx->psum_cur[(size_t)slot]);   // accumulated across calls
     PlanJob pj{ctx->n, n_samples};
     DevicePlan dp;
     KernelArgs a{};
@@ -1075,6 +1086,7 @@ int create_ctx(const xeng_config *cfg, hipStream_t stream, xeng_ctx **out)
     c->acc_t.assign((size_t)cfg->n_slots, 0);
     c->flagged_t.assign((size_t)cfg->n_slots, 0);
     c->psum_t.assign((size_t)cfg->n_slots, 0);
+    c->psum_cur.assign((size_t)cfg->n_slots, 0);
     c->bound.assign((size_t)cfg->n_slots, 0);
     c->count_i32 = count_i32;
     c->st = st;
@@ -1090,7 +1102,7 @@ int create_ctx(const xeng_config *cfg, hipStream_t stream, xeng_ctx **out)
         delete c;
         return map_err(e);
     }
-    const int64_t psum_i32 = (int64_t)cfg->n_slots * 2 * (((int64_t)cfg->n_inputs + 3) / 4 * 4);
+    const int64_t psum_i32 = (int64_t)cfg->n_slots * 4 * (((int64_t)cfg->n_inputs + 3) / 4 * 4);
     if ((e = hipMalloc(&c->d_psum, (size_t)psum_i32 * 4)) != hipSuccess) {
         (void)hipFree(c->d_acc);
         (void)hipFree(c->d_count);
@@ -1371,8 +1383,20 @@ int xeng_dump(xeng_ctx *ctx, int32_t slot, int32_t *out, int32_t reset, void *hi
     if (rc != XENG_OK) return rc;
     int32_t *acc = ctx->d_acc + (int64_t)slot * ctx->slot_i32;
     int32_t *diag = ctx->d_diag + (int64_t)slot * diag_i32(ctx->n);
-    hipError_t e = settle_presum(ctx, slot, stream);
-    if (e == hipSuccess) e = launch_dump(acc, diag, ctx->n, ctx->nt, out, reset != 0, stream);
+    hipError_t e = hipSuccess;
+    if (reset && ctx->psum_t[(size_t)slot] > 0) {
+        // the pending correction inside the export itself
+        const int cur = ctx->psum_cur[(size_t)slot];
+        e = launch_dump_corr(acc, diag, ctx->n, ctx->nt, out, true, psum_buf(ctx, slot, cur), (int)psum_n4(ctx),
+                             ctx->psum_t[(size_t)slot], psum_buf(ctx, slot, 1 - cur), stream);
+        if (e == hipSuccess) {
+            ctx->psum_cur[(size_t)slot] = (uint8_t)(1 - cur);
+            ctx->psum_t[(size_t)slot] = 0;
+        }
+    } else {
+        e = settle_presum(ctx, slot, stream);
+        if (e == hipSuccess) e = launch_dump(acc, diag, ctx->n, ctx->nt, out, reset != 0, stream);
+    }
     if (e != hipSuccess) return map_err(e);
     if (reset) {
         ctx->acc_t[(size_t)slot] = 0;

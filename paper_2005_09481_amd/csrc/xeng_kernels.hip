@@ -574,9 +574,30 @@ constexpr int DUMP_ROWS = 4;
 constexpr int DUMP_PARTS = BLK / DUMP_ROWS;
 constexpr int DUMP_PARTS_PER_TILE = 4 * DUMP_PARTS;   // workgroups per tile
 
+// A pending unsigned-form correction (CORR; see presum_correct): per
+// input, SR at sums[i] and SI at sums[n4 + i] over the t samples that form
+// contributed.  It is added to each staged word in the packed 64-bit form,
+// before the word is split into (Re, Im): the uncorrected real part may have
+// passed the int32 range, which the split would carry into Im.
+struct PendingCorr {
+    const int32_t *sums;
+    int n4;
+    int64_t t;
+};
+__device__ __forceinline__ uint64_t corr_word(const PendingCorr &pc, int n, int i, int j)
+{
+    const int64_t ri = i < n ? pc.sums[i] : 0, ii = i < n ? pc.sums[pc.n4 + i] : 0;
+    const int64_t rj = j < n ? pc.sums[j] : 0, ij = j < n ? pc.sums[pc.n4 + j] : 0;
+    const int64_t d_re = -8 * (ri + ii + rj + ij) + 128 * pc.t;
+    const int64_t d_im = 8 * (ri - ii) - 8 * (rj - ij);
+    return ((uint64_t)d_im << 32) + (uint64_t)d_re;
+}
+
+template <bool CORR = false>
 __device__ __forceinline__ void dump_block_row(int32_t *__restrict__ acc, int n, int nt,
                                                const int32_t *__restrict__ d, int32_t *__restrict__ out,
-                                               int reset, int bx, int by, int2 *stage)
+                                               int reset, int bx, int by, int2 *stage,
+                                               const PendingCorr &pc = PendingCorr{nullptr, 0, 0})
 {
     const int ti = by;
     const int tj = ti + bx / DUMP_PARTS_PER_TILE;
@@ -594,8 +615,13 @@ __device__ __forceinline__ void dump_block_row(int32_t *__restrict__ acc, int n,
         int4 *pw = reinterpret_cast<int4 *>(base);
         const int4 w = *pw;
         if (reset) *pw = make_int4(0, 0, 0, 0);
-        const uint64_t w0 = (uint64_t)(uint32_t)w.x | ((uint64_t)(uint32_t)w.y << 32);
-        const uint64_t w1 = (uint64_t)(uint32_t)w.z | ((uint64_t)(uint32_t)w.w << 32);
+        uint64_t w0 = (uint64_t)(uint32_t)w.x | ((uint64_t)(uint32_t)w.y << 32);
+        uint64_t w1 = (uint64_t)(uint32_t)w.z | ((uint64_t)(uint32_t)w.w << 32);
+        if constexpr (CORR) {
+            const int i = TILE * ti + BLK * ca + ra, j0 = TILE * tj + BLK * cb + cj0;
+            w0 += corr_word(pc, n, i, j0);
+            w1 += corr_word(pc, n, i, j0 + 1);
+        }
         int2 *row = stage + ri * DUMP_PITCH + BLK * cb + cj0;
         row[0] = make_int2(pair_re(w0), pair_im(w0));
         row[1] = make_int2(pair_re(w1), pair_im(w1));
@@ -622,6 +648,32 @@ __global__ __launch_bounds__(256) void vis_dump(int32_t *__restrict__ acc, int n
 {
     __shared__ int2 stage[DUMP_ROWS * DUMP_PITCH];
     dump_block_row(acc, n, nt, d, out, reset, blockIdx.x, blockIdx.y, stage);
+}
+
+// The export of a slot with a pending unsigned-form correction: the
+// diagonal words corrected before d[j] is taken (their imaginary part gets
+// no correction, their real part may have wrapped), and `other` (the slot's
+// second pre-sum buffer, 2 n4 int32, which the next calls of that form will
+// use) cleared.  The unsigned form's contributions carry no imaginary bias,
+// so d[j] stays that of the signed calls alone.
+__global__ __launch_bounds__(256) void diag_im_corr(const int32_t *__restrict__ acc, int n, int nt,
+                                                    int32_t *__restrict__ d, PendingCorr pc,
+                                                    int32_t *__restrict__ other)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j < n) {
+        const uint64_t w = reinterpret_cast<const uint64_t *>(acc)[acc_word(j, j, nt)];
+        d[j] = pair_im(w + corr_word(pc, n, j, j));
+    }
+    if (j < 2 * pc.n4) other[j] = 0;
+}
+
+__global__ __launch_bounds__(256) void vis_dump_corr(int32_t *__restrict__ acc, int n, int nt,
+                                                     const int32_t *__restrict__ d, int32_t *__restrict__ out,
+                                                     int reset, PendingCorr pc)
+{
+    __shared__ int2 stage[DUMP_ROWS * DUMP_PITCH];
+    dump_block_row<true>(acc, n, nt, d, out, reset, blockIdx.x, blockIdx.y, stage, pc);
 }
 
 // Batched export: job blockIdx.z of the descriptor table, the grid sized
@@ -820,6 +872,19 @@ hipError_t launch_dump(int32_t *acc, int32_t *diag, int n, int nt, int32_t *out,
     hipLaunchKernelGGL(diag_im, dim3((n + 255) / 256), dim3(256), 0, stream, acc, n, nt, diag);
     hipLaunchKernelGGL(vis_dump, dim3(DUMP_PARTS_PER_TILE * nt, nt), dim3(256), 0, stream, acc, n, nt, diag, out,
                        reset ? 1 : 0);
+    return hipGetLastError();
+}
+
+// An export that also applies a slot's pending unsigned-form correction
+// (`sums`: its SR, SI over `t` samples, n4 apart) and clears `other`.
+hipError_t launch_dump_corr(int32_t *acc, int32_t *diag, int n, int nt, int32_t *out, bool reset,
+                            const int32_t *sums, int n4, int64_t t, int32_t *other, hipStream_t stream)
+{
+    const PendingCorr pc{sums, n4, t};
+    const int threads = n > 2 * n4 ? n : 2 * n4;
+    hipLaunchKernelGGL(diag_im_corr, dim3((threads + 255) / 256), dim3(256), 0, stream, acc, n, nt, diag, pc, other);
+    hipLaunchKernelGGL(vis_dump_corr, dim3(DUMP_PARTS_PER_TILE * nt, nt), dim3(256), 0, stream, acc, n, nt, diag,
+                       out, reset ? 1 : 0, pc);
     return hipGetLastError();
 }
 

@@ -196,3 +196,32 @@ def test_presum_pending_corrections_in_a_batched_dump(X):
     finally:
         a.close()
         b.close()
+
+
+def test_presum_exports_in_a_row(X):
+    # resetting exports apply the correction in their own kernels and switch
+    # the slot between its two pre-sum buffers (clearing the one the next
+    # calls use): four exports in a row, each of a different mix of calls,
+    # FP8 included, every one against the oracle
+    n = 192
+    xs = [synth.uniform_bytes(n, t, seed=[55, t]) for t in (640, 330, 700, 257, 901, 64)]
+    c = X.Correlator(n, 1)
+    try:
+        c.correlate_presum(0, gpu(xs[0]))
+        np.testing.assert_array_equal(c.dump(0).cpu().numpy().astype(np.int64), oracle.correlate(xs[0]))
+        c.correlate_presum(0, gpu(xs[1]))
+        c.correlate_presum(0, gpu(xs[2]))
+        np.testing.assert_array_equal(c.dump(0).cpu().numpy().astype(np.int64),
+                                      oracle.correlate(np.concatenate(xs[1:3])))
+        c.correlate(0, gpu(xs[3]))
+        X.set_tuning(0, 0, X.XENG_KERNEL_FP8)
+        try:
+            c.correlate(0, gpu(xs[4]))                                      # FP8: the unsigned form
+        finally:
+            X.set_tuning(0, 0, X.XENG_KERNEL_AUTO)
+        np.testing.assert_array_equal(c.dump(0).cpu().numpy().astype(np.int64),
+                                      oracle.correlate(np.concatenate(xs[3:5])))
+        c.correlate_presum(0, gpu(xs[5]))
+        np.testing.assert_array_equal(c.dump(0).cpu().numpy().astype(np.int64), oracle.correlate(xs[5]))
+    finally:
+        c.close()
