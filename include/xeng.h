@@ -290,10 +290,10 @@ int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
  *   of one slot must not run concurrently on different streams (they share
  *   the slot's diagonal staging, and a reset export writes the accumulators
  *   the other reads).  A slot integrated by xeng_correlate_presum (or an FP8
- *   call on the wide kernel) since its last export first takes the pending
- *   O(N) correction into its accumulators, on hip_stream (see
- *   xeng_correlate_presum); xeng_dump_batch does the same per slot, and
- *   xeng_reset discards it.
+ *   call on the wide kernel) since its last export gets the pending O(N)
+ *   correction (see xeng_correlate_presum) on hip_stream: inside the export
+ *   when it resets, else into the accumulators first; xeng_dump_batch
+ *   applies it per slot before its export, and xeng_reset discards it.
  */
 int xeng_dump(xeng_ctx *ctx, int32_t slot, int32_t *out, int32_t reset, void *hip_stream);
 
