@@ -207,10 +207,10 @@ int xeng_dump_counts(xeng_ctx *ctx, int32_t slot, int32_t *out, void *hip_stream
  *   Re: -8 (SR_i + SI_i + SR_j + SI_j) + 128 T,
  *   Im:  8 (SR_i - SI_i) - 8 (SR_j - SI_j).
  * The correction is linear in (SR, SI, T), so it is applied once for all
- * such calls on a slot, in stream order before the slot's next xeng_dump or
- * xeng_dump_batch (on that call's stream, which must be ordered after
- * them, as for any dump) or discarded by xeng_reset: a slot's exports are
- * exactly those of xeng_correlate.  A second, independent route to the same
+ * such calls on a slot, by the slot's next xeng_dump or xeng_dump_batch (on
+ * that call's stream, which must be ordered after them, as for any dump),
+ * or discarded by xeng_reset: a slot's exports are exactly those of
+ * xeng_correlate.  A second, independent route to the same
  * integers on the GPU: the wide kernel's unsigned instance where the array
  * allows it in place (int8, or FP8 under XENG_KERNEL_FP8), else the
  * 128 x 128 kernel's (int8), which XENG_KERNEL_GENERAL also selects.  The
