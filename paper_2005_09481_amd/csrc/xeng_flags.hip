@@ -168,27 +168,32 @@ __global__ __launch_bounds__(256) void mask_rows(const uint8_t *__restrict__ src
     }
 }
 
-// Unflagged masks, bit-packed along blocks: bits[i][w] bit k = block 32 w + k
-// of input i is unflagged.
+// Unflagged masks packed along blocks: bits[i][w] bit k set when block
+// 32 w + k of input i is unflagged.  One wave per (two inputs, word): lane l
+// reads block 32 w + l % 32 of input i0 + l / 32, and one ballot of the
+// unflagged lanes holds both inputs' words.
 __global__ __launch_bounds__(256) void pack_unflagged(const uint8_t *__restrict__ flags, int nb, int n, int words,
                                                       uint32_t *__restrict__ bits)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    const int w = blockIdx.y;
-    if (i >= n) return;
-    uint32_t v = 0;
-    for (int k = 0; k < 32; ++k) {
-        const int b = 32 * w + k;
-        if (b < nb && flags[(int64_t)b * n + i] == 0) v |= 1u << k;
-    }
-    bits[(int64_t)i * words + w] = v;
+    const int lane = (int)threadIdx.x & 63;
+    const int64_t wv = (int64_t)blockIdx.x * 4 + ((int)threadIdx.x >> 6);
+    const int64_t pairs = (n + 1) / 2;
+    if (wv >= pairs * words) return;   // whole waves
+    const int w = (int)(wv % words), i0 = 2 * (int)(wv / words);
+    const int i = i0 + (lane >> 5), b = 32 * w + (lane & 31);
+    const bool unflagged = i < n && b < nb && flags[(int64_t)b * n + i] == 0;
+    const uint64_t m = __ballot(unflagged);
+    if (lane == 0) bits[(int64_t)i0 * words + w] = (uint32_t)m;
+    if (lane == 32 && i < n) bits[(int64_t)i * words + w] = (uint32_t)(m >> 32);
 }
 
 // Per-pair sample counts added into counts[k(i, j)] (packed upper triangle).
 // A workgroup takes a 64 x 64 block of pairs (row block by, column block
-// bx >= by), a thread 4 x 4 pairs; the masks of the 64 + 64 inputs go
-// through LDS in chunks of CW words.  Blocks 0 .. nb-2 weigh block_len each,
-// the last `last_len`.
+// bx >= by); thread (ty, tx) takes rows 4 ty .. + 3 and columns tx + 16 q
+// (q < 4), so that each row's 64 counts are updated by 16 consecutive
+// threads at a time.  The masks of the 64 + 64 inputs go through LDS in
+// chunks of up to CW words.  Blocks 0 .. nb-2 weigh block_len each, the
+// last `last_len`.
 constexpr int CW = 32;
 __global__ __launch_bounds__(256) void count_pairs(const uint32_t *__restrict__ bits, int words, int nb, int n,
                                                    int block_len, int last_len, int32_t *__restrict__ counts)
@@ -202,22 +207,22 @@ __global__ __launch_bounds__(256) void count_pairs(const uint32_t *__restrict__ 
     const int last_w = (nb - 1) >> 5;
     const uint32_t last_bit = 1u << ((nb - 1) & 31);
     for (int w0 = 0; w0 < words; w0 += CW) {
-        for (int e = tid; e < 64 * CW; e += 256) {
-            const int r = e / CW, w = e % CW;
+        const int cw = words - w0 < CW ? words - w0 : CW;
+        for (int e = tid; e < 64 * cw; e += 256) {
+            const int r = e / cw, w = e % cw;
             const int ia = 64 * by + r, ib = 64 * bx + r;
-            const bool inw = w0 + w < words;
-            ra[r][w] = (ia < n && inw) ? bits[(int64_t)ia * words + w0 + w] : 0u;
-            cb[r][w] = (ib < n && inw) ? bits[(int64_t)ib * words + w0 + w] : 0u;
+            ra[r][w] = ia < n ? bits[(int64_t)ia * words + w0 + w] : 0u;
+            cb[r][w] = ib < n ? bits[(int64_t)ib * words + w0 + w] : 0u;
         }
         __syncthreads();
-        for (int w = 0; w < CW && w0 + w < words; ++w) {
+        for (int w = 0; w < cw; ++w) {
             // the last block counts with its own length, below
             const uint32_t keep = (w0 + w == last_w) ? ~last_bit : 0xFFFFFFFFu;
             uint32_t a[4], b[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 a[k] = ra[4 * ty + k][w] & keep;
-                b[k] = cb[4 * tx + k][w];
+                b[k] = cb[tx + 16 * k][w];
             }
 #pragma unroll
             for (int p = 0; p < 4; ++p)
@@ -226,18 +231,23 @@ __global__ __launch_bounds__(256) void count_pairs(const uint32_t *__restrict__ 
         }
         __syncthreads();
     }
+    bool lj[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = 64 * bx + tx + 16 * q;
+        lj[q] = j < n && (bits[(int64_t)j * words + last_w] & last_bit) != 0;
+    }
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const int i = 64 * by + 4 * ty + p;
         if (i >= n) continue;
         const bool li = (bits[(int64_t)i * words + last_w] & last_bit) != 0;
+        const int64_t row = (int64_t)i * n - (int64_t)i * (i - 1) / 2 - i;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int j = 64 * bx + 4 * tx + q;
+            const int j = 64 * bx + tx + 16 * q;
             if (j >= n || j < i) continue;
-            const bool lj = (bits[(int64_t)j * words + last_w] & last_bit) != 0;
-            const int64_t k = (int64_t)i * n - (int64_t)i * (i - 1) / 2 + (j - i);
-            counts[k] += c[p][q] * block_len + ((li && lj) ? last_len : 0);
+            counts[row + j] += c[p][q] * block_len + ((li && lj[q]) ? last_len : 0);
         }
     }
 }
@@ -290,8 +300,9 @@ hipError_t launch_counts(const uint8_t *flags, int nb, int n, int block_len, int
 {
     if (nb <= 0) return hipSuccess;
     const int words = (nb + 31) / 32;
-    hipLaunchKernelGGL(pack_unflagged, dim3((unsigned)((n + 255) / 256), (unsigned)words), dim3(256), 0, stream,
-                       flags, nb, n, words, bits);
+    const int64_t waves = (int64_t)((n + 1) / 2) * words;   // one per (two inputs, word)
+    hipLaunchKernelGGL(pack_unflagged, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, stream, flags, nb, n, words,
+                       bits);
     const unsigned tiles = (unsigned)((n + 63) / 64);
     hipLaunchKernelGGL(count_pairs, dim3(tiles, tiles), dim3(256), 0, stream, bits, words, nb, n, block_len,
                        last_len, counts);
