@@ -27,9 +27,10 @@
 
 namespace xeng {
 // The correlation kernels: general (128 x 128 tiles, any layout), wide
-// (DMA, 128 x 256), narrow (N <= 64, time split over the waves) and the
-// general kernel's exact FP8 instance.
-enum class Kind { General, Wide, Narrow, Fp8 };
+// (DMA, 128 x 256), narrow (N <= 64, time split over the waves), the
+// general kernel's exact FP8 instance and the wide kernel's (the unsigned
+// form, for batch jobs whose slot pre-sums are set up).
+enum class Kind { General, Wide, Narrow, Fp8, WideFp8 };
 
 hipError_t launch_correlate(const KernelArgs &a, int grid, bool aligned, hipStream_t stream);
 hipError_t launch_correlate_unsigned(const KernelArgs &a, int grid, bool aligned, hipStream_t stream);
@@ -623,6 +624,7 @@ JobDesc make_job(const xeng_ctx *c, int32_t slot, const uint8_t *d_samples, int6
     if ((stride % 16) == 0 && (addr % 16) == 0 && c->n % 16 == 0) jd.flags |= JOB_DMA;
     if (may_store && c->acc_t[(size_t)slot] == 0 && c->bound[(size_t)slot] == 0) jd.flags |= JOB_FRESH;
     jd.pad = 0;
+    jd.presum = nullptr;
     return jd;
 }
 
@@ -637,27 +639,36 @@ bool use_dma(uint32_t flags, const Tuning &tu)
 
 Kind kind_of(const JobDesc &jd, const Tuning &tu)
 {
-    if (tu.kernel == XENG_KERNEL_FP8) return Kind::Fp8;
+    // FP8: the wide kernel's instance of the unsigned form for jobs whose
+    // caller set up the slot's pre-sums (eager batches), else the general
+    // kernel's
+    if (tu.kernel == XENG_KERNEL_FP8) return (jd.flags & JOB_DMA) && jd.presum ? Kind::WideFp8 : Kind::Fp8;
     if (!use_dma(jd.flags, tu)) return Kind::General;
     return jd.n <= NARROW_MAX_N ? Kind::Narrow : Kind::Wide;
 }
 
 TileShape shape_of(Kind k)
 {
-    return k == Kind::Wide ? TileShape::Wide : k == Kind::Narrow ? TileShape::Narrow : TileShape::Square;
+    return k == Kind::Wide || k == Kind::WideFp8 ? TileShape::Wide
+           : k == Kind::Narrow                   ? TileShape::Narrow
+                                                 : TileShape::Square;
 }
 
 // Longest piece of a kernel, in stages (0: its shape's default).  The FP8
 // instance's fp32 sums stay exact integers below 2^24: at most 128 per
 // sample, so pieces below 2^17 samples.
 constexpr int64_t MAX_PIECE_STAGES_FP8 = ((1 << 17) - 1) / STAGE;   // 2047 stages
-int64_t cap_of(Kind k) { return k == Kind::Fp8 ? MAX_PIECE_STAGES_FP8 : 0; }
+int64_t cap_of(Kind k)
+{
+    return k == Kind::Fp8 ? MAX_PIECE_STAGES_FP8 : k == Kind::WideFp8 ? MAX_PIECE_STAGES_FP8_UNSIGNED : 0;
+}
 
 hipError_t launch(const KernelArgs &a, int32_t grid, Kind kind, int waves, uint32_t flags_and, hipStream_t stream)
 {
     if (kind == Kind::Wide) return launch_correlate_dma(a, grid, waves, stream);
     if (kind == Kind::Narrow) return launch_correlate_narrow(a, grid, stream);
     if (kind == Kind::Fp8) return launch_correlate_fp8(a, grid, (flags_and & JOB_ALIGNED8) != 0, stream);
+    if (kind == Kind::WideFp8) return launch_correlate_dma_unsigned(a, grid, true, stream);
     return launch_correlate(a, grid, (flags_and & JOB_ALIGNED8) != 0, stream);
 }
 
@@ -805,7 +816,9 @@ struct Part {
 int pad_batch_jobs(JobList &jl, const Tuning &tu, hipStream_t stream, uint8_t **scratch)
 {
     *scratch = nullptr;
-    if (tu.kernel == XENG_KERNEL_GENERAL) return XENG_OK;
+    // (FP8 jobs read in place: the general kernel's instance any array, the
+    // wide kernel's the arrays it takes as they are)
+    if (tu.kernel == XENG_KERNEL_GENERAL || tu.kernel == XENG_KERNEL_FP8) return XENG_OK;
     std::vector<size_t> pick;
     std::vector<int64_t> off;
     int64_t total = 0;
@@ -850,10 +863,11 @@ bool any_dma_job(const JobList &jl)
 
 std::vector<Part> split_by_kernel(const JobList &jl, const Tuning &tu)
 {
-    Part by_kind[4];
+    Part by_kind[5];
     by_kind[(int)Kind::Wide].kind = Kind::Wide;
     by_kind[(int)Kind::Narrow].kind = Kind::Narrow;
     by_kind[(int)Kind::Fp8].kind = Kind::Fp8;
+    by_kind[(int)Kind::WideFp8].kind = Kind::WideFp8;
     for (size_t k = 0; k < jl.descs.size(); ++k) {
         Part &p = by_kind[(int)kind_of(jl.descs[k], tu)];
         p.pj.push_back(jl.pj[k]);
@@ -861,7 +875,7 @@ std::vector<Part> split_by_kernel(const JobList &jl, const Tuning &tu)
         p.flags_and &= jl.descs[k].flags;
     }
     std::vector<Part> parts;
-    for (Kind k : {Kind::Wide, Kind::Narrow, Kind::General, Kind::Fp8})
+    for (Kind k : {Kind::Wide, Kind::Narrow, Kind::General, Kind::Fp8, Kind::WideFp8})
         if (!by_kind[(int)k].descs.empty()) parts.push_back(std::move(by_kind[(int)k]));
     return parts;
 }
@@ -959,7 +973,8 @@ int run_parts(DeviceState *st, const std::vector<Part> &parts, const Tuning &tu,
         sg.bytes = bytes;
         sg.a = KernelArgs{};
         sg.a.jobs = reinterpret_cast<const JobDesc *>(tbp->d);
-        sg.a.zeros = st->d_zeros;
+        // the unsigned form's zero sample is the nibble pair (0, 0)
+        sg.a.zeros = part.kind == Kind::WideFp8 ? st->d_zeros + ZERO_BYTES : st->d_zeros;
         sg.a.clock = st->clock.load();
         sg.a.pieces = reinterpret_cast<const Piece *>(tbp->d + o_pieces);
         sg.a.wg_off = reinterpret_cast<const int32_t *>(tbp->d + o_off);
@@ -1357,6 +1372,15 @@ int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
     if (rc != XENG_OK || jl.descs.empty()) return rc;
     std::lock_guard<std::mutex> lk(jl.st->mu);
     const Tuning tu = tuning_for(jl.st, jl.pj.data(), (int)jl.pj.size(), any_dma_job(jl));
+    // FP8 on arrays the wide kernel reads in place: its instance of the
+    // unsigned form, adding into the slot's current pre-sums (the
+    // correction follows at the slot's export)
+    if (tu.kernel == XENG_KERNEL_FP8)
+        for (size_t d = 0; d < jl.descs.size(); ++d)
+            if (jl.descs[d].flags & JOB_DMA) {
+                const xeng_job &j = jobs[jl.idx[d]];
+                jl.descs[d].presum = psum_buf(j.ctx, j.slot, j.ctx->psum_cur[(size_t)j.slot]);
+            }
     uint8_t *scratch = nullptr;
     rc = pad_batch_jobs(jl, tu, stream, &scratch);
     if (rc == XENG_OK) rc = run_parts(jl.st, split_by_kernel(jl, tu), tu, stream);
@@ -1365,6 +1389,8 @@ int xeng_correlate_batch(const xeng_job *jobs, int32_t n_jobs, void *hip_stream)
         if (rc == XENG_OK && e != hipSuccess) rc = map_err(e);
     }
     if (rc != XENG_OK) return rc;
+    for (size_t d = 0; d < jl.descs.size(); ++d)
+        if (jl.descs[d].presum) jobs[jl.idx[d]].ctx->psum_t[(size_t)jobs[jl.idx[d]].slot] += jobs[jl.idx[d]].n_samples;
     for (int32_t k : jl.idx) {
         jobs[k].ctx->acc_t[(size_t)jobs[k].slot] += jobs[k].n_samples;
         const hipError_t e = publish_count(jobs[k].ctx, jobs[k].slot, stream);

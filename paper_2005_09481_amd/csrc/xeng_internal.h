@@ -88,6 +88,8 @@ struct JobDesc {
     int32_t nt;               // tiles per side
     uint32_t flags;           // JOB_* bits
     int32_t pad;
+    int32_t *presum;          // optional: the slot's pre-sums ([SR | SI], N rounded up to 4 apart) for the
+                              // wide kernel's FP8 instance of the unsigned form in a batch
 };
 constexpr uint32_t JOB_RE_LOW = 1u;    // real part in the low nibble
 constexpr uint32_t JOB_ALIGNED8 = 2u;   // samples, stride and N are multiples of 8 bytes

@@ -823,7 +823,8 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
         // rows hold inputs), so their nibble sums are the job's pre-sums;
         // lanes l and l + 32 hold the same row
         if constexpr (U) {
-            if (diag && args.presum != nullptr && !outside) {
+            int32_t *const presum = args.presum != nullptr ? args.presum : jd.presum;
+            if (diag && presum != nullptr && !outside) {
                 const int n4 = (jd.n + 3) & ~3;
 #pragma unroll
                 for (int a = 0; a < 2; ++a) {
@@ -831,9 +832,9 @@ __global__ __launch_bounds__(64 * NW, 1) void xcorr_dma(KernelArgs args)
                     const uint32_t i = ps.i[a] + (uint32_t)__shfl_xor((int)ps.i[a], 32);
                     const int row = WA_ROWS * ti + 64 * wa + 32 * a + lane;
                     if (lane < 32 && row < jd.n) {
-                        __hip_atomic_fetch_add(args.presum + row, (int32_t)r, __ATOMIC_RELAXED,
+                        __hip_atomic_fetch_add(presum + row, (int32_t)r, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_fetch_add(args.presum + n4 + row, (int32_t)i, __ATOMIC_RELAXED,
+                        __hip_atomic_fetch_add(presum + n4 + row, (int32_t)i, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }

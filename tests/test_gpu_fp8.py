@@ -180,3 +180,34 @@ def test_fp8_full_size_digest(X, fp8, path):
         pu.assert_matches_oracle_digest("channel_n2048_t32768", c.dump(0), x)
     finally:
         c.close()
+
+
+def test_fp8_batches_eager_and_prepared(X, fp8):
+    # eager batches take the wide kernel's FP8 instance for the arrays it
+    # reads in place (N = 128, 96), whose pre-sums add up in the slots over
+    # two calls and are corrected at a batched export, and the general
+    # kernel's for the rest (N = 100); prepared batches take the general
+    # kernel's instance throughout
+    shapes = [(128, 900), (96, 333), (100, 500)]
+    xs = [synth.uniform_bytes(n, t, seed=5400 + i) for i, (n, t) in enumerate(shapes)]
+    refs = [oracle.correlate(np.concatenate([x, x])) for x in xs]
+    cs = [X.Correlator(n, 1) for n, _ in shapes]
+    bufs = [gpu(x) for x in xs]
+    try:
+        X.correlate_batch([(c, 0, b) for c, b in zip(cs, bufs)])
+        X.correlate_batch([(c, 0, b) for c, b in zip(cs, bufs)])
+        outs = X.dump_batch([(c, 0) for c in cs])
+        for o, r in zip(outs, refs):
+            np.testing.assert_array_equal(o.cpu().numpy().astype(np.int64), r)
+        b = X.Batch([(c, 0, t) for c, t in zip(cs, bufs)])
+        try:
+            b.launch()
+            b.launch()
+            assert b.check() == X.XENG_OK
+            for c, r in zip(cs, refs):
+                np.testing.assert_array_equal(c.dump(0).cpu().numpy().astype(np.int64), r)
+        finally:
+            b.close()
+    finally:
+        for c in cs:
+            c.close()
