@@ -627,7 +627,10 @@ int xeng_server_export_ring(xeng_server *s, int32_t channel, int32_t *ring, int3
  * the unsigned form on the wide kernel's FP8 instance: a stored nibble u is
  * the E4M3 code of u * 2^-9 as it stands (subnormals and the first binade),
  * its negation the same code with the sign bit set; pieces of at most 582
- * stages; the O(N) pre-sum correction of xeng_correlate_presum.  Batches
+ * stages; the O(N) pre-sum correction of xeng_correlate_presum.  Jobs of
+ * xeng_correlate_batch that the wide kernel reads in place do the same
+ * (their slots' pre-sums add up, the correction follows at the export).
+ * Prepared batches (xeng_batch_*, whose replays the library does not see)
  * and other arrays take the general kernel's FP8 instance: each signed
  * 4-bit value as its E4M3 code, pieces below 2^17 samples.  The same
  * results as every other kernel.
